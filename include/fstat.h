@@ -1,0 +1,186 @@
+/*
+ * fstat.h - C ABI of the MI355X (gfx950) resampling F-statistic library.
+ *
+ * The library computes the F-statistic of arXiv:2201.00451 (Sec. 2, eq. Fstat)
+ * by the resampling algorithm of Sec. 3, steps (iii)-(vii), for many templates
+ * over the full frequency band of a heterodyned, downsampled complex series.
+ *
+ * Units: times in seconds on one time base, angles in radians, frequencies in
+ * Hz, distances in light-seconds.  All device pointers are HIP device memory
+ * owned by the caller; the library allocates no device memory, frees nothing
+ * it did not allocate, and never synchronises the stream except where stated.
+ * Every call is asynchronous on the stream given (a hipStream_t passed as
+ * void*, NULL = the null stream).  Every function returns an fstat_status;
+ * on failure no kernel has been launched and fstat_last_error() returns a
+ * thread-local message.  Nothing is thrown across this boundary.
+ */
+#ifndef FSTAT_H
+#define FSTAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define FSTAT_API __attribute__((visibility("default")))
+#else
+#define FSTAT_API
+#endif
+
+#define FSTAT_MAX_DET 4
+#define FSTAT_TEMPLATE_STRIDE 8
+
+typedef enum {
+  FSTAT_OK = 0,
+  FSTAT_EINVAL = -1,       /* an argument is invalid (null, out of range, inconsistent) */
+  FSTAT_EUNSUPPORTED = -2, /* valid, but outside what this build implements */
+  FSTAT_EWORKSPACE = -3,   /* workspace smaller than fstat_workspace_size() */
+  FSTAT_EHIP = -4          /* the HIP runtime reported an error */
+} fstat_status;
+
+/* One detector: its site (for a(t), b(t) of Sec. 2 and the Roemer delay t_m)
+ * and its input series x_h(t^k) of step (ii), sampled at t0 + j*dt. */
+typedef struct {
+  double lat;       /* geocentric latitude */
+  double lon;       /* east longitude */
+  double az_x;      /* azimuth of the x arm, counter-clockwise from local East */
+  double az_y;      /* azimuth of the y arm; arms are orthogonal */
+  double t0;        /* time of sample 0 */
+  int64_t n;        /* number of samples, >= 1 */
+  double noise_var; /* E|n|^2 of the complex noise; the weight is 1/noise_var (Sec. 2, S_h) */
+} fstat_detector;
+
+/* Search set-up shared by every template (host memory, copied at plan creation). */
+typedef struct {
+  int32_t ndet;                        /* 1..FSTAT_MAX_DET */
+  int32_t sinc_halfwidth;              /* D: the step (v) interpolation uses 2D taps, 2..32 */
+  fstat_detector det[FSTAT_MAX_DET];
+  double dt;                           /* sample step of the inputs and of the source-frame grid (step iv) */
+  double f_het;                        /* heterodyne frequency f_h of step (ii) */
+  double t_ref;                        /* reference time of the spin-down Taylor series Phi_s */
+  double tau0;                         /* source-frame grid origin: tau_k = tau0 + k*dt (step iv) */
+  double max_delay;                    /* bound on |t_src - t| over every template and sample */
+  double sid_angle0;                   /* sidereal angle of the prime meridian at t = 0 */
+  double sid_rate;                     /* sidereal rotation rate (rad/s) */
+  int64_t n_fft;                       /* FFT length (step vi, zero-padded): power of two, 2^12..2^24 */
+  int64_t bin_lo;                      /* first output bin of the ascending band, 0 <= bin_lo */
+  int64_t n_bins;                      /* output bins; bin_lo + n_bins <= n_fft.  Bin i is at
+                                          f_het + df + (i - n_fft/2)/(n_fft*dt) (Sec. 3: one pass
+                                          gives the band centred on f_h) */
+  /* Launch-shape tuning of the step (vi) FFT (0 = automatic).  They change
+   * only how the work is laid out, never the result beyond FP32 rounding:
+   *   tune_col_log_len: log2 of the column-pass FFT length, the row pass has
+   *     log2(n_fft) - tune_col_log_len; both must lie in [6, 12];
+   *   tune_col_lines: columns per workgroup of the column pass;
+   *   tune_row_lines: rows per workgroup of the row pass.
+   * Accepted line counts are the automatic value or half of it. */
+  int32_t tune_col_log_len;
+  int32_t tune_col_lines;
+  int32_t tune_row_lines;
+  uint32_t flags;                      /* reserved, must be 0 */
+} fstat_plan_desc;
+
+/* Device-resident data, crossed to the device once (Sec. 3: the host-to-device
+ * copy happens only between steps (ii) and (iii)). */
+typedef struct {
+  const void* x[FSTAT_MAX_DET];        /* float2 [det.n]: heterodyned series, zero in gaps */
+  const uint8_t* valid[FSTAT_MAX_DET]; /* uint8 [det.n]: 1 = science sample; NULL = all valid */
+  const double* ephem[FSTAT_MAX_DET];  /* double [n_eph][6]: detector position (light-s) and
+                                          velocity (light-s/s) in the equatorial barycentric frame
+                                          at eph_t0 + i*eph_dt, interpolated cubically */
+  int64_t n_eph;
+  double eph_t0;
+  double eph_dt;
+  const double* moments;               /* double [ndet][10] from fstat_antenna_moments(); read
+                                          by fstat_compute_2f* for A, B, C of eq. Fstat */
+} fstat_inputs;
+
+typedef struct fstat_plan fstat_plan;  /* opaque, host memory owned by the library */
+
+/* Validate a set-up and build a plan.  Fails with FSTAT_EINVAL when: ndet out of
+ * range; dt, noise_var or sid_rate not positive and finite; n_fft not a power of
+ * two in [2^12, 2^24]; the band [bin_lo, bin_lo+n_bins) not inside [0, n_fft) or
+ * empty; D out of [2, 32]; the source-frame grid [tau0, tau0 + n_fft*dt) does not
+ * cover every sample's source time widened by max_delay; flags != 0. */
+FSTAT_API fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out);
+FSTAT_API void fstat_plan_destroy(fstat_plan* plan);
+
+/* Bytes of device workspace for `batch` templates in flight (batch >= 1).
+ * The plain path needs batch = 1; larger workspaces let the batched path keep
+ * more templates in flight. */
+FSTAT_API fstat_status fstat_workspace_size(const fstat_plan* plan, int64_t batch, size_t* bytes);
+
+/* A, B, C of eq. Fstat (Sec. 2) are noise-weighted sums over the valid samples
+ * of products of a(t), b(t).  With a, b trigonometric polynomials of degree 2 in
+ * the local sidereal angle phi_X(t), every such sum follows from the five
+ * per-detector moments M_n = sum_j valid_j exp(i n phi_X(t_j)), n = 0..4.  This
+ * call computes them once per data set: moments[X][2n], moments[X][2n+1] =
+ * Re, Im M_n.  Uses the workspace; deterministic (fixed reduction order). */
+FSTAT_API fstat_status fstat_antenna_moments(const fstat_plan* plan, const fstat_inputs* in,
+                                   double* moments, void* workspace, size_t ws_bytes,
+                                   void* stream);
+
+/* Plain path (Sec. 3, steps (iii)-(vii), one template after another): for each
+ * template row p[8] = (alpha, delta, df, f1dot, f2dot, asini, porb, tp) of the
+ * device array `templates` [ntmpl][8]:
+ *   (iii) correct each input sample by exp(-2 pi i f_h (t_src - t)),
+ *   (iv)  find the detector epochs T_k of the regular source-frame grid tau_k
+ *         through the Roemer delay and the circular binary delay
+ *         asini*sin(2 pi (t_src - tp)/porb) (asini = 0: isolated source),
+ *   (v)   interpolate with a Hann-windowed sinc of half-width D,
+ *   (vi)  weight by a(T_k), b(T_k) and 1/noise_var, sum detectors, remove the
+ *         spin-down phase Phi_s(tau_k) (about t_ref) and the sub-bin offset df,
+ *         and Fourier transform (length n_fft),
+ *   (vii) form 2F = 2 (B|Fa|^2 + A|Fb|^2 - 2C Re(Fa Fb*)) / (AB - C^2).
+ * Output twoF: float [ntmpl][n_bins] on the device, ascending frequency.
+ * fafb (nullable): float2 [ntmpl][2][n_bins] receives Fa then Fb.
+ * A template whose delays exceed max_delay, or whose parameters are not finite,
+ * gets NaN in every bin.  Needs fstat_workspace_size(plan, 1). */
+FSTAT_API fstat_status fstat_compute_2f(const fstat_plan* plan, const fstat_inputs* in,
+                              const double* templates, int64_t ntmpl, float* twoF, void* fafb,
+                              void* workspace, size_t ws_bytes, void* stream);
+
+/* Batched path: the same result as fstat_compute_2f (bit-identical: same
+ * kernels, same arithmetic), with as many templates in flight per launch as
+ * the workspace holds (Sec. 6 names searching several templates at once as an
+ * optimisation the CUDA code did not make). */
+FSTAT_API fstat_status fstat_compute_2f_batched(const fstat_plan* plan, const fstat_inputs* in,
+                                      const double* templates, int64_t ntmpl, float* twoF,
+                                      void* fafb, void* workspace, size_t ws_bytes,
+                                      void* stream);
+
+/* fstat_compute_2f_batched with per-kernel timing: HIP events are recorded on
+ * `stream` around every launch and, after synchronising the stream, the
+ * summed device time of each kernel is returned in kernel_ms[4] (prologue,
+ * resample, column FFT pass, row FFT pass with 2F) and the launch counts in
+ * launches[4].  max_batch (>= 1) caps the templates in flight per launch
+ * (1 = the plain per-template path).  Synchronises the stream. */
+FSTAT_API fstat_status fstat_compute_2f_profiled(const fstat_plan* plan, const fstat_inputs* in,
+                                       const double* templates, int64_t ntmpl, float* twoF,
+                                       void* workspace, size_t ws_bytes, int64_t max_batch,
+                                       void* stream, float* kernel_ms, int64_t* launches);
+
+/* Diagnostic: steps (iii)-(v) and the weighting of (vi) only.  Writes the
+ * weighted, resampled series before the transform, y: float2 [ntmpl][2][n_fft]
+ * (y_a then y_b, zero beyond the data).  Needs fstat_workspace_size(plan, 1). */
+FSTAT_API fstat_status fstat_resample(const fstat_plan* plan, const fstat_inputs* in,
+                            const double* templates, int64_t ntmpl, void* y, void* workspace,
+                            size_t ws_bytes, void* stream);
+
+/* Wait for the stream and report any asynchronous HIP error as FSTAT_EHIP. */
+FSTAT_API fstat_status fstat_sync_check(void* stream);
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+FSTAT_API const char* fstat_last_error(void);
+
+/* Library version string. */
+FSTAT_API const char* fstat_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSTAT_H */

@@ -354,15 +354,23 @@ def direct_twoF(ds, tm, freqs):
 # Comparison metrics of Sec. 4.2
 # ----------------------------------------------------------------------------
 
+def _f64(v):
+    v = np.ravel(v)
+    return v.astype(np.complex128) if np.iscomplexobj(v) else v.astype(np.float64)
+
+
 def rel_err(x, y, p):
-    """r_p(x, y) = 2 |x - y|_p / (|x|_p + |y|_p)."""
-    x, y = np.ravel(x), np.ravel(y)
+    """r_p(x, y) = 2 |x - y|_p / (|x|_p + |y|_p), evaluated in float64."""
+    x, y = _f64(x), _f64(y)
     n = lambda v: np.linalg.norm(v, ord=p)
     return 2.0 * n(x - y) / (n(x) + n(y))
 
 
 def angle(x, y):
-    """theta = arccos[Re(x* . y) / (|x|_2 |y|_2)]."""
-    x, y = np.ravel(x), np.ravel(y)
-    c = np.real(np.vdot(x, y)) / (np.linalg.norm(x) * np.linalg.norm(y))
-    return float(np.arccos(np.clip(c, -1.0, 1.0)))
+    """theta = arccos[Re(x* . y) / (|x|_2 |y|_2)]: the angle between x and y
+    as real vectors, evaluated in float64 as 2 atan2(|u - v|, |u + v|) on the
+    unit vectors u, v (the same angle, without arccos's loss near 0)."""
+    x, y = _f64(x), _f64(y)
+    u = x / np.linalg.norm(x)
+    v = y / np.linalg.norm(y)
+    return float(2.0 * np.arctan2(np.linalg.norm(u - v), np.linalg.norm(u + v)))

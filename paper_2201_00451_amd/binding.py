@@ -1,0 +1,259 @@
+"""ctypes binding of the C ABI in include/fstat.h.
+
+Argument marshalling only: torch supplies device memory and streams, every
+step of the computation runs in the HIP library.  If the library is missing
+the functions raise; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfstat.so")
+MAX_DET = 4
+TEMPLATE_STRIDE = 8
+
+FSTAT_OK, FSTAT_EINVAL, FSTAT_EUNSUPPORTED, FSTAT_EWORKSPACE, FSTAT_EHIP = 0, -1, -2, -3, -4
+
+EXPORTED = ("fstat_plan_create", "fstat_plan_destroy", "fstat_workspace_size",
+            "fstat_antenna_moments", "fstat_compute_2f", "fstat_compute_2f_batched",
+            "fstat_compute_2f_profiled", "fstat_resample", "fstat_sync_check",
+            "fstat_last_error", "fstat_version")
+
+
+class FstatDetector(ctypes.Structure):
+    _fields_ = [("lat", ctypes.c_double), ("lon", ctypes.c_double), ("az_x", ctypes.c_double),
+                ("az_y", ctypes.c_double), ("t0", ctypes.c_double), ("n", ctypes.c_int64),
+                ("noise_var", ctypes.c_double)]
+
+
+class FstatPlanDesc(ctypes.Structure):
+    _fields_ = [("ndet", ctypes.c_int32), ("sinc_halfwidth", ctypes.c_int32),
+                ("det", FstatDetector * MAX_DET), ("dt", ctypes.c_double),
+                ("f_het", ctypes.c_double), ("t_ref", ctypes.c_double), ("tau0", ctypes.c_double),
+                ("max_delay", ctypes.c_double), ("sid_angle0", ctypes.c_double),
+                ("sid_rate", ctypes.c_double), ("n_fft", ctypes.c_int64),
+                ("bin_lo", ctypes.c_int64), ("n_bins", ctypes.c_int64),
+                ("tune_col_log_len", ctypes.c_int32), ("tune_col_lines", ctypes.c_int32),
+                ("tune_row_lines", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class FstatInputs(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p * MAX_DET), ("valid", ctypes.c_void_p * MAX_DET),
+                ("ephem", ctypes.c_void_p * MAX_DET), ("n_eph", ctypes.c_int64),
+                ("eph_t0", ctypes.c_double), ("eph_dt", ctypes.c_double),
+                ("moments", ctypes.c_void_p)]
+
+
+class FstatError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fstat status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libfstat.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FstatError(FSTAT_EUNSUPPORTED,
+                         f"{path} not built; run __graft_entry__.build() or "
+                         "python paper_2201_00451_amd/build.py")
+    lib = ctypes.CDLL(path)
+    vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+    lib.fstat_plan_create.argtypes = [ctypes.POINTER(FstatPlanDesc), ctypes.POINTER(vp)]
+    lib.fstat_plan_destroy.argtypes = [vp]
+    lib.fstat_plan_destroy.restype = None
+    lib.fstat_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
+    lib.fstat_antenna_moments.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, vp, sz, vp]
+    for name in ("fstat_compute_2f", "fstat_compute_2f_batched"):
+        getattr(lib, name).argtypes = [vp, ctypes.POINTER(FstatInputs), vp, i64, vp, vp, vp, sz, vp]
+    lib.fstat_compute_2f_profiled.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, i64, vp, vp,
+                                              sz, i64, vp, ctypes.POINTER(ctypes.c_float),
+                                              ctypes.POINTER(ctypes.c_int64)]
+    lib.fstat_resample.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, i64, vp, vp, sz, vp]
+    lib.fstat_sync_check.argtypes = [vp]
+    lib.fstat_last_error.restype = ctypes.c_char_p
+    lib.fstat_last_error.argtypes = []
+    lib.fstat_version.restype = ctypes.c_char_p
+    lib.fstat_version.argtypes = []
+    for name in EXPORTED:
+        if name not in ("fstat_plan_destroy", "fstat_last_error", "fstat_version"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != FSTAT_OK:
+        raise FstatError(status, load_library().fstat_last_error().decode())
+
+
+def last_error() -> str:
+    return load_library().fstat_last_error().decode()
+
+
+def version() -> str:
+    return load_library().fstat_version().decode()
+
+
+def make_plan_desc(ds, tune=None) -> FstatPlanDesc:
+    """Plan descriptor from a search description (see synth.Dataset).
+    tune: optional dict of tune_col_log_len / tune_col_lines / tune_row_lines."""
+    d = FstatPlanDesc()
+    d.ndet = len(ds.detectors)
+    d.sinc_halfwidth = int(ds.sinc_halfwidth)
+    for i, det in enumerate(ds.detectors):
+        d.det[i] = FstatDetector(det.lat, det.lon, det.az_x, det.az_y, det.t0, det.n, det.noise_var)
+    d.dt, d.f_het, d.t_ref, d.tau0 = ds.dt, ds.f_het, ds.t_ref, ds.tau0
+    d.max_delay = ds.max_delay
+    d.sid_angle0 = ds.ephem_model["sidereal_angle0_rad"]
+    d.sid_rate = ds.ephem_model["sidereal_rate_rad_s"]
+    d.n_fft, d.bin_lo, d.n_bins, d.flags = ds.n_fft, ds.bin_lo, ds.n_bins, 0
+    for k, v in (tune or {}).items():
+        setattr(d, k, int(v))
+    return d
+
+
+class Plan:
+    """Owns an fstat_plan handle."""
+
+    def __init__(self, desc: FstatPlanDesc):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.fstat_plan_create(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        self.desc = desc
+
+    def workspace_size(self, batch: int = 1) -> int:
+        out = ctypes.c_size_t()
+        _check(load_library().fstat_workspace_size(self.handle, int(batch), ctypes.byref(out)))
+        return int(out.value)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fstat_plan_destroy(self.handle)
+            self.handle = None
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class DeviceData:
+    """Device copies of a data set (copied once), the antenna moments and a
+    workspace, bound to a plan.  ``ds`` follows synth.Dataset's fields."""
+
+    def __init__(self, ds, device="cuda:0", batch=1, stream=None, tune=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise FstatError(FSTAT_EUNSUPPORTED, "no HIP device visible to torch")
+        self.device = torch.device(device)
+        self.plan = Plan(make_plan_desc(ds, tune))
+        self.ndet = len(ds.detectors)
+        self.n_fft, self.n_bins = int(ds.n_fft), int(ds.n_bins)
+        dev = self.device
+        self.x = [torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).to(dev)
+                  for x in ds.x]
+        self.valid = [torch.from_numpy(np.ascontiguousarray(v, dtype=np.uint8)).to(dev)
+                      for v in ds.valid]
+        self.ephem = [torch.from_numpy(np.ascontiguousarray(t, dtype=np.float64)).to(dev)
+                      for t in ds.eph_tables]
+        self.moments = torch.zeros((self.ndet, 10), dtype=torch.float64, device=dev)
+        self.inputs = FstatInputs()
+        for i in range(self.ndet):
+            self.inputs.x[i] = self.x[i].data_ptr()
+            self.inputs.valid[i] = self.valid[i].data_ptr()
+            self.inputs.ephem[i] = self.ephem[i].data_ptr()
+        self.inputs.n_eph = int(ds.eph_tables[0].shape[0])
+        self.inputs.eph_t0, self.inputs.eph_dt = float(ds.eph_t0), float(ds.eph_dt)
+        self.inputs.moments = self.moments.data_ptr()
+        self.set_batch(batch)
+        antenna_moments(self, stream)
+
+    def set_batch(self, batch):
+        import torch
+        nbytes = self.plan.workspace_size(batch)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.batch = batch
+
+
+def antenna_moments(dd: DeviceData, stream=None):
+    _check(load_library().fstat_antenna_moments(
+        dd.plan.handle, ctypes.byref(dd.inputs), _ptr(dd.moments), _ptr(dd.ws), dd.ws.numel(),
+        _stream_ptr(stream)))
+    return dd.moments
+
+
+def _templates(dd, templates):
+    import torch
+    t = torch.as_tensor(templates, dtype=torch.float64)
+    if t.dim() != 2 or t.shape[1] != TEMPLATE_STRIDE:
+        raise FstatError(FSTAT_EINVAL, "templates must have shape [n, 8]")
+    return t.to(dd.device).contiguous()
+
+
+def compute_2f(dd: DeviceData, templates, fafb=False, batched=False, out=None, stream=None):
+    """2F [n, n_bins] float32 on the device (and Fa, Fb [n, 2, n_bins] complex64)."""
+    import torch
+    tm = _templates(dd, templates)
+    n = tm.shape[0]
+    tf = out if out is not None else torch.empty((n, dd.n_bins), dtype=torch.float32,
+                                                 device=dd.device)
+    fab = torch.empty((n, 2, dd.n_bins), dtype=torch.complex64, device=dd.device) if fafb else None
+    fn = load_library().fstat_compute_2f_batched if batched else load_library().fstat_compute_2f
+    _check(fn(dd.plan.handle, ctypes.byref(dd.inputs), _ptr(tm), n, _ptr(tf), _ptr(fab),
+              _ptr(dd.ws), dd.ws.numel(), _stream_ptr(stream)))
+    return (tf, fab) if fafb else tf
+
+
+def compute_2f_batched(dd: DeviceData, templates, fafb=False, out=None, stream=None):
+    return compute_2f(dd, templates, fafb=fafb, batched=True, out=out, stream=stream)
+
+
+KERNELS = ("prologue", "resample", "fft_columns", "fft_rows_2f")
+
+
+def compute_2f_profiled(dd: DeviceData, templates, max_batch=None, out=None, stream=None):
+    """compute_2f_batched plus per-kernel device time (ms) and launch counts.
+    Synchronises the stream."""
+    import torch
+    tm = _templates(dd, templates)
+    n = tm.shape[0]
+    tf = out if out is not None else torch.empty((n, dd.n_bins), dtype=torch.float32,
+                                                 device=dd.device)
+    ms = (ctypes.c_float * 4)()
+    cnt = (ctypes.c_int64 * 4)()
+    mb = dd.batch if max_batch is None else int(max_batch)
+    _check(load_library().fstat_compute_2f_profiled(
+        dd.plan.handle, ctypes.byref(dd.inputs), _ptr(tm), n, _ptr(tf), _ptr(dd.ws), dd.ws.numel(),
+        mb, _stream_ptr(stream), ms, cnt))
+    return tf, {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNELS)}
+
+
+def resample(dd: DeviceData, templates, stream=None):
+    """Weighted resampled series y [n, 2, n_fft] complex64 (diagnostic)."""
+    import torch
+    tm = _templates(dd, templates)
+    n = tm.shape[0]
+    y = torch.empty((n, 2, dd.n_fft), dtype=torch.complex64, device=dd.device)
+    _check(load_library().fstat_resample(dd.plan.handle, ctypes.byref(dd.inputs), _ptr(tm), n,
+                                         _ptr(y), _ptr(dd.ws), dd.ws.numel(), _stream_ptr(stream)))
+    return y
+
+
+def sync_check(stream=None):
+    _check(load_library().fstat_sync_check(_stream_ptr(stream)))

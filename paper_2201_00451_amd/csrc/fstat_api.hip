@@ -1,0 +1,480 @@
+// Host side of the C ABI declared in include/fstat.h: plan validation,
+// workspace sizing, FFT split selection and kernel launches.  All device
+// memory belongs to the caller; nothing here allocates on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fstat_common.hpp"
+#include "fstat_fft.hpp"
+#include "fstat_prologue.hpp"
+#include "fstat_resample.hpp"
+
+using namespace fstat;
+
+struct fstat_plan {
+  fstat_plan_desc desc;
+  int log_n, log_rr, log_c;  // N = Rr * C
+  int cols_lines, rows_lines;
+  bool cols_half, rows_half;
+  int64_t k_pad, rows_act;
+  double t_lo, t_hi;         // time range any timing evaluation may touch
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+fstat_status fail(fstat_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+fstat_status fail(fstat_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+fstat_status ok() {
+  g_err.clear();
+  return FSTAT_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int ilog2(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+
+// Lines per workgroup of the column pass (B) and rows per workgroup of the
+// row pass (RQ): by default as many as fit 128 KiB of LDS, capped for
+// coalescing; the tuning fields may halve them (then with half the threads,
+// so two workgroups share a CU).
+int cols_lines_max(int log_rr) { return std::min(64, 16384 >> log_rr); }
+int rows_lines_max(int log_c) { return std::min(32, 8192 >> log_c); }
+
+using ColsFn = void (*)(PlanConst, void*, int, int64_t);
+using RowsFn = void (*)(PlanConst, void*, int, float*, float2*, int64_t);
+
+template <int LOGL>
+constexpr int kColsMax = (16384 >> LOGL) < 64 ? (16384 >> LOGL) : 64;
+template <int LOGL>
+constexpr int kRowsMax = (8192 >> LOGL) < 32 ? (8192 >> LOGL) : 32;
+
+struct FftVariant {
+  const void* fn;
+  int threads;
+};
+
+template <int LOGL>
+FftVariant cols_variant(bool half) {
+  if (half) return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL> / 2, 256>), 256};
+  return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL>, 512>), 512};
+}
+template <int LOGL>
+FftVariant rows_variant(bool half) {
+  if (half) return {reinterpret_cast<const void*>(&k_fft_rows_2f<LOGL, kRowsMax<LOGL> / 2, 256>), 256};
+  return {reinterpret_cast<const void*>(&k_fft_rows_2f<LOGL, kRowsMax<LOGL>, 512>), 512};
+}
+
+FftVariant pick_cols(int logl, bool half) {
+  switch (logl) {
+    case 6: return cols_variant<6>(half);
+    case 7: return cols_variant<7>(half);
+    case 8: return cols_variant<8>(half);
+    case 9: return cols_variant<9>(half);
+    case 10: return cols_variant<10>(half);
+    case 11: return cols_variant<11>(half);
+    case 12: return cols_variant<12>(half);
+    default: return {nullptr, 0};
+  }
+}
+FftVariant pick_rows(int logl, bool half) {
+  switch (logl) {
+    case 6: return rows_variant<6>(half);
+    case 7: return rows_variant<7>(half);
+    case 8: return rows_variant<8>(half);
+    case 9: return rows_variant<9>(half);
+    case 10: return rows_variant<10>(half);
+    case 11: return rows_variant<11>(half);
+    case 12: return rows_variant<12>(half);
+    default: return {nullptr, 0};
+  }
+}
+
+fstat_status check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(FSTAT_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return FSTAT_OK;
+}
+
+fstat_status validate_desc(const fstat_plan_desc* d) {
+  if (!d) return fail(FSTAT_EINVAL, "desc is NULL");
+  if (d->flags != 0) return fail(FSTAT_EINVAL, "flags must be 0");
+  if (d->ndet < 1 || d->ndet > FSTAT_MAX_DET)
+    return fail(FSTAT_EINVAL, "ndet=%d outside [1, %d]", d->ndet, FSTAT_MAX_DET);
+  if (d->sinc_halfwidth < 2 || d->sinc_halfwidth > 32)
+    return fail(FSTAT_EINVAL, "sinc_halfwidth=%d outside [2, 32]", d->sinc_halfwidth);
+  if (!finite_pos(d->dt)) return fail(FSTAT_EINVAL, "dt must be positive and finite");
+  if (!std::isfinite(d->f_het) || !std::isfinite(d->t_ref) || !std::isfinite(d->tau0))
+    return fail(FSTAT_EINVAL, "f_het, t_ref and tau0 must be finite");
+  if (!(std::isfinite(d->max_delay) && d->max_delay >= 0.0))
+    return fail(FSTAT_EINVAL, "max_delay must be finite and >= 0");
+  if (!finite_pos(d->sid_rate) || !std::isfinite(d->sid_angle0))
+    return fail(FSTAT_EINVAL, "sid_rate must be positive and finite, sid_angle0 finite");
+  const int64_t n = d->n_fft;
+  if (n < (int64_t(1) << 12) || n > (int64_t(1) << 24) || (n & (n - 1)) != 0)
+    return fail(FSTAT_EINVAL, "n_fft=%lld must be a power of two in [2^12, 2^24]",
+                (long long)n);
+  if (d->n_bins < 1 || d->bin_lo < 0 || d->bin_lo + d->n_bins > n)
+    return fail(FSTAT_EINVAL, "band [bin_lo, bin_lo+n_bins) must be non-empty inside [0, n_fft)");
+  for (int X = 0; X < d->ndet; ++X) {
+    const fstat_detector& t = d->det[X];
+    if (t.n < 1) return fail(FSTAT_EINVAL, "detector %d: n must be >= 1", X);
+    if (!finite_pos(t.noise_var)) return fail(FSTAT_EINVAL, "detector %d: noise_var must be positive and finite", X);
+    if (!std::isfinite(t.t0) || !std::isfinite(t.lat) || !std::isfinite(t.lon) ||
+        !std::isfinite(t.az_x) || !std::isfinite(t.az_y))
+      return fail(FSTAT_EINVAL, "detector %d: geometry and t0 must be finite", X);
+    if (std::fabs(std::fabs(std::remainder(t.az_y - t.az_x, M_PI)) - M_PI / 2) > 1e-6)
+      return fail(FSTAT_EINVAL, "detector %d: arms must be orthogonal", X);
+    if (d->tau0 + d->max_delay > t.t0)
+      return fail(FSTAT_EINVAL,
+                  "detector %d: grid origin tau0 + max_delay = %.6g is after the first sample %.6g",
+                  X, d->tau0 + d->max_delay, t.t0);
+  }
+  return FSTAT_OK;
+}
+
+PlanConst make_const(const fstat_plan* p, const fstat_inputs* in) {
+  const fstat_plan_desc& d = p->desc;
+  PlanConst P;
+  std::memset(&P, 0, sizeof P);
+  P.ndet = d.ndet;
+  P.D = d.sinc_halfwidth;
+  P.dt = d.dt;
+  P.inv_dt = 1.0 / d.dt;
+  P.f_het = d.f_het;
+  P.t_ref = d.t_ref;
+  P.tau0 = d.tau0;
+  P.max_delay = d.max_delay;
+  P.sid_rate_cyc = d.sid_rate / (2.0 * M_PI);
+  P.n_fft = d.n_fft;
+  P.bin_lo = d.bin_lo;
+  P.n_bins = d.n_bins;
+  P.k_pad = p->k_pad;
+  if (in) {
+    P.n_eph = in->n_eph;
+    P.eph_t0 = in->eph_t0;
+    P.eph_dt = in->eph_dt;
+    P.inv_eph_dt = 1.0 / in->eph_dt;
+    P.moments = in->moments;
+  }
+  for (int X = 0; X < d.ndet; ++X) {
+    const fstat_detector& t = d.det[X];
+    DetConst& c = P.det[X];
+    c.t0 = t.t0;
+    c.off = (d.tau0 - t.t0) / d.dt;
+    c.lst0_cyc = (t.lon + d.sid_angle0) / (2.0 * M_PI);
+    c.lat = t.lat;
+    c.gamma = 0.5 * (t.az_x + t.az_y);
+    c.w = 1.0 / t.noise_var;
+    c.n = t.n;
+    if (in) {
+      c.x = static_cast<const float2*>(in->x[X]);
+      c.valid = in->valid[X];
+      c.ephem = in->ephem[X];
+    }
+  }
+  return P;
+}
+
+fstat_status validate_inputs(const fstat_plan* p, const fstat_inputs* in, bool need_moments) {
+  if (!in) return fail(FSTAT_EINVAL, "inputs is NULL");
+  for (int X = 0; X < p->desc.ndet; ++X) {
+    if (!in->x[X]) return fail(FSTAT_EINVAL, "inputs.x[%d] is NULL", X);
+    if (!in->ephem[X]) return fail(FSTAT_EINVAL, "inputs.ephem[%d] is NULL", X);
+  }
+  if (need_moments && !in->moments) return fail(FSTAT_EINVAL, "inputs.moments is NULL");
+  if (!finite_pos(in->eph_dt) || !std::isfinite(in->eph_t0) || in->n_eph < 4)
+    return fail(FSTAT_EINVAL, "ephemeris: need eph_dt > 0, finite eph_t0, n_eph >= 4");
+  const fstat_plan_desc& d = p->desc;
+  const double span = kResTile * d.dt + 2.0 * (d.max_delay + (d.sinc_halfwidth + 2) * d.dt);
+  if (span / in->eph_dt + 4.0 > double(kNodeCap))
+    return fail(FSTAT_EINVAL,
+                "ephemeris spacing %.6g s too fine: a resampling tile spans %.6g s and stages at "
+                "most %d nodes",
+                in->eph_dt, span, kNodeCap);
+  const double e_lo = in->eph_t0, e_hi = in->eph_t0 + double(in->n_eph - 1) * in->eph_dt;
+  if (p->t_lo < e_lo || p->t_hi > e_hi)
+    return fail(FSTAT_EINVAL, "ephemeris covers [%.6g, %.6g] but timing needs [%.6g, %.6g]", e_lo,
+                e_hi, p->t_lo, p->t_hi);
+  return FSTAT_OK;
+}
+
+fstat_status validate_ws(const fstat_plan* p, void* ws, size_t ws_bytes, int64_t* slots) {
+  if (!ws) return fail(FSTAT_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(FSTAT_EINVAL, "workspace must be 256-byte aligned");
+  const size_t sb = slot_bytes(p->desc.n_fft);
+  if (ws_bytes < kHeaderBytes + sb)
+    return fail(FSTAT_EWORKSPACE, "workspace %zu bytes < %zu needed for one template", ws_bytes,
+                kHeaderBytes + sb);
+  *slots = int64_t((ws_bytes - kHeaderBytes) / sb);
+  return FSTAT_OK;
+}
+
+size_t lds_bytes_cols(const fstat_plan* p) { return size_t(p->cols_lines) << p->log_rr << 3; }
+size_t lds_bytes_rows(const fstat_plan* p) { return size_t(2 * p->rows_lines) << p->log_c << 3; }
+
+// Optional per-kernel timing: events recorded before and after each launch.
+struct KernelTimer {
+  static constexpr int kKernels = 4;
+  std::vector<hipEvent_t> ev[kKernels];
+  bool on = false;
+  hipStream_t st = nullptr;
+  fstat_status mark(int k) {
+    if (!on) return FSTAT_OK;
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r == hipSuccess) r = hipEventRecord(e, st);
+    if (r != hipSuccess) return check_hip(r, "timing event");
+    ev[k].push_back(e);
+    return FSTAT_OK;
+  }
+  ~KernelTimer() {
+    for (auto& v : ev)
+      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+  }
+};
+
+// Launch the whole path for templates [t_first, t_first + count) using
+// `count` workspace slots.  y_out: diagnostic path (resampled series only).
+fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double* templates,
+                          int64_t t_first, int count, float* twoF, float2* fafb, float2* y_out,
+                          void* ws, hipStream_t st, KernelTimer& tm) {
+  fstat_status s;
+  if ((s = tm.mark(0)) != FSTAT_OK) return s;
+  hipLaunchKernelGGL(k_prologue, dim3((count + 63) / 64), dim3(64), 0, st, P, templates, t_first,
+                     int64_t(count), ws);
+  if ((s = tm.mark(0)) != FSTAT_OK) return s;
+  if ((s = tm.mark(1)) != FSTAT_OK) return s;
+  hipLaunchKernelGGL(k_resample, dim3(unsigned(p->k_pad / kResTile), count), dim3(kResThreads), 0,
+                     st, P, ws);
+  if ((s = tm.mark(1)) != FSTAT_OK) return s;
+  if (y_out) {
+    hipLaunchKernelGGL(k_copy_series, dim3(256, count), dim3(256), 0, st, P, ws, y_out,
+                       t_first);
+    return check_hip(hipGetLastError(), "resample launch");
+  }
+  const FftVariant cv = pick_cols(p->log_rr, p->cols_half);
+  const FftVariant rv = pick_rows(p->log_c, p->rows_half);
+  if ((s = tm.mark(2)) != FSTAT_OK) return s;
+  hipLaunchKernelGGL(reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn)),
+                     dim3(unsigned((int64_t(1) << p->log_c) / p->cols_lines), 2, count),
+                     dim3(cv.threads), lds_bytes_cols(p), st, P, ws, p->log_c, p->rows_act);
+  if ((s = tm.mark(2)) != FSTAT_OK) return s;
+  if ((s = tm.mark(3)) != FSTAT_OK) return s;
+  hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rv.fn)),
+                     dim3(unsigned((int64_t(1) << p->log_rr) / p->rows_lines), count),
+                     dim3(rv.threads), lds_bytes_rows(p), st, P, ws, p->log_rr, twoF, fafb,
+                     t_first);
+  if ((s = tm.mark(3)) != FSTAT_OK) return s;
+  return check_hip(hipGetLastError(), "kernel launch");
+}
+
+fstat_status set_lds_limits(const fstat_plan* p) {
+  hipError_t e = hipFuncSetAttribute(pick_cols(p->log_rr, p->cols_half).fn,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     int(lds_bytes_cols(p)));
+  if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(cols)");
+  e = hipFuncSetAttribute(pick_rows(p->log_c, p->rows_half).fn,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_rows(p)));
+  if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(rows)");
+  return FSTAT_OK;
+}
+
+fstat_status run(const fstat_plan* p, const fstat_inputs* in, const double* templates,
+                 int64_t ntmpl, float* twoF, void* fafb, void* y_out, void* ws, size_t ws_bytes,
+                 void* stream, int64_t max_slots, KernelTimer* timer = nullptr) {
+  if (!p) return fail(FSTAT_EINVAL, "plan is NULL");
+  if (ntmpl < 0) return fail(FSTAT_EINVAL, "ntmpl < 0");
+  if (ntmpl > 0 && !templates) return fail(FSTAT_EINVAL, "templates is NULL");
+  if (ntmpl > 0 && !twoF && !y_out) return fail(FSTAT_EINVAL, "twoF is NULL");
+  fstat_status s = validate_inputs(p, in, true);
+  if (s != FSTAT_OK) return s;
+  int64_t slots = 0;
+  s = validate_ws(p, ws, ws_bytes, &slots);
+  if (s != FSTAT_OK) return s;
+  if (ntmpl == 0) return ok();
+  slots = std::min(slots, max_slots);
+  slots = std::min<int64_t>(slots, 65535);
+  s = set_lds_limits(p);
+  if (s != FSTAT_OK) return s;
+  PlanConst P = make_const(p, in);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KernelTimer none;
+  KernelTimer& tm = timer ? *timer : none;
+  tm.st = st;
+  hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, ws, p->desc.n_fft);
+  for (int64_t t = 0; t < ntmpl; t += slots) {
+    int count = int(std::min<int64_t>(slots, ntmpl - t));
+    s = launch_chunk(p, P, templates, t, count, twoF, static_cast<float2*>(fafb),
+                     static_cast<float2*>(y_out), ws, st, tm);
+    if (s != FSTAT_OK) return s;
+  }
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fstat_version(void) { return "fstat-gfx950 0.1"; }
+
+const char* fstat_last_error(void) { return g_err.c_str(); }
+
+fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out) {
+  if (!out) return fail(FSTAT_EINVAL, "out is NULL");
+  *out = nullptr;
+  fstat_status s = validate_desc(desc);
+  if (s != FSTAT_OK) return s;
+  fstat_plan* p = new (std::nothrow) fstat_plan;
+  if (!p) return fail(FSTAT_EINVAL, "host allocation failed");
+  p->desc = *desc;
+  p->log_n = ilog2(desc->n_fft);
+  p->log_rr = desc->tune_col_log_len ? desc->tune_col_log_len : (p->log_n + 1) / 2;
+  p->log_c = p->log_n - p->log_rr;
+  if (p->log_rr < 6 || p->log_rr > 12 || p->log_c < 6 || p->log_c > 12) {
+    delete p;
+    return fail(FSTAT_EINVAL, "tune_col_log_len=%d: both FFT passes need lengths 2^6..2^12",
+                desc->tune_col_log_len);
+  }
+  const int cmax = cols_lines_max(p->log_rr), rmax = rows_lines_max(p->log_c);
+  const int tc = desc->tune_col_lines, tr = desc->tune_row_lines;
+  if ((tc != 0 && tc != cmax && tc != cmax / 2) || (tr != 0 && tr != rmax && tr != rmax / 2)) {
+    delete p;
+    return fail(FSTAT_EINVAL,
+                "tune_col_lines=%d / tune_row_lines=%d: accepted 0, %d or %d / 0, %d or %d", tc,
+                tr, cmax, cmax / 2, rmax, rmax / 2);
+  }
+  p->cols_half = tc == cmax / 2 && cmax > 1;
+  p->rows_half = tr == rmax / 2 && rmax > 1;
+  p->cols_lines = p->cols_half ? cmax / 2 : cmax;
+  p->rows_lines = p->rows_half ? rmax / 2 : rmax;
+  // grid points that can be non-zero: up to the last sample plus the delay
+  // bound plus the interpolation half-width
+  double t_end = -INFINITY, t_beg = INFINITY;
+  for (int X = 0; X < desc->ndet; ++X) {
+    t_end = std::max(t_end, desc->det[X].t0 + double(desc->det[X].n - 1) * desc->dt);
+    t_beg = std::min(t_beg, desc->det[X].t0);
+  }
+  const double k_act =
+      std::ceil((t_end + desc->max_delay - desc->tau0) / desc->dt) + desc->sinc_halfwidth + 2;
+  const int64_t quant = std::max<int64_t>(kResTile, int64_t(1) << p->log_c);
+  p->k_pad = (int64_t(k_act) + quant - 1) / quant * quant;
+  if (p->k_pad > desc->n_fft) {
+    delete p;
+    return fail(FSTAT_EINVAL,
+                "n_fft=%lld too short: data span plus delays needs %lld grid points (padded)",
+                (long long)desc->n_fft, (long long)(int64_t(k_act)));
+  }
+  p->rows_act = p->k_pad >> p->log_c;
+  const double margin = desc->max_delay + 4.0 * desc->dt + 1.0;
+  p->t_lo = std::min(desc->tau0, t_beg) - margin;
+  p->t_hi = std::max(desc->tau0 + double(p->k_pad) * desc->dt, t_end) + margin;
+  *out = p;
+  return ok();
+}
+
+void fstat_plan_destroy(fstat_plan* plan) { delete plan; }
+
+fstat_status fstat_workspace_size(const fstat_plan* plan, int64_t batch, size_t* bytes) {
+  if (!plan || !bytes) return fail(FSTAT_EINVAL, "plan or bytes is NULL");
+  if (batch < 1) return fail(FSTAT_EINVAL, "batch must be >= 1");
+  *bytes = kHeaderBytes + size_t(batch) * slot_bytes(plan->desc.n_fft);
+  return ok();
+}
+
+fstat_status fstat_antenna_moments(const fstat_plan* plan, const fstat_inputs* in,
+                                   double* moments, void* workspace, size_t ws_bytes,
+                                   void* stream) {
+  if (!plan) return fail(FSTAT_EINVAL, "plan is NULL");
+  if (!moments) return fail(FSTAT_EINVAL, "moments is NULL");
+  if (!in) return fail(FSTAT_EINVAL, "inputs is NULL");
+  if (!workspace) return fail(FSTAT_EINVAL, "workspace is NULL");
+  if (ws_bytes < kHeaderBytes)
+    return fail(FSTAT_EWORKSPACE, "workspace %zu bytes < %zu", ws_bytes, kHeaderBytes);
+  PlanConst P = make_const(plan, in);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* partial = static_cast<double*>(workspace);
+  hipLaunchKernelGGL(k_moments_partial, dim3(kMomBlocks, plan->desc.ndet), dim3(kMomThreads), 0,
+                     st, P, partial);
+  hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(64), 0, st, plan->desc.ndet, partial, moments);
+  fstat_status s = check_hip(hipGetLastError(), "moments launch");
+  return s == FSTAT_OK ? ok() : s;
+}
+
+fstat_status fstat_compute_2f(const fstat_plan* plan, const fstat_inputs* in,
+                              const double* templates, int64_t ntmpl, float* twoF, void* fafb,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  return run(plan, in, templates, ntmpl, twoF, fafb, nullptr, workspace, ws_bytes, stream, 1);
+}
+
+fstat_status fstat_compute_2f_batched(const fstat_plan* plan, const fstat_inputs* in,
+                                      const double* templates, int64_t ntmpl, float* twoF,
+                                      void* fafb, void* workspace, size_t ws_bytes,
+                                      void* stream) {
+  return run(plan, in, templates, ntmpl, twoF, fafb, nullptr, workspace, ws_bytes, stream,
+             int64_t(1) << 40);
+}
+
+fstat_status fstat_compute_2f_profiled(const fstat_plan* plan, const fstat_inputs* in,
+                                       const double* templates, int64_t ntmpl, float* twoF,
+                                       void* workspace, size_t ws_bytes, int64_t max_batch,
+                                       void* stream, float* kernel_ms, int64_t* launches) {
+  if (!kernel_ms || !launches) return fail(FSTAT_EINVAL, "kernel_ms or launches is NULL");
+  if (max_batch < 1) return fail(FSTAT_EINVAL, "max_batch must be >= 1");
+  KernelTimer tm;
+  tm.on = true;
+  fstat_status s = run(plan, in, templates, ntmpl, twoF, nullptr, nullptr, workspace, ws_bytes,
+                       stream, max_batch, &tm);
+  if (s != FSTAT_OK) return s;
+  s = check_hip(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "timing synchronise");
+  if (s != FSTAT_OK) return s;
+  for (int k = 0; k < KernelTimer::kKernels; ++k) {
+    float total = 0.f;
+    for (size_t i = 0; i + 1 < tm.ev[k].size(); i += 2) {
+      float ms = 0.f;
+      s = check_hip(hipEventElapsedTime(&ms, tm.ev[k][i], tm.ev[k][i + 1]), "event time");
+      if (s != FSTAT_OK) return s;
+      total += ms;
+    }
+    kernel_ms[k] = total;
+    launches[k] = int64_t(tm.ev[k].size() / 2);
+  }
+  return ok();
+}
+
+fstat_status fstat_resample(const fstat_plan* plan, const fstat_inputs* in,
+                            const double* templates, int64_t ntmpl, void* y, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  if (ntmpl > 0 && !y) return fail(FSTAT_EINVAL, "y is NULL");
+  return run(plan, in, templates, ntmpl, nullptr, nullptr, y, workspace, ws_bytes, stream, 1);
+}
+
+fstat_status fstat_sync_check(void* stream) {
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fail(FSTAT_EHIP, "asynchronous HIP error: %s", hipGetErrorString(e));
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+// Shared device-side definitions of the gfx950 resampling F-statistic path:
+// per-plan constants passed by value to every kernel, the per-template
+// constant block written by the prologue kernel, the workspace layout, and
+// the FP64 timing helpers of steps (iii) and (iv) of Sec. 3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fstat.h"
+
+namespace fstat {
+
+constexpr int kMaxDet = FSTAT_MAX_DET;
+constexpr double kPi = 3.14159265358979323846;
+
+// Resampling tile: outputs per workgroup, threads, and the staged-sample
+// capacity (tile + 1/16 drift allowance + 2D taps for D <= 32 + slack).
+constexpr int kResTile = 1024;
+constexpr int kResThreads = 256;
+constexpr int kResPerThread = kResTile / kResThreads;
+constexpr int kResWcap = kResTile + kResTile / 16 + 64 + 8;
+
+// Ephemeris nodes a resampling tile stages in LDS (projected on the sky).
+constexpr int kNodeCap = 512;
+
+// Moment reduction: fixed block count per detector (deterministic order).
+constexpr int kMomBlocks = 256;
+constexpr int kMomThreads = 256;
+
+// Per-detector constants of a plan.
+struct DetConst {
+  double t0;          // time of sample 0
+  double off;         // (tau0 - t0)/dt: grid index offset
+  double lst0_cyc;    // (lon + sidereal angle at t=0) / 2 pi
+  double lat, gamma;  // latitude, arm-bisector azimuth (CCW from East)
+  double w;           // 1/noise_var
+  int64_t n;
+  const float2* x;
+  const uint8_t* valid;
+  const double* ephem;
+};
+
+// Everything a kernel needs about the plan and the inputs (passed by value).
+struct PlanConst {
+  int32_t ndet, D;
+  double dt, inv_dt, f_het, t_ref, tau0, max_delay;
+  double sid_rate_cyc;  // sidereal rate / 2 pi (cycles per s)
+  int64_t n_fft, bin_lo, n_bins;
+  int64_t k_pad;        // grid points computed by the resampler (multiple of tile and row)
+  int64_t n_eph;
+  double eph_t0, eph_dt, inv_eph_dt;
+  const double* moments;
+  DetConst det[kMaxDet];
+};
+
+// Per-template constants, one block per workspace slot.
+struct TmplParams {
+  double nhat[3];
+  double df, f1dot, f2dot, asini, om_b, tp;
+  double alpha_cyc[kMaxDet];  // (alpha - lon - sidereal angle at 0) / 2 pi
+  // Whitened, weighted antenna patterns: with M = [[A, C], [C, B]] = L L^T
+  // (Cholesky), (a', b') = L^-1 (a, b) so that 2F = 2 (|Fa'|^2 + |Fb'|^2).
+  // w_X a'(x) = ca0 + ca1 cos x + ca2 sin x + ca3 cos 2x + ca4 sin 2x.
+  float ca[kMaxDet][5];
+  float cb[kMaxDet][5];
+  float l11, l21, l22;        // L, to report Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
+  int32_t status;             // nonzero: every output bin of the template is NaN
+};
+
+constexpr size_t kParamBytes = 1024;
+static_assert(sizeof(TmplParams) <= kParamBytes, "param block");
+// Workspace header: moment partials, then FP32 twiddle tables written from
+// FP64 at the start of every call: W_4096^e (stage twiddles of every line
+// length <= 4096) and the two levels of W_N^e = W_N^{e mod 4096} W_N^{4096 (e div 4096)}.
+constexpr int kTwLen = 4096;
+constexpr size_t kMomentBytes = size_t(kMaxDet) * kMomBlocks * 10 * sizeof(double);
+constexpr size_t kTwOffset = kMomentBytes;
+constexpr size_t kHeaderBytes = kTwOffset + 3 * kTwLen * sizeof(float2) + 4096;
+__host__ __device__ inline float2* tw_stage(void* ws) {
+  return reinterpret_cast<float2*>(static_cast<char*>(ws) + kTwOffset);
+}
+__host__ __device__ inline float2* tw_lo(void* ws) { return tw_stage(ws) + kTwLen; }
+__host__ __device__ inline float2* tw_hi(void* ws) { return tw_stage(ws) + 2 * kTwLen; }
+
+// Workspace: header (moment partials), then `slots` template slots of
+// [TmplParams | y_a / Z_a : n_fft float2 | y_b / Z_b : n_fft float2].
+__host__ __device__ inline size_t slot_bytes(int64_t n_fft) {
+  return kParamBytes + size_t(n_fft) * 2 * sizeof(float2);
+}
+__host__ __device__ inline char* slot_base(void* ws, int64_t n_fft, int g) {
+  return static_cast<char*>(ws) + kHeaderBytes + size_t(g) * slot_bytes(n_fft);
+}
+__host__ __device__ inline TmplParams* slot_params(void* ws, int64_t n_fft, int g) {
+  return reinterpret_cast<TmplParams*>(slot_base(ws, n_fft, g));
+}
+__host__ __device__ inline float2* slot_buf(void* ws, int64_t n_fft, int g, int arr) {
+  return reinterpret_cast<float2*>(slot_base(ws, n_fft, g) + kParamBytes) + size_t(arr) * n_fft;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 timing (Sec. 2: t_b = t + t_m; binary: t_b = t_src + R(t_src)).
+// ---------------------------------------------------------------------------
+
+// Cubic Hermite interpolation on one interval: positions p0, p1 and slopes
+// v0, v1 (per second) at its ends, u in [0, 1] the fraction of the interval h.
+__device__ inline void hermite(double p0, double v0, double p1, double v1, double u, double h,
+                               double inv_h, double& d, double& dd) {
+  double u2 = u * u, u3 = u2 * u;
+  d = (2.0 * u3 - 3.0 * u2 + 1.0) * p0 + (u3 - 2.0 * u2 + u) * h * v0 +
+      (-2.0 * u3 + 3.0 * u2) * p1 + (u3 - u2) * h * v1;
+  dd = (6.0 * u2 - 6.0 * u) * (p0 - p1) * inv_h + (3.0 * u2 - 4.0 * u + 1.0) * v0 +
+       (3.0 * u2 - 2.0 * u) * v1;
+}
+
+// Roemer delay n.r(t) and its time derivative read from the tabulated
+// detector trajectory in global memory (node index clamped to the table).
+struct GlobalRoemer {
+  const double* tab;
+  const double* nh;
+  int64_t n_eph;
+  double t0, h, inv_h;
+  __device__ void operator()(double t, double& d, double& dd) const {
+    double s = (t - t0) * inv_h;
+    int64_t i = static_cast<int64_t>(floor(s));
+    i = i < 0 ? 0 : (i > n_eph - 2 ? n_eph - 2 : i);
+    const double* e0 = tab + 6 * i;
+    const double* e1 = e0 + 6;
+    double p0 = nh[0] * e0[0] + nh[1] * e0[1] + nh[2] * e0[2];
+    double v0 = nh[0] * e0[3] + nh[1] * e0[4] + nh[2] * e0[5];
+    double p1 = nh[0] * e1[0] + nh[1] * e1[1] + nh[2] * e1[2];
+    double v1 = nh[0] * e1[3] + nh[1] * e1[4] + nh[2] * e1[5];
+    hermite(p0, v0, p1, v1, s - static_cast<double>(i), h, inv_h, d, dd);
+  }
+};
+
+// The same from nodes already projected on the sky (n.r, n.v) and staged in
+// LDS: node i sits at t0 + i h.  An evaluation outside the staged nodes is
+// clamped (memory-safe) and raises `oob`.
+struct NodeRoemer {
+  const double2* nodes;
+  int count;
+  double t0, h, inv_h;
+  __device__ void operator()(double t, double& d, double& dd, bool& oob) const {
+    double s = (t - t0) * inv_h;
+    double fl = floor(s);
+    int i = static_cast<int>(fmin(fmax(fl, -1.0), double(count)));
+    if (i < 0 || i > count - 2) {
+      oob = true;
+      i = i < 0 ? 0 : count - 2;
+    }
+    double2 a = nodes[i], b = nodes[i + 1];
+    hermite(a.x, a.y, b.x, b.y, s - static_cast<double>(i), h, inv_h, d, dd);
+  }
+};
+
+// Step (iv): for the source-frame time tau return T - tau, where the detector
+// time T satisfies T + roemer(T) = tau + R(tau).  One fixed-point step from
+// T = t_b then one Newton step; 1/(1 + roemer') by its series to third order
+// (|roemer'| < 1e-3 for any Earth-bound detector: residual < 1e-12 s).
+template <class RoemerFn, class... Flag>
+__device__ inline double grid_delay(const RoemerFn& roemer, const TmplParams& tp, double tau,
+                                    Flag&... oob) {
+  double rb = 0.0;
+  if (tp.asini != 0.0) rb = tp.asini * sin(tp.om_b * (tau - tp.tp));
+  double d0, dd0;
+  roemer(tau + rb, d0, dd0, oob...);
+  double dl = rb - d0;
+  double d1, x;
+  roemer(tau + dl, d1, x, oob...);
+  double g = dl + d1 - rb;
+  return dl - g * (1.0 - x * (1.0 - x * (1.0 - x)));
+}
+
+// Step (iii): for the detector sample time t return t_src - t, where
+// t_src + R(t_src) = t + roemer(t).  R is found by one Newton step from
+// R(t_b) (contraction asini * om_b < 1e-2: residual < 1e-12 s).
+template <class RoemerFn, class... Flag>
+__device__ inline double sample_delay(const RoemerFn& roemer, const TmplParams& tp, double t,
+                                      Flag&... oob) {
+  double dr, ddr;
+  roemer(t, dr, ddr, oob...);
+  double r = 0.0;
+  if (tp.asini != 0.0) {
+    double tb = t + dr;
+    double r0 = tp.asini * sin(tp.om_b * (tb - tp.tp));
+    double s, c;
+    sincos(tp.om_b * (tb - r0 - tp.tp), &s, &c);
+    double h = r0 - tp.asini * s;
+    r = r0 - h / (1.0 + tp.asini * tp.om_b * c);
+  }
+  return dr - r;
+}
+
+// Split a fractional sample position into floor and fraction, keeping the
+// fraction below one after rounding to float.
+__device__ inline void split_u(double u, int64_t& j0, float& f) {
+  double fl = floor(u);
+  j0 = static_cast<int64_t>(fl);
+  f = static_cast<float>(u - fl);
+  if (f >= 1.0f) {
+    j0 += 1;
+    f = 0.0f;
+  }
+}
+
+// Reduce a phase given in cycles to [-1/2, 1/2] in FP64, then to float.
+__device__ inline float reduce_cycles(double c) { return static_cast<float>(c - rint(c)); }
+
+__device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+}  // namespace fstat

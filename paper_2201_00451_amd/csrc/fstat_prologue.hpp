@@ -1,0 +1,196 @@
+// Per-data-set antenna moments and the per-template prologue.
+//
+// A, B, C of eq. Fstat (Sec. 2) are noise-weighted sums of products of a(t),
+// b(t) over the valid samples.  a and b are trigonometric polynomials of
+// degree two in x = alpha - phi(t) (phi: local sidereal angle), so
+//   sum_j v_j P(x_j) Q(x_j) = 1/2 Re sum_{h,g} [p_h q_g S_{h+g} + p_h conj(q_g) S_{h-g}]
+// with P = Re sum_h p_h e^{i h x}, Q = Re sum_g q_g e^{i g x}, and
+//   S_n = sum_j v_j e^{i n x_j} = e^{i n alpha} conj(M_n),  M_n = sum_j v_j e^{i n phi_j}.
+// The moments M_0..M_4 depend on the data set only; the prologue combines
+// them with the sky position in O(1) per template.
+#pragma once
+
+#include "fstat_common.hpp"
+
+namespace fstat {
+
+// Partial moments: block b of detector X sums a contiguous chunk of samples.
+__global__ __launch_bounds__(kMomThreads) void k_moments_partial(PlanConst P, double* partial) {
+  const int X = blockIdx.y;
+  const DetConst& d = P.det[X];
+  const int64_t n = d.n;
+  const int64_t chunk = (n + kMomBlocks - 1) / kMomBlocks;
+  const int64_t j_beg = int64_t(blockIdx.x) * chunk;
+  const int64_t j_end = j_beg + chunk < n ? j_beg + chunk : n;
+  double acc[10];
+  for (int q = 0; q < 10; ++q) acc[q] = 0.0;
+  const double two_pi = 2.0 * kPi;
+  for (int64_t j = j_beg + threadIdx.x; j < j_end; j += kMomThreads) {
+    double v = d.valid ? double(d.valid[j]) : 1.0;
+    if (v == 0.0) continue;
+    double cyc = d.lst0_cyc + P.sid_rate_cyc * (d.t0 + P.dt * double(j));
+    cyc -= rint(cyc);
+    double s1, c1;
+    sincos(two_pi * cyc, &s1, &c1);
+    double cr = 1.0, ci = 0.0;
+    for (int h = 0; h < 5; ++h) {
+      acc[2 * h] += v * cr;
+      acc[2 * h + 1] += v * ci;
+      double nr = cr * c1 - ci * s1;
+      ci = cr * s1 + ci * c1;
+      cr = nr;
+    }
+  }
+  __shared__ double red[kMomThreads];
+  for (int q = 0; q < 10; ++q) {
+    red[threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = kMomThreads / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t(X) * kMomBlocks + blockIdx.x) * 10 + q] = red[0];
+    __syncthreads();
+  }
+}
+
+// Final sum of the partials in block order.
+__global__ void k_moments_final(int ndet, const double* partial, double* moments) {
+  int t = threadIdx.x;
+  if (t >= ndet * 10) return;
+  int X = t / 10, q = t % 10;
+  double s = 0.0;
+  for (int b = 0; b < kMomBlocks; ++b) s += partial[(size_t(X) * kMomBlocks + b) * 10 + q];
+  moments[X * 10 + q] = s;
+}
+
+struct cd {
+  double r, i;
+};
+__device__ inline cd cd_mul(cd a, cd b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ inline cd cd_conj(cd a) { return {a.r, -a.i}; }
+
+// sum_j v_j P(x_j) Q(x_j) for degree-2 polynomials p, q (complex coefficients)
+// given S_0..S_4.
+__device__ inline double moment_product(const cd p[3], const cd q[3], const cd S[5]) {
+  double acc = 0.0;
+  for (int h = 0; h < 3; ++h)
+    for (int g = 0; g < 3; ++g) {
+      cd t1 = cd_mul(cd_mul(p[h], q[g]), S[h + g]);
+      int dn = h - g;
+      cd sd = dn >= 0 ? S[dn] : cd_conj(S[-dn]);
+      cd t2 = cd_mul(cd_mul(p[h], cd_conj(q[g])), sd);
+      acc += t1.r + t2.r;
+    }
+  return 0.5 * acc;
+}
+
+// One thread per template: sky vector, antenna coefficients (Jaranowski,
+// Krolak & Schutz 1998 eqs. 12-13, cited in Sec. 2 for a(t), b(t)), A, B, C,
+// D of eq. Fstat, and the coverage check of the source-frame grid.
+__global__ void k_prologue(PlanConst P, const double* __restrict__ templates, int64_t t_first,
+                           int64_t count, void* ws) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  const double* row = templates + (t_first + g) * FSTAT_TEMPLATE_STRIDE;
+  TmplParams tp;
+  double alpha = row[0], delta = row[1];
+  tp.df = row[2];
+  tp.f1dot = row[3];
+  tp.f2dot = row[4];
+  tp.asini = row[5];
+  double porb = row[6];
+  tp.tp = row[7];
+  int status = 0;
+  for (int q = 0; q < 8; ++q)
+    if (!isfinite(row[q])) status = 1;
+  if (tp.asini < 0.0 || (tp.asini != 0.0 && !(porb > 0.0))) status = 1;
+  if (tp.asini > P.max_delay) status = 2;
+  tp.om_b = (tp.asini != 0.0 && porb > 0.0) ? 2.0 * kPi / porb : 0.0;
+  double sa, ca_, sd, cdl;
+  sincos(alpha, &sa, &ca_);
+  sincos(delta, &sd, &cdl);
+  tp.nhat[0] = cdl * ca_;
+  tp.nhat[1] = cdl * sa;
+  tp.nhat[2] = sd;
+  double s2d = 2.0 * sd * cdl, c2d = cdl * cdl - sd * sd;
+  double A = 0.0, B = 0.0, C = 0.0;
+  double pa_all[kMaxDet][5], pb_all[kMaxDet][5];
+  for (int X = 0; X < kMaxDet; ++X) {
+    tp.alpha_cyc[X] = 0.0;
+    for (int q = 0; q < 5; ++q) {
+      tp.ca[X][q] = tp.cb[X][q] = 0.0f;
+      pa_all[X][q] = pb_all[X][q] = 0.0;
+    }
+  }
+  for (int X = 0; X < P.ndet; ++X) {
+    const DetConst& d = P.det[X];
+    double sl, cl, sg, cg;
+    sincos(d.lat, &sl, &cl);
+    sincos(2.0 * d.gamma, &sg, &cg);  // sin 2 gamma, cos 2 gamma
+    double s2l = 2.0 * sl * cl, c2l = cl * cl - sl * sl;
+    double pa[5], pb[5];
+    pa[0] = 0.75 * sg * cl * cl * cdl * cdl;
+    pa[1] = 0.25 * sg * s2l * s2d;
+    pa[2] = -0.5 * cg * cl * s2d;
+    pa[3] = sg * (3.0 - c2l) * (3.0 - c2d) / 16.0;
+    pa[4] = -0.25 * cg * sl * (3.0 - c2d);
+    pb[0] = 0.0;
+    pb[1] = cg * cl * cdl;
+    pb[2] = 0.5 * sg * s2l * cdl;
+    pb[3] = cg * sl * sd;
+    pb[4] = 0.25 * sg * (3.0 - c2l) * sd;
+    for (int q = 0; q < 5; ++q) {
+      pa_all[X][q] = pa[q];
+      pb_all[X][q] = pb[q];
+    }
+    tp.alpha_cyc[X] = alpha / (2.0 * kPi) - d.lst0_cyc;
+    // S_n = e^{i n alpha} conj(M_n)
+    cd S[5];
+    for (int n = 0; n < 5; ++n) {
+      double sn, cn;
+      sincos(n * alpha, &sn, &cn);
+      cd m = {P.moments[X * 10 + 2 * n], P.moments[X * 10 + 2 * n + 1]};
+      S[n] = cd_mul({cn, sn}, cd_conj(m));
+    }
+    cd p[3] = {{pa[0], 0.0}, {pa[1], -pa[2]}, {pa[3], -pa[4]}};
+    cd q[3] = {{pb[0], 0.0}, {pb[1], -pb[2]}, {pb[3], -pb[4]}};
+    A += d.w * moment_product(p, p, S);
+    B += d.w * moment_product(q, q, S);
+    C += d.w * moment_product(p, q, S);
+  }
+  // 2F = 2 F^T M^-1 F is unchanged by a constant invertible map of (a, b).
+  // Whitening by the Cholesky factor of M in FP64 makes M' = I, so the FP32
+  // epilogue sums two squares instead of cancelling terms of size cond(M).
+  double Dd = A * B - C * C;
+  if (!(A > 0.0) || !(Dd > 0.0) || !isfinite(Dd)) status = 1;
+  const double l11 = sqrt(A), l21 = C / l11, l22 = sqrt(Dd / A);
+  const double r = C / A;
+  for (int X = 0; X < P.ndet; ++X) {
+    const double w = P.det[X].w;
+    for (int q = 0; q < 5; ++q) {
+      tp.ca[X][q] = static_cast<float>(w * pa_all[X][q] / l11);
+      tp.cb[X][q] = static_cast<float>(w * (pb_all[X][q] - r * pa_all[X][q]) / l22);
+    }
+  }
+  tp.l11 = static_cast<float>(l11);
+  tp.l21 = static_cast<float>(l21);
+  tp.l22 = static_cast<float>(l22);
+  // Coverage: every sample's source time lies inside the computed grid, and
+  // the interpolation taps of the last sample end before the last computed
+  // point, so grid points beyond k_pad are exactly zero.
+  if (status == 0) {
+    for (int X = 0; X < P.ndet; ++X) {
+      const DetConst& d = P.det[X];
+      const GlobalRoemer re{d.ephem, tp.nhat, P.n_eph, P.eph_t0, P.eph_dt, P.inv_eph_dt};
+      double u_first = 0.0 + d.off + grid_delay(re, tp, P.tau0) * P.inv_dt;
+      double k_last = double(P.k_pad - 1);
+      double u_last = k_last + d.off + grid_delay(re, tp, P.tau0 + k_last * P.dt) * P.inv_dt;
+      if (!(u_first <= 0.0) || !(u_last >= double(d.n - 1 + P.D))) status = 2;
+    }
+  }
+  tp.status = status;
+  *slot_params(ws, P.n_fft, g) = tp;
+}
+
+}  // namespace fstat

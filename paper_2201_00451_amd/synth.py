@@ -290,8 +290,10 @@ def duty_gaps(rng, n, dt, block_s, drop_p):
 def finish(ds, model=None, spacing=60.0):
     """Attach ephemeris tables and the delay bound."""
     model = model or ds.ephem_model
-    t_lo = min(d.t0 for d in ds.detectors) - 2000.0
-    t_hi = max(d.t0 + d.n * ds.dt for d in ds.detectors) + 2000.0
+    # cover every sample and the whole source-frame grid, widened by the delays
+    t_lo = min(min(d.t0 for d in ds.detectors), ds.tau0) - 2000.0
+    t_hi = max(max(d.t0 + d.n * ds.dt for d in ds.detectors),
+               ds.tau0 + ds.n_fft * ds.dt) + 2000.0
     tabs = []
     for d in ds.detectors:
         tab, t0, sp = ephemeris_table(model, d, t_lo, t_hi, spacing)

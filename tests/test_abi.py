@@ -1,0 +1,182 @@
+"""Host-only checks of the C ABI: the library loads, exports what the header
+declares, the ctypes mirror matches the C layout, and plan validation rejects
+bad set-ups with the documented status (no kernel runs here)."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2201_00451_amd import binding as B
+from paper_2201_00451_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fstat.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libfstat.so is not built: run python paper_2201_00451_amd/build.py")
+    return B.load_library()
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"FSTAT_API\s+[\w\s\*]+?\b(fstat_\w+)\s*\(", txt)))
+
+
+def test_header_declares_binding_exports():
+    assert declared_functions() == sorted(B.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (fstat_\w+)", out))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    for f in declared_functions():
+        assert hasattr(lib, f)
+    assert B.version().startswith("fstat-gfx950")
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "fstat.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m))
+int main(void) {
+  printf("fstat_detector %zu\nfstat_plan_desc %zu\nfstat_inputs %zu\n",
+         sizeof(fstat_detector), sizeof(fstat_plan_desc), sizeof(fstat_inputs));
+  F(fstat_plan_desc, det); F(fstat_plan_desc, dt); F(fstat_plan_desc, n_fft);
+  F(fstat_plan_desc, flags); F(fstat_inputs, valid); F(fstat_inputs, n_eph);
+  F(fstat_inputs, moments); F(fstat_detector, n); F(fstat_detector, noise_var);
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run(
+        [str(exe)], capture_output=True, text=True, check=True).stdout.strip().splitlines())
+    want = {
+        "fstat_detector": ctypes.sizeof(B.FstatDetector),
+        "fstat_plan_desc": ctypes.sizeof(B.FstatPlanDesc),
+        "fstat_inputs": ctypes.sizeof(B.FstatInputs),
+        "fstat_plan_desc.det": B.FstatPlanDesc.det.offset,
+        "fstat_plan_desc.dt": B.FstatPlanDesc.dt.offset,
+        "fstat_plan_desc.n_fft": B.FstatPlanDesc.n_fft.offset,
+        "fstat_plan_desc.flags": B.FstatPlanDesc.flags.offset,
+        "fstat_inputs.valid": B.FstatInputs.valid.offset,
+        "fstat_inputs.n_eph": B.FstatInputs.n_eph.offset,
+        "fstat_inputs.moments": B.FstatInputs.moments.offset,
+        "fstat_detector.n": B.FstatDetector.n.offset,
+        "fstat_detector.noise_var": B.FstatDetector.noise_var.offset,
+    }
+    assert {k: int(v) for k, v in got.items()} == want
+
+
+def good_desc():
+    ds = synth.small_case(seed=3, n=3000, n_fft=1 << 13, ndet=2)
+    return ds, B.make_plan_desc(ds)
+
+
+def status_of(desc):
+    lib = B.load_library()
+    h = ctypes.c_void_p()
+    st = lib.fstat_plan_create(ctypes.byref(desc), ctypes.byref(h))
+    if st == 0:
+        lib.fstat_plan_destroy(h)
+    return st, B.last_error()
+
+
+def test_plan_accepts_valid_setup(lib):
+    ds, d = good_desc()
+    p = B.Plan(d)
+    # every documented tuning choice is accepted (n_fft = 2^13: passes 2^7 x 2^6 by default)
+    for log_len, cl, rl in ((7, 64, 32), (7, 32, 16), (6, 64, 32), (6, 32, 16)):
+        d2 = B.make_plan_desc(ds, dict(tune_col_log_len=log_len, tune_col_lines=cl,
+                                       tune_row_lines=rl))
+        B.Plan(d2)
+    # header + one slot of two n_fft complex64 arrays
+    assert p.workspace_size(1) >= 2 * 8 * ds.n_fft
+    assert p.workspace_size(3) - p.workspace_size(2) == p.workspace_size(2) - p.workspace_size(1)
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda d: setattr(d, "ndet", 0), "ndet"),
+    (lambda d: setattr(d, "ndet", 5), "ndet"),
+    (lambda d: setattr(d, "n_fft", 3 << 12), "power of two"),
+    (lambda d: setattr(d, "n_fft", 1 << 11), "power of two"),
+    (lambda d: setattr(d, "n_fft", 1 << 25), "power of two"),
+    (lambda d: setattr(d, "n_bins", 0), "band"),
+    (lambda d: setattr(d, "bin_lo", (1 << 13) - 5), "band"),
+    (lambda d: setattr(d, "sinc_halfwidth", 1), "sinc_halfwidth"),
+    (lambda d: setattr(d, "sinc_halfwidth", 33), "sinc_halfwidth"),
+    (lambda d: setattr(d, "dt", 0.0), "dt"),
+    (lambda d: setattr(d, "dt", float("nan")), "dt"),
+    (lambda d: setattr(d, "sid_rate", -1.0), "sid_rate"),
+    (lambda d: setattr(d, "flags", 1), "flags"),
+    (lambda d: setattr(d.det[1], "noise_var", 0.0), "noise_var"),
+    (lambda d: setattr(d.det[0], "n", 0), "n must be"),
+    (lambda d: setattr(d.det[0], "az_y", d.det[0].az_x + 1.0), "orthogonal"),
+    (lambda d: setattr(d, "tau0", 0.0), "grid origin"),
+    (lambda d: setattr(d, "max_delay", float("inf")), "max_delay"),
+    (lambda d: setattr(d, "tune_col_log_len", 5), "tune_col_log_len"),
+    (lambda d: setattr(d, "tune_col_log_len", 13), "tune_col_log_len"),
+    (lambda d: setattr(d, "tune_col_lines", 3), "tune_col_lines"),
+    (lambda d: setattr(d, "tune_row_lines", 7), "tune_row_lines"),
+    (lambda d: (setattr(d, "n_fft", 1 << 12), setattr(d, "n_bins", 1 << 12),
+               setattr(d.det[0], "n", 4000)), "too short"),
+])
+def test_plan_rejects_invalid_setup(lib, mutate, needle):
+    _, d = good_desc()
+    mutate(d)
+    st, msg = status_of(d)
+    assert st == B.FSTAT_EINVAL
+    assert needle in msg
+
+
+def test_null_arguments_rejected_before_any_launch(lib):
+    ds, d = good_desc()
+    p = B.Plan(d)
+    vp = ctypes.c_void_p
+    inp = B.FstatInputs()
+    # null inputs / templates / outputs / workspace: EINVAL from host validation
+    assert lib.fstat_compute_2f(p.handle, None, vp(0), 1, vp(0), vp(0), vp(0), 0, vp(0)) == B.FSTAT_EINVAL
+    assert "templates" in B.last_error()
+    assert lib.fstat_compute_2f(p.handle, None, vp(4096), 1, vp(4096), vp(0), vp(0), 0,
+                                vp(0)) == B.FSTAT_EINVAL
+    assert "inputs" in B.last_error()
+    assert lib.fstat_compute_2f(p.handle, ctypes.byref(inp), vp(0), 1, vp(0), vp(0), vp(0), 0,
+                                vp(0)) == B.FSTAT_EINVAL
+    assert lib.fstat_compute_2f(None, ctypes.byref(inp), vp(0), 1, vp(0), vp(0), vp(0), 0,
+                                vp(0)) == B.FSTAT_EINVAL
+    # fake (never dereferenced) device pointers pass pointer checks; the
+    # ephemeris does not cover the data span -> EINVAL
+    for i in range(2):
+        inp.x[i] = inp.ephem[i] = 4096
+    inp.moments = 4096
+    inp.n_eph, inp.eph_t0, inp.eph_dt = 10, 0.0, 60.0
+    st = lib.fstat_compute_2f(p.handle, ctypes.byref(inp), vp(4096), 1, vp(4096), vp(0), vp(4096),
+                              1 << 30, vp(0))
+    assert st == B.FSTAT_EINVAL and "ephemeris" in B.last_error()
+    # covering ephemeris, workspace too small -> EWORKSPACE; misaligned -> EINVAL
+    inp.eph_t0, inp.n_eph = ds.eph_t0, ds.eph_tables[0].shape[0]
+    st = lib.fstat_compute_2f(p.handle, ctypes.byref(inp), vp(4096), 1, vp(4096), vp(0), vp(4096),
+                              1024, vp(0))
+    assert st == B.FSTAT_EWORKSPACE
+    st = lib.fstat_compute_2f(p.handle, ctypes.byref(inp), vp(4096), 1, vp(4096), vp(0), vp(4100),
+                              1 << 30, vp(0))
+    assert st == B.FSTAT_EINVAL and "aligned" in B.last_error()
+    assert lib.fstat_compute_2f(p.handle, ctypes.byref(inp), vp(4096), -1, vp(4096), vp(0),
+                                vp(4096), 1 << 30, vp(0)) == B.FSTAT_EINVAL
+    # zero templates is a no-op that succeeds without touching the device
+    assert lib.fstat_compute_2f(p.handle, ctypes.byref(inp), vp(0), 0, vp(0), vp(0), vp(4096),
+                                1 << 30, vp(0)) == B.FSTAT_OK

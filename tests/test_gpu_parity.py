@@ -1,0 +1,192 @@
+"""GPU path vs the FP64 oracle on the same seeded inputs, through the C ABI.
+
+Bar (2F, float32 path vs float64 oracle): relative error <= 1e-4 in bins where
+the oracle's 2F >= 10, absolute error <= 1e-3 elsewhere.  Intermediate
+results (resampled series, Fa, Fb) are compared with the accuracy metrics of
+Sec. 4.2 (r_1, r_2, theta).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fstat_oracle as O
+from paper_2201_00451_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL, ABS_TOL, STRONG = 1e-4, 1e-3, 10.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_2201_00451_amd import binding
+    binding.load_library()
+    return torch
+
+
+def assert_2f_parity(gpu, ref, label=""):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert gpu.shape == ref.shape
+    assert np.all(np.isfinite(gpu)), f"{label}: non-finite GPU output"
+    strong = ref >= STRONG
+    rel = np.abs(gpu[strong] - ref[strong]) / ref[strong] if strong.any() else np.zeros(1)
+    ab = np.abs(gpu[~strong] - ref[~strong])
+    say(f"  {label}: max rel (2F>=10, {strong.sum()} bins) {rel.max():.3e}; "
+        f"max abs (else) {ab.max():.3e}; r2 {O.rel_err(gpu, ref, 2):.3e}")
+    assert rel.max() <= REL_TOL, f"{label}: relative error {rel.max():.3e}"
+    assert ab.max() <= ABS_TOL, f"{label}: absolute error {ab.max():.3e}"
+
+
+def run_gpu(ds, templates=None, fafb=False, batched=False, batch=1):
+    from paper_2201_00451_amd import binding
+    dd = binding.DeviceData(ds, batch=batch)
+    tm = ds.templates if templates is None else templates
+    out = binding.compute_2f(dd, tm, fafb=fafb, batched=batched)
+    binding.sync_check()
+    if fafb:
+        return out[0].cpu().numpy(), out[1].cpu().numpy()
+    return out.cpu().numpy()
+
+
+CASES = {
+    "one_det": dict(seed=31, n=6000, n_fft=1 << 14, ndet=1),
+    "two_det_gaps": dict(seed=32, n=7000, n_fft=1 << 15, ndet=2, gaps=True, noise_vars=[0.8, 1.2]),
+    "binary": dict(seed=33, n=7000, n_fft=1 << 14, ndet=2, binary=True, gaps=True),
+    "ragged_band": dict(seed=34, n=5000, n_fft=1 << 13, ndet=1, bin_lo=1001, n_bins=3333),
+    "d4": dict(seed=35, n=5000, n_fft=1 << 13, ndet=1, D=4),
+    "d12": dict(seed=36, n=5000, n_fft=1 << 13, ndet=2, D=12, binary=True),
+    "n_fft_2e12": dict(seed=37, n=1200, n_fft=1 << 12, ndet=1, dt=2.0),
+    "n_fft_2e16": dict(seed=38, n=20000, n_fft=1 << 16, ndet=2, dt=2.0),
+    "three_det": dict(seed=39, n=3000, n_fft=1 << 13, ndet=3, noise_vars=[1.0, 0.7, 1.4]),
+}
+
+
+def test_antenna_moments_definition(torch_dev):
+    """M_n = sum_j v_j exp(i n phi(t_j)), evaluated here by its definition."""
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(**CASES["two_det_gaps"])
+    dd = binding.DeviceData(ds)
+    binding.sync_check()
+    got = dd.moments.cpu().numpy()
+    m = ds.ephem_model
+    for X, det in enumerate(ds.detectors):
+        t = det.t0 + ds.dt * np.arange(det.n)
+        phi = det.lon + m["sidereal_angle0_rad"] + m["sidereal_rate_rad_s"] * t
+        for n in range(5):
+            ref = np.sum(ds.valid[X] * np.exp(1j * n * phi))
+            assert abs(got[X, 2 * n] + 1j * got[X, 2 * n + 1] - ref) < 1e-9 * det.n
+
+
+@pytest.mark.parametrize("case", ["two_det_gaps", "binary"])
+def test_resampled_series_parity(torch_dev, case):
+    from paper_2201_00451_amd import binding
+    say(f"resample parity {case}")
+    ds = synth.small_case(**CASES[case])
+    dd = binding.DeviceData(ds)
+    y = binding.resample(dd, ds.templates[:2])
+    binding.sync_check()
+    y = y.cpu().numpy()
+    for i in range(2):
+        ya, yb = O.resampled_series(ds, O.template_dict(ds.templates[i]))
+        for got, ref, nm in ((y[i, 0], ya, "ya"), (y[i, 1], yb, "yb")):
+            r2 = O.rel_err(got, ref, 2)
+            mx = np.abs(got - ref).max() / np.abs(ref).max()
+            say(f"  tmpl {i} {nm}: r2 {r2:.3e} max/peak {mx:.3e}")
+            assert r2 < 2e-6 and mx < 5e-6
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_2f_parity_small(torch_dev, case):
+    say(f"2F parity {case}: {CASES[case]}")
+    ds = synth.small_case(**CASES[case])
+    ref, fab_ref = O.oracle_twoF(ds, return_fafb=True)
+    gpu, fab = run_gpu(ds, fafb=True)
+    for i in range(ds.ntmpl):
+        assert_2f_parity(gpu[i], ref[i], f"{case} tmpl {i}")
+        Fa, Fb, _ = fab_ref[i]
+        for got, want, nm in ((fab[i, 0], Fa, "Fa"), (fab[i, 1], Fb, "Fb")):
+            assert O.rel_err(got, want, 2) < 1e-5, nm
+            assert O.rel_err(got, want, 1) < 1e-5, nm
+            assert O.angle(got, want) < 1e-5, nm
+
+
+def test_tiny_config_full_parity(torch_dev):
+    """One detector, 1 day at 2 s, 11 spin-down templates, n_fft = 2^17."""
+    say("tiny config parity")
+    ds = synth.config_tiny()
+    ref = O.oracle_twoF(ds)
+    gpu = run_gpu(ds)
+    for i in range(ds.ntmpl):
+        assert_2f_parity(gpu[i], ref[i], f"tiny tmpl {i}")
+    # the template at the injected spin-down recovers the injection
+    inj = ds.injections[0]
+    i5 = int(np.argmin(np.abs(ds.templates[:, 3] - inj["f1dot"])))
+    fpk = ds.bin_frequencies()[int(np.argmax(gpu[i5]))]
+    assert abs(fpk - inj["f"]) < 2.0 / (ds.n_fft * ds.dt)
+    assert gpu[i5].max() > 0.8 * inj["rho2"]
+
+
+def test_batched_equals_plain_and_deterministic(torch_dev):
+    ds = synth.small_case(**dict(CASES["binary"], ntmpl=7))
+    plain = run_gpu(ds)
+    again = run_gpu(ds)
+    batched = run_gpu(ds, batched=True, batch=3)
+    np.testing.assert_array_equal(plain, again)
+    np.testing.assert_array_equal(plain, batched)
+
+
+def test_invalid_templates_give_nan_rows(torch_dev):
+    ds = synth.small_case(**dict(CASES["one_det"], ntmpl=4))
+    tm = ds.templates.copy()
+    tm[1, 3] = np.nan                 # non-finite parameter
+    tm[2, 5], tm[2, 6] = 0.3, -5.0    # binary with a negative period
+    gpu = run_gpu(ds, templates=tm)
+    assert np.all(np.isnan(gpu[1])) and np.all(np.isnan(gpu[2]))
+    ref = O.oracle_twoF(ds, tm[[0, 3]])
+    assert_2f_parity(gpu[0], ref[0], "valid row 0")
+    assert_2f_parity(gpu[3], ref[1], "valid row 3")
+
+
+def test_delay_bound_violation_gives_nan(torch_dev):
+    """A binary delay beyond the plan's max_delay breaks the grid coverage the
+    plan was sized for: the template is flagged, not silently truncated."""
+    ds = synth.small_case(**dict(CASES["one_det"], ntmpl=2))
+    tm = ds.templates.copy()
+    # a 3000 light-s orbit near its extremum R = -3000 s: the last samples map
+    # beyond the grid the plan computes
+    porb = 1.0e7
+    tm[1, 5], tm[1, 6], tm[1, 7] = 3000.0, porb, 6000.0 + porb / 4
+    gpu = run_gpu(ds, templates=tm)
+    assert np.all(np.isfinite(gpu[0]))
+    assert np.all(np.isnan(gpu[1]))
+
+
+@pytest.mark.parametrize("tune", [
+    dict(tune_col_lines=32, tune_row_lines=16),     # half lines, same split: same arithmetic
+    dict(tune_col_log_len=6),                        # other split of 2^13
+])
+def test_fft_launch_shapes(torch_dev, tune):
+    from paper_2201_00451_amd import binding
+    say(f"launch shape {tune}")
+    ds = synth.small_case(**dict(CASES["two_det_gaps"], n=3000, n_fft=1 << 13, ntmpl=3))
+    base = run_gpu(ds)
+    dd = binding.DeviceData(ds, tune=tune, batch=2)
+    got = binding.compute_2f_batched(dd, ds.templates).cpu().numpy()
+    binding.sync_check()
+    if "tune_col_log_len" not in tune:
+        np.testing.assert_array_equal(got, base)
+    ref = O.oracle_twoF(ds)
+    for i in range(ds.ntmpl):
+        assert_2f_parity(got[i], ref[i], f"{tune} tmpl {i}")

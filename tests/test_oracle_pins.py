@@ -319,3 +319,15 @@ def test_signal_mean_is_4_plus_rho2():
         vals.append(O.direct_twoF(ds, O.template_dict(ds.templates[0]), [inj["f"]])[0])
     vals = np.array(vals)
     assert abs(vals.mean() - (4 + 36.0)) < 4 * math.sqrt((8 + 4 * 36.0) / vals.size)
+
+
+def test_accuracy_metrics_closed_forms():
+    """r_1, r_2 and theta of Sec. 4.2 on vectors with known answers."""
+    x = np.array([1.0 + 0j, 0.0])
+    th = 1e-6
+    y = np.array([np.cos(th) + 0j, np.sin(th) + 0j])
+    assert abs(O.angle(x, y) - th) < 1e-15
+    assert abs(O.angle(x.astype(np.complex64), (1j * x).astype(np.complex64)) - np.pi / 2) < 1e-12
+    assert O.rel_err([1.0, 2.0], [1.0, 2.0], 2) == 0.0
+    assert abs(O.rel_err([3.0, 0.0], [0.0, 4.0], 1) - 2 * 7.0 / 7.0) < 1e-15
+    assert abs(O.rel_err([3.0, 0.0], [0.0, 4.0], 2) - 2 * 5.0 / 7.0) < 1e-15
