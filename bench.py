@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--cpu-templates", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the measurements, run one plain device copy of this many MiB "
+                         "(a reference kernel of known traffic for hardware counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -136,17 +139,31 @@ def main():
             "bytes_per_launch": per_launch[dom], "templates_per_launch": G}
 
     # plain per-template path (one template in flight)
-    print("bench: plain path", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.plain_steps):
-        binding.compute_2f(dd, tm, out=out)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    plain_ms = e0.elapsed_time(e1) / max(args.plain_steps, 1)
-    plain = {"value": round(ds.ntmpl / (plain_ms / 1e3), 1), "ms_per_step": round(plain_ms, 3)}
+    plain = None
+    if args.plain_steps > 0:
+        print("bench: plain path", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.plain_steps):
+            binding.compute_2f(dd, tm, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = e0.elapsed_time(e1) / args.plain_steps
+        plain = {"value": round(ds.ntmpl / (plain_ms / 1e3), 1), "ms_per_step": round(plain_ms, 3),
+                 "steps": args.plain_steps}
     binding.sync_check()
+
+    calib = None
+    if args.calibrate_copy_mib > 0:
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dd.device).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        calib = {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -166,13 +183,15 @@ def main():
                    "n_bins": ds.n_bins, "detectors": ds.ndet, "samples_per_detector": ds.detectors[0].n,
                    "sinc_halfwidth": ds.sinc_halfwidth, "batch": G, "timing_dtype": "f64"},
         "plain": plain,
-        "batched_over_plain": round(value / plain["value"], 3),
+        "batched_over_plain": round(value / plain["value"], 3) if plain else None,
         "tau_eff_s_per_bin_per_det": (ms_step / 1e3) / (n_bins_total * ds.ndet),
         "kernels": kern,
         "roofline": roof,
         "cpu_baseline": cpu,
         "wall_s_timed": round(wall, 3),
     }
+    if calib:
+        line["calibration_copy"] = calib
     print(json.dumps(line), flush=True)
 
 

@@ -56,7 +56,8 @@ typedef struct {
 /* Search set-up shared by every template (host memory, copied at plan creation). */
 typedef struct {
   int32_t ndet;                        /* 1..FSTAT_MAX_DET */
-  int32_t sinc_halfwidth;              /* D: the step (v) interpolation uses 2D taps, 2..32 */
+  int32_t sinc_halfwidth;              /* D: the step (v) interpolation uses 2D taps;
+                                          one of 4, 6, 8, 10, 12, 16 */
   fstat_detector det[FSTAT_MAX_DET];
   double dt;                           /* sample step of the inputs and of the source-frame grid (step iv) */
   double f_het;                        /* heterodyne frequency f_h of step (ii) */
@@ -103,7 +104,7 @@ typedef struct fstat_plan fstat_plan;  /* opaque, host memory owned by the libra
 /* Validate a set-up and build a plan.  Fails with FSTAT_EINVAL when: ndet out of
  * range; dt, noise_var or sid_rate not positive and finite; n_fft not a power of
  * two in [2^12, 2^24]; the band [bin_lo, bin_lo+n_bins) not inside [0, n_fft) or
- * empty; D out of [2, 32]; the source-frame grid [tau0, tau0 + n_fft*dt) does not
+ * empty; D not one of 4, 6, 8, 10, 12, 16; the source-frame grid [tau0, tau0 + n_fft*dt) does not
  * cover every sample's source time widened by max_delay; flags != 0. */
 FSTAT_API fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out);
 FSTAT_API void fstat_plan_destroy(fstat_plan* plan);

@@ -121,8 +121,10 @@ fstat_status validate_desc(const fstat_plan_desc* d) {
   if (d->flags != 0) return fail(FSTAT_EINVAL, "flags must be 0");
   if (d->ndet < 1 || d->ndet > FSTAT_MAX_DET)
     return fail(FSTAT_EINVAL, "ndet=%d outside [1, %d]", d->ndet, FSTAT_MAX_DET);
-  if (d->sinc_halfwidth < 2 || d->sinc_halfwidth > 32)
-    return fail(FSTAT_EINVAL, "sinc_halfwidth=%d outside [2, 32]", d->sinc_halfwidth);
+  if (d->sinc_halfwidth != 4 && d->sinc_halfwidth != 6 && d->sinc_halfwidth != 8 &&
+      d->sinc_halfwidth != 10 && d->sinc_halfwidth != 12 && d->sinc_halfwidth != 16)
+    return fail(FSTAT_EINVAL, "sinc_halfwidth=%d not one of 4, 6, 8, 10, 12, 16",
+                d->sinc_halfwidth);
   if (!finite_pos(d->dt)) return fail(FSTAT_EINVAL, "dt must be positive and finite");
   if (!std::isfinite(d->f_het) || !std::isfinite(d->t_ref) || !std::isfinite(d->tau0))
     return fail(FSTAT_EINVAL, "f_het, t_ref and tau0 must be finite");
@@ -231,8 +233,28 @@ fstat_status validate_ws(const fstat_plan* p, void* ws, size_t ws_bytes, int64_t
   return FSTAT_OK;
 }
 
-size_t lds_bytes_cols(const fstat_plan* p) { return size_t(p->cols_lines) << p->log_rr << 3; }
-size_t lds_bytes_rows(const fstat_plan* p) { return size_t(2 * p->rows_lines) << p->log_c << 3; }
+// LDS of a pass: NL lines at the padded pitch L + L/16 + 1 (see LdsLayout).
+size_t lds_pitch(int logl) { return (size_t(1) << logl) + (size_t(1) << logl) / 16 + 1; }
+size_t lds_bytes_cols(const fstat_plan* p) {
+  return size_t(p->cols_lines) * lds_pitch(p->log_rr) * sizeof(float2);
+}
+size_t lds_bytes_rows(const fstat_plan* p) {
+  return size_t(2 * p->rows_lines) * lds_pitch(p->log_c) * sizeof(float2);
+}
+
+// Resampling kernel for a supported interpolation half-width.
+using ResFn = void (*)(PlanConst, void*);
+ResFn resample_kernel(int D) {
+  switch (D) {
+    case 4: return &k_resample<4>;
+    case 6: return &k_resample<6>;
+    case 8: return &k_resample<8>;
+    case 10: return &k_resample<10>;
+    case 12: return &k_resample<12>;
+    case 16: return &k_resample<16>;
+    default: return nullptr;
+  }
+}
 
 // Optional per-kernel timing: events recorded before and after each launch.
 struct KernelTimer {
@@ -266,8 +288,8 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
                      int64_t(count), ws);
   if ((s = tm.mark(0)) != FSTAT_OK) return s;
   if ((s = tm.mark(1)) != FSTAT_OK) return s;
-  hipLaunchKernelGGL(k_resample, dim3(unsigned(p->k_pad / kResTile), count), dim3(kResThreads), 0,
-                     st, P, ws);
+  hipLaunchKernelGGL(resample_kernel(p->desc.sinc_halfwidth), dim3(unsigned(p->k_pad / kResTile), count),
+                     dim3(kResThreads), 0, st, P, ws);
   if ((s = tm.mark(1)) != FSTAT_OK) return s;
   if (y_out) {
     hipLaunchKernelGGL(k_copy_series, dim3(256, count), dim3(256), 0, st, P, ws, y_out,

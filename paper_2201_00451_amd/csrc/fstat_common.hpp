@@ -172,6 +172,24 @@ __device__ inline double grid_delay(const RoemerFn& roemer, const TmplParams& tp
   return dl - g * (1.0 - x * (1.0 - x * (1.0 - x)));
 }
 
+// Binary Roemer delay R(tau) of the source (0 for an isolated source).
+__device__ inline double binary_delay(const TmplParams& tp, double tau) {
+  return tp.asini != 0.0 ? tp.asini * sin(tp.om_b * (tau - tp.tp)) : 0.0;
+}
+
+// Step (iv) from a prediction: one Newton step on T + roemer(T) = tau + rb
+// (rb = R(tau)) started at T = tau + guess.  The caller predicts from a
+// solved neighbour by linearising the Roemer delay only (the binary delay is
+// exact), so the guess is off by |roemer''| dT^2 / 2 < 2e-3 s within a tile and
+// the step leaves < 1e-15 s.  Returns T - tau; x receives roemer'(T).
+template <class RoemerFn, class... Flag>
+__device__ inline double grid_delay_newton(const RoemerFn& roemer, double tau, double rb,
+                                           double guess, double& x, Flag&... oob) {
+  double d1;
+  roemer(tau + guess, d1, x, oob...);
+  return guess - (guess + d1 - rb) * (1.0 - x * (1.0 - x * (1.0 - x)));
+}
+
 // Step (iii): for the detector sample time t return t_src - t, where
 // t_src + R(t_src) = t + roemer(t).  R is found by one Newton step from
 // R(t_b) (contraction asini * om_b < 1e-2: residual < 1e-12 s).

@@ -96,25 +96,52 @@ __device__ inline uint32_t xcd_remap(uint32_t id, uint32_t total) {
   return (id & 7u) * (full >> 3) + (id >> 3);
 }
 
-// One Stockham stage over NL interleaved lines: element (idx, line) lives at
-// buf[idx * NL + line].  Stage twiddle W_{PR}^{jk} = W_4096^{jk 4096/(PR)}.
+// LDS layout of NL lines of length L: line-major with one pad element every
+// 16 and an odd-ish pitch, addr(idx, line) = line * pitch + idx + idx / 16,
+// pitch = L + L / 16 + 1.  Consecutive butterflies of a stage, consecutive
+// elements of a line and the same element of consecutive lines all land in
+// different LDS banks (the radix-R decimation stride R becomes R + R/16).
+template <int L>
+struct LdsLayout {
+  static constexpr int pitch = L + L / 16 + 1;
+  __device__ static __forceinline__ int at(int idx, int line) {
+    return line * pitch + idx + (idx >> 4);
+  }
+};
+
+// Butterfly of a Stockham stage with P > 1: twiddle W_{PR}^{jk} (table
+// W_4096^{jk 4096/(PR)}), then the R-point DFT in registers.
+template <int R, int P>
+__device__ __forceinline__ void twiddle_dft(float2 (&v)[R], int k, const float2* __restrict__ tw) {
+  if constexpr (P > 1) {
+    constexpr int TWS = kTwLen / (P * R);
+#pragma unroll
+    for (int j = 1; j < R; ++j) v[j] = cmul(v[j], tw[j * k * TWS]);
+  }
+  dft<R>(v);
+}
+
+// A middle Stockham stage (LDS to LDS) over NL lines.  Butterfly b covers
+// index i = b mod (L/R) of line b div (L/R); reads finish (barrier) before
+// the in-place writes, which finish (barrier) before the next stage.
 template <int LOGL, int NL, int NT, int S>
 __device__ __forceinline__ void fft_stage(float2* buf, const float2* __restrict__ tw) {
   constexpr int LOGR = stage_logr(LOGL, S), R = 1 << LOGR;
   constexpr int P = 1 << stage_logp(LOGL, S);
   constexpr int L = 1 << LOGL;
-  constexpr int NB = NL * (L / R);
+  constexpr int NBL = L / R;
+  constexpr int NB = NL * NBL;
   constexpr int PER = (NB + NT - 1) / NT;
-  constexpr int TWS = kTwLen / (P * R);
+  using Lay = LdsLayout<L>;
   const int tid = threadIdx.x;
   float2 v[PER][R];
 #pragma unroll
   for (int s = 0; s < PER; ++s) {
     const int b = tid + s * NT;
     if (NB % NT == 0 || b < NB) {
-      const int line = b % NL, i = b / NL;
+      const int i = b % NBL, line = b / NBL;
 #pragma unroll
-      for (int j = 0; j < R; ++j) v[s][j] = buf[(i + j * (L / R)) * NL + line];
+      for (int j = 0; j < R; ++j) v[s][j] = buf[Lay::at(i + j * NBL, line)];
     }
   }
   __syncthreads();
@@ -122,26 +149,23 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* __restrict_
   for (int s = 0; s < PER; ++s) {
     const int b = tid + s * NT;
     if (NB % NT == 0 || b < NB) {
-      const int line = b % NL, i = b / NL;
+      const int i = b % NBL, line = b / NBL;
       const int k = i & (P - 1);
-      if (P > 1) {
-#pragma unroll
-        for (int j = 1; j < R; ++j) v[s][j] = cmul(v[s][j], tw[j * k * TWS]);
-      }
-      dft<R>(v[s]);
+      twiddle_dft<R, P>(v[s], k, tw);
       const int base = (i - k) * R + k;
 #pragma unroll
-      for (int m = 0; m < R; ++m) buf[(base + m * P) * NL + line] = v[s][m];
+      for (int m = 0; m < R; ++m) buf[Lay::at(base + m * P, line)] = v[s][m];
     }
   }
   __syncthreads();
 }
 
+// Middle stages 1 .. last-1.
 template <int LOGL, int NL, int NT, int S>
-__device__ __forceinline__ void fft_stages(float2* buf, const float2* __restrict__ tw) {
-  if constexpr (S < stage_count(LOGL)) {
+__device__ __forceinline__ void fft_middle(float2* buf, const float2* __restrict__ tw) {
+  if constexpr (S < stage_count(LOGL) - 1) {
     fft_stage<LOGL, NL, NT, S>(buf, tw);
-    fft_stages<LOGL, NL, NT, S + 1>(buf, tw);
+    fft_middle<LOGL, NL, NT, S + 1>(buf, tw);
   }
 }
 
@@ -163,12 +187,20 @@ __global__ void k_twiddles(void* ws, int64_t n_fft) {
 
 // Column pass: lines are NL consecutive columns [c0, c0 + NL) of one array of
 // one template slot; line length Rr = 2^LOGL.  Rows at or beyond rows_act are
-// zero padding and are not read.  Grid: (C / NL) x 2 arrays x templates.
+// zero padding and are not read.  The first Stockham stage reads its inputs
+// straight from HBM and the last one writes its outputs, times the four-step
+// twiddle W_N^{q c}, straight back (both with columns fastest across
+// threads: NL-element contiguous runs); only the middle stages go through
+// LDS.  Grid: (C / NL) x 2 arrays x templates.
 template <int LOGL, int NL, int NT>
 __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, int log_c,
                                                  int64_t rows_act) {
   extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
+  constexpr int NS = stage_count(LOGL);
+  constexpr int R0 = 1 << stage_logr(LOGL, 0), NB0 = NL * (L / R0);
+  constexpr int RL = 1 << stage_logr(LOGL, NS - 1), PL = L / RL, NBL = NL * PL;
+  using Lay = LdsLayout<L>;
   const uint32_t total = gridDim.x * gridDim.y * gridDim.z;
   const uint32_t id = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
                                 total);
@@ -178,30 +210,74 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, int log_
   const int64_t C = int64_t(1) << log_c;
   const int64_t c0 = int64_t(gx) * NL;
   float2* buf = slot_buf(ws, P.n_fft, g, arr);
-  for (int e = threadIdx.x; e < L * NL; e += NT) {
-    const int r = e / NL, line = e % NL;
-    float2 v = make_float2(0.f, 0.f);
-    if (r < rows_act) v = buf[int64_t(r) * C + c0 + line];
-    lds[e] = v;
+  const float2* __restrict__ tw = tw_stage(ws);
+  const int tid = threadIdx.x;
+  // stage 0: HBM -> registers -> DFT -> LDS
+  {
+    constexpr int PER = (NB0 + NT - 1) / NT;
+    float2 v[PER][R0];
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int b = tid + s * NT;
+      if (NB0 % NT == 0 || b < NB0) {
+        const int line = b % NL, i = b / NL;
+#pragma unroll
+        for (int j = 0; j < R0; ++j) {
+          const int r = i + j * (L / R0);
+          v[s][j] = r < rows_act ? buf[int64_t(r) * C + c0 + line] : make_float2(0.f, 0.f);
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int b = tid + s * NT;
+      if (NB0 % NT == 0 || b < NB0) {
+        const int line = b % NL, i = b / NL;
+        dft<R0>(v[s]);
+#pragma unroll
+        for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
+      }
+    }
   }
   __syncthreads();
-  fft_stages<LOGL, NL, NT, 0>(lds, tw_stage(ws));
-  const int64_t nmask = P.n_fft - 1;
-  const float2* __restrict__ wlo = tw_lo(ws);
-  const float2* __restrict__ whi = tw_hi(ws);
-  for (int e = threadIdx.x; e < L * NL; e += NT) {
-    const int q = e / NL, line = e % NL;
-    const int64_t c = c0 + line;
-    const int64_t ex = (int64_t(q) * c) & nmask;
-    const float2 w = cmul(wlo[ex & (kTwLen - 1)], whi[ex >> 12]);
-    buf[int64_t(q) * C + c] = cmul(lds[e], w);
+  fft_middle<LOGL, NL, NT, 1>(lds, tw);
+  // last stage: LDS -> registers -> DFT -> x W_N^{q c} -> HBM
+  {
+    constexpr int PER = (NBL + NT - 1) / NT;
+    const int64_t nmask = P.n_fft - 1;
+    const float2* __restrict__ wlo = tw_lo(ws);
+    const float2* __restrict__ whi = tw_hi(ws);
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int b = tid + s * NT;
+      if (NBL % NT == 0 || b < NBL) {
+        const int line = b % NL, i = b / NL;
+        float2 v[RL];
+#pragma unroll
+        for (int j = 0; j < RL; ++j) v[j] = lds[Lay::at(i + j * PL, line)];
+        twiddle_dft<RL, PL>(v, i, tw);
+        const int64_t c = c0 + line;
+        // W_N^{c (i + m PL)} = W_N^{c i} (W_N^{c PL})^m
+        const int64_t e0 = (int64_t(i) * c) & nmask, e1 = (int64_t(PL) * c) & nmask;
+        float2 w = cmul(wlo[e0 & (kTwLen - 1)], whi[e0 >> 12]);
+        const float2 step = cmul(wlo[e1 & (kTwLen - 1)], whi[e1 >> 12]);
+#pragma unroll
+        for (int m = 0; m < RL; ++m) {
+          buf[int64_t(i + m * PL) * C + c] = cmul(v[m], w);
+          w = cmul(w, step);
+        }
+      }
+    }
   }
 }
 
 // Row pass with the 2F epilogue (eq. Fstat, normalised as 2F = 2 F^T M^-1 F,
 // which is 2 (|Fa'|^2 + |Fb'|^2) for the whitened antenna patterns).  Lines
 // 0..RQ-1 are rows q0..q0+RQ-1 of y_a', lines RQ..2RQ-1 the same rows of y_b';
-// line length C = 2^LOGL.  Grid: (Rr / RQ) x templates.
+// line length C = 2^LOGL.  The first stage reads the rows straight from HBM
+// (contiguous across threads); the last stage transforms the a and b rows of
+// the same bins in one thread and writes 2F (rows fastest across threads:
+// RQ-element runs of the output).  Grid: (Rr / RQ) x templates.
 template <int LOGL, int RQ, int NT>
 __global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, int log_rr,
                                                     float* __restrict__ twoF, float2* fafb,
@@ -209,6 +285,10 @@ __global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, int l
   extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
   constexpr int NL = 2 * RQ;
+  constexpr int NS = stage_count(LOGL);
+  constexpr int R0 = 1 << stage_logr(LOGL, 0), NBL0 = L / R0, NB0 = NL * NBL0;
+  constexpr int RL = 1 << stage_logr(LOGL, NS - 1), PL = L / RL, NBL = RQ * PL;
+  using Lay = LdsLayout<L>;
   const uint32_t total = gridDim.x * gridDim.y;
   const uint32_t id = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, total);
   const uint32_t gx = id % gridDim.x;
@@ -219,42 +299,84 @@ __global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, int l
   const int64_t Rr = int64_t(1) << log_rr;
   const int64_t N = P.n_fft;
   const int status = tp.status;
-  if (status == 0) {
+  const float2* __restrict__ tw = tw_stage(ws);
+  const int tid = threadIdx.x;
+  const float qnan = __builtin_nanf("");
+  if (status != 0) {
+    // flagged template: NaN in every bin it owns
+    for (int e = tid; e < L * RQ; e += NT) {
+      const int ql = e % RQ, p = e / RQ;
+      const int64_t i = (q0 + ql + Rr * p + N / 2) & (N - 1);
+      if (i < P.bin_lo || i >= P.bin_lo + P.n_bins) continue;
+      const int64_t o = i - P.bin_lo;
+      twoF[tmpl * P.n_bins + o] = qnan;
+      if (fafb) {
+        fafb[(tmpl * 2 + 0) * P.n_bins + o] = make_float2(qnan, qnan);
+        fafb[(tmpl * 2 + 1) * P.n_bins + o] = make_float2(qnan, qnan);
+      }
+    }
+    return;
+  }
+  // stage 0: HBM -> registers -> DFT -> LDS
+  {
     const float2* ba = slot_buf(ws, N, g, 0);
     const float2* bb = slot_buf(ws, N, g, 1);
-    for (int e = threadIdx.x; e < L * NL; e += NT) {
-      const int line = e / L, c = e % L;
-      const int ql = line % RQ;
-      const float2* src = line < RQ ? ba : bb;
-      lds[c * NL + line] = src[(q0 + ql) * L + c];
+    constexpr int PER = (NB0 + NT - 1) / NT;
+    float2 v[PER][R0];
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int b = tid + s * NT;
+      if (NB0 % NT == 0 || b < NB0) {
+        const int i = b % NBL0, line = b / NBL0;
+        const float2* src = (line < RQ ? ba : bb) + (q0 + line % RQ) * L;
+#pragma unroll
+        for (int j = 0; j < R0; ++j) v[s][j] = src[i + j * NBL0];
+      }
     }
-    __syncthreads();
-    fft_stages<LOGL, NL, NT, 0>(lds, tw_stage(ws));
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int b = tid + s * NT;
+      if (NB0 % NT == 0 || b < NB0) {
+        const int i = b % NBL0, line = b / NBL0;
+        dft<R0>(v[s]);
+#pragma unroll
+        for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
+      }
+    }
   }
+  __syncthreads();
+  fft_middle<LOGL, NL, NT, 1>(lds, tw);
+  // last stage of both arrays + 2F
   const float l11 = tp.l11, l21 = tp.l21, l22 = tp.l22;
-  const float qnan = __builtin_nanf("");
-  for (int e = threadIdx.x; e < L * RQ; e += NT) {
-    const int ql = e % RQ, p = e / RQ;
-    const int64_t m = q0 + ql + Rr * p;
-    const int64_t i = (m + N / 2) & (N - 1);
-    if (i < P.bin_lo || i >= P.bin_lo + P.n_bins) continue;
-    const int64_t o = i - P.bin_lo;
-    float2 fa = make_float2(qnan, qnan), fb = fa;
-    float v = qnan;
-    if (status == 0) {
-      // whitened Fa', Fb': 2F = 2 (|Fa'|^2 + |Fb'|^2)
-      fa = lds[p * NL + ql];
-      fb = lds[p * NL + RQ + ql];
-      v = 2.0f * ((fa.x * fa.x + fa.y * fa.y) + (fb.x * fb.x + fb.y * fb.y));
-    }
-    twoF[tmpl * P.n_bins + o] = v;
-    if (fafb) {
-      // undo the whitening: Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
-      const float2 wa = fa, wb = fb;
-      fa = cscale(wa, l11);
-      fb = make_float2(l21 * wa.x + l22 * wb.x, l21 * wa.y + l22 * wb.y);
-      fafb[(tmpl * 2 + 0) * P.n_bins + o] = fa;
-      fafb[(tmpl * 2 + 1) * P.n_bins + o] = fb;
+  constexpr int PER = (NBL + NT - 1) / NT;
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int b = tid + s * NT;
+    if (NBL % NT == 0 || b < NBL) {
+      const int ql = b % RQ, i = b / RQ;
+      float2 va[RL], vb[RL];
+#pragma unroll
+      for (int j = 0; j < RL; ++j) {
+        va[j] = lds[Lay::at(i + j * PL, ql)];
+        vb[j] = lds[Lay::at(i + j * PL, RQ + ql)];
+      }
+      twiddle_dft<RL, PL>(va, i, tw);
+      twiddle_dft<RL, PL>(vb, i, tw);
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        const int64_t ib = (q0 + ql + Rr * int64_t(i + m * PL) + N / 2) & (N - 1);
+        if (ib < P.bin_lo || ib >= P.bin_lo + P.n_bins) continue;
+        const int64_t o = ib - P.bin_lo;
+        const float2 fa = va[m], fb = vb[m];
+        twoF[tmpl * P.n_bins + o] =
+            2.0f * ((fa.x * fa.x + fa.y * fa.y) + (fb.x * fb.x + fb.y * fb.y));
+        if (fafb) {
+          // undo the whitening: Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
+          fafb[(tmpl * 2 + 0) * P.n_bins + o] = cscale(fa, l11);
+          fafb[(tmpl * 2 + 1) * P.n_bins + o] =
+              make_float2(l21 * fa.x + l22 * fb.x, l21 * fa.y + l22 * fb.y);
+        }
+      }
     }
   }
 }

@@ -6,8 +6,10 @@
 //      sky direction once per node (n.r, n.v), so every later delay
 //      evaluation is a cubic Hermite on LDS data;
 //   2. solves the detector epochs T_k of step (iv) for the thread's own grid
-//      points (FP64); T_k is monotonic in k, so the first and last points of
-//      the tile bound the input samples its interpolation windows touch;
+//      points (FP64): the tile's first point by a fixed-point and a Newton
+//      step, every other point by one Newton step from the first point's
+//      solution extrapolated along dT/dtau; T_k is monotonic in k, so the
+//      tile's first and last points bound the input samples it touches;
 //   3. stages those samples in LDS after the step (iii) heterodyne correction
 //      z_j = x_j exp(-2 pi i f_h (t_src,j - t_j)) (FP64 delay, reduced to
 //      [-1/2, 1/2] cycles, FP32 rotation): each input sample is read from HBM
@@ -19,12 +21,77 @@
 // Finally it removes the spin-down phase Phi_s(tau_k) and the sub-bin offset
 // df (FP64 phase, FP32 rotation) and writes y_a', y_b' (float2) with
 // coalesced stores.  FP64 is used only for times and phases.
+//
+// The half-width D is a template parameter: with s = f + c_t, c_t = D-1-t,
+//   h_t = sin(pi f) * [A_t cos(pi f/D) + B_t sin(pi f/D) + C_t] / s,
+//   A_t = (-1)^{c_t} cos(pi c_t/D) / (2 pi), B_t = -(-1)^{c_t} sin(pi c_t/D) / (2 pi),
+//   C_t = (-1)^{c_t} / (2 pi),
+// so each tap costs one reciprocal, two FMAs for the window and two for the
+// accumulation; sin(pi f) multiplies the finished sum.
 #pragma once
 
 #include "fstat_common.hpp"
 
 namespace fstat {
 
+// Compile-time cos and sin of pi * n / d (Taylor series after reduction to
+// [-pi/4, pi/4]); used only to build tap constants.
+__host__ __device__ constexpr double ct_poly_sin(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / double((2 * k) * (2 * k + 1));
+    sum += term;
+  }
+  return sum;
+}
+__host__ __device__ constexpr double ct_poly_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / double((2 * k - 1) * (2 * k));
+    sum += term;
+  }
+  return sum;
+}
+// cos(pi q / 4) and sin(pi q / 4) for integer q, then angle addition
+__host__ __device__ constexpr double ct_cospi(int n, int d) {
+  // pi n/d = pi (q/4) + r with |r| <= pi/8
+  const double x = double(n) / double(d);
+  const int q = int(x * 4.0 + (x >= 0 ? 0.5 : -0.5));
+  const double r = kPi * (x - q / 4.0);
+  const int qm = ((q % 8) + 8) % 8;
+  const double h = 0.70710678118654752440;
+  const double cq = qm == 0 ? 1.0 : qm == 1 ? h : qm == 2 ? 0.0 : qm == 3 ? -h
+                  : qm == 4 ? -1.0 : qm == 5 ? -h : qm == 6 ? 0.0 : h;
+  const double sq = qm == 0 ? 0.0 : qm == 1 ? h : qm == 2 ? 1.0 : qm == 3 ? h
+                  : qm == 4 ? 0.0 : qm == 5 ? -h : qm == 6 ? -1.0 : -h;
+  return cq * ct_poly_cos(r) - sq * ct_poly_sin(r);
+}
+__host__ __device__ constexpr double ct_sinpi(int n, int d) {
+  const double x = double(n) / double(d);
+  const int q = int(x * 4.0 + (x >= 0 ? 0.5 : -0.5));
+  const double r = kPi * (x - q / 4.0);
+  const int qm = ((q % 8) + 8) % 8;
+  const double h = 0.70710678118654752440;
+  const double cq = qm == 0 ? 1.0 : qm == 1 ? h : qm == 2 ? 0.0 : qm == 3 ? -h
+                  : qm == 4 ? -1.0 : qm == 5 ? -h : qm == 6 ? 0.0 : h;
+  const double sq = qm == 0 ? 0.0 : qm == 1 ? h : qm == 2 ? 1.0 : qm == 3 ? h
+                  : qm == 4 ? 0.0 : qm == 5 ? -h : qm == 6 ? -1.0 : -h;
+  return sq * ct_poly_cos(r) + cq * ct_poly_sin(r);
+}
+
+template <int D>
+struct Taps {
+  static constexpr double sgn(int t) { return ((D - 1 - t) & 1) ? -1.0 : 1.0; }
+  static constexpr float A(int t) {
+    return float(sgn(t) * ct_cospi(D - 1 - t, D) / (2.0 * kPi));
+  }
+  static constexpr float B(int t) {
+    return float(-sgn(t) * ct_sinpi(D - 1 - t, D) / (2.0 * kPi));
+  }
+  static constexpr float C(int t) { return float(sgn(t) / (2.0 * kPi)); }
+};
+
+template <int D>
 __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws) {
   const int g = blockIdx.y;
   TmplParams* tpp = slot_params(ws, P.n_fft, g);
@@ -36,11 +103,9 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws)
 
   __shared__ float2 zs[kResWcap];
   __shared__ double2 nodes[kNodeCap];
-  __shared__ float tap_c[64], tap_s[64];
   __shared__ int64_t win_lo, win_hi;
   __shared__ int bad;
 
-  const int D = P.D;
   if (tp.status != 0) {
     for (int i = 0; i < kResPerThread; ++i) {
       int64_t k = k_s + tid + i * kResThreads;
@@ -48,13 +113,6 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws)
       yb[k] = make_float2(0.f, 0.f);
     }
     return;
-  }
-  // cos, sin of pi (D - 1 - t) / D for the window's angle addition
-  if (tid < 2 * D) {
-    float s, c;
-    sincospif(float(D - 1 - tid) / float(D), &s, &c);
-    tap_c[tid] = c;
-    tap_s[tid] = s;
   }
   if (tid == 0) bad = 0;
   bool oob = false;
@@ -74,6 +132,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws)
   int n_count = int(n_hi - n_lo + 1);
   n_count = n_count > kNodeCap ? kNodeCap : (n_count < 2 ? 2 : n_count);
   const NodeRoemer re{nodes, n_count, P.eph_t0 + double(n_lo) * P.eph_dt, P.eph_dt, P.inv_eph_dt};
+  const double tau_s = P.tau0 + P.dt * double(k_s);
 
   for (int X = 0; X < P.ndet; ++X) {
     const DetConst& d = P.det[X];
@@ -84,21 +143,36 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws)
                               tp.nhat[0] * e[3] + tp.nhat[1] * e[4] + tp.nhat[2] * e[5]);
     }
     __syncthreads();
-    // 2. detector epochs of this thread's grid points
+    // 2. detector epochs: the tile's first point in full (fixed point, two
+    // Newton steps), the rest by one Newton step from a prediction that
+    // carries the exact binary delay and linearises the Roemer delay about
+    // the first point: T ~ T_s + (t_b - t_b,s) / (1 + roemer'(T_s)).
+    const double rb0 = binary_delay(tp, tau_s);
+    double x0;
+    double d0 = grid_delay(re, tp, tau_s, oob);
+    d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
+    d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
+    const double inv0 = 1.0 - x0 * (1.0 - x0 * (1.0 - x0));
     double dly[kResPerThread];
     int64_t j0[kResPerThread];
     float fr[kResPerThread];
+#pragma unroll
     for (int i = 0; i < kResPerThread; ++i) {
-      const int64_t k = k_s + tid + i * kResThreads;
-      dly[i] = grid_delay(re, tp, P.tau0 + P.dt * double(k), oob);
-      split_u(double(k) + d.off + dly[i] * P.inv_dt, j0[i], fr[i]);
+      const int64_t kk = tid + i * kResThreads;
+      const double dtau = P.dt * double(kk);
+      const double tau = tau_s + dtau;
+      const double rb = binary_delay(tp, tau);
+      const double guess = d0 + (dtau + rb - rb0) * inv0 - dtau;
+      double x;
+      dly[i] = grid_delay_newton(re, tau, rb, guess, x, oob);
+      split_u(double(k_s + kk) + d.off + dly[i] * P.inv_dt, j0[i], fr[i]);
     }
     if (tid == 0) win_lo = j0[0] - D + 1;
     if (tid == kResThreads - 1) win_hi = j0[kResPerThread - 1] + D;
     __syncthreads();
     const int64_t lo = win_lo;
     const int64_t nwin = win_hi - lo + 1;
-    if (nwin > kResWcap || nwin < 1) {
+    if (nwin > kResWcap || nwin < 2 * D) {
       // delay drift beyond 1/16 per tile: flag the template (NaN output)
       if (tid == 0) atomicOr(&tpp->status, 4);
       return;
@@ -121,33 +195,34 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws)
     }
     __syncthreads();
     // 4. interpolation and antenna weighting
-    const float inv_pi = 0.318309886183790671f;
+#pragma unroll
     for (int i = 0; i < kResPerThread; ++i) {
-      const int64_t k = k_s + tid + i * kResThreads;
       const float f = fr[i];
-      float2 zh = make_float2(0.f, 0.f);
-      const int64_t base = j0[i] - D + 1 - lo;
+      // taps j0-D+1 .. j0+D; monotonic T_k keeps them inside the window,
+      // the clamp only guards memory
+      int base = int(j0[i] - lo) - (D - 1);
+      base = base < 0 ? 0 : (base > W - 2 * D ? W - 2 * D : base);
+      const float2* zp = zs + base;
+      float2 zh;
       if (f == 0.0f) {
-        int64_t idx = j0[i] - lo;
-        idx = idx < 0 ? 0 : (idx >= W ? W - 1 : idx);
-        zh = zs[idx];
+        zh = zp[D - 1];
       } else {
-        const float sp = sinpif(f) * inv_pi;
         float ws_, wc_;
-        sincospif(f / float(D), &ws_, &wc_);
+        sincospif(f * (1.0f / float(D)), &ws_, &wc_);
+        float sx = 0.f, sy = 0.f;
+#pragma unroll
         for (int t = 0; t < 2 * D; ++t) {
-          const float s = f + float(D - 1 - t);
-          const float win = 0.5f + 0.5f * (wc_ * tap_c[t] - ws_ * tap_s[t]);
-          const float h = (((D - 1 - t) & 1) ? -sp : sp) * __builtin_amdgcn_rcpf(s) * win;
-          int64_t idx = base + t;
-          idx = idx < 0 ? 0 : (idx >= W ? W - 1 : idx);
-          const float2 zv = zs[idx];
-          zh.x += h * zv.x;
-          zh.y += h * zv.y;
+          const float win = fmaf(Taps<D>::B(t), ws_, fmaf(Taps<D>::A(t), wc_, Taps<D>::C(t)));
+          const float h = win * __builtin_amdgcn_rcpf(f + float(D - 1 - t));
+          const float2 zv = zp[t];
+          sx = fmaf(h, zv.x, sx);
+          sy = fmaf(h, zv.y, sy);
         }
+        const float sp = sinpif(f);
+        zh = make_float2(sx * sp, sy * sp);
       }
       // antenna patterns at T_k: x = alpha - phi(T_k), in cycles
-      const double tau = P.tau0 + P.dt * double(k);
+      const double tau = tau_s + P.dt * double(tid + i * kResThreads);
       const float xc = reduce_cycles(tp.alpha_cyc[X] - P.sid_rate_cyc * (tau + dly[i]));
       float sx, cx;
       sincospif(2.0f * xc, &sx, &cx);
@@ -156,10 +231,10 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws)
                       tp.ca[X][4] * s2;
       const float b = tp.cb[X][0] + tp.cb[X][1] * cx + tp.cb[X][2] * sx + tp.cb[X][3] * c2 +
                       tp.cb[X][4] * s2;
-      acc_a[i].x += a * zh.x;
-      acc_a[i].y += a * zh.y;
-      acc_b[i].x += b * zh.x;
-      acc_b[i].y += b * zh.y;
+      acc_a[i].x = fmaf(a, zh.x, acc_a[i].x);
+      acc_a[i].y = fmaf(a, zh.y, acc_a[i].y);
+      acc_b[i].x = fmaf(b, zh.x, acc_b[i].x);
+      acc_b[i].y = fmaf(b, zh.y, acc_b[i].y);
     }
     __syncthreads();
   }

@@ -118,6 +118,7 @@ def test_plan_accepts_valid_setup(lib):
     (lambda d: setattr(d, "n_bins", 0), "band"),
     (lambda d: setattr(d, "bin_lo", (1 << 13) - 5), "band"),
     (lambda d: setattr(d, "sinc_halfwidth", 1), "sinc_halfwidth"),
+    (lambda d: setattr(d, "sinc_halfwidth", 7), "sinc_halfwidth"),
     (lambda d: setattr(d, "sinc_halfwidth", 33), "sinc_halfwidth"),
     (lambda d: setattr(d, "dt", 0.0), "dt"),
     (lambda d: setattr(d, "dt", float("nan")), "dt"),
