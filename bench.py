@@ -27,20 +27,21 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err ≤1e-4"
 
 
-def kernel_bytes(ds, plan_k_pad, log_c, G):
-    """Algorithmic HBM bytes per launch of each kernel for G templates.
+def step_bytes(ds, k_pad, n_resampled):
+    """Algorithmic HBM bytes of one step, per kernel.
 
-    resample: read the input series once (8 B/sample/detector), write y_a, y_b
-      on the computed grid (2 x k_pad x 8 B);
-    fft_columns: read y_a, y_b rows that hold data (2 x k_pad x 8 B), write the
-      full transposed-twiddled arrays (2 x n_fft x 8 B);
-    fft_rows_2f: read them (2 x n_fft x 8 B), write 2F (4 B/bin)."""
+    resample: read every input series once (8 B/sample/detector) and write the
+      two resampled series on the computed grid (2 x k_pad x 8 B), once per
+      resampled series (per sky/orbit group on the grouped path);
+    fft_columns: read the two series on the computed grid (2 x k_pad x 8 B) and
+      write the full column-transformed arrays (2 x n_fft x 8 B), per template;
+    fft_rows_2f: read those (2 x n_fft x 8 B) and write 2F (4 B/bin), per template."""
     n_in = sum(d.n for d in ds.detectors)
     return {
-        "prologue": G * 1024,
-        "resample": G * (8 * n_in + 2 * 8 * plan_k_pad),
-        "fft_columns": G * (2 * 8 * plan_k_pad + 2 * 8 * ds.n_fft),
-        "fft_rows_2f": G * (2 * 8 * ds.n_fft + 4 * ds.n_bins),
+        "prologue": ds.ntmpl * 1024,
+        "resample": n_resampled * (8 * n_in + 2 * 8 * k_pad),
+        "fft_columns": ds.ntmpl * (2 * 8 * k_pad + 2 * 8 * ds.n_fft),
+        "fft_rows_2f": ds.ntmpl * (2 * 8 * ds.n_fft + 4 * ds.n_bins),
     }
 
 
@@ -73,8 +74,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=32, help="templates in flight per launch")
+    ap.add_argument("--batch", type=int, default=8, help="templates in flight per launch")
     ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--graph-steps", type=int, default=5)
     ap.add_argument("--cpu-templates", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -99,14 +101,19 @@ def main():
     tm = torch.from_numpy(ds.templates).to(dd.device)
     out = torch.empty((ds.ntmpl, ds.n_bins), dtype=torch.float32, device=dd.device)
     stream = torch.cuda.current_stream()
-    k_pad, log_c = k_pad_of(ds)
+    k_pad, _ = k_pad_of(ds)
+
+    sr = binding.Search(dd, ds.templates, slots=args.batch)
+    print(f"bench: {ds.ntmpl} templates in {sr.ngroups} sky/orbit groups, "
+          f"{sr.nchunks} launch sequences of {args.batch} slots", file=sys.stderr, flush=True)
 
     print("bench: warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        binding.compute_2f_profiled(dd, tm, out=out)
+        sr.run_profiled(out=out)
     torch.cuda.synchronize()
 
-    # timed region: K steps of the batched path, per-kernel HIP events inside
+    # timed region: K steps of the grouped batched path, per-kernel HIP events
+    # recorded on the library's stream around every launch
     print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
     totals = {k: [0.0, 0] for k in binding.KERNELS}
     torch.cuda.synchronize()
@@ -114,7 +121,7 @@ def main():
     ev0.record(stream)
     t_wall = time.perf_counter()
     for _ in range(args.steps):
-        _, kt = binding.compute_2f_profiled(dd, tm, out=out)
+        _, kt = sr.run_profiled(out=out)
         for k, (ms, n) in kt.items():
             totals[k][0] += ms
             totals[k][1] += n
@@ -124,34 +131,61 @@ def main():
     ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
     value = ds.ntmpl * args.steps / (ms_total / 1e3)
+    binding.sync_check()
 
-    G = min(args.batch, ds.ntmpl)
-    per_launch = kernel_bytes(ds, k_pad, log_c, G)
+    bytes_step = step_bytes(ds, k_pad, sr.ngroups)
     kern = {}
     for k, (ms, n) in totals.items():
         avg = ms / max(n, 1)
-        kern[k] = {"ms_total": round(ms, 4), "launches": n, "avg_us": round(avg * 1e3, 2),
-                   "gbs": round(per_launch[k] / (avg / 1e3) / 1e9, 1) if avg > 0 else None}
+        b_launch = bytes_step[k] * args.steps / max(n, 1)
+        kern[k] = {"ms_per_step": round(ms / args.steps, 4), "launches_per_step": n // args.steps,
+                   "avg_us": round(avg * 1e3, 2), "bytes_per_launch": int(b_launch),
+                   "gbs": round(b_launch / (avg / 1e3) / 1e9, 1) if avg > 0 else None}
     dom = max((k for k in kern if k != "prologue"), key=lambda k: totals[k][0])
     achieved = kern[dom]["gbs"]
     roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-            "bytes_per_launch": per_launch[dom], "templates_per_launch": G}
+            "bytes_per_launch": kern[dom]["bytes_per_launch"]}
 
-    # plain per-template path (one template in flight)
-    plain = None
-    if args.plain_steps > 0:
-        print("bench: plain path", file=sys.stderr, flush=True)
+    def timed(fn, steps):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.plain_steps):
-            binding.compute_2f(dd, tm, out=out)
-        e1.record(stream)
+        e0.record(torch.cuda.current_stream())
+        for _ in range(steps):
+            fn()
+        e1.record(torch.cuda.current_stream())
         torch.cuda.synchronize()
-        plain_ms = e0.elapsed_time(e1) / args.plain_steps
-        plain = {"value": round(ds.ntmpl / (plain_ms / 1e3), 1), "ms_per_step": round(plain_ms, 3),
-                 "steps": args.plain_steps}
+        ms = e0.elapsed_time(e1) / steps
+        return {"value": round(ds.ntmpl / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
+                "steps": steps}
+
+    # the same grouped path replayed from a captured HIP graph
+    graph = None
+    if args.graph_steps > 0:
+        print("bench: graph replay", file=sys.stderr, flush=True)
+        srg = binding.Search(dd, ds.templates, slots=args.batch, graph=True)
+        gs = torch.cuda.Stream()
+        torch.cuda.synchronize()
+
+        def run_graph():
+            with torch.cuda.stream(gs):
+                srg.run(out=out, stream=gs)
+            gs.synchronize()
+        run_graph()
+        graph = timed(run_graph, args.graph_steps)
+        del srg
+
+    # every template resampled on its own, several templates per launch
+    ungrouped = None
+    plain = None
+    if args.plain_steps > 0:
+        print("bench: ungrouped batched path", file=sys.stderr, flush=True)
+        ungrouped = timed(lambda: binding.compute_2f_batched(dd, tm, out=out), args.plain_steps)
+        # the plain per-template path (one template in flight, as in the paper)
+        print("bench: plain path", file=sys.stderr, flush=True)
+        dd1 = binding.DeviceData(ds, batch=1)
+        plain = timed(lambda: binding.compute_2f(dd1, tm, out=out), args.plain_steps)
+        del dd1
     binding.sync_check()
 
     calib = None
@@ -180,8 +214,14 @@ def main():
         "config": {"workload": "two detectors, 10 d at 1 s (864000 samples each), 150 Hz, "
                                "1000 templates (10x10 sky x 10 spin-down), n_fft 2^21, "
                                "full band", "templates": ds.ntmpl, "n_fft": ds.n_fft,
-                   "n_bins": ds.n_bins, "detectors": ds.ndet, "samples_per_detector": ds.detectors[0].n,
-                   "sinc_halfwidth": ds.sinc_halfwidth, "batch": G, "timing_dtype": "f64"},
+                   "n_bins": ds.n_bins, "detectors": ds.ndet,
+                   "samples_per_detector": ds.detectors[0].n,
+                   "sinc_halfwidth": ds.sinc_halfwidth, "slots": args.batch,
+                   "timing_dtype": "f64", "path": "grouped: one resampled series per sky "
+                   "position, spin-down phase applied in the FFT load",
+                   "sky_orbit_groups": sr.ngroups},
+        "graph_replay": graph,
+        "batched_ungrouped": ungrouped,
         "plain": plain,
         "batched_over_plain": round(value / plain["value"], 3) if plain else None,
         "tau_eff_s_per_bin_per_det": (ms_step / 1e3) / (n_bins_total * ds.ndet),

@@ -164,6 +164,42 @@ FSTAT_API fstat_status fstat_compute_2f_profiled(const fstat_plan* plan, const f
                                        void* workspace, size_t ws_bytes, int64_t max_batch,
                                        void* stream, float* kernel_ms, int64_t* launches);
 
+/* Grouped path for a template bank.  Sec. 4.1 measures that searching over
+ * spin-down parameters at a fixed sky position can reuse the sky-dependent
+ * barycentring; here every maximal run of consecutive templates with the
+ * same sky position and orbit (alpha, delta, asini, porb, tp; porb and tp
+ * ignored when asini = 0) is resampled once (steps (iii)-(v) and the antenna
+ * weighting), and each template applies its own spin-down phase and sub-bin
+ * offset as the FFT loads the shared series.  The result equals
+ * fstat_compute_2f bit for bit.
+ *
+ * fstat_search_create plans the bank from a HOST copy of the templates (the
+ * same rows the device array will hold at run time, in the same order),
+ * with `slots` (1..32) templates in flight per launch sequence; flags may be
+ * FSTAT_SEARCH_GRAPH: fstat_search_run then captures its launch sequence in
+ * a HIP graph on the first call and replays it while the pointers it was
+ * captured with (inputs, templates, outputs, workspace) stay the same
+ * (needs a non-null stream).  The search keeps a pointer to the plan, which
+ * must outlive it.  fstat_search_info reports the workspace bytes, the
+ * number of groups and of launch sequences.  fstat_search_run_profiled runs
+ * without a graph and returns per-kernel device time like
+ * fstat_compute_2f_profiled (synchronises the stream). */
+#define FSTAT_SEARCH_GRAPH 1u
+typedef struct fstat_search fstat_search;  /* opaque, host memory owned by the library */
+FSTAT_API fstat_status fstat_search_create(const fstat_plan* plan, const double* templates_host,
+                                           int64_t ntmpl, int32_t slots, uint32_t flags,
+                                           fstat_search** out);
+FSTAT_API void fstat_search_destroy(fstat_search* search);
+FSTAT_API fstat_status fstat_search_info(const fstat_search* search, size_t* ws_bytes,
+                                         int64_t* ngroups, int64_t* nchunks);
+FSTAT_API fstat_status fstat_search_run(fstat_search* search, const fstat_inputs* in,
+                                        const double* templates, float* twoF, void* fafb,
+                                        void* workspace, size_t ws_bytes, void* stream);
+FSTAT_API fstat_status fstat_search_run_profiled(fstat_search* search, const fstat_inputs* in,
+                                                 const double* templates, float* twoF,
+                                                 void* workspace, size_t ws_bytes, void* stream,
+                                                 float* kernel_ms, int64_t* launches);
+
 /* Diagnostic: steps (iii)-(v) and the weighting of (vi) only.  Writes the
  * weighted, resampled series before the transform, y: float2 [ntmpl][2][n_fft]
  * (y_a then y_b, zero beyond the data).  Needs fstat_workspace_size(plan, 1). */

@@ -21,7 +21,9 @@ FSTAT_OK, FSTAT_EINVAL, FSTAT_EUNSUPPORTED, FSTAT_EWORKSPACE, FSTAT_EHIP = 0, -1
 EXPORTED = ("fstat_plan_create", "fstat_plan_destroy", "fstat_workspace_size",
             "fstat_antenna_moments", "fstat_compute_2f", "fstat_compute_2f_batched",
             "fstat_compute_2f_profiled", "fstat_resample", "fstat_sync_check",
-            "fstat_last_error", "fstat_version")
+            "fstat_last_error", "fstat_version", "fstat_search_create", "fstat_search_destroy",
+            "fstat_search_info", "fstat_search_run", "fstat_search_run_profiled")
+SEARCH_GRAPH = 1
 
 
 class FstatDetector(ctypes.Structure):
@@ -79,13 +81,24 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                               sz, i64, vp, ctypes.POINTER(ctypes.c_float),
                                               ctypes.POINTER(ctypes.c_int64)]
     lib.fstat_resample.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, i64, vp, vp, sz, vp]
+    lib.fstat_search_create.argtypes = [vp, vp, i64, ctypes.c_int32, ctypes.c_uint32,
+                                        ctypes.POINTER(vp)]
+    lib.fstat_search_destroy.argtypes = [vp]
+    lib.fstat_search_destroy.restype = None
+    lib.fstat_search_info.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64)]
+    lib.fstat_search_run.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, vp, vp, vp, sz, vp]
+    lib.fstat_search_run_profiled.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, vp, vp, sz, vp,
+                                              ctypes.POINTER(ctypes.c_float),
+                                              ctypes.POINTER(ctypes.c_int64)]
     lib.fstat_sync_check.argtypes = [vp]
     lib.fstat_last_error.restype = ctypes.c_char_p
     lib.fstat_last_error.argtypes = []
     lib.fstat_version.restype = ctypes.c_char_p
     lib.fstat_version.argtypes = []
     for name in EXPORTED:
-        if name not in ("fstat_plan_destroy", "fstat_last_error", "fstat_version"):
+        if name not in ("fstat_plan_destroy", "fstat_last_error", "fstat_version",
+                        "fstat_search_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -257,3 +270,57 @@ def resample(dd: DeviceData, templates, stream=None):
 
 def sync_check(stream=None):
     _check(load_library().fstat_sync_check(_stream_ptr(stream)))
+
+
+class Search:
+    """Grouped path for a template bank (fstat_search_*): templates sharing a
+    sky position and orbit are resampled once.  ``templates`` is the bank in
+    host memory; the same rows are copied to the device once."""
+
+    def __init__(self, dd: DeviceData, templates, slots=8, graph=False):
+        import torch
+        lib = load_library()
+        host = np.ascontiguousarray(np.asarray(templates, dtype=np.float64))
+        if host.ndim != 2 or host.shape[1] != TEMPLATE_STRIDE:
+            raise FstatError(FSTAT_EINVAL, "templates must have shape [n, 8]")
+        self.dd, self.ntmpl = dd, host.shape[0]
+        h = ctypes.c_void_p()
+        _check(lib.fstat_search_create(dd.plan.handle, host.ctypes.data_as(ctypes.c_void_p),
+                                       self.ntmpl, int(slots), SEARCH_GRAPH if graph else 0,
+                                       ctypes.byref(h)))
+        self.handle = h
+        ws, ng, nc = ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.fstat_search_info(h, ctypes.byref(ws), ctypes.byref(ng), ctypes.byref(nc)))
+        self.ws_bytes, self.ngroups, self.nchunks = int(ws.value), int(ng.value), int(nc.value)
+        self.templates = torch.from_numpy(host).to(dd.device)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dd.device)
+        self.graph = graph
+
+    def run(self, out=None, fafb=False, stream=None):
+        import torch
+        dd = self.dd
+        tf = out if out is not None else torch.empty((self.ntmpl, dd.n_bins), dtype=torch.float32,
+                                                     device=dd.device)
+        fab = (torch.empty((self.ntmpl, 2, dd.n_bins), dtype=torch.complex64, device=dd.device)
+               if fafb else None)
+        _check(load_library().fstat_search_run(self.handle, ctypes.byref(dd.inputs),
+                                               _ptr(self.templates), _ptr(tf), _ptr(fab),
+                                               _ptr(self.ws), self.ws.numel(), _stream_ptr(stream)))
+        return (tf, fab) if fafb else tf
+
+    def run_profiled(self, out=None, stream=None):
+        import torch
+        dd = self.dd
+        tf = out if out is not None else torch.empty((self.ntmpl, dd.n_bins), dtype=torch.float32,
+                                                     device=dd.device)
+        ms = (ctypes.c_float * 4)()
+        cnt = (ctypes.c_int64 * 4)()
+        _check(load_library().fstat_search_run_profiled(
+            self.handle, ctypes.byref(dd.inputs), _ptr(self.templates), _ptr(tf), _ptr(self.ws),
+            self.ws.numel(), _stream_ptr(stream), ms, cnt))
+        return tf, {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNELS)}
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fstat_search_destroy(self.handle)
+            self.handle = None

@@ -62,8 +62,8 @@ int ilog2(int64_t v) {
 int cols_lines_max(int log_rr) { return std::min(64, 16384 >> log_rr); }
 int rows_lines_max(int log_c) { return std::min(32, 8192 >> log_c); }
 
-using ColsFn = void (*)(PlanConst, void*, int, int64_t);
-using RowsFn = void (*)(PlanConst, void*, int, float*, float2*, int64_t);
+using ColsFn = void (*)(PlanConst, void*, ChunkMap, int, int, int64_t);
+using RowsFn = void (*)(PlanConst, void*, ChunkMap, int, float*, float2*);
 
 template <int LOGL>
 constexpr int kColsMax = (16384 >> LOGL) < 64 ? (16384 >> LOGL) : 64;
@@ -75,10 +75,12 @@ struct FftVariant {
   int threads;
 };
 
-template <int LOGL>
+template <int LOGL, bool GROUPED>
 FftVariant cols_variant(bool half) {
-  if (half) return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL> / 2, 256>), 256};
-  return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL>, 512>), 512};
+  if (half)
+    return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL> / 2, 256, GROUPED>),
+            256};
+  return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL>, 512, GROUPED>), 512};
 }
 template <int LOGL>
 FftVariant rows_variant(bool half) {
@@ -86,17 +88,21 @@ FftVariant rows_variant(bool half) {
   return {reinterpret_cast<const void*>(&k_fft_rows_2f<LOGL, kRowsMax<LOGL>, 512>), 512};
 }
 
-FftVariant pick_cols(int logl, bool half) {
+template <bool GROUPED>
+FftVariant pick_cols_g(int logl, bool half) {
   switch (logl) {
-    case 6: return cols_variant<6>(half);
-    case 7: return cols_variant<7>(half);
-    case 8: return cols_variant<8>(half);
-    case 9: return cols_variant<9>(half);
-    case 10: return cols_variant<10>(half);
-    case 11: return cols_variant<11>(half);
-    case 12: return cols_variant<12>(half);
+    case 6: return cols_variant<6, GROUPED>(half);
+    case 7: return cols_variant<7, GROUPED>(half);
+    case 8: return cols_variant<8, GROUPED>(half);
+    case 9: return cols_variant<9, GROUPED>(half);
+    case 10: return cols_variant<10, GROUPED>(half);
+    case 11: return cols_variant<11, GROUPED>(half);
+    case 12: return cols_variant<12, GROUPED>(half);
     default: return {nullptr, 0};
   }
+}
+FftVariant pick_cols(int logl, bool half, bool grouped) {
+  return grouped ? pick_cols_g<true>(logl, half) : pick_cols_g<false>(logl, half);
 }
 FftVariant pick_rows(int logl, bool half) {
   switch (logl) {
@@ -243,17 +249,21 @@ size_t lds_bytes_rows(const fstat_plan* p) {
 }
 
 // Resampling kernel for a supported interpolation half-width.
-using ResFn = void (*)(PlanConst, void*);
-ResFn resample_kernel(int D) {
+using ResFn = void (*)(PlanConst, void*, ChunkMap, int);
+template <bool GROUPED>
+ResFn resample_kernel_g(int D) {
   switch (D) {
-    case 4: return &k_resample<4>;
-    case 6: return &k_resample<6>;
-    case 8: return &k_resample<8>;
-    case 10: return &k_resample<10>;
-    case 12: return &k_resample<12>;
-    case 16: return &k_resample<16>;
+    case 4: return &k_resample<4, GROUPED>;
+    case 6: return &k_resample<6, GROUPED>;
+    case 8: return &k_resample<8, GROUPED>;
+    case 10: return &k_resample<10, GROUPED>;
+    case 12: return &k_resample<12, GROUPED>;
+    case 16: return &k_resample<16, GROUPED>;
     default: return nullptr;
   }
+}
+ResFn resample_kernel(int D, bool grouped) {
+  return grouped ? resample_kernel_g<true>(D) : resample_kernel_g<false>(D);
 }
 
 // Optional per-kernel timing: events recorded before and after each launch.
@@ -277,46 +287,73 @@ struct KernelTimer {
   }
 };
 
-// Launch the whole path for templates [t_first, t_first + count) using
-// `count` workspace slots.  y_out: diagnostic path (resampled series only).
+// Launch the whole path for the template slots of one chunk.  grouped: the
+// chunk's map names the sky/orbit groups to resample (possibly none, when a
+// group continues from the previous chunk) and the group buffer every slot
+// reads.  y_out: diagnostic path (resampled series only, per template).
 fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double* templates,
-                          int64_t t_first, int count, float* twoF, float2* fafb, float2* y_out,
-                          void* ws, hipStream_t st, KernelTimer& tm) {
+                          const ChunkMap& map, int slots, bool grouped, float* twoF, float2* fafb,
+                          float2* y_out, void* ws, hipStream_t st, KernelTimer& tm) {
   fstat_status s;
+  const int n = map.n_tmpl;
   if ((s = tm.mark(0)) != FSTAT_OK) return s;
-  hipLaunchKernelGGL(k_prologue, dim3((count + 63) / 64), dim3(64), 0, st, P, templates, t_first,
-                     int64_t(count), ws);
+  hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, slots,
+                     ws);
   if ((s = tm.mark(0)) != FSTAT_OK) return s;
-  if ((s = tm.mark(1)) != FSTAT_OK) return s;
-  hipLaunchKernelGGL(resample_kernel(p->desc.sinc_halfwidth), dim3(unsigned(p->k_pad / kResTile), count),
-                     dim3(kResThreads), 0, st, P, ws);
-  if ((s = tm.mark(1)) != FSTAT_OK) return s;
+  const int n_res = grouped ? map.n_grp : n;
+  if (n_res > 0) {
+    if ((s = tm.mark(1)) != FSTAT_OK) return s;
+    hipLaunchKernelGGL(resample_kernel(p->desc.sinc_halfwidth, grouped),
+                       dim3(unsigned(p->k_pad / kResTile), n_res), dim3(kResThreads), 0, st, P,
+                       ws, map, slots);
+    if ((s = tm.mark(1)) != FSTAT_OK) return s;
+  }
   if (y_out) {
-    hipLaunchKernelGGL(k_copy_series, dim3(256, count), dim3(256), 0, st, P, ws, y_out,
-                       t_first);
+    hipLaunchKernelGGL(k_copy_series, dim3(256, n), dim3(256), 0, st, P, ws, map, y_out);
     return check_hip(hipGetLastError(), "resample launch");
   }
-  const FftVariant cv = pick_cols(p->log_rr, p->cols_half);
+  const FftVariant cv = pick_cols(p->log_rr, p->cols_half, grouped);
   const FftVariant rv = pick_rows(p->log_c, p->rows_half);
   if ((s = tm.mark(2)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn)),
-                     dim3(unsigned((int64_t(1) << p->log_c) / p->cols_lines), 2, count),
-                     dim3(cv.threads), lds_bytes_cols(p), st, P, ws, p->log_c, p->rows_act);
+                     dim3(unsigned((int64_t(1) << p->log_c) / p->cols_lines), 2, n),
+                     dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, p->log_c,
+                     p->rows_act);
   if ((s = tm.mark(2)) != FSTAT_OK) return s;
   if ((s = tm.mark(3)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rv.fn)),
-                     dim3(unsigned((int64_t(1) << p->log_rr) / p->rows_lines), count),
-                     dim3(rv.threads), lds_bytes_rows(p), st, P, ws, p->log_rr, twoF, fafb,
-                     t_first);
+                     dim3(unsigned((int64_t(1) << p->log_rr) / p->rows_lines), n),
+                     dim3(rv.threads), lds_bytes_rows(p), st, P, ws, map, p->log_rr, twoF, fafb);
   if ((s = tm.mark(3)) != FSTAT_OK) return s;
   return check_hip(hipGetLastError(), "kernel launch");
 }
 
+// Wait for the stream, then sum each kernel's event intervals.
+fstat_status finish_timer(KernelTimer& tm, hipStream_t st, float* kernel_ms, int64_t* launches) {
+  fstat_status s = check_hip(hipStreamSynchronize(st), "timing synchronise");
+  if (s != FSTAT_OK) return s;
+  for (int k = 0; k < KernelTimer::kKernels; ++k) {
+    float total = 0.f;
+    for (size_t i = 0; i + 1 < tm.ev[k].size(); i += 2) {
+      float ms = 0.f;
+      s = check_hip(hipEventElapsedTime(&ms, tm.ev[k][i], tm.ev[k][i + 1]), "event time");
+      if (s != FSTAT_OK) return s;
+      total += ms;
+    }
+    kernel_ms[k] = total;
+    launches[k] = int64_t(tm.ev[k].size() / 2);
+  }
+  g_err.clear();
+  return FSTAT_OK;
+}
+
 fstat_status set_lds_limits(const fstat_plan* p) {
-  hipError_t e = hipFuncSetAttribute(pick_cols(p->log_rr, p->cols_half).fn,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     int(lds_bytes_cols(p)));
-  if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(cols)");
+  hipError_t e = hipSuccess;
+  for (bool grouped : {false, true}) {
+    e = hipFuncSetAttribute(pick_cols(p->log_rr, p->cols_half, grouped).fn,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_cols(p)));
+    if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(cols)");
+  }
   e = hipFuncSetAttribute(pick_rows(p->log_c, p->rows_half).fn,
                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_rows(p)));
   if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(rows)");
@@ -337,7 +374,7 @@ fstat_status run(const fstat_plan* p, const fstat_inputs* in, const double* temp
   if (s != FSTAT_OK) return s;
   if (ntmpl == 0) return ok();
   slots = std::min(slots, max_slots);
-  slots = std::min<int64_t>(slots, 65535);
+  slots = std::min<int64_t>(slots, kMaxSlots);
   s = set_lds_limits(p);
   if (s != FSTAT_OK) return s;
   PlanConst P = make_const(p, in);
@@ -347,8 +384,11 @@ fstat_status run(const fstat_plan* p, const fstat_inputs* in, const double* temp
   tm.st = st;
   hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, ws, p->desc.n_fft);
   for (int64_t t = 0; t < ntmpl; t += slots) {
-    int count = int(std::min<int64_t>(slots, ntmpl - t));
-    s = launch_chunk(p, P, templates, t, count, twoF, static_cast<float2*>(fafb),
+    ChunkMap map;
+    std::memset(&map, 0, sizeof map);
+    map.n_tmpl = int(std::min<int64_t>(slots, ntmpl - t));
+    for (int i = 0; i < map.n_tmpl; ++i) map.tmpl[i] = t + i;
+    s = launch_chunk(p, P, templates, map, int(slots), false, twoF, static_cast<float2*>(fafb),
                      static_cast<float2*>(y_out), ws, st, tm);
     if (s != FSTAT_OK) return s;
   }
@@ -357,7 +397,187 @@ fstat_status run(const fstat_plan* p, const fstat_inputs* in, const double* temp
 
 }  // namespace
 
+// A template bank planned for the grouped path.
+struct fstat_search {
+  const fstat_plan* plan;
+  int slots;
+  uint32_t flags;
+  int64_t ntmpl, ngroups;
+  std::vector<ChunkMap> chunks;
+  // captured launch sequence and the arguments it was captured with
+  hipGraphExec_t exec = nullptr;
+  const void* key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  size_t key_ws = 0;
+  ~fstat_search() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
+namespace {
+
+// Templates with the same sky position and orbit share the resampled series;
+// an isolated source (asini = 0) ignores porb and tp.
+bool same_timing(const double* a, const double* b) {
+  if (a[0] != b[0] || a[1] != b[1] || a[5] != b[5]) return false;
+  if (a[5] == 0.0) return true;
+  return a[6] == b[6] && a[7] == b[7];
+}
+
+size_t search_ws_bytes(const fstat_search* sr) {
+  const fstat_plan* p = sr->plan;
+  return kHeaderBytes + size_t(sr->slots) * slot_bytes(p->desc.n_fft) +
+         size_t(sr->slots) * group_bytes(p->k_pad);
+}
+
+fstat_status search_launch(fstat_search* sr, const fstat_inputs* in, const double* templates,
+                           float* twoF, float2* fafb, void* ws, hipStream_t st, KernelTimer& tm) {
+  const fstat_plan* p = sr->plan;
+  PlanConst P = make_const(p, in);
+  hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, ws, p->desc.n_fft);
+  for (const ChunkMap& map : sr->chunks) {
+    fstat_status s =
+        launch_chunk(p, P, templates, map, sr->slots, true, twoF, fafb, nullptr, ws, st, tm);
+    if (s != FSTAT_OK) return s;
+  }
+  return FSTAT_OK;
+}
+
+fstat_status search_check(fstat_search* sr, const fstat_inputs* in, const double* templates,
+                          float* twoF, void* ws, size_t ws_bytes) {
+  if (!sr) return fail(FSTAT_EINVAL, "search is NULL");
+  if (sr->ntmpl > 0 && (!templates || !twoF)) return fail(FSTAT_EINVAL, "templates or twoF is NULL");
+  fstat_status s = validate_inputs(sr->plan, in, true);
+  if (s != FSTAT_OK) return s;
+  if (!ws) return fail(FSTAT_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(FSTAT_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < search_ws_bytes(sr))
+    return fail(FSTAT_EWORKSPACE, "workspace %zu bytes < %zu for this search", ws_bytes,
+                search_ws_bytes(sr));
+  return set_lds_limits(sr->plan);
+}
+
+}  // namespace
+
 extern "C" {
+
+fstat_status fstat_search_create(const fstat_plan* plan, const double* templates, int64_t ntmpl,
+                                 int32_t slots, uint32_t flags, fstat_search** out) {
+  if (!out) return fail(FSTAT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!plan) return fail(FSTAT_EINVAL, "plan is NULL");
+  if (ntmpl < 0 || (ntmpl > 0 && !templates)) return fail(FSTAT_EINVAL, "templates / ntmpl invalid");
+  if (slots < 1 || slots > kMaxSlots)
+    return fail(FSTAT_EINVAL, "slots=%d outside [1, %d]", slots, kMaxSlots);
+  if (flags & ~uint32_t(FSTAT_SEARCH_GRAPH)) return fail(FSTAT_EINVAL, "unknown flags");
+  fstat_search* sr = new (std::nothrow) fstat_search;
+  if (!sr) return fail(FSTAT_EINVAL, "host allocation failed");
+  sr->plan = plan;
+  sr->slots = slots;
+  sr->flags = flags;
+  sr->ntmpl = ntmpl;
+  // group = maximal run of consecutive templates with the same timing; the
+  // group buffer of group number g is g mod slots (a chunk holds at most
+  // `slots` templates, so at most `slots` groups, all distinct mod slots)
+  ChunkMap map;
+  std::memset(&map, 0, sizeof map);
+  int64_t group = -1;
+  for (int64_t t = 0; t < ntmpl; ++t) {
+    const double* row = templates + t * FSTAT_TEMPLATE_STRIDE;
+    const bool fresh = t == 0 || !same_timing(row, row - FSTAT_TEMPLATE_STRIDE);
+    if (map.n_tmpl == slots) {
+      sr->chunks.push_back(map);
+      std::memset(&map, 0, sizeof map);
+    }
+    const int slot = map.n_tmpl++;
+    if (fresh) {
+      ++group;
+      map.grp_slot[map.n_grp] = slot;
+      map.grp_buf[map.n_grp] = int32_t(group % slots);
+      ++map.n_grp;
+    }
+    map.tmpl[slot] = t;
+    map.tmpl_buf[slot] = int32_t(group % slots);
+  }
+  if (map.n_tmpl > 0) sr->chunks.push_back(map);
+  sr->ngroups = group + 1;
+  *out = sr;
+  return ok();
+}
+
+void fstat_search_destroy(fstat_search* search) { delete search; }
+
+fstat_status fstat_search_info(const fstat_search* search, size_t* ws_bytes, int64_t* ngroups,
+                               int64_t* nchunks) {
+  if (!search) return fail(FSTAT_EINVAL, "search is NULL");
+  if (ws_bytes) *ws_bytes = search_ws_bytes(search);
+  if (ngroups) *ngroups = search->ngroups;
+  if (nchunks) *nchunks = int64_t(search->chunks.size());
+  return ok();
+}
+
+fstat_status fstat_search_run(fstat_search* search, const fstat_inputs* in,
+                              const double* templates, float* twoF, void* fafb, void* workspace,
+                              size_t ws_bytes, void* stream) {
+  fstat_status s = search_check(search, in, templates, twoF, workspace, ws_bytes);
+  if (s != FSTAT_OK) return s;
+  if (search->ntmpl == 0) return ok();
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KernelTimer none;
+  none.st = st;
+  if (!(search->flags & FSTAT_SEARCH_GRAPH)) {
+    s = search_launch(search, in, templates, twoF, static_cast<float2*>(fafb), workspace, st,
+                      none);
+    return s == FSTAT_OK ? ok() : s;
+  }
+  if (!st) return fail(FSTAT_EINVAL, "graph replay needs a non-null stream");
+  const void* key[6] = {in->x[0], in->moments, templates, twoF, fafb, workspace};
+  bool same = search->exec && ws_bytes == search->key_ws;
+  for (int i = 0; i < 6 && same; ++i) same = key[i] == search->key[i];
+  if (!same) {
+    if (search->exec) {
+      (void)hipGraphExecDestroy(search->exec);
+      search->exec = nullptr;
+    }
+    s = check_hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (s != FSTAT_OK) return s;
+    fstat_status ls = search_launch(search, in, templates, twoF, static_cast<float2*>(fafb),
+                                    workspace, st, none);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (ls != FSTAT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return ls;
+    }
+    if ((s = check_hip(e, "end capture")) != FSTAT_OK) return s;
+    e = hipGraphInstantiate(&search->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if ((s = check_hip(e, "graph instantiate")) != FSTAT_OK) return s;
+    for (int i = 0; i < 6; ++i) search->key[i] = key[i];
+    search->key_ws = ws_bytes;
+  }
+  s = check_hip(hipGraphLaunch(search->exec, st), "graph launch");
+  return s == FSTAT_OK ? ok() : s;
+}
+
+fstat_status fstat_search_run_profiled(fstat_search* search, const fstat_inputs* in,
+                                       const double* templates, float* twoF, void* workspace,
+                                       size_t ws_bytes, void* stream, float* kernel_ms,
+                                       int64_t* launches) {
+  if (!kernel_ms || !launches) return fail(FSTAT_EINVAL, "kernel_ms or launches is NULL");
+  fstat_status s = search_check(search, in, templates, twoF, workspace, ws_bytes);
+  if (s != FSTAT_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KernelTimer tm;
+  tm.on = true;
+  tm.st = st;
+  if (search->ntmpl > 0) {
+    s = search_launch(search, in, templates, twoF, nullptr, workspace, st, tm);
+    if (s != FSTAT_OK) return s;
+  }
+  return finish_timer(tm, st, kernel_ms, launches);
+}
+
 
 const char* fstat_version(void) { return "fstat-gfx950 0.1"; }
 
@@ -469,20 +689,7 @@ fstat_status fstat_compute_2f_profiled(const fstat_plan* plan, const fstat_input
   fstat_status s = run(plan, in, templates, ntmpl, twoF, nullptr, nullptr, workspace, ws_bytes,
                        stream, max_batch, &tm);
   if (s != FSTAT_OK) return s;
-  s = check_hip(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "timing synchronise");
-  if (s != FSTAT_OK) return s;
-  for (int k = 0; k < KernelTimer::kKernels; ++k) {
-    float total = 0.f;
-    for (size_t i = 0; i + 1 < tm.ev[k].size(); i += 2) {
-      float ms = 0.f;
-      s = check_hip(hipEventElapsedTime(&ms, tm.ev[k][i], tm.ev[k][i + 1]), "event time");
-      if (s != FSTAT_OK) return s;
-      total += ms;
-    }
-    kernel_ms[k] = total;
-    launches[k] = int64_t(tm.ev[k].size() / 2);
-  }
-  return ok();
+  return finish_timer(tm, static_cast<hipStream_t>(stream), kernel_ms, launches);
 }
 
 fstat_status fstat_resample(const fstat_plan* plan, const fstat_inputs* in,

@@ -68,6 +68,27 @@ struct TmplParams {
   int32_t status;             // nonzero: every output bin of the template is NaN
 };
 
+// Status bits of a template (any bit: NaN in every output bin).
+constexpr int32_t kStatusTiming = 1;    // non-finite or invalid sky / orbit parameters
+constexpr int32_t kStatusCoverage = 2;  // delays exceed the plan's max_delay
+constexpr int32_t kStatusWindow = 4;    // a tile's input window overflowed the staging
+constexpr int32_t kStatusNodes = 8;     // a delay evaluation left the staged ephemeris
+constexpr int32_t kStatusPhase = 16;    // non-finite spin-down or sub-bin parameters
+// Bits that concern the resampled series of a sky/orbit group.
+constexpr int32_t kStatusGroupMask = kStatusTiming | kStatusCoverage | kStatusWindow | kStatusNodes;
+
+// Template slots of one launch sequence and, for the grouped path, the
+// sky/orbit groups it resamples.  Passed by value to every kernel.
+constexpr int kMaxSlots = 32;
+struct ChunkMap {
+  int32_t n_tmpl;               // slots in use
+  int32_t n_grp;                // groups resampled by this chunk (grouped path)
+  int64_t tmpl[kMaxSlots];      // template (output row) of slot s
+  int32_t tmpl_buf[kMaxSlots];  // group buffer slot s reads (grouped path)
+  int32_t grp_slot[kMaxSlots];  // slot holding the parameters of resampled group i
+  int32_t grp_buf[kMaxSlots];   // group buffer resampled group i writes
+};
+
 constexpr size_t kParamBytes = 1024;
 static_assert(sizeof(TmplParams) <= kParamBytes, "param block");
 // Workspace header: moment partials, then FP32 twiddle tables written from
@@ -96,6 +117,27 @@ __host__ __device__ inline TmplParams* slot_params(void* ws, int64_t n_fft, int 
 }
 __host__ __device__ inline float2* slot_buf(void* ws, int64_t n_fft, int g, int arr) {
   return reinterpret_cast<float2*>(slot_base(ws, n_fft, g) + kParamBytes) + size_t(arr) * n_fft;
+}
+
+// Grouped path: after `slots` template slots come group buffers of
+// [status (256 B) | y_a : k_pad float2 | y_b : k_pad float2], the resampled
+// series of one sky/orbit group before its spin-down phase.
+constexpr size_t kGroupHeader = 256;
+__host__ __device__ inline size_t group_bytes(int64_t k_pad) {
+  return kGroupHeader + size_t(k_pad) * 2 * sizeof(float2);
+}
+__host__ __device__ inline char* group_base(void* ws, int64_t n_fft, int slots, int64_t k_pad,
+                                            int b) {
+  return slot_base(ws, n_fft, slots) + size_t(b) * group_bytes(k_pad);
+}
+__host__ __device__ inline int32_t* group_status(void* ws, int64_t n_fft, int slots,
+                                                 int64_t k_pad, int b) {
+  return reinterpret_cast<int32_t*>(group_base(ws, n_fft, slots, k_pad, b));
+}
+__host__ __device__ inline float2* group_buf(void* ws, int64_t n_fft, int slots, int64_t k_pad,
+                                             int b, int arr) {
+  return reinterpret_cast<float2*>(group_base(ws, n_fft, slots, k_pad, b) + kGroupHeader) +
+         size_t(arr) * k_pad;
 }
 
 // ---------------------------------------------------------------------------
@@ -225,7 +267,31 @@ __device__ inline void split_u(double u, int64_t& j0, float& f) {
 // Reduce a phase given in cycles to [-1/2, 1/2] in FP64, then to float.
 __device__ inline float reduce_cycles(double c) { return static_cast<float>(c - rint(c)); }
 
+// exp(-i Phi_s(tau_k)) exp(-2 pi i df (tau_k - tau0)): the spin-down phase of
+// Sec. 2 about t_ref and the sub-bin frequency offset, FP64 cycles reduced to
+// [-1/2, 1/2] before the FP32 rotation.  One definition for every kernel
+// that applies it, so the per-template and grouped paths agree bit for bit.
+// Evaluated without FMA contraction, so every kernel gets the same bits.
+__device__ inline float2 spindown_rotation(const PlanConst& P, double f1dot, double f2dot,
+                                           double df, int64_t k) {
+#pragma clang fp contract(off)
+  const double tau = P.tau0 + P.dt * double(k);
+  const double dtr = tau - P.t_ref;
+  double cyc = f1dot * dtr * dtr * 0.5 + f2dot * dtr * dtr * dtr * (1.0 / 6.0);
+  cyc = cyc - rint(cyc) + df * (P.dt * double(k));
+  const float c = reduce_cycles(cyc);
+  float sn, cs;
+  sincospif(2.0f * c, &sn, &cs);
+  return make_float2(cs, -sn);
+}
+
 __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// Complex product without FMA contraction: applying the spin-down rotation
+// in different kernels must give the same bits.
+__device__ inline float2 cmul_exact(float2 a, float2 b) {
+#pragma clang fp contract(off)
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }

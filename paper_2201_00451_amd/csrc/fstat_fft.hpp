@@ -191,10 +191,13 @@ __global__ void k_twiddles(void* ws, int64_t n_fft) {
 // straight from HBM and the last one writes its outputs, times the four-step
 // twiddle W_N^{q c}, straight back (both with columns fastest across
 // threads: NL-element contiguous runs); only the middle stages go through
-// LDS.  Grid: (C / NL) x 2 arrays x templates.
-template <int LOGL, int NL, int NT>
-__global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, int log_c,
-                                                 int64_t rows_act) {
+// LDS.  Grid: (C / NL) x 2 arrays x template slots.
+// GROUPED: the input is the unphased series of the slot's sky/orbit group;
+// stage 0 applies the template's spin-down phase while loading and the
+// output goes to the slot's own buffer.
+template <int LOGL, int NL, int NT, bool GROUPED>
+__global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap map, int slots,
+                                                 int log_c, int64_t rows_act) {
   extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
   constexpr int NS = stage_count(LOGL);
@@ -206,10 +209,20 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, int log_
                                 total);
   const uint32_t gx = id % gridDim.x, rest = id / gridDim.x;
   const int arr = int(rest % gridDim.y), g = int(rest / gridDim.y);
-  if (slot_params(ws, P.n_fft, g)->status != 0) return;
+  TmplParams* tpp = slot_params(ws, P.n_fft, g);
+  int32_t status = tpp->status;
+  if (GROUPED) {
+    const int32_t gs = *group_status(ws, P.n_fft, slots, P.k_pad, map.tmpl_buf[g]);
+    if (gs != 0 && threadIdx.x == 0) atomicOr(&tpp->status, gs);
+    status |= gs;
+  }
+  if (status != 0) return;
   const int64_t C = int64_t(1) << log_c;
   const int64_t c0 = int64_t(gx) * NL;
   float2* buf = slot_buf(ws, P.n_fft, g, arr);
+  const float2* src =
+      GROUPED ? group_buf(ws, P.n_fft, slots, P.k_pad, map.tmpl_buf[g], arr) : buf;
+  const double f1dot = tpp->f1dot, f2dot = tpp->f2dot, df = tpp->df;
   const float2* __restrict__ tw = tw_stage(ws);
   const int tid = threadIdx.x;
   // stage 0: HBM -> registers -> DFT -> LDS
@@ -224,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, int log_
 #pragma unroll
         for (int j = 0; j < R0; ++j) {
           const int r = i + j * (L / R0);
-          v[s][j] = r < rows_act ? buf[int64_t(r) * C + c0 + line] : make_float2(0.f, 0.f);
+          v[s][j] = r < rows_act ? src[int64_t(r) * C + c0 + line] : make_float2(0.f, 0.f);
         }
       }
     }
@@ -233,6 +246,15 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, int log_
       const int b = tid + s * NT;
       if (NB0 % NT == 0 || b < NB0) {
         const int line = b % NL, i = b / NL;
+        if (GROUPED) {
+#pragma unroll
+          for (int j = 0; j < R0; ++j) {
+            const int r = i + j * (L / R0);
+            if (r < rows_act)
+              v[s][j] = cmul_exact(
+                  v[s][j], spindown_rotation(P, f1dot, f2dot, df, int64_t(r) * C + c0 + line));
+          }
+        }
         dft<R0>(v[s]);
 #pragma unroll
         for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
@@ -279,9 +301,9 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, int log_
 // the same bins in one thread and writes 2F (rows fastest across threads:
 // RQ-element runs of the output).  Grid: (Rr / RQ) x templates.
 template <int LOGL, int RQ, int NT>
-__global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, int log_rr,
-                                                    float* __restrict__ twoF, float2* fafb,
-                                                    int64_t t_first) {
+__global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, ChunkMap map,
+                                                    int log_rr, float* __restrict__ twoF,
+                                                    float2* fafb) {
   extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
   constexpr int NL = 2 * RQ;
@@ -294,7 +316,7 @@ __global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, int l
   const uint32_t gx = id % gridDim.x;
   const int g = int(id / gridDim.x);
   const TmplParams& tp = *slot_params(ws, P.n_fft, g);
-  const int64_t tmpl = t_first + g;
+  const int64_t tmpl = map.tmpl[g];
   const int64_t q0 = int64_t(gx) * RQ;
   const int64_t Rr = int64_t(1) << log_rr;
   const int64_t N = P.n_fft;
@@ -384,18 +406,22 @@ __global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, int l
 // Copy of the resampled series for the diagnostic entry point: y_a, y_b of
 // slot g into out[t][2][n_fft], zero beyond the computed grid, with the
 // whitening undone (y_a = l11 y_a', y_b = l21 y_a' + l22 y_b').
-__global__ void k_copy_series(PlanConst P, void* ws, float2* out, int64_t t_first) {
+__global__ void k_copy_series(PlanConst P, void* ws, ChunkMap map, float2* out) {
   const int g = blockIdx.y;
   const TmplParams& tp = *slot_params(ws, P.n_fft, g);
   const float2* sa = slot_buf(ws, P.n_fft, g, 0);
   const float2* sb = slot_buf(ws, P.n_fft, g, 1);
-  float2* da = out + ((t_first + g) * 2 + 0) * P.n_fft;
-  float2* db = out + ((t_first + g) * 2 + 1) * P.n_fft;
+  float2* da = out + (map.tmpl[g] * 2 + 0) * P.n_fft;
+  float2* db = out + (map.tmpl[g] * 2 + 1) * P.n_fft;
   const float l11 = tp.l11, l21 = tp.l21, l22 = tp.l22;
+  const float qnan = __builtin_nanf("");
+  const bool flagged = tp.status != 0;
   for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < P.n_fft;
        k += int64_t(gridDim.x) * blockDim.x) {
     float2 a = make_float2(0.f, 0.f), b = a;
-    if (k < P.k_pad) {
+    if (flagged) {
+      a = b = make_float2(qnan, qnan);
+    } else if (k < P.k_pad) {
       const float2 wa = sa[k], wb = sb[k];
       a = cscale(wa, l11);
       b = make_float2(l21 * wa.x + l22 * wb.x, l21 * wa.y + l22 * wb.y);

@@ -88,11 +88,11 @@ __device__ inline double moment_product(const cd p[3], const cd q[3], const cd S
 // One thread per template: sky vector, antenna coefficients (Jaranowski,
 // Krolak & Schutz 1998 eqs. 12-13, cited in Sec. 2 for a(t), b(t)), A, B, C,
 // D of eq. Fstat, and the coverage check of the source-frame grid.
-__global__ void k_prologue(PlanConst P, const double* __restrict__ templates, int64_t t_first,
-                           int64_t count, void* ws) {
+__global__ void k_prologue(PlanConst P, const double* __restrict__ templates, ChunkMap map,
+                           int slots, void* ws) {
   int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= count) return;
-  const double* row = templates + (t_first + g) * FSTAT_TEMPLATE_STRIDE;
+  if (g >= map.n_tmpl) return;
+  const double* row = templates + map.tmpl[g] * FSTAT_TEMPLATE_STRIDE;
   TmplParams tp;
   double alpha = row[0], delta = row[1];
   tp.df = row[2];
@@ -102,10 +102,12 @@ __global__ void k_prologue(PlanConst P, const double* __restrict__ templates, in
   double porb = row[6];
   tp.tp = row[7];
   int status = 0;
-  for (int q = 0; q < 8; ++q)
-    if (!isfinite(row[q])) status = 1;
-  if (tp.asini < 0.0 || (tp.asini != 0.0 && !(porb > 0.0))) status = 1;
-  if (tp.asini > P.max_delay) status = 2;
+  if (!isfinite(alpha) || !isfinite(delta) || !isfinite(tp.asini) || !isfinite(porb) ||
+      !isfinite(tp.tp))
+    status |= kStatusTiming;
+  if (!isfinite(tp.df) || !isfinite(tp.f1dot) || !isfinite(tp.f2dot)) status |= kStatusPhase;
+  if (tp.asini < 0.0 || (tp.asini != 0.0 && !(porb > 0.0))) status |= kStatusTiming;
+  if (tp.asini > P.max_delay) status |= kStatusCoverage;
   tp.om_b = (tp.asini != 0.0 && porb > 0.0) ? 2.0 * kPi / porb : 0.0;
   double sa, ca_, sd, cdl;
   sincos(alpha, &sa, &ca_);
@@ -163,7 +165,7 @@ __global__ void k_prologue(PlanConst P, const double* __restrict__ templates, in
   // Whitening by the Cholesky factor of M in FP64 makes M' = I, so the FP32
   // epilogue sums two squares instead of cancelling terms of size cond(M).
   double Dd = A * B - C * C;
-  if (!(A > 0.0) || !(Dd > 0.0) || !isfinite(Dd)) status = 1;
+  if (!(A > 0.0) || !(Dd > 0.0) || !isfinite(Dd)) status |= kStatusTiming;
   const double l11 = sqrt(A), l21 = C / l11, l22 = sqrt(Dd / A);
   const double r = C / A;
   for (int X = 0; X < P.ndet; ++X) {
@@ -179,18 +181,23 @@ __global__ void k_prologue(PlanConst P, const double* __restrict__ templates, in
   // Coverage: every sample's source time lies inside the computed grid, and
   // the interpolation taps of the last sample end before the last computed
   // point, so grid points beyond k_pad are exactly zero.
-  if (status == 0) {
+  if ((status & kStatusGroupMask) == 0) {
     for (int X = 0; X < P.ndet; ++X) {
       const DetConst& d = P.det[X];
       const GlobalRoemer re{d.ephem, tp.nhat, P.n_eph, P.eph_t0, P.eph_dt, P.inv_eph_dt};
       double u_first = 0.0 + d.off + grid_delay(re, tp, P.tau0) * P.inv_dt;
       double k_last = double(P.k_pad - 1);
       double u_last = k_last + d.off + grid_delay(re, tp, P.tau0 + k_last * P.dt) * P.inv_dt;
-      if (!(u_first <= 0.0) || !(u_last >= double(d.n - 1 + P.D))) status = 2;
+      if (!(u_first <= 0.0) || !(u_last >= double(d.n - 1 + P.D))) status |= kStatusCoverage;
     }
   }
   tp.status = status;
   *slot_params(ws, P.n_fft, g) = tp;
+  // grouped path: a group resampled in this chunk starts from the status of
+  // the template whose parameters it uses
+  for (int i = 0; i < map.n_grp; ++i)
+    if (map.grp_slot[i] == g)
+      *group_status(ws, P.n_fft, slots, P.k_pad, map.grp_buf[i]) = status & kStatusGroupMask;
 }
 
 }  // namespace fstat

@@ -91,13 +91,24 @@ struct Taps {
   static constexpr float C(int t) { return float(sgn(t) / (2.0 * kPi)); }
 };
 
-template <int D>
-__global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws) {
-  const int g = blockIdx.y;
-  TmplParams* tpp = slot_params(ws, P.n_fft, g);
-  const TmplParams& tp = *tpp;
-  float2* ya = slot_buf(ws, P.n_fft, g, 0);
-  float2* yb = slot_buf(ws, P.n_fft, g, 1);
+// GROUPED = false: blockIdx.y is a template slot; the spin-down phase is
+// applied and y_a', y_b' go to the slot's buffers.  GROUPED = true: blockIdx.y
+// is a sky/orbit group of the chunk; the series is written without the
+// spin-down phase to the group's buffer, which every template of the group
+// reads (the reuse of the sky-dependent barycentring across spin-down
+// templates that Sec. 4.1 measures).
+template <int D, bool GROUPED>
+__global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws, ChunkMap map,
+                                                         int slots) {
+  const int gi = blockIdx.y;
+  const int slot = GROUPED ? map.grp_slot[gi] : gi;
+  const TmplParams& tp = *slot_params(ws, P.n_fft, slot);
+  int32_t* status_word = GROUPED ? group_status(ws, P.n_fft, slots, P.k_pad, map.grp_buf[gi])
+                                 : &slot_params(ws, P.n_fft, slot)->status;
+  float2* ya = GROUPED ? group_buf(ws, P.n_fft, slots, P.k_pad, map.grp_buf[gi], 0)
+                       : slot_buf(ws, P.n_fft, slot, 0);
+  float2* yb = GROUPED ? group_buf(ws, P.n_fft, slots, P.k_pad, map.grp_buf[gi], 1)
+                       : slot_buf(ws, P.n_fft, slot, 1);
   const int64_t k_s = int64_t(blockIdx.x) * kResTile;
   const int tid = threadIdx.x;
 
@@ -106,14 +117,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws)
   __shared__ int64_t win_lo, win_hi;
   __shared__ int bad;
 
-  if (tp.status != 0) {
-    for (int i = 0; i < kResPerThread; ++i) {
-      int64_t k = k_s + tid + i * kResThreads;
-      ya[k] = make_float2(0.f, 0.f);
-      yb[k] = make_float2(0.f, 0.f);
-    }
-    return;
-  }
+  if ((GROUPED ? (tp.status & kStatusGroupMask) : tp.status) != 0) return;
   if (tid == 0) bad = 0;
   bool oob = false;
   float2 acc_a[kResPerThread], acc_b[kResPerThread];
@@ -174,7 +178,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws)
     const int64_t nwin = win_hi - lo + 1;
     if (nwin > kResWcap || nwin < 2 * D) {
       // delay drift beyond 1/16 per tile: flag the template (NaN output)
-      if (tid == 0) atomicOr(&tpp->status, 4);
+      if (tid == 0) atomicOr(status_word, kStatusWindow);
       return;
     }
     const int W = int(nwin);
@@ -243,22 +247,21 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws)
   if (bad) {
     // a delay evaluation left the staged ephemeris nodes: the delay exceeds
     // the plan's max_delay; flag the template (NaN output)
-    if (tid == 0) atomicOr(&tpp->status, 8);
+    if (tid == 0) atomicOr(status_word, kStatusNodes);
     return;
   }
-  // spin-down phase and sub-bin offset: y = acc * exp(-2 pi i cyc)
+#pragma unroll
   for (int i = 0; i < kResPerThread; ++i) {
     const int64_t k = k_s + tid + i * kResThreads;
-    const double tau = P.tau0 + P.dt * double(k);
-    const double dtr = tau - P.t_ref;
-    double cyc = tp.f1dot * dtr * dtr * 0.5 + tp.f2dot * dtr * dtr * dtr * (1.0 / 6.0);
-    cyc = cyc - rint(cyc) + tp.df * (P.dt * double(k));
-    const float c = reduce_cycles(cyc);
-    float sn, cs;
-    sincospif(2.0f * c, &sn, &cs);
-    const float2 e = make_float2(cs, -sn);
-    ya[k] = cmul(acc_a[i], e);
-    yb[k] = cmul(acc_b[i], e);
+    if (GROUPED) {
+      ya[k] = acc_a[i];
+      yb[k] = acc_b[i];
+    } else {
+      // spin-down phase and sub-bin offset: y = acc * exp(-2 pi i cyc)
+      const float2 e = spindown_rotation(P, tp.f1dot, tp.f2dot, tp.df, k);
+      ya[k] = cmul_exact(acc_a[i], e);
+      yb[k] = cmul_exact(acc_b[i], e);
+    }
   }
 }
 

@@ -181,3 +181,33 @@ def test_null_arguments_rejected_before_any_launch(lib):
     # zero templates is a no-op that succeeds without touching the device
     assert lib.fstat_compute_2f(p.handle, ctypes.byref(inp), vp(0), 0, vp(0), vp(0), vp(4096),
                                 1 << 30, vp(0)) == B.FSTAT_OK
+
+
+def test_search_plan_groups_and_chunks(lib):
+    """Grouping of a bank on the host: runs of equal sky/orbit form one group;
+    an isolated source ignores porb/tp; chunks hold `slots` templates."""
+    ds, d = good_desc()
+    p = B.Plan(d)
+    rows = []
+    for sky in range(3):
+        for f1 in range(5):
+            rows.append([1.0 + sky, -0.5, 0.0, 1e-10 * f1, 0.0, 0.0, 1.0 + f1, 7.0 * f1])
+    rows.append([9.0, 0.1, 0, 0, 0, 0.3, 5000.0, 1.0])
+    rows.append([9.0, 0.1, 0, 1e-10, 0, 0.3, 5000.0, 1.0])
+    rows.append([9.0, 0.1, 0, 0, 0, 0.3, 5000.0, 2.0])     # other periastron time: new group
+    tm = np.array(rows, dtype=np.float64)
+    vp = ctypes.c_void_p
+    for slots, nchunks in ((4, 5), (8, 3), (32, 1)):
+        h = vp()
+        assert lib.fstat_search_create(p.handle, tm.ctypes.data_as(vp), len(tm), slots, 0,
+                                       ctypes.byref(h)) == 0
+        ws, ng, nc = ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_int64()
+        assert lib.fstat_search_info(h, ctypes.byref(ws), ctypes.byref(ng), ctypes.byref(nc)) == 0
+        assert (ng.value, nc.value) == (5, nchunks)
+        assert ws.value >= slots * 2 * 8 * ds.n_fft
+        lib.fstat_search_destroy(h)
+    h = vp()
+    assert lib.fstat_search_create(p.handle, tm.ctypes.data_as(vp), len(tm), 33, 0,
+                                   ctypes.byref(h)) == B.FSTAT_EINVAL
+    assert lib.fstat_search_create(p.handle, tm.ctypes.data_as(vp), len(tm), 4, 2,
+                                   ctypes.byref(h)) == B.FSTAT_EINVAL

@@ -190,3 +190,70 @@ def test_fft_launch_shapes(torch_dev, tune):
     ref = O.oracle_twoF(ds)
     for i in range(ds.ntmpl):
         assert_2f_parity(got[i], ref[i], f"{tune} tmpl {i}")
+
+
+def grouped_bank(ds, nsky=3, nf1=5, binary_rows=2):
+    """Sky x spin-down bank (spin-down fastest) plus a short binary run."""
+    base = ds.templates[0]
+    rows = []
+    for sky in range(nsky):
+        for f1 in range(nf1):
+            r = base.copy()
+            r[0] += 0.03 * sky
+            r[3] = base[3] + 1e-10 * (f1 - nf1 // 2)
+            r[2] = 2e-6 * f1
+            rows.append(r)
+    for b in range(binary_rows):
+        r = base.copy()
+        r[5], r[6], r[7] = 0.2, 0.4 * 86400, 500.0
+        r[3] = base[3] + 1e-10 * b
+        rows.append(r)
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("slots", [1, 4, 8])
+def test_search_grouped_equals_plain(torch_dev, slots):
+    """Shared resampling per sky/orbit group gives the per-template result bit
+    for bit, also when groups span launch sequences and for a template whose
+    own spin-down parameter is invalid (only its row is NaN)."""
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(seed=41, n=5000, n_fft=1 << 13, ndet=2, gaps=True, ntmpl=1)
+    tm = grouped_bank(ds)
+    tm[7, 3] = np.nan
+    dd = binding.DeviceData(ds)
+    plain = binding.compute_2f(dd, tm).cpu().numpy()
+    binding.sync_check()
+    sr = binding.Search(dd, tm, slots=slots)
+    assert sr.ngroups == 4
+    got = sr.run().cpu().numpy()
+    binding.sync_check()
+    np.testing.assert_array_equal(got, plain)
+    assert np.all(np.isnan(got[7])) and np.isfinite(got[6]).all() and np.isfinite(got[8]).all()
+    ref = O.oracle_twoF(ds, tm[[0, 16]])
+    assert_2f_parity(got[0], ref[0], "grouped sky 0")
+    assert_2f_parity(got[16], ref[1], "grouped binary")
+
+
+def test_search_graph_replays(torch_dev):
+    """The captured launch sequence replays correctly several times, with other
+    work on the device in between."""
+    import torch
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(seed=42, n=4000, n_fft=1 << 13, ndet=2, ntmpl=1)
+    tm = grouped_bank(ds, nsky=2, nf1=4, binary_rows=1)
+    dd = binding.DeviceData(ds)
+    eager = binding.compute_2f(dd, tm).cpu().numpy()
+    torch.cuda.synchronize()
+    sr = binding.Search(dd, tm, slots=4, graph=True)
+    s = torch.cuda.Stream()
+    out = torch.empty((tm.shape[0], ds.n_bins), dtype=torch.float32, device=dd.device)
+    for rep in range(4):
+        out.fill_(-1.0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            sr.run(out=out, stream=s)
+        s.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), eager)
+        # unrelated eager work between replays
+        binding.compute_2f(dd, tm[:2])
+        torch.cuda.synchronize()
