@@ -66,6 +66,12 @@ struct TmplParams {
   float cb[kMaxDet][5];
   float l11, l21, l22;        // L, to report Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
   int32_t status;             // nonzero: every output bin of the template is NaN
+  // Adjoint only: derivatives of the sky direction and of the whitened
+  // coefficients with respect to (alpha, delta) at fixed x, and 2 pi / porb.
+  double dnhat[2][3];
+  float dca[2][kMaxDet][5];
+  float dcb[2][kMaxDet][5];
+  double porb;
 };
 
 // Status bits of a template (any bit: NaN in every output bin).

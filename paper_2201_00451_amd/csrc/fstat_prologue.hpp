@@ -67,12 +67,12 @@ __global__ void k_moments_final(int ndet, const double* partial, double* moments
 struct cd {
   double r, i;
 };
-__device__ inline cd cd_mul(cd a, cd b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
-__device__ inline cd cd_conj(cd a) { return {a.r, -a.i}; }
+__host__ __device__ inline cd cd_mul(cd a, cd b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__host__ __device__ inline cd cd_conj(cd a) { return {a.r, -a.i}; }
 
 // sum_j v_j P(x_j) Q(x_j) for degree-2 polynomials p, q (complex coefficients)
 // given S_0..S_4.
-__device__ inline double moment_product(const cd p[3], const cd q[3], const cd S[5]) {
+__host__ __device__ inline double moment_product(const cd p[3], const cd q[3], const cd S[5]) {
   double acc = 0.0;
   for (int h = 0; h < 3; ++h)
     for (int g = 0; g < 3; ++g) {
@@ -88,12 +88,8 @@ __device__ inline double moment_product(const cd p[3], const cd q[3], const cd S
 // One thread per template: sky vector, antenna coefficients (Jaranowski,
 // Krolak & Schutz 1998 eqs. 12-13, cited in Sec. 2 for a(t), b(t)), A, B, C,
 // D of eq. Fstat, and the coverage check of the source-frame grid.
-__global__ void k_prologue(PlanConst P, const double* __restrict__ templates, ChunkMap map,
-                           int slots, void* ws) {
-  int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= map.n_tmpl) return;
-  const double* row = templates + map.tmpl[g] * FSTAT_TEMPLATE_STRIDE;
-  TmplParams tp;
+__host__ __device__ inline void template_params(const PlanConst& P, const double* row,
+                                                TmplParams& tp) {
   double alpha = row[0], delta = row[1];
   tp.df = row[2];
   tp.f1dot = row[3];
@@ -102,10 +98,10 @@ __global__ void k_prologue(PlanConst P, const double* __restrict__ templates, Ch
   double porb = row[6];
   tp.tp = row[7];
   int status = 0;
-  if (!isfinite(alpha) || !isfinite(delta) || !isfinite(tp.asini) || !isfinite(porb) ||
-      !isfinite(tp.tp))
+  if (!__builtin_isfinite(alpha) || !__builtin_isfinite(delta) || !__builtin_isfinite(tp.asini) || !__builtin_isfinite(porb) ||
+      !__builtin_isfinite(tp.tp))
     status |= kStatusTiming;
-  if (!isfinite(tp.df) || !isfinite(tp.f1dot) || !isfinite(tp.f2dot)) status |= kStatusPhase;
+  if (!__builtin_isfinite(tp.df) || !__builtin_isfinite(tp.f1dot) || !__builtin_isfinite(tp.f2dot)) status |= kStatusPhase;
   if (tp.asini < 0.0 || (tp.asini != 0.0 && !(porb > 0.0))) status |= kStatusTiming;
   if (tp.asini > P.max_delay) status |= kStatusCoverage;
   tp.om_b = (tp.asini != 0.0 && porb > 0.0) ? 2.0 * kPi / porb : 0.0;
@@ -116,13 +112,24 @@ __global__ void k_prologue(PlanConst P, const double* __restrict__ templates, Ch
   tp.nhat[1] = cdl * sa;
   tp.nhat[2] = sd;
   double s2d = 2.0 * sd * cdl, c2d = cdl * cdl - sd * sd;
+  tp.porb = porb;
+  // d nhat / d alpha, d nhat / d delta
+  tp.dnhat[0][0] = -cdl * sa;
+  tp.dnhat[0][1] = cdl * ca_;
+  tp.dnhat[0][2] = 0.0;
+  tp.dnhat[1][0] = -sd * ca_;
+  tp.dnhat[1][1] = -sd * sa;
+  tp.dnhat[1][2] = cdl;
   double A = 0.0, B = 0.0, C = 0.0;
-  double pa_all[kMaxDet][5], pb_all[kMaxDet][5];
+  // derivatives of A, B, C with respect to alpha (index 0) and delta (1)
+  double dA[2] = {0.0, 0.0}, dB[2] = {0.0, 0.0}, dC[2] = {0.0, 0.0};
+  double pa_all[kMaxDet][5], pb_all[kMaxDet][5], dpa_all[kMaxDet][5], dpb_all[kMaxDet][5];
   for (int X = 0; X < kMaxDet; ++X) {
     tp.alpha_cyc[X] = 0.0;
     for (int q = 0; q < 5; ++q) {
       tp.ca[X][q] = tp.cb[X][q] = 0.0f;
-      pa_all[X][q] = pb_all[X][q] = 0.0;
+      pa_all[X][q] = pb_all[X][q] = dpa_all[X][q] = dpb_all[X][q] = 0.0;
+      for (int th = 0; th < 2; ++th) tp.dca[th][X][q] = tp.dcb[th][X][q] = 0.0f;
     }
   }
   for (int X = 0; X < P.ndet; ++X) {
@@ -142,9 +149,23 @@ __global__ void k_prologue(PlanConst P, const double* __restrict__ templates, Ch
     pb[2] = 0.5 * sg * s2l * cdl;
     pb[3] = cg * sl * sd;
     pb[4] = 0.25 * sg * (3.0 - c2l) * sd;
+    // d/d delta of the coefficients (d sin2d = 2 cos2d, d cos2d = -2 sin2d)
+    double dpa[5], dpb[5];
+    dpa[0] = -0.75 * sg * cl * cl * s2d;
+    dpa[1] = 0.5 * sg * s2l * c2d;
+    dpa[2] = -cg * cl * c2d;
+    dpa[3] = sg * (3.0 - c2l) * s2d / 8.0;
+    dpa[4] = -0.5 * cg * sl * s2d;
+    dpb[0] = 0.0;
+    dpb[1] = -cg * cl * sd;
+    dpb[2] = -0.5 * sg * s2l * sd;
+    dpb[3] = cg * sl * cdl;
+    dpb[4] = 0.25 * sg * (3.0 - c2l) * cdl;
     for (int q = 0; q < 5; ++q) {
       pa_all[X][q] = pa[q];
       pb_all[X][q] = pb[q];
+      dpa_all[X][q] = dpa[q];
+      dpb_all[X][q] = dpb[q];
     }
     tp.alpha_cyc[X] = alpha / (2.0 * kPi) - d.lst0_cyc;
     // S_n = e^{i n alpha} conj(M_n)
@@ -160,12 +181,24 @@ __global__ void k_prologue(PlanConst P, const double* __restrict__ templates, Ch
     A += d.w * moment_product(p, p, S);
     B += d.w * moment_product(q, q, S);
     C += d.w * moment_product(p, q, S);
+    // alpha enters through S_n = e^{i n alpha} conj(M_n): dS_n = i n S_n
+    cd dS[5];
+    for (int n = 0; n < 5; ++n) dS[n] = {-double(n) * S[n].i, double(n) * S[n].r};
+    dA[0] += d.w * moment_product(p, p, dS);
+    dB[0] += d.w * moment_product(q, q, dS);
+    dC[0] += d.w * moment_product(p, q, dS);
+    // delta enters through the coefficients (the product is bilinear)
+    cd dp[3] = {{dpa[0], 0.0}, {dpa[1], -dpa[2]}, {dpa[3], -dpa[4]}};
+    cd dq[3] = {{dpb[0], 0.0}, {dpb[1], -dpb[2]}, {dpb[3], -dpb[4]}};
+    dA[1] += d.w * 2.0 * moment_product(dp, p, S);
+    dB[1] += d.w * 2.0 * moment_product(dq, q, S);
+    dC[1] += d.w * (moment_product(dp, q, S) + moment_product(p, dq, S));
   }
   // 2F = 2 F^T M^-1 F is unchanged by a constant invertible map of (a, b).
   // Whitening by the Cholesky factor of M in FP64 makes M' = I, so the FP32
   // epilogue sums two squares instead of cancelling terms of size cond(M).
   double Dd = A * B - C * C;
-  if (!(A > 0.0) || !(Dd > 0.0) || !isfinite(Dd)) status |= kStatusTiming;
+  if (!(A > 0.0) || !(Dd > 0.0) || !__builtin_isfinite(Dd)) status |= kStatusTiming;
   const double l11 = sqrt(A), l21 = C / l11, l22 = sqrt(Dd / A);
   const double r = C / A;
   for (int X = 0; X < P.ndet; ++X) {
@@ -178,6 +211,35 @@ __global__ void k_prologue(PlanConst P, const double* __restrict__ templates, Ch
   tp.l11 = static_cast<float>(l11);
   tp.l21 = static_cast<float>(l21);
   tp.l22 = static_cast<float>(l22);
+  // derivatives of the whitened coefficients: a' = a / l11,
+  // b' = (b - r a) / l22 with r = C/A, l11^2 = A, l22^2 = B - C^2/A
+  for (int th = 0; th < 2; ++th) {
+    const double dl11 = dA[th] / (2.0 * l11);
+    const double dr = (dC[th] * A - C * dA[th]) / (A * A);
+    const double dl22 = (dB[th] - (2.0 * C * dC[th] * A - C * C * dA[th]) / (A * A)) / (2.0 * l22);
+    for (int X = 0; X < P.ndet; ++X) {
+      const double w = P.det[X].w;
+      for (int q = 0; q < 5; ++q) {
+        const double dpaq = th == 1 ? dpa_all[X][q] : 0.0;
+        const double dpbq = th == 1 ? dpb_all[X][q] : 0.0;
+        const double bq = pb_all[X][q] - r * pa_all[X][q];
+        const double dbq = dpbq - dr * pa_all[X][q] - r * dpaq;
+        tp.dca[th][X][q] = static_cast<float>(w * (dpaq / l11 - pa_all[X][q] * dl11 / (l11 * l11)));
+        tp.dcb[th][X][q] = static_cast<float>(w * (dbq / l22 - bq * dl22 / (l22 * l22)));
+      }
+    }
+  }
+  tp.status = status;
+}
+
+__global__ void k_prologue(PlanConst P, const double* __restrict__ templates, ChunkMap map,
+                           int slots, void* ws) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= map.n_tmpl) return;
+  const double* row = templates + map.tmpl[g] * FSTAT_TEMPLATE_STRIDE;
+  TmplParams tp;
+  template_params(P, row, tp);
+  int status = tp.status;
   // Coverage: every sample's source time lies inside the computed grid, and
   // the interpolation taps of the last sample end before the last computed
   // point, so grid points beyond k_pad are exactly zero.
