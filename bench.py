@@ -45,17 +45,6 @@ def step_bytes(ds, k_pad, n_resampled):
     }
 
 
-def k_pad_of(ds):
-    """Grid points the library computes (mirrors its plan rule, for byte counts)."""
-    import math
-    t_end = max(d.t0 + (d.n - 1) * ds.dt for d in ds.detectors)
-    k_act = math.ceil((t_end + ds.max_delay - ds.tau0) / ds.dt) + ds.sinc_halfwidth + 2
-    log_n = ds.n_fft.bit_length() - 1
-    log_c = log_n - (log_n + 1) // 2
-    quant = max(1024, 1 << log_c)
-    return (k_act + quant - 1) // quant * quant, log_c
-
-
 def cpu_baseline(ds, ntmpl):
     """The FP64 oracle on the first ntmpl templates, single-threaded."""
     from threadpoolctl import threadpool_limits
@@ -101,7 +90,7 @@ def main():
     tm = torch.from_numpy(ds.templates).to(dd.device)
     out = torch.empty((ds.ntmpl, ds.n_bins), dtype=torch.float32, device=dd.device)
     stream = torch.cuda.current_stream()
-    k_pad, _ = k_pad_of(ds)
+    k_pad, _, _ = dd.plan.info()
 
     sr = binding.Search(dd, ds.templates, slots=args.batch)
     print(f"bench: {ds.ntmpl} templates in {sr.ngroups} sky/orbit groups, "

@@ -109,6 +109,15 @@ typedef struct fstat_plan fstat_plan;  /* opaque, host memory owned by the libra
 FSTAT_API fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out);
 FSTAT_API void fstat_plan_destroy(fstat_plan* plan);
 
+/* What the plan derived from the set-up: k_pad, the number of source-frame
+ * grid points that can be non-zero (data span plus delay bound plus the
+ * interpolation half-width, rounded up to the resampling tile and to the FFT
+ * row length) and the four-step FFT split n_fft = 2^log_col_len *
+ * 2^log_row_len (column transforms of length 2^log_col_len first).  Any
+ * output pointer may be NULL. */
+FSTAT_API fstat_status fstat_plan_info(const fstat_plan* plan, int64_t* k_pad,
+                                       int32_t* log_col_len, int32_t* log_row_len);
+
 /* Bytes of device workspace for `batch` templates in flight (batch >= 1).
  * The plain path needs batch = 1; larger workspaces let the batched path keep
  * more templates in flight. */
@@ -206,6 +215,36 @@ FSTAT_API fstat_status fstat_search_run_profiled(fstat_search* search, const fst
 FSTAT_API fstat_status fstat_resample(const fstat_plan* plan, const fstat_inputs* in,
                             const double* templates, int64_t ntmpl, void* y, void* workspace,
                             size_t ws_bytes, void* stream);
+
+/* Gradient of a weighted sum of 2F with respect to the template parameters
+ * (the derivative of the pipeline of Sec. 3, steps (iii)-(vii), and of
+ * eq. Fstat; the paper itself computes no derivatives).  For each template m:
+ *   grad[m][q] = d/d theta_q sum_b grad_twoF[m][b] * 2F_m[b],
+ *   theta = (df, f1dot, alpha, delta, asini, porb, tp)
+ * through the spin-down phase, the FFT, the sinc interpolation, the timing
+ * model (both delay solves), the sample correction and the antenna weights
+ * including the dependence of A, B, C on the sky position.  f2dot is held
+ * fixed.  For an isolated source (asini = 0) the orbit derivatives are 0.
+ * The forward path is run again inside this call (nothing is kept from an
+ * earlier 2F call): the resampled series is recomputed, the adjoint
+ * spectrum g conj(F) is transformed by the same FFT kernels, and one kernel
+ * recomputes the series with its derivatives and reduces the gradient in
+ * FP64 per template (fixed order: deterministic).
+ *   templates: device double [ntmpl][8] as for fstat_compute_2f;
+ *   grad_twoF: device float [ntmpl][n_bins], the weights g (e.g. the upstream
+ *              gradient of a loss with respect to twoF);
+ *   grad:      device double [ntmpl][7] (output);
+ *   twoF:      nullable device float [ntmpl][n_bins], receives 2F as well.
+ * A template flagged as in fstat_compute_2f gets NaN in all seven entries
+ * (and in its 2F row).  The workspace must hold fstat_grad_workspace_size
+ * (plan, 1) bytes at least; more lets more templates (up to 32) share each
+ * launch. */
+FSTAT_API fstat_status fstat_grad_workspace_size(const fstat_plan* plan, int64_t batch,
+                                                 size_t* bytes);
+FSTAT_API fstat_status fstat_compute_2f_grad(const fstat_plan* plan, const fstat_inputs* in,
+                                             const double* templates, int64_t ntmpl,
+                                             const float* grad_twoF, double* grad, float* twoF,
+                                             void* workspace, size_t ws_bytes, void* stream);
 
 /* Wait for the stream and report any asynchronous HIP error as FSTAT_EHIP. */
 FSTAT_API fstat_status fstat_sync_check(void* stream);

@@ -160,8 +160,8 @@ def template_params(row):
 
 def oracle_grad(ds, row, weights):
     """(2F, d(sum_m weights_m 2F_m)/d theta) for one template row, theta in
-    PARAMS order.  For an isolated source (asini = 0) the porb and tp
-    derivatives are zero."""
+    PARAMS order.  For an isolated source (asini = 0) the orbit is not a
+    parameter of the template: its three derivatives are reported as zero."""
     p = template_params(row)
     for n in PARAMS:
         p[n].requires_grad_(True)
@@ -169,4 +169,6 @@ def oracle_grad(ds, row, weights):
     loss = torch.sum(_t(np.asarray(weights, dtype=np.float64)) * tf)
     grads = torch.autograd.grad(loss, [p[n] for n in PARAMS], allow_unused=True)
     g = np.array([0.0 if gr is None else float(gr) for gr in grads])
+    if float(row[5]) == 0.0:
+        g[4:7] = 0.0
     return tf.detach().numpy(), g

@@ -22,7 +22,11 @@ EXPORTED = ("fstat_plan_create", "fstat_plan_destroy", "fstat_workspace_size",
             "fstat_antenna_moments", "fstat_compute_2f", "fstat_compute_2f_batched",
             "fstat_compute_2f_profiled", "fstat_resample", "fstat_sync_check",
             "fstat_last_error", "fstat_version", "fstat_search_create", "fstat_search_destroy",
-            "fstat_search_info", "fstat_search_run", "fstat_search_run_profiled")
+            "fstat_search_info", "fstat_search_run", "fstat_search_run_profiled",
+            "fstat_grad_workspace_size", "fstat_compute_2f_grad", "fstat_plan_info")
+GRAD_PARAMS = ("df", "f1dot", "alpha", "delta", "asini", "porb", "tp")
+# template-row column of each gradient parameter
+GRAD_COLUMNS = (2, 3, 0, 1, 5, 6, 7)
 SEARCH_GRAPH = 1
 
 
@@ -91,6 +95,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fstat_search_run_profiled.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, vp, vp, sz, vp,
                                               ctypes.POINTER(ctypes.c_float),
                                               ctypes.POINTER(ctypes.c_int64)]
+    lib.fstat_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]
+    lib.fstat_grad_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
+    lib.fstat_compute_2f_grad.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, i64, vp, vp, vp,
+                                          vp, sz, vp]
     lib.fstat_sync_check.argtypes = [vp]
     lib.fstat_last_error.restype = ctypes.c_char_p
     lib.fstat_last_error.argtypes = []
@@ -148,6 +157,19 @@ class Plan:
     def workspace_size(self, batch: int = 1) -> int:
         out = ctypes.c_size_t()
         _check(load_library().fstat_workspace_size(self.handle, int(batch), ctypes.byref(out)))
+        return int(out.value)
+
+    def info(self):
+        """(k_pad, log2 column length, log2 row length) of the plan."""
+        k, lc, lr = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().fstat_plan_info(self.handle, ctypes.byref(k), ctypes.byref(lc),
+                                              ctypes.byref(lr)))
+        return int(k.value), int(lc.value), int(lr.value)
+
+    def grad_workspace_size(self, batch: int = 1) -> int:
+        out = ctypes.c_size_t()
+        _check(load_library().fstat_grad_workspace_size(self.handle, int(batch),
+                                                        ctypes.byref(out)))
         return int(out.value)
 
     def __del__(self):
@@ -266,6 +288,117 @@ def resample(dd: DeviceData, templates, stream=None):
     _check(load_library().fstat_resample(dd.plan.handle, ctypes.byref(dd.inputs), _ptr(tm), n,
                                          _ptr(y), _ptr(dd.ws), dd.ws.numel(), _stream_ptr(stream)))
     return y
+
+
+def compute_2f_grad(dd: DeviceData, templates, grad_twoF, want_twoF=False, batch=4,
+                    stream=None):
+    """d(sum grad_twoF * 2F)/d theta per template, theta = GRAD_PARAMS:
+    float64 [n, 7] on the device (and 2F [n, n_bins] if want_twoF).  The
+    adjoint workspace (``batch`` templates in flight) is kept on ``dd``."""
+    import torch
+    tm = _templates(dd, templates)
+    n = tm.shape[0]
+    g = torch.as_tensor(grad_twoF, dtype=torch.float32).to(dd.device).contiguous()
+    if tuple(g.shape) != (n, dd.n_bins):
+        raise FstatError(FSTAT_EINVAL, f"grad_twoF must have shape [{n}, {dd.n_bins}]")
+    nbytes = dd.plan.grad_workspace_size(batch)
+    if getattr(dd, "grad_ws", None) is None or dd.grad_ws.numel() != nbytes:
+        dd.grad_ws = torch.empty(nbytes, dtype=torch.uint8, device=dd.device)
+    grad = torch.empty((n, len(GRAD_PARAMS)), dtype=torch.float64, device=dd.device)
+    tf = torch.empty((n, dd.n_bins), dtype=torch.float32, device=dd.device) if want_twoF else None
+    _check(load_library().fstat_compute_2f_grad(
+        dd.plan.handle, ctypes.byref(dd.inputs), _ptr(tm), n, _ptr(g), _ptr(grad), _ptr(tf),
+        _ptr(dd.grad_ws), dd.grad_ws.numel(), _stream_ptr(stream)))
+    return (grad, tf) if want_twoF else grad
+
+
+def template_rows(params, f2dot=None):
+    """Template rows [n, 8] from params [n, 7] in GRAD_PARAMS order (float64)."""
+    import torch
+    p = torch.as_tensor(params, dtype=torch.float64)
+    rows = torch.zeros((p.shape[0], TEMPLATE_STRIDE), dtype=torch.float64, device=p.device)
+    for i, c in enumerate(GRAD_COLUMNS):
+        rows[:, c] = p[:, i]
+    if f2dot is not None:
+        rows[:, 4] = torch.as_tensor(f2dot, dtype=torch.float64, device=p.device)
+    return rows
+
+
+def _fstat_fn():
+    import torch
+
+    class FStatFn(torch.autograd.Function):
+        """2F [n, n_bins] of params [n, 7] (GRAD_PARAMS order; f2dot fixed).
+        Forward: fstat_compute_2f_batched.  Backward: fstat_compute_2f_grad
+        with the incoming gradient as the bin weights (float64 result)."""
+
+        @staticmethod
+        def forward(ctx, params, dd, f2dot):
+            rows = template_rows(params.detach(), f2dot)
+            ctx.dd, ctx.rows = dd, rows
+            return compute_2f_batched(dd, rows)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = compute_2f_grad(ctx.dd, ctx.rows, grad_out.detach().float())
+            return g, None, None
+
+    return FStatFn
+
+
+_FSTAT_FN = None
+
+
+def twoF(dd: DeviceData, params, f2dot=None):
+    """Differentiable 2F: ``params`` [n, 7] float64 (GRAD_PARAMS order) on the
+    device; gradients flow back through the adjoint kernels."""
+    global _FSTAT_FN
+    if _FSTAT_FN is None:
+        _FSTAT_FN = _fstat_fn()
+    return _FSTAT_FN.apply(params, dd, f2dot)
+
+
+def refine(dd: DeviceData, templates, bins, scales, steps=50, lr=0.5, free=None):
+    """Gradient-ascent refinement of candidates: maximise 2F in bin bins[m]
+    of template m over the free parameters (default: all seven for binary
+    rows, df/f1dot/alpha/delta for isolated ones).  The ascent runs on log 2F
+    in coordinates scaled by ``scales`` [7] (one metric spacing per
+    parameter): u = scales * grad / 2F, capped at unit length, and
+    theta += lr * scales * u.  A step is kept only where 2F does not decrease;
+    then lr grows by 1.5 (at most 4), else it halves, per candidate.  Every 2F
+    and gradient comes from the HIP kernels.  Returns (rows, 2F at bins) as
+    host arrays."""
+    import torch
+    rows = torch.as_tensor(np.asarray(templates, dtype=np.float64)).clone()
+    n = rows.shape[0]
+    idx = torch.arange(n)
+    bins = torch.as_tensor(np.asarray(bins, dtype=np.int64))
+    sc = torch.as_tensor(np.asarray(scales, dtype=np.float64))
+    mask = torch.ones((n, 7), dtype=torch.float64)
+    mask[rows[:, 5] == 0.0, 4:] = 0.0
+    if free is not None:
+        keep = torch.tensor([1.0 if p in free else 0.0 for p in GRAD_PARAMS], dtype=torch.float64)
+        mask = mask * keep
+    onehot = torch.zeros((n, dd.n_bins), dtype=torch.float32)
+    onehot[idx, bins] = 1.0
+    step = torch.full((n,), float(lr), dtype=torch.float64)
+    cols = list(GRAD_COLUMNS)
+    g, tf = compute_2f_grad(dd, rows, onehot, want_twoF=True)
+    cur = tf.cpu()[idx, bins].double()
+    g = g.cpu()
+    for _ in range(steps):
+        u = sc * g * mask / torch.clamp(cur, min=1.0)[:, None]
+        u = u / torch.clamp(torch.linalg.vector_norm(u, dim=1), min=1.0)[:, None]
+        trial = rows.clone()
+        trial[:, cols] = rows[:, cols] + step[:, None] * sc * u
+        g_t, tf_t = compute_2f_grad(dd, trial, onehot, want_twoF=True)
+        val = tf_t.cpu()[idx, bins].double()
+        ok = torch.isfinite(val) & (val >= cur)
+        rows[ok] = trial[ok]
+        cur = torch.where(ok, val, cur)
+        g = torch.where(ok[:, None], g_t.cpu(), g)
+        step = torch.where(ok, torch.clamp(step * 1.5, max=4.0), step * 0.5)
+    return rows.numpy(), cur.numpy()
 
 
 def sync_check(stream=None):

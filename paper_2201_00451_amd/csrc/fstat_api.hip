@@ -15,6 +15,7 @@
 #include "fstat_fft.hpp"
 #include "fstat_prologue.hpp"
 #include "fstat_resample.hpp"
+#include "fstat_adjoint.hpp"
 
 using namespace fstat;
 
@@ -62,8 +63,8 @@ int ilog2(int64_t v) {
 int cols_lines_max(int log_rr) { return std::min(64, 16384 >> log_rr); }
 int rows_lines_max(int log_c) { return std::min(32, 8192 >> log_c); }
 
-using ColsFn = void (*)(PlanConst, void*, ChunkMap, int, int, int64_t);
-using RowsFn = void (*)(PlanConst, void*, ChunkMap, int, float*, float2*);
+using ColsFn = void (*)(PlanConst, void*, ChunkMap, int, int, int, int64_t);
+using RowsFn = void (*)(PlanConst, void*, ChunkMap, int, float*, float2*, const float*);
 
 template <int LOGL>
 constexpr int kColsMax = (16384 >> LOGL) < 64 ? (16384 >> LOGL) : 64;
@@ -82,10 +83,11 @@ FftVariant cols_variant(bool half) {
             256};
   return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL>, 512, GROUPED>), 512};
 }
-template <int LOGL>
+template <int LOGL, int MODE>
 FftVariant rows_variant(bool half) {
-  if (half) return {reinterpret_cast<const void*>(&k_fft_rows_2f<LOGL, kRowsMax<LOGL> / 2, 256>), 256};
-  return {reinterpret_cast<const void*>(&k_fft_rows_2f<LOGL, kRowsMax<LOGL>, 512>), 512};
+  if (half)
+    return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, kRowsMax<LOGL> / 2, 256, MODE>), 256};
+  return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, kRowsMax<LOGL>, 512, MODE>), 512};
 }
 
 template <bool GROUPED>
@@ -104,17 +106,23 @@ FftVariant pick_cols_g(int logl, bool half) {
 FftVariant pick_cols(int logl, bool half, bool grouped) {
   return grouped ? pick_cols_g<true>(logl, half) : pick_cols_g<false>(logl, half);
 }
-FftVariant pick_rows(int logl, bool half) {
+template <int MODE>
+FftVariant pick_rows_m(int logl, bool half) {
   switch (logl) {
-    case 6: return rows_variant<6>(half);
-    case 7: return rows_variant<7>(half);
-    case 8: return rows_variant<8>(half);
-    case 9: return rows_variant<9>(half);
-    case 10: return rows_variant<10>(half);
-    case 11: return rows_variant<11>(half);
-    case 12: return rows_variant<12>(half);
+    case 6: return rows_variant<6, MODE>(half);
+    case 7: return rows_variant<7, MODE>(half);
+    case 8: return rows_variant<8, MODE>(half);
+    case 9: return rows_variant<9, MODE>(half);
+    case 10: return rows_variant<10, MODE>(half);
+    case 11: return rows_variant<11, MODE>(half);
+    case 12: return rows_variant<12, MODE>(half);
     default: return {nullptr, 0};
   }
+}
+FftVariant pick_rows(int logl, bool half, int mode = kRow2F) {
+  return mode == kRowAdjoint ? pick_rows_m<kRowAdjoint>(logl, half)
+         : mode == kRowConj  ? pick_rows_m<kRowConj>(logl, half)
+                             : pick_rows_m<kRow2F>(logl, half);
 }
 
 fstat_status check_hip(hipError_t e, const char* what) {
@@ -178,6 +186,7 @@ PlanConst make_const(const fstat_plan* p, const fstat_inputs* in) {
   P.bin_lo = d.bin_lo;
   P.n_bins = d.n_bins;
   P.k_pad = p->k_pad;
+  P.slot_stride = int64_t(slot_bytes(d.n_fft));
   if (in) {
     P.n_eph = in->n_eph;
     P.eph_t0 = in->eph_t0;
@@ -193,6 +202,10 @@ PlanConst make_const(const fstat_plan* p, const fstat_inputs* in) {
     c.lst0_cyc = (t.lon + d.sid_angle0) / (2.0 * M_PI);
     c.lat = t.lat;
     c.gamma = 0.5 * (t.az_x + t.az_y);
+    c.sl = std::sin(c.lat);
+    c.cl = std::cos(c.lat);
+    c.s2g = std::sin(2.0 * c.gamma);
+    c.c2g = std::cos(2.0 * c.gamma);
     c.w = 1.0 / t.noise_var;
     c.n = t.n;
     if (in) {
@@ -317,13 +330,14 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
   if ((s = tm.mark(2)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn)),
                      dim3(unsigned((int64_t(1) << p->log_c) / p->cols_lines), 2, n),
-                     dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, p->log_c,
+                     dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 0, p->log_c,
                      p->rows_act);
   if ((s = tm.mark(2)) != FSTAT_OK) return s;
   if ((s = tm.mark(3)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rv.fn)),
                      dim3(unsigned((int64_t(1) << p->log_rr) / p->rows_lines), n),
-                     dim3(rv.threads), lds_bytes_rows(p), st, P, ws, map, p->log_rr, twoF, fafb);
+                     dim3(rv.threads), lds_bytes_rows(p), st, P, ws, map, p->log_rr, twoF, fafb,
+                     static_cast<const float*>(nullptr));
   if ((s = tm.mark(3)) != FSTAT_OK) return s;
   return check_hip(hipGetLastError(), "kernel launch");
 }
@@ -354,9 +368,11 @@ fstat_status set_lds_limits(const fstat_plan* p) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_cols(p)));
     if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(cols)");
   }
-  e = hipFuncSetAttribute(pick_rows(p->log_c, p->rows_half).fn,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_rows(p)));
-  if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(rows)");
+  for (int mode : {int(kRow2F), int(kRowAdjoint), int(kRowConj)}) {
+    e = hipFuncSetAttribute(pick_rows(p->log_c, p->rows_half, mode).fn,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_rows(p)));
+    if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(rows)");
+  }
   return FSTAT_OK;
 }
 
@@ -393,6 +409,63 @@ fstat_status run(const fstat_plan* p, const fstat_inputs* in, const double* temp
     if (s != FSTAT_OK) return s;
   }
   return ok();
+}
+
+// Adjoint workspace slot: parameters, four arrays (y' / F', then the adjoint
+// spectrum and its transform) and 8 doubles of gradient partials per
+// resampling tile, padded to 256 bytes.
+size_t grad_slot_bytes(const fstat_plan* p) {
+  const size_t tiles = size_t(p->k_pad / kResTile);
+  return slot_bytes(p->desc.n_fft, 4, (tiles * 8 * sizeof(double) + 255) / 256 * 256);
+}
+
+using GradFn = void (*)(PlanConst, void*);
+GradFn grad_kernel(int D) {
+  switch (D) {
+    case 4: return &k_grad<4>;
+    case 6: return &k_grad<6>;
+    case 8: return &k_grad<8>;
+    case 10: return &k_grad<10>;
+    case 12: return &k_grad<12>;
+    case 16: return &k_grad<16>;
+    default: return nullptr;
+  }
+}
+
+// Adjoint launch sequence for the template slots of one chunk: the forward
+// path up to F' (with 2F when twoF is set), H = g conj(F') into arrays 2/3,
+// X = FFT(H) (conjugated) back into arrays 0/1, then the per-tile gradient
+// sums and their per-template totals.
+fstat_status launch_grad_chunk(const fstat_plan* p, const PlanConst& P, const double* templates,
+                               const ChunkMap& map, int slots, const float* gin, double* grad,
+                               float* twoF, void* ws, hipStream_t st) {
+  const int n = map.n_tmpl;
+  const unsigned tiles = unsigned(p->k_pad / kResTile);
+  hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, slots,
+                     ws);
+  hipLaunchKernelGGL(resample_kernel(p->desc.sinc_halfwidth, false), dim3(tiles, n),
+                     dim3(kResThreads), 0, st, P, ws, map, slots);
+  const FftVariant cv = pick_cols(p->log_rr, p->cols_half, false);
+  const ColsFn cols = reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn));
+  const dim3 cgrid(unsigned((int64_t(1) << p->log_c) / p->cols_lines), 2, n);
+  const dim3 rgrid(unsigned((int64_t(1) << p->log_rr) / p->rows_lines), n);
+  const FftVariant ra = pick_rows(p->log_c, p->rows_half, kRowAdjoint);
+  const FftVariant rc = pick_rows(p->log_c, p->rows_half, kRowConj);
+  hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 0,
+                     p->log_c, p->rows_act);
+  hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(ra.fn)), rgrid, dim3(ra.threads),
+                     lds_bytes_rows(p), st, P, ws, map, p->log_rr, twoF,
+                     static_cast<float2*>(nullptr), gin);
+  hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 2,
+                     p->log_c, int64_t(1) << p->log_rr);
+  hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rc.fn)), rgrid, dim3(rc.threads),
+                     lds_bytes_rows(p), st, P, ws, map, p->log_rr, static_cast<float*>(nullptr),
+                     static_cast<float2*>(nullptr), static_cast<const float*>(nullptr));
+  hipLaunchKernelGGL(grad_kernel(p->desc.sinc_halfwidth), dim3(tiles, n), dim3(kResThreads), 0,
+                     st, P, ws);
+  hipLaunchKernelGGL(k_grad_final, dim3((n * kGradParams + 63) / 64), dim3(64), 0, st, P, ws, map,
+                     int64_t(tiles), grad);
+  return check_hip(hipGetLastError(), "adjoint launch");
 }
 
 }  // namespace
@@ -592,7 +665,9 @@ fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out) {
   if (!p) return fail(FSTAT_EINVAL, "host allocation failed");
   p->desc = *desc;
   p->log_n = ilog2(desc->n_fft);
-  p->log_rr = desc->tune_col_log_len ? desc->tune_col_log_len : (p->log_n + 1) / 2;
+  // column length 2^floor(log N / 2): the shorter column pass gets the wider
+  // (better coalesced) line groups
+  p->log_rr = desc->tune_col_log_len ? desc->tune_col_log_len : p->log_n / 2;
   p->log_c = p->log_n - p->log_rr;
   if (p->log_rr < 6 || p->log_rr > 12 || p->log_c < 6 || p->log_c > 12) {
     delete p;
@@ -637,6 +712,15 @@ fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out) {
 }
 
 void fstat_plan_destroy(fstat_plan* plan) { delete plan; }
+
+fstat_status fstat_plan_info(const fstat_plan* plan, int64_t* k_pad, int32_t* log_col_len,
+                             int32_t* log_row_len) {
+  if (!plan) return fail(FSTAT_EINVAL, "plan is NULL");
+  if (k_pad) *k_pad = plan->k_pad;
+  if (log_col_len) *log_col_len = plan->log_rr;
+  if (log_row_len) *log_row_len = plan->log_c;
+  return ok();
+}
 
 fstat_status fstat_workspace_size(const fstat_plan* plan, int64_t batch, size_t* bytes) {
   if (!plan || !bytes) return fail(FSTAT_EINVAL, "plan or bytes is NULL");
@@ -697,6 +781,50 @@ fstat_status fstat_resample(const fstat_plan* plan, const fstat_inputs* in,
                             size_t ws_bytes, void* stream) {
   if (ntmpl > 0 && !y) return fail(FSTAT_EINVAL, "y is NULL");
   return run(plan, in, templates, ntmpl, nullptr, nullptr, y, workspace, ws_bytes, stream, 1);
+}
+
+fstat_status fstat_grad_workspace_size(const fstat_plan* plan, int64_t batch, size_t* bytes) {
+  if (!plan || !bytes) return fail(FSTAT_EINVAL, "plan or bytes is NULL");
+  if (batch < 1) return fail(FSTAT_EINVAL, "batch must be >= 1");
+  *bytes = kHeaderBytes + size_t(batch) * grad_slot_bytes(plan);
+  return ok();
+}
+
+fstat_status fstat_compute_2f_grad(const fstat_plan* plan, const fstat_inputs* in,
+                                   const double* templates, int64_t ntmpl,
+                                   const float* grad_twoF, double* grad, float* twoF,
+                                   void* workspace, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(FSTAT_EINVAL, "plan is NULL");
+  if (ntmpl < 0) return fail(FSTAT_EINVAL, "ntmpl < 0");
+  if (ntmpl > 0 && (!templates || !grad_twoF || !grad))
+    return fail(FSTAT_EINVAL, "templates, grad_twoF or grad is NULL");
+  fstat_status s = validate_inputs(plan, in, true);
+  if (s != FSTAT_OK) return s;
+  if (!workspace) return fail(FSTAT_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(FSTAT_EINVAL, "workspace must be 256-byte aligned");
+  const size_t sb = grad_slot_bytes(plan);
+  if (ws_bytes < kHeaderBytes + sb)
+    return fail(FSTAT_EWORKSPACE, "workspace %zu bytes < %zu needed for one template", ws_bytes,
+                kHeaderBytes + sb);
+  if (ntmpl == 0) return ok();
+  const int64_t slots = std::min<int64_t>(int64_t((ws_bytes - kHeaderBytes) / sb), kMaxSlots);
+  if ((s = set_lds_limits(plan)) != FSTAT_OK) return s;
+  PlanConst P = make_const(plan, in);
+  P.slot_stride = int64_t(sb);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, workspace,
+                     plan->desc.n_fft);
+  for (int64_t t = 0; t < ntmpl; t += slots) {
+    ChunkMap map;
+    std::memset(&map, 0, sizeof map);
+    map.n_tmpl = int(std::min<int64_t>(slots, ntmpl - t));
+    for (int i = 0; i < map.n_tmpl; ++i) map.tmpl[i] = t + i;
+    s = launch_grad_chunk(plan, P, templates, map, int(slots), grad_twoF, grad, twoF, workspace,
+                          st);
+    if (s != FSTAT_OK) return s;
+  }
+  return ok();
 }
 
 fstat_status fstat_sync_check(void* stream) {

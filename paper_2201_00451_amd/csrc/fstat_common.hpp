@@ -34,6 +34,8 @@ struct DetConst {
   double off;         // (tau0 - t0)/dt: grid index offset
   double lst0_cyc;    // (lon + sidereal angle at t=0) / 2 pi
   double lat, gamma;  // latitude, arm-bisector azimuth (CCW from East)
+  double sl, cl;      // sin, cos of the latitude
+  double s2g, c2g;    // sin, cos of twice the arm-bisector azimuth
   double w;           // 1/noise_var
   int64_t n;
   const float2* x;
@@ -48,6 +50,7 @@ struct PlanConst {
   double sid_rate_cyc;  // sidereal rate / 2 pi (cycles per s)
   int64_t n_fft, bin_lo, n_bins;
   int64_t k_pad;        // grid points computed by the resampler (multiple of tile and row)
+  int64_t slot_stride;  // bytes per template slot of the workspace (path dependent)
   int64_t n_eph;
   double eph_t0, eph_dt, inv_eph_dt;
   const double* moments;
@@ -110,19 +113,27 @@ __host__ __device__ inline float2* tw_stage(void* ws) {
 __host__ __device__ inline float2* tw_lo(void* ws) { return tw_stage(ws) + kTwLen; }
 __host__ __device__ inline float2* tw_hi(void* ws) { return tw_stage(ws) + 2 * kTwLen; }
 
-// Workspace: header (moment partials), then `slots` template slots of
-// [TmplParams | y_a / Z_a : n_fft float2 | y_b / Z_b : n_fft float2].
-__host__ __device__ inline size_t slot_bytes(int64_t n_fft) {
-  return kParamBytes + size_t(n_fft) * 2 * sizeof(float2);
+// Workspace: header (moment partials, twiddles), then template slots of
+// [TmplParams | narr arrays of n_fft float2 | extra bytes], narr = 2 for the
+// forward paths (y_a / Z_a, y_b / Z_b) and 4 plus per-tile gradient partials
+// for the adjoint.
+__host__ __device__ inline size_t slot_bytes(int64_t n_fft, int narr = 2, size_t extra = 0) {
+  return kParamBytes + size_t(n_fft) * narr * sizeof(float2) + extra;
 }
-__host__ __device__ inline char* slot_base(void* ws, int64_t n_fft, int g) {
-  return static_cast<char*>(ws) + kHeaderBytes + size_t(g) * slot_bytes(n_fft);
+__host__ __device__ inline char* slot_base(void* ws, const PlanConst& P, int g) {
+  return static_cast<char*>(ws) + kHeaderBytes + size_t(g) * size_t(P.slot_stride);
 }
-__host__ __device__ inline TmplParams* slot_params(void* ws, int64_t n_fft, int g) {
-  return reinterpret_cast<TmplParams*>(slot_base(ws, n_fft, g));
+__host__ __device__ inline TmplParams* slot_params(void* ws, const PlanConst& P, int g) {
+  return reinterpret_cast<TmplParams*>(slot_base(ws, P, g));
 }
-__host__ __device__ inline float2* slot_buf(void* ws, int64_t n_fft, int g, int arr) {
-  return reinterpret_cast<float2*>(slot_base(ws, n_fft, g) + kParamBytes) + size_t(arr) * n_fft;
+__host__ __device__ inline float2* slot_buf(void* ws, const PlanConst& P, int g, int arr) {
+  return reinterpret_cast<float2*>(slot_base(ws, P, g) + kParamBytes) + size_t(arr) * P.n_fft;
+}
+// Adjoint: per-tile partial sums of the 7 gradient components (8 doubles per
+// tile), after the four arrays of the slot.
+__host__ __device__ inline double* slot_partials(void* ws, const PlanConst& P, int g) {
+  return reinterpret_cast<double*>(slot_base(ws, P, g) + kParamBytes +
+                                   size_t(4) * P.n_fft * sizeof(float2));
 }
 
 // Grouped path: after `slots` template slots come group buffers of
@@ -132,18 +143,16 @@ constexpr size_t kGroupHeader = 256;
 __host__ __device__ inline size_t group_bytes(int64_t k_pad) {
   return kGroupHeader + size_t(k_pad) * 2 * sizeof(float2);
 }
-__host__ __device__ inline char* group_base(void* ws, int64_t n_fft, int slots, int64_t k_pad,
-                                            int b) {
-  return slot_base(ws, n_fft, slots) + size_t(b) * group_bytes(k_pad);
+__host__ __device__ inline char* group_base(void* ws, const PlanConst& P, int slots, int b) {
+  return slot_base(ws, P, slots) + size_t(b) * group_bytes(P.k_pad);
 }
-__host__ __device__ inline int32_t* group_status(void* ws, int64_t n_fft, int slots,
-                                                 int64_t k_pad, int b) {
-  return reinterpret_cast<int32_t*>(group_base(ws, n_fft, slots, k_pad, b));
+__host__ __device__ inline int32_t* group_status(void* ws, const PlanConst& P, int slots, int b) {
+  return reinterpret_cast<int32_t*>(group_base(ws, P, slots, b));
 }
-__host__ __device__ inline float2* group_buf(void* ws, int64_t n_fft, int slots, int64_t k_pad,
-                                             int b, int arr) {
-  return reinterpret_cast<float2*>(group_base(ws, n_fft, slots, k_pad, b) + kGroupHeader) +
-         size_t(arr) * k_pad;
+__host__ __device__ inline float2* group_buf(void* ws, const PlanConst& P, int slots, int b,
+                                             int arr) {
+  return reinterpret_cast<float2*>(group_base(ws, P, slots, b) + kGroupHeader) +
+         size_t(arr) * P.k_pad;
 }
 
 // ---------------------------------------------------------------------------

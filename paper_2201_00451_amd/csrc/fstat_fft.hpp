@@ -197,7 +197,7 @@ __global__ void k_twiddles(void* ws, int64_t n_fft) {
 // output goes to the slot's own buffer.
 template <int LOGL, int NL, int NT, bool GROUPED>
 __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap map, int slots,
-                                                 int log_c, int64_t rows_act) {
+                                                 int arr_base, int log_c, int64_t rows_act) {
   extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
   constexpr int NS = stage_count(LOGL);
@@ -209,19 +209,19 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
                                 total);
   const uint32_t gx = id % gridDim.x, rest = id / gridDim.x;
   const int arr = int(rest % gridDim.y), g = int(rest / gridDim.y);
-  TmplParams* tpp = slot_params(ws, P.n_fft, g);
+  TmplParams* tpp = slot_params(ws, P, g);
   int32_t status = tpp->status;
   if (GROUPED) {
-    const int32_t gs = *group_status(ws, P.n_fft, slots, P.k_pad, map.tmpl_buf[g]);
+    const int32_t gs = *group_status(ws, P, slots, map.tmpl_buf[g]);
     if (gs != 0 && threadIdx.x == 0) atomicOr(&tpp->status, gs);
     status |= gs;
   }
   if (status != 0) return;
   const int64_t C = int64_t(1) << log_c;
   const int64_t c0 = int64_t(gx) * NL;
-  float2* buf = slot_buf(ws, P.n_fft, g, arr);
+  float2* buf = slot_buf(ws, P, g, arr_base + arr);
   const float2* src =
-      GROUPED ? group_buf(ws, P.n_fft, slots, P.k_pad, map.tmpl_buf[g], arr) : buf;
+      GROUPED ? group_buf(ws, P, slots, map.tmpl_buf[g], arr) : buf;
   const double f1dot = tpp->f1dot, f2dot = tpp->f2dot, df = tpp->df;
   const float2* __restrict__ tw = tw_stage(ws);
   const int tid = threadIdx.x;
@@ -300,10 +300,17 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
 // (contiguous across threads); the last stage transforms the a and b rows of
 // the same bins in one thread and writes 2F (rows fastest across threads:
 // RQ-element runs of the output).  Grid: (Rr / RQ) x templates.
-template <int LOGL, int RQ, int NT>
-__global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, ChunkMap map,
-                                                    int log_rr, float* __restrict__ twoF,
-                                                    float2* fafb) {
+// Row-pass epilogues: 2F (forward); the adjoint spectrum H = g conj(F') of
+// both arrays at every natural FFT index m (zero outside the band), written to
+// arrays 2 and 3 of the slot, with 2F if twoF is not null; or the complex
+// transform itself, conjugated, written to arrays 0 and 1 at the natural
+// index for indices below k_pad (the inverse transform of the adjoint).
+enum RowMode { kRow2F = 0, kRowAdjoint = 1, kRowConj = 2 };
+
+template <int LOGL, int RQ, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap map, int log_rr,
+                                                 float* __restrict__ twoF, float2* fafb,
+                                                 const float* __restrict__ gin) {
   extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
   constexpr int NL = 2 * RQ;
@@ -315,7 +322,7 @@ __global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, Chunk
   const uint32_t id = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, total);
   const uint32_t gx = id % gridDim.x;
   const int g = int(id / gridDim.x);
-  const TmplParams& tp = *slot_params(ws, P.n_fft, g);
+  const TmplParams& tp = *slot_params(ws, P, g);
   const int64_t tmpl = map.tmpl[g];
   const int64_t q0 = int64_t(gx) * RQ;
   const int64_t Rr = int64_t(1) << log_rr;
@@ -325,13 +332,14 @@ __global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, Chunk
   const int tid = threadIdx.x;
   const float qnan = __builtin_nanf("");
   if (status != 0) {
+    if (MODE == kRowConj) return;
     // flagged template: NaN in every bin it owns
     for (int e = tid; e < L * RQ; e += NT) {
       const int ql = e % RQ, p = e / RQ;
       const int64_t i = (q0 + ql + Rr * p + N / 2) & (N - 1);
       if (i < P.bin_lo || i >= P.bin_lo + P.n_bins) continue;
       const int64_t o = i - P.bin_lo;
-      twoF[tmpl * P.n_bins + o] = qnan;
+      if (twoF) twoF[tmpl * P.n_bins + o] = qnan;
       if (fafb) {
         fafb[(tmpl * 2 + 0) * P.n_bins + o] = make_float2(qnan, qnan);
         fafb[(tmpl * 2 + 1) * P.n_bins + o] = make_float2(qnan, qnan);
@@ -341,8 +349,8 @@ __global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, Chunk
   }
   // stage 0: HBM -> registers -> DFT -> LDS
   {
-    const float2* ba = slot_buf(ws, N, g, 0);
-    const float2* bb = slot_buf(ws, N, g, 1);
+    const float2* ba = slot_buf(ws, P, g, MODE == kRowConj ? 2 : 0);
+    const float2* bb = slot_buf(ws, P, g, MODE == kRowConj ? 3 : 1);
     constexpr int PER = (NB0 + NT - 1) / NT;
     float2 v[PER][R0];
 #pragma unroll
@@ -386,12 +394,27 @@ __global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, Chunk
       twiddle_dft<RL, PL>(vb, i, tw);
 #pragma unroll
       for (int m = 0; m < RL; ++m) {
-        const int64_t ib = (q0 + ql + Rr * int64_t(i + m * PL) + N / 2) & (N - 1);
-        if (ib < P.bin_lo || ib >= P.bin_lo + P.n_bins) continue;
+        const int64_t nat = q0 + ql + Rr * int64_t(i + m * PL);
+        if (MODE == kRowConj) {
+          if (nat < P.k_pad) {
+            slot_buf(ws, P, g, 0)[nat] = make_float2(va[m].x, -va[m].y);
+            slot_buf(ws, P, g, 1)[nat] = make_float2(vb[m].x, -vb[m].y);
+          }
+          continue;
+        }
+        const int64_t ib = (nat + N / 2) & (N - 1);
+        const bool in_band = ib >= P.bin_lo && ib < P.bin_lo + P.n_bins;
         const int64_t o = ib - P.bin_lo;
         const float2 fa = va[m], fb = vb[m];
-        twoF[tmpl * P.n_bins + o] =
-            2.0f * ((fa.x * fa.x + fa.y * fa.y) + (fb.x * fb.x + fb.y * fb.y));
+        if (MODE == kRowAdjoint) {
+          const float gv = in_band ? gin[tmpl * P.n_bins + o] : 0.0f;
+          slot_buf(ws, P, g, 2)[nat] = make_float2(gv * fa.x, -gv * fa.y);
+          slot_buf(ws, P, g, 3)[nat] = make_float2(gv * fb.x, -gv * fb.y);
+        }
+        if (!in_band) continue;
+        if (twoF)
+          twoF[tmpl * P.n_bins + o] =
+              2.0f * ((fa.x * fa.x + fa.y * fa.y) + (fb.x * fb.x + fb.y * fb.y));
         if (fafb) {
           // undo the whitening: Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
           fafb[(tmpl * 2 + 0) * P.n_bins + o] = cscale(fa, l11);
@@ -408,9 +431,9 @@ __global__ __launch_bounds__(NT) void k_fft_rows_2f(PlanConst P, void* ws, Chunk
 // whitening undone (y_a = l11 y_a', y_b = l21 y_a' + l22 y_b').
 __global__ void k_copy_series(PlanConst P, void* ws, ChunkMap map, float2* out) {
   const int g = blockIdx.y;
-  const TmplParams& tp = *slot_params(ws, P.n_fft, g);
-  const float2* sa = slot_buf(ws, P.n_fft, g, 0);
-  const float2* sb = slot_buf(ws, P.n_fft, g, 1);
+  const TmplParams& tp = *slot_params(ws, P, g);
+  const float2* sa = slot_buf(ws, P, g, 0);
+  const float2* sb = slot_buf(ws, P, g, 1);
   float2* da = out + (map.tmpl[g] * 2 + 0) * P.n_fft;
   float2* db = out + (map.tmpl[g] * 2 + 1) * P.n_fft;
   const float l11 = tp.l11, l21 = tp.l21, l22 = tp.l22;

@@ -74,7 +74,9 @@ __host__ __device__ inline cd cd_conj(cd a) { return {a.r, -a.i}; }
 // given S_0..S_4.
 __host__ __device__ inline double moment_product(const cd p[3], const cd q[3], const cd S[5]) {
   double acc = 0.0;
+#pragma unroll
   for (int h = 0; h < 3; ++h)
+#pragma unroll
     for (int g = 0; g < 3; ++g) {
       cd t1 = cd_mul(cd_mul(p[h], q[g]), S[h + g]);
       int dn = h - g;
@@ -85,9 +87,45 @@ __host__ __device__ inline double moment_product(const cd p[3], const cd q[3], c
   return 0.5 * acc;
 }
 
-// One thread per template: sky vector, antenna coefficients (Jaranowski,
-// Krolak & Schutz 1998 eqs. 12-13, cited in Sec. 2 for a(t), b(t)), A, B, C,
-// D of eq. Fstat, and the coverage check of the source-frame grid.
+// Coefficients of a(t), b(t) (Jaranowski, Krolak & Schutz 1998 eqs. 12-13,
+// cited in Sec. 2) in the basis (1, cos x, sin x, cos 2x, sin 2x) of
+// x = alpha - phi(t), for one detector at declination delta, and their delta
+// derivatives (d sin 2delta = 2 cos 2delta, d cos 2delta = -2 sin 2delta).
+struct Jks {
+  double pa[5], pb[5], dpa[5], dpb[5];
+};
+__host__ __device__ inline Jks jks_coeffs(const DetConst& d, double sd, double cdl) {
+  const double sl = d.sl, cl = d.cl, sg = d.s2g, cg = d.c2g;
+  const double s2l = 2.0 * sl * cl, c2l = cl * cl - sl * sl;
+  const double s2d = 2.0 * sd * cdl, c2d = cdl * cdl - sd * sd;
+  Jks k;
+  k.pa[0] = 0.75 * sg * cl * cl * cdl * cdl;
+  k.pa[1] = 0.25 * sg * s2l * s2d;
+  k.pa[2] = -0.5 * cg * cl * s2d;
+  k.pa[3] = sg * (3.0 - c2l) * (3.0 - c2d) / 16.0;
+  k.pa[4] = -0.25 * cg * sl * (3.0 - c2d);
+  k.pb[0] = 0.0;
+  k.pb[1] = cg * cl * cdl;
+  k.pb[2] = 0.5 * sg * s2l * cdl;
+  k.pb[3] = cg * sl * sd;
+  k.pb[4] = 0.25 * sg * (3.0 - c2l) * sd;
+  k.dpa[0] = -0.75 * sg * cl * cl * s2d;
+  k.dpa[1] = 0.5 * sg * s2l * c2d;
+  k.dpa[2] = -cg * cl * c2d;
+  k.dpa[3] = sg * (3.0 - c2l) * s2d / 8.0;
+  k.dpa[4] = -0.5 * cg * sl * s2d;
+  k.dpb[0] = 0.0;
+  k.dpb[1] = -cg * cl * sd;
+  k.dpb[2] = -0.5 * sg * s2l * sd;
+  k.dpb[3] = cg * sl * cdl;
+  k.dpb[4] = 0.25 * sg * (3.0 - c2l) * cdl;
+  return k;
+}
+
+// Per template: sky vector, antenna coefficients, A, B, C, D of eq. Fstat,
+// the whitening of (a, b) and the alpha/delta derivatives of the whitened
+// coefficients.  The detector loops run over the compile-time maximum so that
+// every index is static and the parameter block stays in registers.
 __host__ __device__ inline void template_params(const PlanConst& P, const double* row,
                                                 TmplParams& tp) {
   double alpha = row[0], delta = row[1];
@@ -98,10 +136,12 @@ __host__ __device__ inline void template_params(const PlanConst& P, const double
   double porb = row[6];
   tp.tp = row[7];
   int status = 0;
-  if (!__builtin_isfinite(alpha) || !__builtin_isfinite(delta) || !__builtin_isfinite(tp.asini) || !__builtin_isfinite(porb) ||
-      !__builtin_isfinite(tp.tp))
+  if (!__builtin_isfinite(alpha) || !__builtin_isfinite(delta) || !__builtin_isfinite(tp.asini) ||
+      !__builtin_isfinite(porb) || !__builtin_isfinite(tp.tp))
     status |= kStatusTiming;
-  if (!__builtin_isfinite(tp.df) || !__builtin_isfinite(tp.f1dot) || !__builtin_isfinite(tp.f2dot)) status |= kStatusPhase;
+  if (!__builtin_isfinite(tp.df) || !__builtin_isfinite(tp.f1dot) ||
+      !__builtin_isfinite(tp.f2dot))
+    status |= kStatusPhase;
   if (tp.asini < 0.0 || (tp.asini != 0.0 && !(porb > 0.0))) status |= kStatusTiming;
   if (tp.asini > P.max_delay) status |= kStatusCoverage;
   tp.om_b = (tp.asini != 0.0 && porb > 0.0) ? 2.0 * kPi / porb : 0.0;
@@ -111,7 +151,6 @@ __host__ __device__ inline void template_params(const PlanConst& P, const double
   tp.nhat[0] = cdl * ca_;
   tp.nhat[1] = cdl * sa;
   tp.nhat[2] = sd;
-  double s2d = 2.0 * sd * cdl, c2d = cdl * cdl - sd * sd;
   tp.porb = porb;
   // d nhat / d alpha, d nhat / d delta
   tp.dnhat[0][0] = -cdl * sa;
@@ -120,76 +159,47 @@ __host__ __device__ inline void template_params(const PlanConst& P, const double
   tp.dnhat[1][0] = -sd * ca_;
   tp.dnhat[1][1] = -sd * sa;
   tp.dnhat[1][2] = cdl;
+  // e^{i n alpha}, n = 0..4
+  cd ea[5];
+  ea[0] = {1.0, 0.0};
+  ea[1] = {ca_, sa};
+#pragma unroll
+  for (int n = 2; n < 5; ++n) ea[n] = cd_mul(ea[n - 1], ea[1]);
   double A = 0.0, B = 0.0, C = 0.0;
   // derivatives of A, B, C with respect to alpha (index 0) and delta (1)
   double dA[2] = {0.0, 0.0}, dB[2] = {0.0, 0.0}, dC[2] = {0.0, 0.0};
-  double pa_all[kMaxDet][5], pb_all[kMaxDet][5], dpa_all[kMaxDet][5], dpb_all[kMaxDet][5];
+#pragma unroll
   for (int X = 0; X < kMaxDet; ++X) {
     tp.alpha_cyc[X] = 0.0;
+#pragma unroll
     for (int q = 0; q < 5; ++q) {
       tp.ca[X][q] = tp.cb[X][q] = 0.0f;
-      pa_all[X][q] = pb_all[X][q] = dpa_all[X][q] = dpb_all[X][q] = 0.0;
-      for (int th = 0; th < 2; ++th) tp.dca[th][X][q] = tp.dcb[th][X][q] = 0.0f;
+      tp.dca[0][X][q] = tp.dcb[0][X][q] = tp.dca[1][X][q] = tp.dcb[1][X][q] = 0.0f;
     }
-  }
-  for (int X = 0; X < P.ndet; ++X) {
+    if (X >= P.ndet) continue;
     const DetConst& d = P.det[X];
-    double sl, cl, sg, cg;
-    sincos(d.lat, &sl, &cl);
-    sincos(2.0 * d.gamma, &sg, &cg);  // sin 2 gamma, cos 2 gamma
-    double s2l = 2.0 * sl * cl, c2l = cl * cl - sl * sl;
-    double pa[5], pb[5];
-    pa[0] = 0.75 * sg * cl * cl * cdl * cdl;
-    pa[1] = 0.25 * sg * s2l * s2d;
-    pa[2] = -0.5 * cg * cl * s2d;
-    pa[3] = sg * (3.0 - c2l) * (3.0 - c2d) / 16.0;
-    pa[4] = -0.25 * cg * sl * (3.0 - c2d);
-    pb[0] = 0.0;
-    pb[1] = cg * cl * cdl;
-    pb[2] = 0.5 * sg * s2l * cdl;
-    pb[3] = cg * sl * sd;
-    pb[4] = 0.25 * sg * (3.0 - c2l) * sd;
-    // d/d delta of the coefficients (d sin2d = 2 cos2d, d cos2d = -2 sin2d)
-    double dpa[5], dpb[5];
-    dpa[0] = -0.75 * sg * cl * cl * s2d;
-    dpa[1] = 0.5 * sg * s2l * c2d;
-    dpa[2] = -cg * cl * c2d;
-    dpa[3] = sg * (3.0 - c2l) * s2d / 8.0;
-    dpa[4] = -0.5 * cg * sl * s2d;
-    dpb[0] = 0.0;
-    dpb[1] = -cg * cl * sd;
-    dpb[2] = -0.5 * sg * s2l * sd;
-    dpb[3] = cg * sl * cdl;
-    dpb[4] = 0.25 * sg * (3.0 - c2l) * cdl;
-    for (int q = 0; q < 5; ++q) {
-      pa_all[X][q] = pa[q];
-      pb_all[X][q] = pb[q];
-      dpa_all[X][q] = dpa[q];
-      dpb_all[X][q] = dpb[q];
-    }
+    const Jks k = jks_coeffs(d, sd, cdl);
     tp.alpha_cyc[X] = alpha / (2.0 * kPi) - d.lst0_cyc;
     // S_n = e^{i n alpha} conj(M_n)
     cd S[5];
-    for (int n = 0; n < 5; ++n) {
-      double sn, cn;
-      sincos(n * alpha, &sn, &cn);
-      cd m = {P.moments[X * 10 + 2 * n], P.moments[X * 10 + 2 * n + 1]};
-      S[n] = cd_mul({cn, sn}, cd_conj(m));
-    }
-    cd p[3] = {{pa[0], 0.0}, {pa[1], -pa[2]}, {pa[3], -pa[4]}};
-    cd q[3] = {{pb[0], 0.0}, {pb[1], -pb[2]}, {pb[3], -pb[4]}};
+#pragma unroll
+    for (int n = 0; n < 5; ++n)
+      S[n] = cd_mul(ea[n], cd_conj({P.moments[X * 10 + 2 * n], P.moments[X * 10 + 2 * n + 1]}));
+    const cd p[3] = {{k.pa[0], 0.0}, {k.pa[1], -k.pa[2]}, {k.pa[3], -k.pa[4]}};
+    const cd q[3] = {{k.pb[0], 0.0}, {k.pb[1], -k.pb[2]}, {k.pb[3], -k.pb[4]}};
     A += d.w * moment_product(p, p, S);
     B += d.w * moment_product(q, q, S);
     C += d.w * moment_product(p, q, S);
     // alpha enters through S_n = e^{i n alpha} conj(M_n): dS_n = i n S_n
     cd dS[5];
+#pragma unroll
     for (int n = 0; n < 5; ++n) dS[n] = {-double(n) * S[n].i, double(n) * S[n].r};
     dA[0] += d.w * moment_product(p, p, dS);
     dB[0] += d.w * moment_product(q, q, dS);
     dC[0] += d.w * moment_product(p, q, dS);
     // delta enters through the coefficients (the product is bilinear)
-    cd dp[3] = {{dpa[0], 0.0}, {dpa[1], -dpa[2]}, {dpa[3], -dpa[4]}};
-    cd dq[3] = {{dpb[0], 0.0}, {dpb[1], -dpb[2]}, {dpb[3], -dpb[4]}};
+    const cd dp[3] = {{k.dpa[0], 0.0}, {k.dpa[1], -k.dpa[2]}, {k.dpa[3], -k.dpa[4]}};
+    const cd dq[3] = {{k.dpb[0], 0.0}, {k.dpb[1], -k.dpb[2]}, {k.dpb[3], -k.dpb[4]}};
     dA[1] += d.w * 2.0 * moment_product(dp, p, S);
     dB[1] += d.w * 2.0 * moment_product(dq, q, S);
     dC[1] += d.w * (moment_product(dp, q, S) + moment_product(p, dq, S));
@@ -201,38 +211,43 @@ __host__ __device__ inline void template_params(const PlanConst& P, const double
   if (!(A > 0.0) || !(Dd > 0.0) || !__builtin_isfinite(Dd)) status |= kStatusTiming;
   const double l11 = sqrt(A), l21 = C / l11, l22 = sqrt(Dd / A);
   const double r = C / A;
-  for (int X = 0; X < P.ndet; ++X) {
-    const double w = P.det[X].w;
-    for (int q = 0; q < 5; ++q) {
-      tp.ca[X][q] = static_cast<float>(w * pa_all[X][q] / l11);
-      tp.cb[X][q] = static_cast<float>(w * (pb_all[X][q] - r * pa_all[X][q]) / l22);
-    }
-  }
   tp.l11 = static_cast<float>(l11);
   tp.l21 = static_cast<float>(l21);
   tp.l22 = static_cast<float>(l22);
   // derivatives of the whitened coefficients: a' = a / l11,
   // b' = (b - r a) / l22 with r = C/A, l11^2 = A, l22^2 = B - C^2/A
+  double dl11[2], dr[2], dl22[2];
+#pragma unroll
   for (int th = 0; th < 2; ++th) {
-    const double dl11 = dA[th] / (2.0 * l11);
-    const double dr = (dC[th] * A - C * dA[th]) / (A * A);
-    const double dl22 = (dB[th] - (2.0 * C * dC[th] * A - C * C * dA[th]) / (A * A)) / (2.0 * l22);
-    for (int X = 0; X < P.ndet; ++X) {
-      const double w = P.det[X].w;
-      for (int q = 0; q < 5; ++q) {
-        const double dpaq = th == 1 ? dpa_all[X][q] : 0.0;
-        const double dpbq = th == 1 ? dpb_all[X][q] : 0.0;
-        const double bq = pb_all[X][q] - r * pa_all[X][q];
-        const double dbq = dpbq - dr * pa_all[X][q] - r * dpaq;
-        tp.dca[th][X][q] = static_cast<float>(w * (dpaq / l11 - pa_all[X][q] * dl11 / (l11 * l11)));
-        tp.dcb[th][X][q] = static_cast<float>(w * (dbq / l22 - bq * dl22 / (l22 * l22)));
+    dl11[th] = dA[th] / (2.0 * l11);
+    dr[th] = (dC[th] * A - C * dA[th]) / (A * A);
+    dl22[th] = (dB[th] - (2.0 * C * dC[th] * A - C * C * dA[th]) / (A * A)) / (2.0 * l22);
+  }
+#pragma unroll
+  for (int X = 0; X < kMaxDet; ++X) {
+    if (X >= P.ndet) continue;
+    const double w = P.det[X].w;
+    const Jks k = jks_coeffs(P.det[X], sd, cdl);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const double bq = k.pb[q] - r * k.pa[q];
+      tp.ca[X][q] = static_cast<float>(w * k.pa[q] / l11);
+      tp.cb[X][q] = static_cast<float>(w * bq / l22);
+#pragma unroll
+      for (int th = 0; th < 2; ++th) {
+        const double dpaq = th == 1 ? k.dpa[q] : 0.0;
+        const double dpbq = th == 1 ? k.dpb[q] : 0.0;
+        const double dbq = dpbq - dr[th] * k.pa[q] - r * dpaq;
+        tp.dca[th][X][q] =
+            static_cast<float>(w * (dpaq / l11 - k.pa[q] * dl11[th] / (l11 * l11)));
+        tp.dcb[th][X][q] = static_cast<float>(w * (dbq / l22 - bq * dl22[th] / (l22 * l22)));
       }
     }
   }
   tp.status = status;
 }
 
-__global__ void k_prologue(PlanConst P, const double* __restrict__ templates, ChunkMap map,
+__global__ __launch_bounds__(64) void k_prologue(PlanConst P, const double* __restrict__ templates, ChunkMap map,
                            int slots, void* ws) {
   int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= map.n_tmpl) return;
@@ -244,7 +259,9 @@ __global__ void k_prologue(PlanConst P, const double* __restrict__ templates, Ch
   // the interpolation taps of the last sample end before the last computed
   // point, so grid points beyond k_pad are exactly zero.
   if ((status & kStatusGroupMask) == 0) {
-    for (int X = 0; X < P.ndet; ++X) {
+#pragma unroll
+    for (int X = 0; X < kMaxDet; ++X) {
+      if (X >= P.ndet) continue;
       const DetConst& d = P.det[X];
       const GlobalRoemer re{d.ephem, tp.nhat, P.n_eph, P.eph_t0, P.eph_dt, P.inv_eph_dt};
       double u_first = 0.0 + d.off + grid_delay(re, tp, P.tau0) * P.inv_dt;
@@ -254,12 +271,12 @@ __global__ void k_prologue(PlanConst P, const double* __restrict__ templates, Ch
     }
   }
   tp.status = status;
-  *slot_params(ws, P.n_fft, g) = tp;
+  *slot_params(ws, P, g) = tp;
   // grouped path: a group resampled in this chunk starts from the status of
   // the template whose parameters it uses
   for (int i = 0; i < map.n_grp; ++i)
     if (map.grp_slot[i] == g)
-      *group_status(ws, P.n_fft, slots, P.k_pad, map.grp_buf[i]) = status & kStatusGroupMask;
+      *group_status(ws, P, slots, map.grp_buf[i]) = status & kStatusGroupMask;
 }
 
 }  // namespace fstat

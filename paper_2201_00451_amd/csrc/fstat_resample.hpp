@@ -79,17 +79,29 @@ __host__ __device__ constexpr double ct_sinpi(int n, int d) {
   return sq * ct_poly_cos(r) + cq * ct_poly_sin(r);
 }
 
-template <int D>
-struct Taps {
-  static constexpr double sgn(int t) { return ((D - 1 - t) & 1) ? -1.0 : 1.0; }
-  static constexpr float A(int t) {
-    return float(sgn(t) * ct_cospi(D - 1 - t, D) / (2.0 * kPi));
-  }
-  static constexpr float B(int t) {
-    return float(-sgn(t) * ct_sinpi(D - 1 - t, D) / (2.0 * kPi));
-  }
-  static constexpr float C(int t) { return float(sgn(t) / (2.0 * kPi)); }
+// Tap constants of half-width D, built at compile time into constant memory
+// (read with uniform indices, whether or not the tap loop is unrolled):
+//   A_t, B_t, C_t as above; Ct_t = cos(pi c_t / D), St_t = sin(pi c_t / D).
+struct TapConst {
+  float A[64], B[64], C[64], Ct[64], St[64];
 };
+template <int D>
+__host__ __device__ constexpr TapConst make_taps() {
+  TapConst k{};
+  for (int t = 0; t < 2 * D; ++t) {
+    const int c = D - 1 - t;
+    const double sgn = (c & 1) ? -1.0 : 1.0;
+    const double cc = ct_cospi(c, D), ss = ct_sinpi(c, D);
+    k.A[t] = float(sgn * cc / (2.0 * kPi));
+    k.B[t] = float(-sgn * ss / (2.0 * kPi));
+    k.C[t] = float(sgn / (2.0 * kPi));
+    k.Ct[t] = float(cc);
+    k.St[t] = float(ss);
+  }
+  return k;
+}
+template <int D>
+__constant__ TapConst kTaps = make_taps<D>();
 
 // GROUPED = false: blockIdx.y is a template slot; the spin-down phase is
 // applied and y_a', y_b' go to the slot's buffers.  GROUPED = true: blockIdx.y
@@ -102,13 +114,13 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws,
                                                          int slots) {
   const int gi = blockIdx.y;
   const int slot = GROUPED ? map.grp_slot[gi] : gi;
-  const TmplParams& tp = *slot_params(ws, P.n_fft, slot);
-  int32_t* status_word = GROUPED ? group_status(ws, P.n_fft, slots, P.k_pad, map.grp_buf[gi])
-                                 : &slot_params(ws, P.n_fft, slot)->status;
-  float2* ya = GROUPED ? group_buf(ws, P.n_fft, slots, P.k_pad, map.grp_buf[gi], 0)
-                       : slot_buf(ws, P.n_fft, slot, 0);
-  float2* yb = GROUPED ? group_buf(ws, P.n_fft, slots, P.k_pad, map.grp_buf[gi], 1)
-                       : slot_buf(ws, P.n_fft, slot, 1);
+  const TmplParams& tp = *slot_params(ws, P, slot);
+  int32_t* status_word = GROUPED ? group_status(ws, P, slots, map.grp_buf[gi])
+                                 : &slot_params(ws, P, slot)->status;
+  float2* ya = GROUPED ? group_buf(ws, P, slots, map.grp_buf[gi], 0)
+                       : slot_buf(ws, P, slot, 0);
+  float2* yb = GROUPED ? group_buf(ws, P, slots, map.grp_buf[gi], 1)
+                       : slot_buf(ws, P, slot, 1);
   const int64_t k_s = int64_t(blockIdx.x) * kResTile;
   const int tid = threadIdx.x;
 
@@ -216,7 +228,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws,
         float sx = 0.f, sy = 0.f;
 #pragma unroll
         for (int t = 0; t < 2 * D; ++t) {
-          const float win = fmaf(Taps<D>::B(t), ws_, fmaf(Taps<D>::A(t), wc_, Taps<D>::C(t)));
+          const float win = fmaf(kTaps<D>.B[t], ws_, fmaf(kTaps<D>.A[t], wc_, kTaps<D>.C[t]));
           const float h = win * __builtin_amdgcn_rcpf(f + float(D - 1 - t));
           const float2 zv = zp[t];
           sx = fmaf(h, zv.x, sx);

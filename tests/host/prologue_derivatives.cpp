@@ -28,6 +28,10 @@ int main() {
   for (int X = 0; X < 2; ++X) {
     P.det[X].lat = lat[X];
     P.det[X].gamma = gam[X];
+    P.det[X].sl = std::sin(lat[X]);
+    P.det[X].cl = std::cos(lat[X]);
+    P.det[X].s2g = std::sin(2.0 * gam[X]);
+    P.det[X].c2g = std::cos(2.0 * gam[X]);
     P.det[X].w = wgt[X];
     P.det[X].lst0_cyc = lon[X] / (2 * kPi);
     // moments of 1.5 days of samples every 60 s with a gap

@@ -99,11 +99,14 @@ def status_of(desc):
 def test_plan_accepts_valid_setup(lib):
     ds, d = good_desc()
     p = B.Plan(d)
-    # every documented tuning choice is accepted (n_fft = 2^13: passes 2^7 x 2^6 by default)
+    # every documented tuning choice is accepted (n_fft = 2^13: columns 2^6 x rows 2^7 by default)
     for log_len, cl, rl in ((7, 64, 32), (7, 32, 16), (6, 64, 32), (6, 32, 16)):
         d2 = B.make_plan_desc(ds, dict(tune_col_log_len=log_len, tune_col_lines=cl,
                                        tune_row_lines=rl))
         B.Plan(d2)
+    k_pad, lc, lr = p.info()
+    assert (lc, lr) == (6, 7) and k_pad % (1 << lr) == 0 and k_pad % 1024 == 0
+    assert k_pad >= ds.detectors[0].n and k_pad <= ds.n_fft
     # header + one slot of two n_fft complex64 arrays
     assert p.workspace_size(1) >= 2 * 8 * ds.n_fft
     assert p.workspace_size(3) - p.workspace_size(2) == p.workspace_size(2) - p.workspace_size(1)
@@ -181,6 +184,44 @@ def test_null_arguments_rejected_before_any_launch(lib):
     # zero templates is a no-op that succeeds without touching the device
     assert lib.fstat_compute_2f(p.handle, ctypes.byref(inp), vp(0), 0, vp(0), vp(0), vp(4096),
                                 1 << 30, vp(0)) == B.FSTAT_OK
+
+
+def test_gradient_entry_checks_arguments_before_any_launch(lib):
+    ds, d = good_desc()
+    p = B.Plan(d)
+    vp = ctypes.c_void_p
+    # adjoint slot: the forward slot plus two more n_fft arrays and the tile partials
+    g1, g2 = p.grad_workspace_size(1), p.grad_workspace_size(2)
+    assert g2 - g1 >= (p.workspace_size(2) - p.workspace_size(1)) + 2 * 8 * ds.n_fft
+    assert g2 - g1 == p.grad_workspace_size(3) - g2 and (g2 - g1) % 256 == 0
+    sz = ctypes.c_size_t()
+    assert lib.fstat_grad_workspace_size(p.handle, 0, ctypes.byref(sz)) == B.FSTAT_EINVAL
+    assert lib.fstat_grad_workspace_size(None, 1, ctypes.byref(sz)) == B.FSTAT_EINVAL
+    inp = B.FstatInputs()
+    for i in range(2):
+        inp.x[i] = inp.ephem[i] = 4096
+    inp.moments = 4096
+    inp.eph_t0, inp.eph_dt, inp.n_eph = ds.eph_t0, ds.eph_dt, ds.eph_tables[0].shape[0]
+    grad = lib.fstat_compute_2f_grad
+    # null weights / gradient output / templates
+    assert grad(p.handle, ctypes.byref(inp), vp(4096), 1, vp(0), vp(4096), vp(0), vp(4096),
+                1 << 30, vp(0)) == B.FSTAT_EINVAL
+    assert "grad" in B.last_error()
+    assert grad(p.handle, ctypes.byref(inp), vp(4096), 1, vp(4096), vp(0), vp(0), vp(4096),
+                1 << 30, vp(0)) == B.FSTAT_EINVAL
+    assert grad(p.handle, ctypes.byref(inp), vp(0), 1, vp(4096), vp(4096), vp(0), vp(4096),
+                1 << 30, vp(0)) == B.FSTAT_EINVAL
+    # the forward workspace is too small for the adjoint
+    assert grad(p.handle, ctypes.byref(inp), vp(4096), 1, vp(4096), vp(4096), vp(0), vp(4096),
+                p.workspace_size(1), vp(0)) == B.FSTAT_EWORKSPACE
+    assert grad(p.handle, ctypes.byref(inp), vp(4096), 1, vp(4096), vp(4096), vp(0), vp(4100),
+                g1, vp(0)) == B.FSTAT_EINVAL
+    assert grad(p.handle, None, vp(4096), 1, vp(4096), vp(4096), vp(0), vp(4096), g1,
+                vp(0)) == B.FSTAT_EINVAL
+    assert grad(p.handle, ctypes.byref(inp), vp(4096), -1, vp(4096), vp(4096), vp(0), vp(4096),
+                g1, vp(0)) == B.FSTAT_EINVAL
+    assert grad(p.handle, ctypes.byref(inp), vp(0), 0, vp(0), vp(0), vp(0), vp(4096), g1,
+                vp(0)) == B.FSTAT_OK
 
 
 def test_search_plan_groups_and_chunks(lib):

@@ -175,7 +175,7 @@ def test_delay_bound_violation_gives_nan(torch_dev):
 
 @pytest.mark.parametrize("tune", [
     dict(tune_col_lines=32, tune_row_lines=16),     # half lines, same split: same arithmetic
-    dict(tune_col_log_len=6),                        # other split of 2^13
+    dict(tune_col_log_len=7),                        # other split of 2^13
 ])
 def test_fft_launch_shapes(torch_dev, tune):
     from paper_2201_00451_amd import binding
