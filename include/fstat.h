@@ -76,11 +76,15 @@ typedef struct {
    *   tune_col_log_len: log2 of the column-pass FFT length, the row pass has
    *     log2(n_fft) - tune_col_log_len; both must lie in [6, 12];
    *   tune_col_lines: columns per workgroup of the column pass;
-   *   tune_row_lines: rows per workgroup of the row pass.
+   *   tune_row_lines: rows per workgroup of the row pass;
+   *   tune_fft_grid: 0 = persistent workgroups (as many as fit the device at
+   *     once, each looping over work items with the next item's loads in
+   *     flight), 1 = one workgroup per work item.
    * Accepted line counts are the automatic value or half of it. */
   int32_t tune_col_log_len;
   int32_t tune_col_lines;
   int32_t tune_row_lines;
+  int32_t tune_fft_grid;
   uint32_t flags;                      /* reserved, must be 0 */
 } fstat_plan_desc;
 
@@ -209,6 +213,21 @@ FSTAT_API fstat_status fstat_search_run_profiled(fstat_search* search, const fst
                                                  void* workspace, size_t ws_bytes, void* stream,
                                                  float* kernel_ms, int64_t* launches);
 
+/* Launch-shape autotuner: for the set-up *desc (its tune fields ignored),
+ * times every FFT launch shape the plan accepts (both column/row splits of
+ * n_fft around its square root, full or half line counts for each pass,
+ * persistent or one-workgroup-per-item grids) by running the batched path
+ * on the given sample of templates (device [ntmpl][8], ntmpl >= 1; twoF a
+ * device [ntmpl][n_bins] scratch output) with the given workspace, once
+ * untimed and once timed with HIP events, and returns the fastest
+ * description in *best (desc with the tune fields set) and its time in
+ * *best_ms.  The interpolation half-width is not tuned (it sets the
+ * accuracy).  Synchronises the stream.  Fails if no shape ran. */
+FSTAT_API fstat_status fstat_autotune(const fstat_plan_desc* desc, const fstat_inputs* in,
+                                      const double* templates, int64_t ntmpl, float* twoF,
+                                      void* workspace, size_t ws_bytes, void* stream,
+                                      fstat_plan_desc* best, float* best_ms);
+
 /* Diagnostic: steps (iii)-(v) and the weighting of (vi) only.  Writes the
  * weighted, resampled series before the transform, y: float2 [ntmpl][2][n_fft]
  * (y_a then y_b, zero beyond the data).  Needs fstat_workspace_size(plan, 1). */
@@ -245,6 +264,25 @@ FSTAT_API fstat_status fstat_compute_2f_grad(const fstat_plan* plan, const fstat
                                              const double* templates, int64_t ntmpl,
                                              const float* grad_twoF, double* grad, float* twoF,
                                              void* workspace, size_t ws_bytes, void* stream);
+
+/* Single-bin refinement form of fstat_compute_2f_grad: template m has one
+ * bin bins[m] (device int64 [ntmpl], index into the band [0, n_bins)) and the
+ * weights are one-hot there, L_m = 2F_m(bins[m]).  The transforms are needed
+ * at that one bin only, so no FFT runs: the resampling kernel reduces the
+ * direct sum Fa'(m), Fb'(m) over the grid (step (vi) for one output bin), and
+ * the gradient kernel forms the adjoint series in closed form
+ * X_k = conj(F'(m)) exp(-2 pi i m k / N).  Two passes over the input data per
+ * template, and a workspace of about 1 KiB plus 64 bytes per 1024 grid points
+ * per template in flight (fstat_grad_bin_workspace_size; up to 32 per
+ * launch).  Outputs: twoF (nullable) device float [ntmpl] = 2F at the bin;
+ * grad device double [ntmpl][7] as in fstat_compute_2f_grad.  A flagged
+ * template or a bin outside the band gives NaN. */
+FSTAT_API fstat_status fstat_grad_bin_workspace_size(const fstat_plan* plan, int64_t batch,
+                                                     size_t* bytes);
+FSTAT_API fstat_status fstat_compute_2f_grad_bin(const fstat_plan* plan, const fstat_inputs* in,
+                                                 const double* templates, int64_t ntmpl,
+                                                 const int64_t* bins, float* twoF, double* grad,
+                                                 void* workspace, size_t ws_bytes, void* stream);
 
 /* Wait for the stream and report any asynchronous HIP error as FSTAT_EHIP. */
 FSTAT_API fstat_status fstat_sync_check(void* stream);

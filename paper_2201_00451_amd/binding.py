@@ -23,7 +23,8 @@ EXPORTED = ("fstat_plan_create", "fstat_plan_destroy", "fstat_workspace_size",
             "fstat_compute_2f_profiled", "fstat_resample", "fstat_sync_check",
             "fstat_last_error", "fstat_version", "fstat_search_create", "fstat_search_destroy",
             "fstat_search_info", "fstat_search_run", "fstat_search_run_profiled",
-            "fstat_grad_workspace_size", "fstat_compute_2f_grad", "fstat_plan_info")
+            "fstat_grad_workspace_size", "fstat_compute_2f_grad", "fstat_plan_info",
+            "fstat_grad_bin_workspace_size", "fstat_compute_2f_grad_bin", "fstat_autotune")
 GRAD_PARAMS = ("df", "f1dot", "alpha", "delta", "asini", "porb", "tp")
 # template-row column of each gradient parameter
 GRAD_COLUMNS = (2, 3, 0, 1, 5, 6, 7)
@@ -44,7 +45,8 @@ class FstatPlanDesc(ctypes.Structure):
                 ("sid_rate", ctypes.c_double), ("n_fft", ctypes.c_int64),
                 ("bin_lo", ctypes.c_int64), ("n_bins", ctypes.c_int64),
                 ("tune_col_log_len", ctypes.c_int32), ("tune_col_lines", ctypes.c_int32),
-                ("tune_row_lines", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("tune_row_lines", ctypes.c_int32), ("tune_fft_grid", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
 
 
 class FstatInputs(ctypes.Structure):
@@ -97,7 +99,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                               ctypes.POINTER(ctypes.c_int64)]
     lib.fstat_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32)]
+    lib.fstat_autotune.argtypes = [ctypes.POINTER(FstatPlanDesc), ctypes.POINTER(FstatInputs),
+                                   vp, i64, vp, vp, sz, vp, ctypes.POINTER(FstatPlanDesc),
+                                   ctypes.POINTER(ctypes.c_float)]
     lib.fstat_grad_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
+    lib.fstat_grad_bin_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
+    lib.fstat_compute_2f_grad_bin.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, i64, vp, vp,
+                                              vp, vp, sz, vp]
     lib.fstat_compute_2f_grad.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, i64, vp, vp, vp,
                                           vp, sz, vp]
     lib.fstat_sync_check.argtypes = [vp]
@@ -165,6 +173,12 @@ class Plan:
         _check(load_library().fstat_plan_info(self.handle, ctypes.byref(k), ctypes.byref(lc),
                                               ctypes.byref(lr)))
         return int(k.value), int(lc.value), int(lr.value)
+
+    def grad_bin_workspace_size(self, batch: int = 1) -> int:
+        out = ctypes.c_size_t()
+        _check(load_library().fstat_grad_bin_workspace_size(self.handle, int(batch),
+                                                            ctypes.byref(out)))
+        return int(out.value)
 
     def grad_workspace_size(self, batch: int = 1) -> int:
         out = ctypes.c_size_t()
@@ -312,6 +326,26 @@ def compute_2f_grad(dd: DeviceData, templates, grad_twoF, want_twoF=False, batch
     return (grad, tf) if want_twoF else grad
 
 
+def compute_2f_grad_bin(dd: DeviceData, templates, bins, batch=32, stream=None):
+    """Single-bin form: (gradient of 2F at bins[m] for template m, float64
+    [n, 7]; 2F at that bin, float32 [n]), both on the device.  No FFT runs."""
+    import torch
+    tm = _templates(dd, templates)
+    n = tm.shape[0]
+    b = torch.as_tensor(np.asarray(bins, dtype=np.int64)).to(dd.device).contiguous()
+    if tuple(b.shape) != (n,):
+        raise FstatError(FSTAT_EINVAL, f"bins must have shape [{n}]")
+    nbytes = dd.plan.grad_bin_workspace_size(batch)
+    if getattr(dd, "grad_bin_ws", None) is None or dd.grad_bin_ws.numel() != nbytes:
+        dd.grad_bin_ws = torch.empty(nbytes, dtype=torch.uint8, device=dd.device)
+    grad = torch.empty((n, len(GRAD_PARAMS)), dtype=torch.float64, device=dd.device)
+    tf = torch.empty((n,), dtype=torch.float32, device=dd.device)
+    _check(load_library().fstat_compute_2f_grad_bin(
+        dd.plan.handle, ctypes.byref(dd.inputs), _ptr(tm), n, _ptr(b), _ptr(tf), _ptr(grad),
+        _ptr(dd.grad_bin_ws), dd.grad_bin_ws.numel(), _stream_ptr(stream)))
+    return grad, tf
+
+
 def template_rows(params, f2dot=None):
     """Template rows [n, 8] from params [n, 7] in GRAD_PARAMS order (float64)."""
     import torch
@@ -366,12 +400,11 @@ def refine(dd: DeviceData, templates, bins, scales, steps=50, lr=0.5, free=None)
     parameter): u = scales * grad / 2F, capped at unit length, and
     theta += lr * scales * u.  A step is kept only where 2F does not decrease;
     then lr grows by 1.5 (at most 4), else it halves, per candidate.  Every 2F
-    and gradient comes from the HIP kernels.  Returns (rows, 2F at bins) as
-    host arrays."""
+    and gradient comes from the HIP kernels (the single-bin adjoint: no FFT).
+    Returns (rows, 2F at bins) as host arrays."""
     import torch
     rows = torch.as_tensor(np.asarray(templates, dtype=np.float64)).clone()
     n = rows.shape[0]
-    idx = torch.arange(n)
     bins = torch.as_tensor(np.asarray(bins, dtype=np.int64))
     sc = torch.as_tensor(np.asarray(scales, dtype=np.float64))
     mask = torch.ones((n, 7), dtype=torch.float64)
@@ -379,26 +412,45 @@ def refine(dd: DeviceData, templates, bins, scales, steps=50, lr=0.5, free=None)
     if free is not None:
         keep = torch.tensor([1.0 if p in free else 0.0 for p in GRAD_PARAMS], dtype=torch.float64)
         mask = mask * keep
-    onehot = torch.zeros((n, dd.n_bins), dtype=torch.float32)
-    onehot[idx, bins] = 1.0
     step = torch.full((n,), float(lr), dtype=torch.float64)
     cols = list(GRAD_COLUMNS)
-    g, tf = compute_2f_grad(dd, rows, onehot, want_twoF=True)
-    cur = tf.cpu()[idx, bins].double()
+    g, tf = compute_2f_grad_bin(dd, rows, bins)
+    cur = tf.cpu().double()
     g = g.cpu()
     for _ in range(steps):
         u = sc * g * mask / torch.clamp(cur, min=1.0)[:, None]
         u = u / torch.clamp(torch.linalg.vector_norm(u, dim=1), min=1.0)[:, None]
         trial = rows.clone()
         trial[:, cols] = rows[:, cols] + step[:, None] * sc * u
-        g_t, tf_t = compute_2f_grad(dd, trial, onehot, want_twoF=True)
-        val = tf_t.cpu()[idx, bins].double()
+        g_t, tf_t = compute_2f_grad_bin(dd, trial, bins)
+        val = tf_t.cpu().double()
         ok = torch.isfinite(val) & (val >= cur)
         rows[ok] = trial[ok]
         cur = torch.where(ok, val, cur)
         g = torch.where(ok[:, None], g_t.cpu(), g)
         step = torch.where(ok, torch.clamp(step * 1.5, max=4.0), step * 0.5)
     return rows.numpy(), cur.numpy()
+
+
+TUNE_FIELDS = ("tune_col_log_len", "tune_col_lines", "tune_row_lines", "tune_fft_grid")
+
+
+def autotune(ds, templates, batch=8, device="cuda:0", stream=None):
+    """fstat_autotune on a sample of templates: returns (tune dict, ms) for the
+    fastest FFT launch shape of this set-up (pass the dict as ``tune`` to
+    DeviceData)."""
+    import torch
+    dd = DeviceData(ds, device=device, batch=batch)
+    tm = _templates(dd, templates)
+    n = tm.shape[0]
+    tf = torch.empty((n, dd.n_bins), dtype=torch.float32, device=dd.device)
+    best = FstatPlanDesc()
+    ms = ctypes.c_float()
+    _check(load_library().fstat_autotune(ctypes.byref(dd.plan.desc), ctypes.byref(dd.inputs),
+                                         _ptr(tm), n, _ptr(tf), _ptr(dd.ws), dd.ws.numel(),
+                                         _stream_ptr(stream), ctypes.byref(best),
+                                         ctypes.byref(ms)))
+    return {k: int(getattr(best, k)) for k in TUNE_FIELDS}, float(ms.value)
 
 
 def sync_check(stream=None):

@@ -18,7 +18,10 @@
 //   d a'    = (d a'/d theta at fixed x) + (d a'/dx) (d alpha - Omega dT)
 // where d roemer = r . d nhat, dR the explicit orbit derivatives; for df and
 // f1dot only E_k depends on theta.  Isolated templates (asini = 0) report zero
-// orbit derivatives.
+// orbit derivatives.  For alpha and delta a constant (the parameter block's
+// dshift) is taken off d delta_j: its contribution to the gradient is exactly
+// zero, and without it the large constant sky phase derivative would cancel
+// in FP32 arithmetic.
 #pragma once
 
 #include "fstat_common.hpp"
@@ -60,7 +63,11 @@ struct NodeRoemer3 {
 
 constexpr int kGradParams = 7;  // df, f1dot, alpha, delta, asini, porb, tp
 
-template <int D>
+// ONEHOT = false: X comes from the transformed adjoint spectrum (arrays 0
+// and 1 hold conj(X)).  ONEHOT = true (single-bin path): L = 2F(m) at one bin
+// m, so H is non-zero only at m and X_k = H_m exp(-2 pi i m k / N) in closed
+// form; the slot holds no arrays.
+template <int D, bool ONEHOT>
 __global__ __launch_bounds__(kResThreads) void k_grad(PlanConst P, void* ws) {
   const int slot = blockIdx.y;
   const TmplParams& tp = *slot_params(ws, P, slot);
@@ -90,9 +97,15 @@ __global__ __launch_bounds__(kResThreads) void k_grad(PlanConst P, void* ws) {
   for (int i = 0; i < kResPerThread; ++i) {
     const int64_t k = k_s + tid + i * kResThreads;
     const float2 e = spindown_rotation(P, tp.f1dot, tp.f2dot, tp.df, k);
-    const float2 ya = slot_buf(ws, P, slot, 0)[k], yb = slot_buf(ws, P, slot, 1)[k];
-    Wa[i] = cmul(make_float2(ya.x, -ya.y), e);
-    Wb[i] = cmul(make_float2(yb.x, -yb.y), e);
+    if (ONEHOT) {
+      const float2 tw = bin_twiddle(tp.bin_nat, k, P.n_fft);
+      Wa[i] = cmul(cmul(make_float2(float(tp.hbin[0]), float(tp.hbin[1])), tw), e);
+      Wb[i] = cmul(cmul(make_float2(float(tp.hbin[2]), float(tp.hbin[3])), tw), e);
+    } else {
+      const float2 ya = slot_buf(ws, P, slot, 0)[k], yb = slot_buf(ws, P, slot, 1)[k];
+      Wa[i] = cmul(make_float2(ya.x, -ya.y), e);
+      Wb[i] = cmul(make_float2(yb.x, -yb.y), e);
+    }
   }
   double acc[kGradParams];
 #pragma unroll
@@ -196,8 +209,8 @@ __global__ __launch_bounds__(kResThreads) void k_grad(PlanConst P, void* ws) {
         float sn, cs;
         sincospif(2.0f * c, &sn, &cs);
         z = make_float2(xv.x * cs + xv.y * sn, xv.y * cs - xv.x * sn);
-        dz[0] = float(da * invb);
-        dz[1] = float(ddl * invb);
+        dz[0] = float(da * invb - tp.dshift[0]);
+        dz[1] = float(ddl * invb - tp.dshift[1]);
         if (binary) {
           dz[2] = float(-s2 * invb);
           dz[3] = float(tp.asini * c2 * om * (tsrc - tp.tp) / tp.porb * invb);

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -64,7 +65,7 @@ int cols_lines_max(int log_rr) { return std::min(64, 16384 >> log_rr); }
 int rows_lines_max(int log_c) { return std::min(32, 8192 >> log_c); }
 
 using ColsFn = void (*)(PlanConst, void*, ChunkMap, int, int, int, int64_t);
-using RowsFn = void (*)(PlanConst, void*, ChunkMap, int, float*, float2*, const float*);
+using RowsFn = void (*)(PlanConst, void*, ChunkMap, int, int, float*, float2*, const float*);
 
 template <int LOGL>
 constexpr int kColsMax = (16384 >> LOGL) < 64 ? (16384 >> LOGL) : 64;
@@ -253,12 +254,53 @@ fstat_status validate_ws(const fstat_plan* p, void* ws, size_t ws_bytes, int64_t
 }
 
 // LDS of a pass: NL lines at the padded pitch L + L/16 + 1 (see LdsLayout).
-size_t lds_pitch(int logl) { return (size_t(1) << logl) + (size_t(1) << logl) / 16 + 1; }
-size_t lds_bytes_cols(const fstat_plan* p) {
-  return size_t(p->cols_lines) * lds_pitch(p->log_rr) * sizeof(float2);
+size_t lds_bytes_cols(const fstat_plan* p) { return fft_lds_bytes(p->log_rr, p->cols_lines); }
+size_t lds_bytes_rows(const fstat_plan* p) { return fft_lds_bytes(p->log_c, 2 * p->rows_lines); }
+
+// Workgroups of an FFT pass over n_items work items: one per item, or
+// (persistent, the default) as many as the device holds at once, from the
+// compute-unit count and the occupancy of that kernel at its LDS size (kept
+// per kernel, LDS size and device).
+unsigned fft_grid(const fstat_plan* p, const FftVariant& v, size_t lds, int64_t n_items) {
+  if (n_items < 1) return 1;
+  if (p->desc.tune_fft_grid == 1) return unsigned(n_items);
+  struct Entry {
+    const void* fn;
+    size_t lds;
+    int dev, blocks;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return unsigned(n_items);
+  }
+  int blocks = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry& e : cache)
+      if (e.fn == v.fn && e.lds == lds && e.dev == dev) blocks = e.blocks;
+  }
+  if (blocks == 0) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, v.fn, v.threads, lds) != hipSuccess ||
+        cus < 1 || per < 1) {
+      (void)hipGetLastError();
+      return unsigned(n_items);
+    }
+    blocks = cus * per;
+    std::lock_guard<std::mutex> lock(mu);
+    cache.push_back({v.fn, lds, dev, blocks});
+  }
+  return unsigned(std::min<int64_t>(n_items, blocks));
 }
-size_t lds_bytes_rows(const fstat_plan* p) {
-  return size_t(2 * p->rows_lines) * lds_pitch(p->log_c) * sizeof(float2);
+int64_t cols_items(const fstat_plan* p, int n) {
+  return ((int64_t(1) << p->log_c) / p->cols_lines) * 2 * n;
+}
+int64_t rows_items(const fstat_plan* p, int n) {
+  return ((int64_t(1) << p->log_rr) / p->rows_lines) * n;
 }
 
 // Resampling kernel for a supported interpolation half-width.
@@ -309,10 +351,12 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
                           float2* y_out, void* ws, hipStream_t st, KernelTimer& tm) {
   fstat_status s;
   const int n = map.n_tmpl;
-  if ((s = tm.mark(0)) != FSTAT_OK) return s;
-  hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, slots,
-                     ws);
-  if ((s = tm.mark(0)) != FSTAT_OK) return s;
+  if (!grouped) {
+    // the grouped (search) path computed every parameter block up front
+    if ((s = tm.mark(0)) != FSTAT_OK) return s;
+    hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, ws);
+    if ((s = tm.mark(0)) != FSTAT_OK) return s;
+  }
   const int n_res = grouped ? map.n_grp : n;
   if (n_res > 0) {
     if ((s = tm.mark(1)) != FSTAT_OK) return s;
@@ -329,15 +373,15 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
   const FftVariant rv = pick_rows(p->log_c, p->rows_half);
   if ((s = tm.mark(2)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn)),
-                     dim3(unsigned((int64_t(1) << p->log_c) / p->cols_lines), 2, n),
+                     dim3(fft_grid(p, cv, lds_bytes_cols(p), cols_items(p, n))),
                      dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 0, p->log_c,
                      p->rows_act);
   if ((s = tm.mark(2)) != FSTAT_OK) return s;
   if ((s = tm.mark(3)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rv.fn)),
-                     dim3(unsigned((int64_t(1) << p->log_rr) / p->rows_lines), n),
-                     dim3(rv.threads), lds_bytes_rows(p), st, P, ws, map, p->log_rr, twoF, fafb,
-                     static_cast<const float*>(nullptr));
+                     dim3(fft_grid(p, rv, lds_bytes_rows(p), rows_items(p, n))),
+                     dim3(rv.threads), lds_bytes_rows(p), st, P, ws, map, slots, p->log_rr, twoF,
+                     fafb, static_cast<const float*>(nullptr));
   if ((s = tm.mark(3)) != FSTAT_OK) return s;
   return check_hip(hipGetLastError(), "kernel launch");
 }
@@ -398,7 +442,7 @@ fstat_status run(const fstat_plan* p, const fstat_inputs* in, const double* temp
   KernelTimer none;
   KernelTimer& tm = timer ? *timer : none;
   tm.st = st;
-  hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, ws, p->desc.n_fft);
+  hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, ws);
   for (int64_t t = 0; t < ntmpl; t += slots) {
     ChunkMap map;
     std::memset(&map, 0, sizeof map);
@@ -420,16 +464,61 @@ size_t grad_slot_bytes(const fstat_plan* p) {
 }
 
 using GradFn = void (*)(PlanConst, void*);
-GradFn grad_kernel(int D) {
+template <bool ONEHOT>
+GradFn grad_kernel_o(int D) {
   switch (D) {
-    case 4: return &k_grad<4>;
-    case 6: return &k_grad<6>;
-    case 8: return &k_grad<8>;
-    case 10: return &k_grad<10>;
-    case 12: return &k_grad<12>;
-    case 16: return &k_grad<16>;
+    case 4: return &k_grad<4, ONEHOT>;
+    case 6: return &k_grad<6, ONEHOT>;
+    case 8: return &k_grad<8, ONEHOT>;
+    case 10: return &k_grad<10, ONEHOT>;
+    case 12: return &k_grad<12, ONEHOT>;
+    case 16: return &k_grad<16, ONEHOT>;
     default: return nullptr;
   }
+}
+GradFn grad_kernel(int D, bool onehot) {
+  return onehot ? grad_kernel_o<true>(D) : grad_kernel_o<false>(D);
+}
+
+using BinFn = void (*)(PlanConst, void*, ChunkMap, const int64_t*);
+BinFn resample_bin_kernel(int D) {
+  switch (D) {
+    case 4: return &k_resample_bin<4>;
+    case 6: return &k_resample_bin<6>;
+    case 8: return &k_resample_bin<8>;
+    case 10: return &k_resample_bin<10>;
+    case 12: return &k_resample_bin<12>;
+    case 16: return &k_resample_bin<16>;
+    default: return nullptr;
+  }
+}
+
+// Single-bin adjoint slot: the parameter block and 8 doubles of partials per
+// resampling tile, padded to 256 bytes.
+size_t grad_bin_slot_bytes(const fstat_plan* p) {
+  const size_t tiles = size_t(p->k_pad / kResTile);
+  return kParamBytes + (tiles * 8 * sizeof(double) + 255) / 256 * 256;
+}
+
+// Single-bin launch sequence: prologue, resampling with the one-bin direct
+// transform reduced per tile, F'(m) / 2F(m) / H per template, the gradient
+// sums with X in closed form, and their per-template totals.
+fstat_status launch_grad_bin_chunk(const fstat_plan* p, const PlanConst& P,
+                                   const double* templates, const ChunkMap& map, int slots,
+                                   const int64_t* bins, float* twoF, double* grad, void* ws,
+                                   hipStream_t st) {
+  const int n = map.n_tmpl;
+  const unsigned tiles = unsigned(p->k_pad / kResTile);
+  hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, ws);
+  hipLaunchKernelGGL(resample_bin_kernel(p->desc.sinc_halfwidth), dim3(tiles, n),
+                     dim3(kResThreads), 0, st, P, ws, map, bins);
+  hipLaunchKernelGGL(k_bin_final, dim3((n + 63) / 64), dim3(64), 0, st, P, ws, map,
+                     int64_t(tiles), bins, twoF);
+  hipLaunchKernelGGL(grad_kernel(p->desc.sinc_halfwidth, true), dim3(tiles, n),
+                     dim3(kResThreads), 0, st, P, ws);
+  hipLaunchKernelGGL(k_grad_final, dim3((n * kGradParams + 63) / 64), dim3(64), 0, st, P, ws, map,
+                     int64_t(tiles), grad);
+  return check_hip(hipGetLastError(), "single-bin adjoint launch");
 }
 
 // Adjoint launch sequence for the template slots of one chunk: the forward
@@ -441,28 +530,28 @@ fstat_status launch_grad_chunk(const fstat_plan* p, const PlanConst& P, const do
                                float* twoF, void* ws, hipStream_t st) {
   const int n = map.n_tmpl;
   const unsigned tiles = unsigned(p->k_pad / kResTile);
-  hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, slots,
-                     ws);
+  hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, ws);
   hipLaunchKernelGGL(resample_kernel(p->desc.sinc_halfwidth, false), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws, map, slots);
   const FftVariant cv = pick_cols(p->log_rr, p->cols_half, false);
   const ColsFn cols = reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn));
-  const dim3 cgrid(unsigned((int64_t(1) << p->log_c) / p->cols_lines), 2, n);
-  const dim3 rgrid(unsigned((int64_t(1) << p->log_rr) / p->rows_lines), n);
+  const dim3 cgrid(fft_grid(p, cv, lds_bytes_cols(p), cols_items(p, n)));
   const FftVariant ra = pick_rows(p->log_c, p->rows_half, kRowAdjoint);
   const FftVariant rc = pick_rows(p->log_c, p->rows_half, kRowConj);
+  const dim3 rgrid(fft_grid(p, ra, lds_bytes_rows(p), rows_items(p, n)));
   hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 0,
                      p->log_c, p->rows_act);
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(ra.fn)), rgrid, dim3(ra.threads),
-                     lds_bytes_rows(p), st, P, ws, map, p->log_rr, twoF,
+                     lds_bytes_rows(p), st, P, ws, map, slots, p->log_rr, twoF,
                      static_cast<float2*>(nullptr), gin);
   hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 2,
                      p->log_c, int64_t(1) << p->log_rr);
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rc.fn)), rgrid, dim3(rc.threads),
-                     lds_bytes_rows(p), st, P, ws, map, p->log_rr, static_cast<float*>(nullptr),
+                     lds_bytes_rows(p), st, P, ws, map, slots, p->log_rr,
+                     static_cast<float*>(nullptr),
                      static_cast<float2*>(nullptr), static_cast<const float*>(nullptr));
-  hipLaunchKernelGGL(grad_kernel(p->desc.sinc_halfwidth), dim3(tiles, n), dim3(kResThreads), 0,
-                     st, P, ws);
+  hipLaunchKernelGGL(grad_kernel(p->desc.sinc_halfwidth, false), dim3(tiles, n),
+                     dim3(kResThreads), 0, st, P, ws);
   hipLaunchKernelGGL(k_grad_final, dim3((n * kGradParams + 63) / 64), dim3(64), 0, st, P, ws, map,
                      int64_t(tiles), grad);
   return check_hip(hipGetLastError(), "adjoint launch");
@@ -496,17 +585,29 @@ bool same_timing(const double* a, const double* b) {
   return a[6] == b[6] && a[7] == b[7];
 }
 
-size_t search_ws_bytes(const fstat_search* sr) {
+// Search workspace: header, template slots, group buffers, then one
+// parameter block per template.
+size_t search_params_offset(const fstat_search* sr) {
   const fstat_plan* p = sr->plan;
   return kHeaderBytes + size_t(sr->slots) * slot_bytes(p->desc.n_fft) +
          size_t(sr->slots) * group_bytes(p->k_pad);
+}
+size_t search_ws_bytes(const fstat_search* sr) {
+  return search_params_offset(sr) + size_t(sr->ntmpl) * kParamBytes;
 }
 
 fstat_status search_launch(fstat_search* sr, const fstat_inputs* in, const double* templates,
                            float* twoF, float2* fafb, void* ws, hipStream_t st, KernelTimer& tm) {
   const fstat_plan* p = sr->plan;
   PlanConst P = make_const(p, in);
-  hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, ws, p->desc.n_fft);
+  P.params = static_cast<char*>(ws) + search_params_offset(sr);
+  hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, ws);
+  fstat_status s0 = tm.mark(0);
+  if (s0 != FSTAT_OK) return s0;
+  const int64_t nt = std::max<int64_t>(sr->ntmpl, sr->slots);
+  hipLaunchKernelGGL(k_params, dim3(unsigned((nt + 63) / 64)), dim3(64), 0, st, P, templates,
+                     sr->ntmpl, ws, sr->slots);
+  if ((s0 = tm.mark(0)) != FSTAT_OK) return s0;
   for (const ChunkMap& map : sr->chunks) {
     fstat_status s =
         launch_chunk(p, P, templates, map, sr->slots, true, twoF, fafb, nullptr, ws, st, tm);
@@ -574,6 +675,14 @@ fstat_status fstat_search_create(const fstat_plan* plan, const double* templates
   }
   if (map.n_tmpl > 0) sr->chunks.push_back(map);
   sr->ngroups = group + 1;
+  // the row pass of chunk i clears the status words of the group buffers
+  // chunk i + 1 resamples (k_params clears them all for chunk 0)
+  for (size_t i = 0; i + 1 < sr->chunks.size(); ++i) {
+    ChunkMap& cur = sr->chunks[i];
+    const ChunkMap& nx = sr->chunks[i + 1];
+    cur.n_reset = nx.n_grp;
+    for (int k = 0; k < nx.n_grp; ++k) cur.reset_buf[k] = nx.grp_buf[k];
+  }
   *out = sr;
   return ok();
 }
@@ -682,6 +791,10 @@ fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out) {
                 "tune_col_lines=%d / tune_row_lines=%d: accepted 0, %d or %d / 0, %d or %d", tc,
                 tr, cmax, cmax / 2, rmax, rmax / 2);
   }
+  if (desc->tune_fft_grid != 0 && desc->tune_fft_grid != 1) {
+    delete p;
+    return fail(FSTAT_EINVAL, "tune_fft_grid=%d: accepted 0 or 1", desc->tune_fft_grid);
+  }
   p->cols_half = tc == cmax / 2 && cmax > 1;
   p->rows_half = tr == rmax / 2 && rmax > 1;
   p->cols_lines = p->cols_half ? cmax / 2 : cmax;
@@ -776,6 +889,77 @@ fstat_status fstat_compute_2f_profiled(const fstat_plan* plan, const fstat_input
   return finish_timer(tm, static_cast<hipStream_t>(stream), kernel_ms, launches);
 }
 
+fstat_status fstat_autotune(const fstat_plan_desc* desc, const fstat_inputs* in,
+                            const double* templates, int64_t ntmpl, float* twoF, void* workspace,
+                            size_t ws_bytes, void* stream, fstat_plan_desc* best,
+                            float* best_ms) {
+  if (!best || !best_ms) return fail(FSTAT_EINVAL, "best or best_ms is NULL");
+  fstat_status s = validate_desc(desc);
+  if (s != FSTAT_OK) return s;
+  if (ntmpl < 1 || !templates || !twoF) return fail(FSTAT_EINVAL, "need ntmpl >= 1 sample templates and twoF");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((s = check_hip(hipEventCreate(&e0), "event")) != FSTAT_OK) return s;
+  if ((s = check_hip(hipEventCreate(&e1), "event")) != FSTAT_OK) {
+    (void)hipEventDestroy(e0);
+    return s;
+  }
+  const int log_n = ilog2(desc->n_fft);
+  const int splits[2] = {log_n / 2, (log_n + 1) / 2};
+  float best_t = INFINITY;
+  fstat_plan_desc cand_best = *desc;
+  fstat_status last = FSTAT_OK;
+  std::string last_msg;
+  for (int si = 0; si < 2; ++si) {
+    if (si == 1 && splits[1] == splits[0]) break;
+    const int lr = splits[si], lc = log_n - lr;
+    if (lr < 6 || lr > 12 || lc < 6 || lc > 12) continue;
+    for (int ch = 0; ch < 2; ++ch)
+      for (int rh = 0; rh < 2; ++rh)
+        for (int grid = 0; grid < 2; ++grid) {
+          fstat_plan_desc d = *desc;
+          d.tune_col_log_len = lr;
+          d.tune_col_lines = ch ? cols_lines_max(lr) / 2 : 0;
+          d.tune_row_lines = rh ? rows_lines_max(lc) / 2 : 0;
+          d.tune_fft_grid = grid;
+          if ((ch && d.tune_col_lines < 1) || (rh && d.tune_row_lines < 1)) continue;
+          fstat_plan* p = nullptr;
+          if (fstat_plan_create(&d, &p) != FSTAT_OK) continue;
+          float ms = INFINITY;
+          // one untimed run, then one timed with events on the stream
+          fstat_status r = run(p, in, templates, ntmpl, twoF, nullptr, nullptr, workspace,
+                               ws_bytes, stream, int64_t(1) << 40);
+          if (r == FSTAT_OK) r = check_hip(hipEventRecord(e0, st), "event record");
+          if (r == FSTAT_OK)
+            r = run(p, in, templates, ntmpl, twoF, nullptr, nullptr, workspace, ws_bytes,
+                    stream, int64_t(1) << 40);
+          if (r == FSTAT_OK) r = check_hip(hipEventRecord(e1, st), "event record");
+          if (r == FSTAT_OK) r = check_hip(hipEventSynchronize(e1), "event synchronise");
+          if (r == FSTAT_OK) r = check_hip(hipEventElapsedTime(&ms, e0, e1), "event time");
+          fstat_plan_destroy(p);
+          if (r != FSTAT_OK) {
+            last = r;
+            last_msg = g_err;
+            if (r == FSTAT_EHIP) break;
+            continue;
+          }
+          if (ms < best_t) {
+            best_t = ms;
+            cand_best = d;
+          }
+        }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!(best_t < INFINITY)) {
+    return fail(last != FSTAT_OK ? last : FSTAT_EINVAL, "autotune: no launch shape ran (%s)",
+                last_msg.c_str());
+  }
+  *best = cand_best;
+  *best_ms = best_t;
+  return ok();
+}
+
 fstat_status fstat_resample(const fstat_plan* plan, const fstat_inputs* in,
                             const double* templates, int64_t ntmpl, void* y, void* workspace,
                             size_t ws_bytes, void* stream) {
@@ -812,9 +996,9 @@ fstat_status fstat_compute_2f_grad(const fstat_plan* plan, const fstat_inputs* i
   if ((s = set_lds_limits(plan)) != FSTAT_OK) return s;
   PlanConst P = make_const(plan, in);
   P.slot_stride = int64_t(sb);
+  P.part_offset = int64_t(kParamBytes + size_t(4) * plan->desc.n_fft * sizeof(float2));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, workspace,
-                     plan->desc.n_fft);
+  hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, workspace);
   for (int64_t t = 0; t < ntmpl; t += slots) {
     ChunkMap map;
     std::memset(&map, 0, sizeof map);
@@ -822,6 +1006,49 @@ fstat_status fstat_compute_2f_grad(const fstat_plan* plan, const fstat_inputs* i
     for (int i = 0; i < map.n_tmpl; ++i) map.tmpl[i] = t + i;
     s = launch_grad_chunk(plan, P, templates, map, int(slots), grad_twoF, grad, twoF, workspace,
                           st);
+    if (s != FSTAT_OK) return s;
+  }
+  return ok();
+}
+
+fstat_status fstat_grad_bin_workspace_size(const fstat_plan* plan, int64_t batch,
+                                           size_t* bytes) {
+  if (!plan || !bytes) return fail(FSTAT_EINVAL, "plan or bytes is NULL");
+  if (batch < 1) return fail(FSTAT_EINVAL, "batch must be >= 1");
+  *bytes = kHeaderBytes + size_t(batch) * grad_bin_slot_bytes(plan);
+  return ok();
+}
+
+fstat_status fstat_compute_2f_grad_bin(const fstat_plan* plan, const fstat_inputs* in,
+                                       const double* templates, int64_t ntmpl,
+                                       const int64_t* bins, float* twoF, double* grad,
+                                       void* workspace, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(FSTAT_EINVAL, "plan is NULL");
+  if (ntmpl < 0) return fail(FSTAT_EINVAL, "ntmpl < 0");
+  if (ntmpl > 0 && (!templates || !bins || !grad))
+    return fail(FSTAT_EINVAL, "templates, bins or grad is NULL");
+  fstat_status s = validate_inputs(plan, in, true);
+  if (s != FSTAT_OK) return s;
+  if (!workspace) return fail(FSTAT_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(FSTAT_EINVAL, "workspace must be 256-byte aligned");
+  const size_t sb = grad_bin_slot_bytes(plan);
+  if (ws_bytes < kHeaderBytes + sb)
+    return fail(FSTAT_EWORKSPACE, "workspace %zu bytes < %zu needed for one template", ws_bytes,
+                kHeaderBytes + sb);
+  if (ntmpl == 0) return ok();
+  const int64_t slots = std::min<int64_t>(int64_t((ws_bytes - kHeaderBytes) / sb), kMaxSlots);
+  PlanConst P = make_const(plan, in);
+  P.slot_stride = int64_t(sb);
+  P.part_offset = int64_t(kParamBytes);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int64_t t = 0; t < ntmpl; t += slots) {
+    ChunkMap map;
+    std::memset(&map, 0, sizeof map);
+    map.n_tmpl = int(std::min<int64_t>(slots, ntmpl - t));
+    for (int i = 0; i < map.n_tmpl; ++i) map.tmpl[i] = t + i;
+    s = launch_grad_bin_chunk(plan, P, templates, map, int(slots), bins, twoF, grad, workspace,
+                              st);
     if (s != FSTAT_OK) return s;
   }
   return ok();

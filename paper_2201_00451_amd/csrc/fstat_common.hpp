@@ -51,6 +51,9 @@ struct PlanConst {
   int64_t n_fft, bin_lo, n_bins;
   int64_t k_pad;        // grid points computed by the resampler (multiple of tile and row)
   int64_t slot_stride;  // bytes per template slot of the workspace (path dependent)
+  int64_t part_offset;  // adjoint paths: bytes from a slot's start to its tile partials
+  char* params;         // search path: per-template parameter blocks (kParamBytes
+                        // each, by template index); null: the slots' own blocks
   int64_t n_eph;
   double eph_t0, eph_dt, inv_eph_dt;
   const double* moments;
@@ -75,6 +78,17 @@ struct TmplParams {
   float dca[2][kMaxDet][5];
   float dcb[2][kMaxDet][5];
   double porb;
+  // Adjoint: a constant subtracted from the input-side delay derivatives
+  // d delta_j / d(alpha, delta) (their value for detector 0 at the middle of
+  // the grid).  A constant c contributes -2 pi i f_h c y'_k to dy'_k, whose
+  // share of the gradient, 8 pi f_h c Im sum_k X_k y'_k = 8 pi f_h c
+  // Im sum_m g_m |F'_m|^2, is exactly zero; removing it before rounding to
+  // FP32 keeps the ~3e5 rad/rad sky phase derivative from cancelling in FP32.
+  double dshift[2];
+  // Single-bin adjoint only: natural FFT index of the template's bin and the
+  // adjoint spectrum there, conj(Fa'), conj(Fb') (re, im, re, im).
+  int64_t bin_nat;
+  double hbin[4];
 };
 
 // Status bits of a template (any bit: NaN in every output bin).
@@ -83,6 +97,7 @@ constexpr int32_t kStatusCoverage = 2;  // delays exceed the plan's max_delay
 constexpr int32_t kStatusWindow = 4;    // a tile's input window overflowed the staging
 constexpr int32_t kStatusNodes = 8;     // a delay evaluation left the staged ephemeris
 constexpr int32_t kStatusPhase = 16;    // non-finite spin-down or sub-bin parameters
+constexpr int32_t kStatusBin = 32;      // single-bin path: bin outside the band
 // Bits that concern the resampled series of a sky/orbit group.
 constexpr int32_t kStatusGroupMask = kStatusTiming | kStatusCoverage | kStatusWindow | kStatusNodes;
 
@@ -96,13 +111,15 @@ struct ChunkMap {
   int32_t tmpl_buf[kMaxSlots];  // group buffer slot s reads (grouped path)
   int32_t grp_slot[kMaxSlots];  // slot holding the parameters of resampled group i
   int32_t grp_buf[kMaxSlots];   // group buffer resampled group i writes
+  int32_t n_reset;              // grouped path: group buffers whose status word the
+  int32_t reset_buf[kMaxSlots]; //   row pass clears for the next chunk's resampling
 };
 
 constexpr size_t kParamBytes = 1024;
 static_assert(sizeof(TmplParams) <= kParamBytes, "param block");
-// Workspace header: moment partials, then FP32 twiddle tables written from
-// FP64 at the start of every call: W_4096^e (stage twiddles of every line
-// length <= 4096) and the two levels of W_N^e = W_N^{e mod 4096} W_N^{4096 (e div 4096)}.
+// Workspace header: moment partials, then the FP32 twiddle table W_4096^e
+// (stage twiddles of every line length <= 4096) written from FP64 at the
+// start of every call, and reserved space.
 constexpr int kTwLen = 4096;
 constexpr size_t kMomentBytes = size_t(kMaxDet) * kMomBlocks * 10 * sizeof(double);
 constexpr size_t kTwOffset = kMomentBytes;
@@ -110,8 +127,6 @@ constexpr size_t kHeaderBytes = kTwOffset + 3 * kTwLen * sizeof(float2) + 4096;
 __host__ __device__ inline float2* tw_stage(void* ws) {
   return reinterpret_cast<float2*>(static_cast<char*>(ws) + kTwOffset);
 }
-__host__ __device__ inline float2* tw_lo(void* ws) { return tw_stage(ws) + kTwLen; }
-__host__ __device__ inline float2* tw_hi(void* ws) { return tw_stage(ws) + 2 * kTwLen; }
 
 // Workspace: header (moment partials, twiddles), then template slots of
 // [TmplParams | narr arrays of n_fft float2 | extra bytes], narr = 2 for the
@@ -126,14 +141,21 @@ __host__ __device__ inline char* slot_base(void* ws, const PlanConst& P, int g) 
 __host__ __device__ inline TmplParams* slot_params(void* ws, const PlanConst& P, int g) {
   return reinterpret_cast<TmplParams*>(slot_base(ws, P, g));
 }
+// Parameter block of the template in slot g: the slot's own, or on the search
+// path the template's block of the per-template array.
+__host__ __device__ inline TmplParams* tmpl_params(void* ws, const PlanConst& P,
+                                                  const ChunkMap& map, int g) {
+  return P.params ? reinterpret_cast<TmplParams*>(P.params + size_t(map.tmpl[g]) * kParamBytes)
+                  : slot_params(ws, P, g);
+}
 __host__ __device__ inline float2* slot_buf(void* ws, const PlanConst& P, int g, int arr) {
   return reinterpret_cast<float2*>(slot_base(ws, P, g) + kParamBytes) + size_t(arr) * P.n_fft;
 }
-// Adjoint: per-tile partial sums of the 7 gradient components (8 doubles per
-// tile), after the four arrays of the slot.
+// Adjoint paths: per-tile partial sums (8 doubles per tile) at part_offset
+// from the slot's start (after the four arrays of the general adjoint, right
+// after the parameter block on the single-bin path).
 __host__ __device__ inline double* slot_partials(void* ws, const PlanConst& P, int g) {
-  return reinterpret_cast<double*>(slot_base(ws, P, g) + kParamBytes +
-                                   size_t(4) * P.n_fft * sizeof(float2));
+  return reinterpret_cast<double*>(slot_base(ws, P, g) + P.part_offset);
 }
 
 // Grouped path: after `slots` template slots come group buffers of
@@ -153,6 +175,22 @@ __host__ __device__ inline float2* group_buf(void* ws, const PlanConst& P, int s
                                              int arr) {
   return reinterpret_cast<float2*>(group_base(ws, P, slots, b) + kGroupHeader) +
          size_t(arr) * P.k_pad;
+}
+
+// Raw buffer access (gfx9 buffer descriptor): a 32-bit per-lane byte offset
+// plus a uniform one, so a run of loads shares one address register; a load
+// at or past num_bytes returns zero without touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t num_bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(num_bytes), 0x00020000);
+}
+__device__ __forceinline__ float2 buf_load2(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                            uint32_t soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store2(float2 x, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                           uint32_t soff) {
+  using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), r, voff, soff, 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -10,11 +10,9 @@
 //     frequency: output index (m + N/2) mod N).
 // Inside a pass, lines are transformed in LDS by a mixed-radix Stockham
 // autosort: every thread holds whole radix-R butterflies (R <= 16) in
-// registers.  Twiddles come from FP32 tables written from FP64 once per call.
-// The HBM traffic is one read and one write of the series per pass.
-// Workgroups are remapped so that the ones an XCD runs together handle
-// neighbouring columns (rows), whose partial cache lines then meet in that
-// XCD's L2.
+// registers.  Stage twiddles come from an FP32 table written from FP64 once
+// per call and copied to LDS; the four-step twiddles from sincospi.  The HBM
+// traffic is one read and one write of the series per pass.
 #pragma once
 
 #include "fstat_common.hpp"
@@ -88,14 +86,6 @@ __host__ __device__ constexpr int stage_logp(int logl, int s) {
   return s == 0 ? 0 : stage_logp(logl, s - 1) + stage_logr(logl, s - 1);
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs: give the ones an
-// XCD holds at the same time consecutive logical indices.
-__device__ inline uint32_t xcd_remap(uint32_t id, uint32_t total) {
-  const uint32_t full = total & ~7u;
-  if (id >= full) return id;
-  return (id & 7u) * (full >> 3) + (id >> 3);
-}
-
 // LDS layout of NL lines of length L: line-major with one pad element every
 // 16 and an odd-ish pitch, addr(idx, line) = line * pitch + idx + idx / 16,
 // pitch = L + L / 16 + 1.  Consecutive butterflies of a stage, consecutive
@@ -109,14 +99,21 @@ struct LdsLayout {
   }
 };
 
-// Butterfly of a Stockham stage with P > 1: twiddle W_{PR}^{jk} (table
-// W_4096^{jk 4096/(PR)}), then the R-point DFT in registers.
-template <int R, int P>
-__device__ __forceinline__ void twiddle_dft(float2 (&v)[R], int k, const float2* __restrict__ tw) {
+// W_L^e from the LDS half table T[e] = W_L^e, e < L/2 (W_L^{e+L/2} = -W_L^e).
+template <int L>
+__device__ __forceinline__ float2 tw_half(const float2* twl, int e) {
+  const float2 w = twl[e & (L / 2 - 1)];
+  return e < L / 2 ? w : make_float2(-w.x, -w.y);
+}
+
+// Butterfly of a Stockham stage with P > 1: twiddle W_{PR}^{jk} = W_L^{jk L/(PR)},
+// then the R-point DFT in registers.
+template <int R, int P, int L>
+__device__ __forceinline__ void twiddle_dft(float2 (&v)[R], int k, const float2* twl) {
   if constexpr (P > 1) {
-    constexpr int TWS = kTwLen / (P * R);
+    constexpr int TWS = L / (P * R);
 #pragma unroll
-    for (int j = 1; j < R; ++j) v[j] = cmul(v[j], tw[j * k * TWS]);
+    for (int j = 1; j < R; ++j) v[j] = cmul(v[j], tw_half<L>(twl, j * k * TWS));
   }
   dft<R>(v);
 }
@@ -125,7 +122,7 @@ __device__ __forceinline__ void twiddle_dft(float2 (&v)[R], int k, const float2*
 // index i = b mod (L/R) of line b div (L/R); reads finish (barrier) before
 // the in-place writes, which finish (barrier) before the next stage.
 template <int LOGL, int NL, int NT, int S>
-__device__ __forceinline__ void fft_stage(float2* buf, const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft_stage(float2* buf, const float2* twl) {
   constexpr int LOGR = stage_logr(LOGL, S), R = 1 << LOGR;
   constexpr int P = 1 << stage_logp(LOGL, S);
   constexpr int L = 1 << LOGL;
@@ -151,7 +148,7 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* __restrict_
     if (NB % NT == 0 || b < NB) {
       const int i = b % NBL, line = b / NBL;
       const int k = i & (P - 1);
-      twiddle_dft<R, P>(v[s], k, tw);
+      twiddle_dft<R, P, L>(v[s], k, twl);
       const int base = (i - k) * R + k;
 #pragma unroll
       for (int m = 0; m < R; ++m) buf[Lay::at(base + m * P, line)] = v[s][m];
@@ -162,28 +159,51 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* __restrict_
 
 // Middle stages 1 .. last-1.
 template <int LOGL, int NL, int NT, int S>
-__device__ __forceinline__ void fft_middle(float2* buf, const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft_middle(float2* buf, const float2* twl) {
   if constexpr (S < stage_count(LOGL) - 1) {
-    fft_stage<LOGL, NL, NT, S>(buf, tw);
-    fft_middle<LOGL, NL, NT, S + 1>(buf, tw);
+    fft_stage<LOGL, NL, NT, S>(buf, twl);
+    fft_middle<LOGL, NL, NT, S + 1>(buf, twl);
   }
 }
 
-// FP32 twiddle tables from FP64 (see the workspace header layout).
-__global__ void k_twiddles(void* ws, int64_t n_fft) {
+// FP32 stage twiddle table W_4096^e from FP64, written at the start of every
+// call; each FFT workgroup copies the W_L^e, e < L/2, it needs into LDS.
+__global__ void k_twiddles(void* ws) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= kTwLen) return;
   double s, c;
   sincospi(-2.0 * double(e) / double(kTwLen), &s, &c);
   tw_stage(ws)[e] = make_float2(float(c), float(s));
-  sincospi(-2.0 * double(e) / double(n_fft), &s, &c);
-  tw_lo(ws)[e] = make_float2(float(c), float(s));
-  const int64_t eh = int64_t(e) * kTwLen;
-  if (eh < n_fft) {
-    sincospi(-2.0 * double(eh) / double(n_fft), &s, &c);
-    tw_hi(ws)[e] = make_float2(float(c), float(s));
-  }
 }
+
+// W_N^e for 0 <= e < N <= 2^24 (e / N is exact in FP32).
+__device__ __forceinline__ float2 tw_n(int64_t e, int64_t n_fft) {
+  float s, c;
+  sincospif(-2.0f * (float(e) / float(n_fft)), &s, &c);
+  return make_float2(c, s);
+}
+
+// Bytes of LDS a pass with NL lines of 2^LOGL uses: the padded lines plus the
+// half twiddle table.
+__host__ __device__ constexpr size_t fft_lds_bytes(int logl, int nl) {
+  return (size_t(nl) * size_t((1 << logl) + (1 << logl) / 16 + 1) + size_t(1 << logl) / 2) *
+         sizeof(float2);
+}
+
+// Both passes are persistent: workgroup w transforms work items w, w + G,
+// w + 2G, ... (G = gridDim.x; with G = number of items every workgroup takes
+// one).  The first stage's HBM loads of the next item are issued before the
+// current item is transformed, so they are in flight during its LDS stages
+// and stores; the transform itself reads no global memory (stage twiddles
+// from LDS, four-step twiddles from sincospi), so nothing waits on them early.
+// Item order is template slot fastest: the templates of one sky/orbit group
+// read the same group series at about the same time.
+
+struct ColItem {
+  int live, g, arr;
+  int64_t c0;
+  double f1dot, f2dot, df;
+};
 
 // Column pass: lines are NL consecutive columns [c0, c0 + NL) of one array of
 // one template slot; line length Rr = 2^LOGL.  Rows at or beyond rows_act are
@@ -191,10 +211,58 @@ __global__ void k_twiddles(void* ws, int64_t n_fft) {
 // straight from HBM and the last one writes its outputs, times the four-step
 // twiddle W_N^{q c}, straight back (both with columns fastest across
 // threads: NL-element contiguous runs); only the middle stages go through
-// LDS.  Grid: (C / NL) x 2 arrays x template slots.
+// LDS.  Items: (C / NL column groups) x 2 arrays x template slots.
 // GROUPED: the input is the unphased series of the slot's sky/orbit group;
 // stage 0 applies the template's spin-down phase while loading and the
 // output goes to the slot's own buffer.
+template <int LOGL, int NL, int NT, bool GROUPED>
+__device__ __forceinline__ ColItem cols_fetch(const PlanConst& P, void* ws, const ChunkMap& map,
+                                              int slots, int arr_base, int64_t C,
+                                              int64_t rows_act, int item, int n_items,
+                                              float2 (&v)[((NL << LOGL) / (1 << stage_logr(LOGL, 0)) + NT - 1) / NT]
+                                                         [1 << stage_logr(LOGL, 0)]) {
+  constexpr int L = 1 << LOGL;
+  constexpr int R0 = 1 << stage_logr(LOGL, 0), NB0 = NL * (L / R0);
+  constexpr int PER = (NB0 + NT - 1) / NT;
+  ColItem it;
+  it.live = 0;
+  if (item >= n_items) return it;
+  const int n = map.n_tmpl;
+  it.g = item % n;
+  const int rest = item / n;
+  it.arr = rest & 1;
+  it.c0 = int64_t(rest >> 1) * NL;
+  TmplParams* tpp = tmpl_params(ws, P, map, it.g);
+  int32_t status = tpp->status;
+  if (GROUPED) {
+    const int32_t gs = *group_status(ws, P, slots, map.tmpl_buf[it.g]);
+    if (gs != 0 && threadIdx.x == 0) atomicOr(&tpp->status, gs);
+    status |= gs;
+  }
+  if (status != 0) return it;
+  it.live = 1;
+  it.f1dot = tpp->f1dot;
+  it.f2dot = tpp->f2dot;
+  it.df = tpp->df;
+  const float2* src = GROUPED ? group_buf(ws, P, slots, map.tmpl_buf[it.g], it.arr)
+                              : slot_buf(ws, P, it.g, arr_base + it.arr);
+  // rows at or beyond rows_act lie past the descriptor's end and read as zero
+  const auto rs = buf_rsrc(src, uint32_t(rows_act * C * int64_t(sizeof(float2))));
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int b = tid + s * NT;
+    if (NB0 % NT == 0 || b < NB0) {
+      const int line = b % NL, i = b / NL;
+      const uint32_t voff = uint32_t((int64_t(i) * C + it.c0 + line) * int64_t(sizeof(float2)));
+#pragma unroll
+      for (int j = 0; j < R0; ++j)
+        v[s][j] = buf_load2(rs, voff, uint32_t(int64_t(j) * (L / R0) * C * int64_t(sizeof(float2))));
+    }
+  }
+  return it;
+}
+
 template <int LOGL, int NL, int NT, bool GROUPED>
 __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap map, int slots,
                                                  int arr_base, int log_c, int64_t rows_act) {
@@ -203,93 +271,83 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
   constexpr int NS = stage_count(LOGL);
   constexpr int R0 = 1 << stage_logr(LOGL, 0), NB0 = NL * (L / R0);
   constexpr int RL = 1 << stage_logr(LOGL, NS - 1), PL = L / RL, NBL = NL * PL;
+  constexpr int PER0 = (NB0 + NT - 1) / NT;
   using Lay = LdsLayout<L>;
-  const uint32_t total = gridDim.x * gridDim.y * gridDim.z;
-  const uint32_t id = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
-                                total);
-  const uint32_t gx = id % gridDim.x, rest = id / gridDim.x;
-  const int arr = int(rest % gridDim.y), g = int(rest / gridDim.y);
-  TmplParams* tpp = slot_params(ws, P, g);
-  int32_t status = tpp->status;
-  if (GROUPED) {
-    const int32_t gs = *group_status(ws, P, slots, map.tmpl_buf[g]);
-    if (gs != 0 && threadIdx.x == 0) atomicOr(&tpp->status, gs);
-    status |= gs;
-  }
-  if (status != 0) return;
-  const int64_t C = int64_t(1) << log_c;
-  const int64_t c0 = int64_t(gx) * NL;
-  float2* buf = slot_buf(ws, P, g, arr_base + arr);
-  const float2* src =
-      GROUPED ? group_buf(ws, P, slots, map.tmpl_buf[g], arr) : buf;
-  const double f1dot = tpp->f1dot, f2dot = tpp->f2dot, df = tpp->df;
-  const float2* __restrict__ tw = tw_stage(ws);
+  float2* twl = lds + NL * Lay::pitch;
   const int tid = threadIdx.x;
-  // stage 0: HBM -> registers -> DFT -> LDS
+  const int64_t C = int64_t(1) << log_c;
+  const int n_items = int(C / NL) * 2 * map.n_tmpl;
+  const int64_t nmask = P.n_fft - 1;
   {
-    constexpr int PER = (NB0 + NT - 1) / NT;
-    float2 v[PER][R0];
+    const float2* __restrict__ tws = tw_stage(ws);
+    for (int e = tid; e < L / 2; e += NT) twl[e] = tws[e * (kTwLen / L)];
+  }
+  int item = blockIdx.x;
+  float2 v[PER0][R0];
+  ColItem it = cols_fetch<LOGL, NL, NT, GROUPED>(P, ws, map, slots, arr_base, C, rows_act, item,
+                                                 n_items, v);
+  while (item < n_items) {
+    const int next = item + int(gridDim.x);
+    float2 vn[PER0][R0];
+    const ColItem nt = cols_fetch<LOGL, NL, NT, GROUPED>(P, ws, map, slots, arr_base, C,
+                                                         rows_act, next, n_items, vn);
+    if (it.live) {
+      const auto wr = buf_rsrc(slot_buf(ws, P, it.g, arr_base + it.arr),
+                               uint32_t(P.n_fft * int64_t(sizeof(float2))));
+      // stage 0: registers -> DFT -> LDS
 #pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int b = tid + s * NT;
-      if (NB0 % NT == 0 || b < NB0) {
-        const int line = b % NL, i = b / NL;
+      for (int s = 0; s < PER0; ++s) {
+        const int b = tid + s * NT;
+        if (NB0 % NT == 0 || b < NB0) {
+          const int line = b % NL, i = b / NL;
+          if (GROUPED) {
 #pragma unroll
-        for (int j = 0; j < R0; ++j) {
-          const int r = i + j * (L / R0);
-          v[s][j] = r < rows_act ? src[int64_t(r) * C + c0 + line] : make_float2(0.f, 0.f);
+            for (int j = 0; j < R0; ++j) {
+              const int r = i + j * (L / R0);
+              if (r < rows_act)
+                v[s][j] = cmul_exact(v[s][j], spindown_rotation(P, it.f1dot, it.f2dot, it.df,
+                                                                int64_t(r) * C + it.c0 + line));
+            }
+          }
+          dft<R0>(v[s]);
+#pragma unroll
+          for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
         }
       }
-    }
+      __syncthreads();
+      fft_middle<LOGL, NL, NT, 1>(lds, twl);
+      // last stage: LDS -> registers -> DFT -> x W_N^{q c} -> HBM
+      constexpr int PER = (NBL + NT - 1) / NT;
 #pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int b = tid + s * NT;
-      if (NB0 % NT == 0 || b < NB0) {
-        const int line = b % NL, i = b / NL;
-        if (GROUPED) {
+      for (int s = 0; s < PER; ++s) {
+        const int b = tid + s * NT;
+        if (NBL % NT == 0 || b < NBL) {
+          const int line = b % NL, i = b / NL;
+          float2 u[RL];
 #pragma unroll
-          for (int j = 0; j < R0; ++j) {
-            const int r = i + j * (L / R0);
-            if (r < rows_act)
-              v[s][j] = cmul_exact(
-                  v[s][j], spindown_rotation(P, f1dot, f2dot, df, int64_t(r) * C + c0 + line));
+          for (int j = 0; j < RL; ++j) u[j] = lds[Lay::at(i + j * PL, line)];
+          twiddle_dft<RL, PL, L>(u, i, twl);
+          const int64_t c = it.c0 + line;
+          // W_N^{c (i + m PL)} = W_N^{c i} (W_N^{c PL})^m
+          float2 w = tw_n((int64_t(i) * c) & nmask, P.n_fft);
+          const float2 step = tw_n((int64_t(PL) * c) & nmask, P.n_fft);
+          const uint32_t voff = uint32_t((int64_t(i) * C + c) * int64_t(sizeof(float2)));
+#pragma unroll
+          for (int m = 0; m < RL; ++m) {
+            buf_store2(cmul(u[m], w), wr, voff,
+                       uint32_t(int64_t(m) * PL * C * int64_t(sizeof(float2))));
+            w = cmul(w, step);
           }
         }
-        dft<R0>(v[s]);
-#pragma unroll
-        for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
       }
+      __syncthreads();
     }
-  }
-  __syncthreads();
-  fft_middle<LOGL, NL, NT, 1>(lds, tw);
-  // last stage: LDS -> registers -> DFT -> x W_N^{q c} -> HBM
-  {
-    constexpr int PER = (NBL + NT - 1) / NT;
-    const int64_t nmask = P.n_fft - 1;
-    const float2* __restrict__ wlo = tw_lo(ws);
-    const float2* __restrict__ whi = tw_hi(ws);
 #pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int b = tid + s * NT;
-      if (NBL % NT == 0 || b < NBL) {
-        const int line = b % NL, i = b / NL;
-        float2 v[RL];
+    for (int s = 0; s < PER0; ++s)
 #pragma unroll
-        for (int j = 0; j < RL; ++j) v[j] = lds[Lay::at(i + j * PL, line)];
-        twiddle_dft<RL, PL>(v, i, tw);
-        const int64_t c = c0 + line;
-        // W_N^{c (i + m PL)} = W_N^{c i} (W_N^{c PL})^m
-        const int64_t e0 = (int64_t(i) * c) & nmask, e1 = (int64_t(PL) * c) & nmask;
-        float2 w = cmul(wlo[e0 & (kTwLen - 1)], whi[e0 >> 12]);
-        const float2 step = cmul(wlo[e1 & (kTwLen - 1)], whi[e1 >> 12]);
-#pragma unroll
-        for (int m = 0; m < RL; ++m) {
-          buf[int64_t(i + m * PL) * C + c] = cmul(v[m], w);
-          w = cmul(w, step);
-        }
-      }
-    }
+      for (int j = 0; j < R0; ++j) v[s][j] = vn[s][j];
+    it = nt;
+    item = next;
   }
 }
 
@@ -299,7 +357,7 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
 // line length C = 2^LOGL.  The first stage reads the rows straight from HBM
 // (contiguous across threads); the last stage transforms the a and b rows of
 // the same bins in one thread and writes 2F (rows fastest across threads:
-// RQ-element runs of the output).  Grid: (Rr / RQ) x templates.
+// RQ-element runs of the output).  Items: (Rr / RQ) row groups x template slots.
 // Row-pass epilogues: 2F (forward); the adjoint spectrum H = g conj(F') of
 // both arrays at every natural FFT index m (zero outside the band), written to
 // arrays 2 and 3 of the slot, with 2F if twoF is not null; or the complex
@@ -307,122 +365,171 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
 // index for indices below k_pad (the inverse transform of the adjoint).
 enum RowMode { kRow2F = 0, kRowAdjoint = 1, kRowConj = 2 };
 
+struct RowItem {
+  int live, flagged, g;
+  int64_t q0, tmpl;
+  float l11, l21, l22;
+};
+
 template <int LOGL, int RQ, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap map, int log_rr,
-                                                 float* __restrict__ twoF, float2* fafb,
-                                                 const float* __restrict__ gin) {
+__device__ __forceinline__ RowItem rows_fetch(const PlanConst& P, void* ws, const ChunkMap& map,
+                                              int item, int n_items,
+                                              float2 (&v)[((2 * RQ << LOGL) / (1 << stage_logr(LOGL, 0)) + NT - 1) / NT]
+                                                         [1 << stage_logr(LOGL, 0)]) {
+  constexpr int L = 1 << LOGL;
+  constexpr int NL = 2 * RQ;
+  constexpr int R0 = 1 << stage_logr(LOGL, 0), NBL0 = L / R0, NB0 = NL * NBL0;
+  constexpr int PER = (NB0 + NT - 1) / NT;
+  RowItem it;
+  it.live = it.flagged = 0;
+  if (item >= n_items) return it;
+  const int n = map.n_tmpl;
+  it.g = item % n;
+  it.q0 = int64_t(item / n) * RQ;
+  it.tmpl = map.tmpl[it.g];
+  const TmplParams& tp = *tmpl_params(ws, P, map, it.g);
+  if (tp.status != 0) {
+    it.flagged = 1;
+    return it;
+  }
+  it.live = 1;
+  it.l11 = tp.l11;
+  it.l21 = tp.l21;
+  it.l22 = tp.l22;
+  // arrays a and b of the slot are adjacent: one descriptor covers both
+  const auto rs = buf_rsrc(slot_buf(ws, P, it.g, MODE == kRowConj ? 2 : 0),
+                           uint32_t(2 * P.n_fft * int64_t(sizeof(float2))));
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int b = tid + s * NT;
+    if (NB0 % NT == 0 || b < NB0) {
+      const int i = b % NBL0, line = b / NBL0;
+      const int64_t e0 = (line < RQ ? 0 : P.n_fft) + (it.q0 + line % RQ) * L + i;
+      const uint32_t voff = uint32_t(e0 * int64_t(sizeof(float2)));
+#pragma unroll
+      for (int j = 0; j < R0; ++j)
+        v[s][j] = buf_load2(rs, voff, uint32_t(j * NBL0 * int(sizeof(float2))));
+    }
+  }
+  return it;
+}
+
+template <int LOGL, int RQ, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap map, int slots,
+                                                 int log_rr, float* __restrict__ twoF,
+                                                 float2* fafb, const float* __restrict__ gin) {
   extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
   constexpr int NL = 2 * RQ;
   constexpr int NS = stage_count(LOGL);
   constexpr int R0 = 1 << stage_logr(LOGL, 0), NBL0 = L / R0, NB0 = NL * NBL0;
   constexpr int RL = 1 << stage_logr(LOGL, NS - 1), PL = L / RL, NBL = RQ * PL;
+  constexpr int PER0 = (NB0 + NT - 1) / NT;
   using Lay = LdsLayout<L>;
-  const uint32_t total = gridDim.x * gridDim.y;
-  const uint32_t id = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, total);
-  const uint32_t gx = id % gridDim.x;
-  const int g = int(id / gridDim.x);
-  const TmplParams& tp = *slot_params(ws, P, g);
-  const int64_t tmpl = map.tmpl[g];
-  const int64_t q0 = int64_t(gx) * RQ;
+  float2* twl = lds + NL * Lay::pitch;
   const int64_t Rr = int64_t(1) << log_rr;
   const int64_t N = P.n_fft;
-  const int status = tp.status;
-  const float2* __restrict__ tw = tw_stage(ws);
   const int tid = threadIdx.x;
+  const int n_items = int(Rr / RQ) * map.n_tmpl;
   const float qnan = __builtin_nanf("");
-  if (status != 0) {
-    if (MODE == kRowConj) return;
-    // flagged template: NaN in every bin it owns
-    for (int e = tid; e < L * RQ; e += NT) {
-      const int ql = e % RQ, p = e / RQ;
-      const int64_t i = (q0 + ql + Rr * p + N / 2) & (N - 1);
-      if (i < P.bin_lo || i >= P.bin_lo + P.n_bins) continue;
-      const int64_t o = i - P.bin_lo;
-      if (twoF) twoF[tmpl * P.n_bins + o] = qnan;
-      if (fafb) {
-        fafb[(tmpl * 2 + 0) * P.n_bins + o] = make_float2(qnan, qnan);
-        fafb[(tmpl * 2 + 1) * P.n_bins + o] = make_float2(qnan, qnan);
-      }
-    }
-    return;
-  }
-  // stage 0: HBM -> registers -> DFT -> LDS
+  // grouped path: every reader of the group buffers the next chunk resamples
+  // has finished (column pass of this chunk), so their status words restart
+  if (blockIdx.x == 0 && tid < map.n_reset) *group_status(ws, P, slots, map.reset_buf[tid]) = 0;
   {
-    const float2* ba = slot_buf(ws, P, g, MODE == kRowConj ? 2 : 0);
-    const float2* bb = slot_buf(ws, P, g, MODE == kRowConj ? 3 : 1);
-    constexpr int PER = (NB0 + NT - 1) / NT;
-    float2 v[PER][R0];
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int b = tid + s * NT;
-      if (NB0 % NT == 0 || b < NB0) {
-        const int i = b % NBL0, line = b / NBL0;
-        const float2* src = (line < RQ ? ba : bb) + (q0 + line % RQ) * L;
-#pragma unroll
-        for (int j = 0; j < R0; ++j) v[s][j] = src[i + j * NBL0];
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int b = tid + s * NT;
-      if (NB0 % NT == 0 || b < NB0) {
-        const int i = b % NBL0, line = b / NBL0;
-        dft<R0>(v[s]);
-#pragma unroll
-        for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
-      }
-    }
+    const float2* __restrict__ tws = tw_stage(ws);
+    for (int e = tid; e < L / 2; e += NT) twl[e] = tws[e * (kTwLen / L)];
   }
-  __syncthreads();
-  fft_middle<LOGL, NL, NT, 1>(lds, tw);
-  // last stage of both arrays + 2F
-  const float l11 = tp.l11, l21 = tp.l21, l22 = tp.l22;
-  constexpr int PER = (NBL + NT - 1) / NT;
-#pragma unroll
-  for (int s = 0; s < PER; ++s) {
-    const int b = tid + s * NT;
-    if (NBL % NT == 0 || b < NBL) {
-      const int ql = b % RQ, i = b / RQ;
-      float2 va[RL], vb[RL];
-#pragma unroll
-      for (int j = 0; j < RL; ++j) {
-        va[j] = lds[Lay::at(i + j * PL, ql)];
-        vb[j] = lds[Lay::at(i + j * PL, RQ + ql)];
-      }
-      twiddle_dft<RL, PL>(va, i, tw);
-      twiddle_dft<RL, PL>(vb, i, tw);
-#pragma unroll
-      for (int m = 0; m < RL; ++m) {
-        const int64_t nat = q0 + ql + Rr * int64_t(i + m * PL);
-        if (MODE == kRowConj) {
-          if (nat < P.k_pad) {
-            slot_buf(ws, P, g, 0)[nat] = make_float2(va[m].x, -va[m].y);
-            slot_buf(ws, P, g, 1)[nat] = make_float2(vb[m].x, -vb[m].y);
-          }
-          continue;
-        }
-        const int64_t ib = (nat + N / 2) & (N - 1);
-        const bool in_band = ib >= P.bin_lo && ib < P.bin_lo + P.n_bins;
-        const int64_t o = ib - P.bin_lo;
-        const float2 fa = va[m], fb = vb[m];
-        if (MODE == kRowAdjoint) {
-          const float gv = in_band ? gin[tmpl * P.n_bins + o] : 0.0f;
-          slot_buf(ws, P, g, 2)[nat] = make_float2(gv * fa.x, -gv * fa.y);
-          slot_buf(ws, P, g, 3)[nat] = make_float2(gv * fb.x, -gv * fb.y);
-        }
-        if (!in_band) continue;
-        if (twoF)
-          twoF[tmpl * P.n_bins + o] =
-              2.0f * ((fa.x * fa.x + fa.y * fa.y) + (fb.x * fb.x + fb.y * fb.y));
+  int item = blockIdx.x;
+  float2 v[PER0][R0];
+  RowItem it = rows_fetch<LOGL, RQ, NT, MODE>(P, ws, map, item, n_items, v);
+  while (item < n_items) {
+    const int next = item + int(gridDim.x);
+    float2 vn[PER0][R0];
+    const RowItem nt = rows_fetch<LOGL, RQ, NT, MODE>(P, ws, map, next, n_items, vn);
+    if (it.flagged && MODE != kRowConj) {
+      // flagged template: NaN in every bin this item owns
+      for (int e = tid; e < L * RQ; e += NT) {
+        const int ql = e % RQ, p = e / RQ;
+        const int64_t i = (it.q0 + ql + Rr * p + N / 2) & (N - 1);
+        if (i < P.bin_lo || i >= P.bin_lo + P.n_bins) continue;
+        const int64_t o = i - P.bin_lo;
+        if (twoF) twoF[it.tmpl * P.n_bins + o] = qnan;
         if (fafb) {
-          // undo the whitening: Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
-          fafb[(tmpl * 2 + 0) * P.n_bins + o] = cscale(fa, l11);
-          fafb[(tmpl * 2 + 1) * P.n_bins + o] =
-              make_float2(l21 * fa.x + l22 * fb.x, l21 * fa.y + l22 * fb.y);
+          fafb[(it.tmpl * 2 + 0) * P.n_bins + o] = make_float2(qnan, qnan);
+          fafb[(it.tmpl * 2 + 1) * P.n_bins + o] = make_float2(qnan, qnan);
         }
       }
     }
+    if (it.live) {
+      // stage 0: registers -> DFT -> LDS
+#pragma unroll
+      for (int s = 0; s < PER0; ++s) {
+        const int b = tid + s * NT;
+        if (NB0 % NT == 0 || b < NB0) {
+          const int i = b % NBL0, line = b / NBL0;
+          dft<R0>(v[s]);
+#pragma unroll
+          for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
+        }
+      }
+      __syncthreads();
+      fft_middle<LOGL, NL, NT, 1>(lds, twl);
+      // last stage of both arrays + epilogue
+      constexpr int PER = (NBL + NT - 1) / NT;
+#pragma unroll
+      for (int s = 0; s < PER; ++s) {
+        const int b = tid + s * NT;
+        if (NBL % NT == 0 || b < NBL) {
+          const int ql = b % RQ, i = b / RQ;
+          float2 va[RL], vb[RL];
+#pragma unroll
+          for (int j = 0; j < RL; ++j) {
+            va[j] = lds[Lay::at(i + j * PL, ql)];
+            vb[j] = lds[Lay::at(i + j * PL, RQ + ql)];
+          }
+          twiddle_dft<RL, PL, L>(va, i, twl);
+          twiddle_dft<RL, PL, L>(vb, i, twl);
+#pragma unroll
+          for (int m = 0; m < RL; ++m) {
+            const int64_t nat = it.q0 + ql + Rr * int64_t(i + m * PL);
+            if (MODE == kRowConj) {
+              if (nat < P.k_pad) {
+                slot_buf(ws, P, it.g, 0)[nat] = make_float2(va[m].x, -va[m].y);
+                slot_buf(ws, P, it.g, 1)[nat] = make_float2(vb[m].x, -vb[m].y);
+              }
+              continue;
+            }
+            const int64_t ib = (nat + N / 2) & (N - 1);
+            const bool in_band = ib >= P.bin_lo && ib < P.bin_lo + P.n_bins;
+            const int64_t o = ib - P.bin_lo;
+            const float2 fa = va[m], fb = vb[m];
+            if (MODE == kRowAdjoint) {
+              const float gv = in_band ? gin[it.tmpl * P.n_bins + o] : 0.0f;
+              slot_buf(ws, P, it.g, 2)[nat] = make_float2(gv * fa.x, -gv * fa.y);
+              slot_buf(ws, P, it.g, 3)[nat] = make_float2(gv * fb.x, -gv * fb.y);
+            }
+            if (!in_band) continue;
+            if (twoF)
+              twoF[it.tmpl * P.n_bins + o] =
+                  2.0f * ((fa.x * fa.x + fa.y * fa.y) + (fb.x * fb.x + fb.y * fb.y));
+            if (fafb) {
+              // undo the whitening: Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
+              fafb[(it.tmpl * 2 + 0) * P.n_bins + o] = cscale(fa, it.l11);
+              fafb[(it.tmpl * 2 + 1) * P.n_bins + o] =
+                  make_float2(it.l21 * fa.x + it.l22 * fb.x, it.l21 * fa.y + it.l22 * fb.y);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < PER0; ++s)
+#pragma unroll
+      for (int j = 0; j < R0; ++j) v[s][j] = vn[s][j];
+    it = nt;
+    item = next;
   }
 }
 
@@ -431,7 +538,7 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
 // whitening undone (y_a = l11 y_a', y_b = l21 y_a' + l22 y_b').
 __global__ void k_copy_series(PlanConst P, void* ws, ChunkMap map, float2* out) {
   const int g = blockIdx.y;
-  const TmplParams& tp = *slot_params(ws, P, g);
+  const TmplParams& tp = *tmpl_params(ws, P, map, g);
   const float2* sa = slot_buf(ws, P, g, 0);
   const float2* sb = slot_buf(ws, P, g, 1);
   float2* da = out + (map.tmpl[g] * 2 + 0) * P.n_fft;

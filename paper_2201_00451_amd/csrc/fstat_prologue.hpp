@@ -247,12 +247,9 @@ __host__ __device__ inline void template_params(const PlanConst& P, const double
   tp.status = status;
 }
 
-__global__ __launch_bounds__(64) void k_prologue(PlanConst P, const double* __restrict__ templates, ChunkMap map,
-                           int slots, void* ws) {
-  int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= map.n_tmpl) return;
-  const double* row = templates + map.tmpl[g] * FSTAT_TEMPLATE_STRIDE;
-  TmplParams tp;
+// Everything the kernels need about one template: template_params plus the
+// coverage check of the source-frame grid and the adjoint's sky shift.
+__device__ inline void full_params(const PlanConst& P, const double* row, TmplParams& tp) {
   template_params(P, row, tp);
   int status = tp.status;
   // Coverage: every sample's source time lies inside the computed grid, and
@@ -271,12 +268,38 @@ __global__ __launch_bounds__(64) void k_prologue(PlanConst P, const double* __re
     }
   }
   tp.status = status;
+  const double t_mid = P.tau0 + 0.5 * double(P.k_pad) * P.dt;
+  const DetConst& d0 = P.det[0];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const GlobalRoemer rq{d0.ephem, tp.dnhat[q], P.n_eph, P.eph_t0, P.eph_dt, P.inv_eph_dt};
+    double v, dv;
+    rq(t_mid, v, dv);
+    tp.dshift[q] = v;
+  }
+}
+
+// Parameter blocks of the templates of one chunk, into their slots.
+__global__ __launch_bounds__(64) void k_prologue(PlanConst P, const double* __restrict__ templates,
+                                                 ChunkMap map, void* ws) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= map.n_tmpl) return;
+  TmplParams tp;
+  full_params(P, templates + map.tmpl[g] * FSTAT_TEMPLATE_STRIDE, tp);
   *slot_params(ws, P, g) = tp;
-  // grouped path: a group resampled in this chunk starts from the status of
-  // the template whose parameters it uses
-  for (int i = 0; i < map.n_grp; ++i)
-    if (map.grp_slot[i] == g)
-      *group_status(ws, P, slots, map.grp_buf[i]) = status & kStatusGroupMask;
+}
+
+// Search path, once per run: the parameter blocks of all templates into the
+// per-template array P.params, and the status words of the group buffers
+// cleared for the first chunk.
+__global__ __launch_bounds__(64) void k_params(PlanConst P, const double* __restrict__ templates,
+                                               int64_t ntmpl, void* ws, int slots) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < slots) *group_status(ws, P, slots, int(t)) = 0;
+  if (t >= ntmpl) return;
+  TmplParams tp;
+  full_params(P, templates + t * FSTAT_TEMPLATE_STRIDE, tp);
+  *reinterpret_cast<TmplParams*>(P.params + size_t(t) * kParamBytes) = tp;
 }
 
 }  // namespace fstat

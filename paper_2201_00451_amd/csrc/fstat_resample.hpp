@@ -103,36 +103,25 @@ __host__ __device__ constexpr TapConst make_taps() {
 template <int D>
 __constant__ TapConst kTaps = make_taps<D>();
 
-// GROUPED = false: blockIdx.y is a template slot; the spin-down phase is
-// applied and y_a', y_b' go to the slot's buffers.  GROUPED = true: blockIdx.y
-// is a sky/orbit group of the chunk; the series is written without the
-// spin-down phase to the group's buffer, which every template of the group
-// reads (the reuse of the sky-dependent barycentring across spin-down
-// templates that Sec. 4.1 measures).
-template <int D, bool GROUPED>
-__global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws, ChunkMap map,
-                                                         int slots) {
-  const int gi = blockIdx.y;
-  const int slot = GROUPED ? map.grp_slot[gi] : gi;
-  const TmplParams& tp = *slot_params(ws, P, slot);
-  int32_t* status_word = GROUPED ? group_status(ws, P, slots, map.grp_buf[gi])
-                                 : &slot_params(ws, P, slot)->status;
-  float2* ya = GROUPED ? group_buf(ws, P, slots, map.grp_buf[gi], 0)
-                       : slot_buf(ws, P, slot, 0);
-  float2* yb = GROUPED ? group_buf(ws, P, slots, map.grp_buf[gi], 1)
-                       : slot_buf(ws, P, slot, 1);
-  const int64_t k_s = int64_t(blockIdx.x) * kResTile;
+// Steps (iii)-(v) and the antenna weighting for the kResTile grid points of
+// the tile starting at k_s: acc_a[i], acc_b[i] receive sum_X a'_X(T_k)
+// zhat_X(u_k) (and b'), k = k_s + tid + i kResThreads, before the spin-down
+// phase.  Returns false, after flagging the template's status word, when the
+// template must report NaN (the return is uniform across the block).
+template <int D>
+__device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
+                                     int32_t* status_word, int64_t k_s,
+                                     float2 (&acc_a)[kResPerThread],
+                                     float2 (&acc_b)[kResPerThread]) {
   const int tid = threadIdx.x;
-
   __shared__ float2 zs[kResWcap];
   __shared__ double2 nodes[kNodeCap];
   __shared__ int64_t win_lo, win_hi;
   __shared__ int bad;
 
-  if ((GROUPED ? (tp.status & kStatusGroupMask) : tp.status) != 0) return;
   if (tid == 0) bad = 0;
   bool oob = false;
-  float2 acc_a[kResPerThread], acc_b[kResPerThread];
+#pragma unroll
   for (int i = 0; i < kResPerThread; ++i) {
     acc_a[i] = make_float2(0.f, 0.f);
     acc_b[i] = make_float2(0.f, 0.f);
@@ -191,7 +180,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws,
     if (nwin > kResWcap || nwin < 2 * D) {
       // delay drift beyond 1/16 per tile: flag the template (NaN output)
       if (tid == 0) atomicOr(status_word, kStatusWindow);
-      return;
+      return false;
     }
     const int W = int(nwin);
     // 3. corrected input samples
@@ -260,11 +249,36 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws,
     // a delay evaluation left the staged ephemeris nodes: the delay exceeds
     // the plan's max_delay; flag the template (NaN output)
     if (tid == 0) atomicOr(status_word, kStatusNodes);
-    return;
+    return false;
   }
+  return true;
+}
+
+// GROUPED = false: blockIdx.y is a template slot; the spin-down phase is
+// applied and y_a', y_b' go to the slot's arrays 0 and 1.  GROUPED = true:
+// blockIdx.y is a sky/orbit group of the chunk; the series is written without
+// the spin-down phase to the group's buffer, which every template of the
+// group reads (the reuse of the sky-dependent barycentring across spin-down
+// templates that Sec. 4.1 measures).
+template <int D, bool GROUPED>
+__global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws, ChunkMap map,
+                                                         int slots) {
+  const int gi = blockIdx.y;
+  const int slot = GROUPED ? map.grp_slot[gi] : gi;
+  const TmplParams& tp = *tmpl_params(ws, P, map, slot);
+  int32_t* status_word = GROUPED ? group_status(ws, P, slots, map.grp_buf[gi])
+                                 : &tmpl_params(ws, P, map, slot)->status;
+  float2* ya = GROUPED ? group_buf(ws, P, slots, map.grp_buf[gi], 0)
+                       : slot_buf(ws, P, slot, 0);
+  float2* yb = GROUPED ? group_buf(ws, P, slots, map.grp_buf[gi], 1)
+                       : slot_buf(ws, P, slot, 1);
+  const int64_t k_s = int64_t(blockIdx.x) * kResTile;
+  if ((GROUPED ? (tp.status & kStatusGroupMask) : tp.status) != 0) return;
+  float2 acc_a[kResPerThread], acc_b[kResPerThread];
+  if (!resample_tile<D>(P, tp, status_word, k_s, acc_a, acc_b)) return;
 #pragma unroll
   for (int i = 0; i < kResPerThread; ++i) {
-    const int64_t k = k_s + tid + i * kResThreads;
+    const int64_t k = k_s + threadIdx.x + i * kResThreads;
     if (GROUPED) {
       ya[k] = acc_a[i];
       yb[k] = acc_b[i];
@@ -275,6 +289,90 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws,
       yb[k] = cmul_exact(acc_b[i], e);
     }
   }
+}
+
+// exp(-2 pi i nat k / N) with the product reduced exactly in integers.
+__device__ inline float2 bin_twiddle(int64_t nat, int64_t k, int64_t n_fft) {
+  const int64_t r = (nat * k) & (n_fft - 1);
+  float s, c;
+  sincospif(2.0f * float(r) / float(n_fft), &s, &c);
+  return make_float2(c, -s);
+}
+
+// Natural FFT index of band bin i (bins ascend in frequency from bin_lo of
+// the centred spectrum).
+__host__ __device__ inline int64_t band_bin_nat(const PlanConst& P, int64_t i) {
+  return (P.bin_lo + i + P.n_fft / 2) & (P.n_fft - 1);
+}
+
+// Single-bin forward path: the whitened transforms Fa'(m), Fb'(m) at one bin
+// m per template as a direct sum over the grid, sum_k y'_k exp(-2 pi i m k/N)
+// (step (vi) restricted to one output bin), reduced per tile into the slot's
+// partials (Fa'.re, Fa'.im, Fb'.re, Fb'.im in FP64).
+template <int D>
+__global__ __launch_bounds__(kResThreads) void k_resample_bin(PlanConst P, void* ws, ChunkMap map,
+                                                             const int64_t* __restrict__ bins) {
+  const int slot = blockIdx.y;
+  TmplParams* tpp = slot_params(ws, P, slot);
+  const TmplParams& tp = *tpp;
+  double* partial = slot_partials(ws, P, slot) + size_t(blockIdx.x) * 8;
+  const int64_t k_s = int64_t(blockIdx.x) * kResTile;
+  const int tid = threadIdx.x;
+  if (tp.status != 0) return;
+  float2 acc_a[kResPerThread], acc_b[kResPerThread];
+  if (!resample_tile<D>(P, tp, &tpp->status, k_s, acc_a, acc_b)) return;
+  const int64_t bin = bins[map.tmpl[slot]];
+  const int64_t nat = band_bin_nat(P, bin);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < kResPerThread; ++i) {
+    const int64_t k = k_s + tid + i * kResThreads;
+    const float2 e = cmul(spindown_rotation(P, tp.f1dot, tp.f2dot, tp.df, k),
+                          bin_twiddle(nat, k, P.n_fft));
+    const float2 ya = cmul(acc_a[i], e), yb = cmul(acc_b[i], e);
+    s[0] += double(ya.x);
+    s[1] += double(ya.y);
+    s[2] += double(yb.x);
+    s[3] += double(yb.y);
+  }
+  __shared__ double red[kResThreads / 64][4];
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double v = s[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wave][q] = v;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    double v = 0.0;
+    for (int w = 0; w < kResThreads / 64; ++w) v += red[w][tid];
+    partial[tid] = v;
+  }
+}
+
+// Per template: Fa'(m), Fb'(m) from the tile partials (tile order), 2F at the
+// bin, and the adjoint spectrum of L = 2F(m) at that bin, H = conj(F'(m))
+// (kept in the parameter block for the gradient kernel).  A bin outside the
+// band flags the template.
+__global__ void k_bin_final(PlanConst P, void* ws, ChunkMap map, int64_t ntiles,
+                            const int64_t* __restrict__ bins, float* __restrict__ twoF) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= map.n_tmpl) return;
+  TmplParams& tp = *slot_params(ws, P, slot);
+  const double* part = slot_partials(ws, P, slot);
+  const int64_t bin = bins[map.tmpl[slot]];
+  if (bin < 0 || bin >= P.n_bins) tp.status |= kStatusBin;
+  double f[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t b = 0; b < ntiles; ++b)
+    for (int q = 0; q < 4; ++q) f[q] += part[b * 8 + q];
+  tp.bin_nat = band_bin_nat(P, bin);
+  tp.hbin[0] = f[0];
+  tp.hbin[1] = -f[1];
+  tp.hbin[2] = f[2];
+  tp.hbin[3] = -f[3];
+  const double v = 2.0 * (f[0] * f[0] + f[1] * f[1] + f[2] * f[2] + f[3] * f[3]);
+  if (twoF) twoF[map.tmpl[slot]] = tp.status != 0 ? __builtin_nanf("") : float(v);
 }
 
 }  // namespace fstat

@@ -407,6 +407,66 @@ def config_binary(seed=3, ndays=120.0, dt=2.0, n_fft=1 << 23, ntmpl=10000, D=8, 
     return finish(ds)
 
 
+def config_refine(seed=5, ndays=30.0, dt=1.0, n_fft=1 << 22, f_het=400.0, band=0.2, ninj=8,
+                  per_inj=8, D=8, noise=True, mu=0.1 / 3.0):
+    """Candidate refinement: two detectors, 30 d at 1 s around 400 Hz, output
+    band 0.2 Hz; ninj circular-binary injections (rho U(10, 40), asini
+    U(0.005, 0.05) ls, porb U(0.5, 2) d) at frequencies 0.025 Hz apart, and
+    per injection per_inj candidates displaced 0.3-1 metric spacing (mismatch
+    mu per axis) in a random direction of (f, asini, porb, tp).  The dataset's
+    templates are the candidates; ds.cand_bins holds each candidate's bin in
+    the band and ds.cand_inj its injection."""
+    ss = np.random.SeedSequence(seed)
+    s_par, s_cand = ss.spawn(2)
+    rng = np.random.default_rng(s_par)
+    n = int(round(ndays * DAY / dt))
+    dets = [make_detector("H", 0.0, n, 1.0), make_detector("L", 0.0, n, 1.0)]
+    alpha, delta = 3.52004, -0.828935
+    injs = []
+    for i in range(ninj):
+        porb = float(rng.uniform(0.5, 2.0)) * DAY
+        injs.append(dict(alpha=alpha, delta=delta,
+                         f=f_het + 0.025 * (i - (ninj - 1) / 2.0) + float(rng.uniform(-2e-3, 2e-3)),
+                         f1dot=0.0, cosi=float(rng.uniform(-1, 1)),
+                         psi=float(rng.uniform(-math.pi / 4, math.pi / 4)),
+                         phi0=float(rng.uniform(0, 2 * math.pi)), rho=float(rng.uniform(10, 40)),
+                         asini=float(rng.uniform(0.005, 0.05)), porb=porb,
+                         tp=float(rng.uniform(0.0, porb))))
+    xs, vs = make_data(dets, dt, f_het, 0.0, injs, seed, noise=noise)
+    tspan = n * dt
+    n_bins = int(round(band * n_fft * dt))
+    bin_lo = n_fft // 2 - n_bins // 2
+    rc = np.random.default_rng(s_cand)
+    rows, bins, which = [], [], []
+    for i, inj in enumerate(injs):
+        om = 2.0 * math.pi / inj["porb"]
+        d_f = math.sqrt(3.0 * mu) / (math.pi * tspan)
+        d_a = math.sqrt(2 * mu) / (2 * math.pi * inj["f"])
+        d_tp = math.sqrt(2 * mu) / (2 * math.pi * inj["f"] * inj["asini"] * om)
+        d_om = math.sqrt(24 * mu) / (2 * math.pi * inj["f"] * inj["asini"] * tspan)
+        for _ in range(per_inj):
+            u = rc.normal(size=4)
+            u *= rc.uniform(0.3, 1.0) / np.linalg.norm(u)
+            fc = inj["f"] + u[0] * d_f
+            m = int(round((fc - f_het) * n_fft * dt)) + n_fft // 2
+            r = np.zeros(8)
+            r[0], r[1] = alpha, delta
+            r[2] = (fc - f_het) - (m - n_fft // 2) / (n_fft * dt)
+            r[5] = inj["asini"] + u[1] * d_a
+            r[6] = 2.0 * math.pi / (om + u[2] * d_om)
+            r[7] = inj["tp"] + u[3] * d_tp
+            rows.append(r)
+            bins.append(m - bin_lo)
+            which.append(i)
+    tm = np.array(rows)
+    max_a = float(np.max(tm[:, 5]))
+    ds = Dataset("refine", dt, f_het, 0.0, grid_origin(0.0, dt, 512.0 + max_a), n_fft, D, bin_lo,
+                 n_bins, dets, xs, vs, tm, injections=injs)
+    ds.cand_bins = np.array(bins, dtype=np.int64)
+    ds.cand_inj = np.array(which, dtype=np.int64)
+    return finish(ds)
+
+
 def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmpl=4, D=8,
                rho=15.0, noise=True, binary=False, gaps=False, noise_vars=None, f_inj=None,
                bin_lo=0, n_bins=None, keep_f64=False, model=None, sites=None, f1dot=None):
@@ -451,4 +511,5 @@ CONFIGS = {
     "tiny": config_tiny,
     "sky_spindown": config_sky_spindown,
     "binary": config_binary,
+    "refine": config_refine,
 }

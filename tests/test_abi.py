@@ -101,9 +101,10 @@ def test_plan_accepts_valid_setup(lib):
     p = B.Plan(d)
     # every documented tuning choice is accepted (n_fft = 2^13: columns 2^6 x rows 2^7 by default)
     for log_len, cl, rl in ((7, 64, 32), (7, 32, 16), (6, 64, 32), (6, 32, 16)):
-        d2 = B.make_plan_desc(ds, dict(tune_col_log_len=log_len, tune_col_lines=cl,
-                                       tune_row_lines=rl))
-        B.Plan(d2)
+        for grid in (0, 1):
+            d2 = B.make_plan_desc(ds, dict(tune_col_log_len=log_len, tune_col_lines=cl,
+                                           tune_row_lines=rl, tune_fft_grid=grid))
+            B.Plan(d2)
     k_pad, lc, lr = p.info()
     assert (lc, lr) == (6, 7) and k_pad % (1 << lr) == 0 and k_pad % 1024 == 0
     assert k_pad >= ds.detectors[0].n and k_pad <= ds.n_fft
@@ -136,6 +137,7 @@ def test_plan_accepts_valid_setup(lib):
     (lambda d: setattr(d, "tune_col_log_len", 13), "tune_col_log_len"),
     (lambda d: setattr(d, "tune_col_lines", 3), "tune_col_lines"),
     (lambda d: setattr(d, "tune_row_lines", 7), "tune_row_lines"),
+    (lambda d: setattr(d, "tune_fft_grid", 2), "tune_fft_grid"),
     (lambda d: (setattr(d, "n_fft", 1 << 12), setattr(d, "n_bins", 1 << 12),
                setattr(d.det[0], "n", 4000)), "too short"),
 ])
@@ -252,3 +254,23 @@ def test_search_plan_groups_and_chunks(lib):
                                    ctypes.byref(h)) == B.FSTAT_EINVAL
     assert lib.fstat_search_create(p.handle, tm.ctypes.data_as(vp), len(tm), 4, 2,
                                    ctypes.byref(h)) == B.FSTAT_EINVAL
+
+
+def test_autotune_checks_arguments_before_any_launch(lib):
+    ds, d = good_desc()
+    vp = ctypes.c_void_p
+    best = B.FstatPlanDesc()
+    ms = ctypes.c_float()
+    inp = B.FstatInputs()
+    tune = lib.fstat_autotune
+    assert tune(ctypes.byref(d), ctypes.byref(inp), vp(4096), 1, vp(4096), vp(4096), 1 << 30,
+                vp(0), None, ctypes.byref(ms)) == B.FSTAT_EINVAL
+    assert tune(None, ctypes.byref(inp), vp(4096), 1, vp(4096), vp(4096), 1 << 30, vp(0),
+                ctypes.byref(best), ctypes.byref(ms)) == B.FSTAT_EINVAL
+    assert tune(ctypes.byref(d), ctypes.byref(inp), vp(4096), 0, vp(4096), vp(4096), 1 << 30,
+                vp(0), ctypes.byref(best), ctypes.byref(ms)) == B.FSTAT_EINVAL
+    assert "sample" in B.last_error()
+    bad = B.make_plan_desc(ds)
+    bad.ndet = 0
+    assert tune(ctypes.byref(bad), ctypes.byref(inp), vp(4096), 1, vp(4096), vp(4096), 1 << 30,
+                vp(0), ctypes.byref(best), ctypes.byref(ms)) == B.FSTAT_EINVAL

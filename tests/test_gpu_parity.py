@@ -176,6 +176,8 @@ def test_delay_bound_violation_gives_nan(torch_dev):
 @pytest.mark.parametrize("tune", [
     dict(tune_col_lines=32, tune_row_lines=16),     # half lines, same split: same arithmetic
     dict(tune_col_log_len=7),                        # other split of 2^13
+    dict(tune_fft_grid=1),                           # one workgroup per work item
+    dict(tune_col_lines=32, tune_row_lines=16, tune_fft_grid=1),
 ])
 def test_fft_launch_shapes(torch_dev, tune):
     from paper_2201_00451_amd import binding
@@ -257,3 +259,74 @@ def test_search_graph_replays(torch_dev):
         # unrelated eager work between replays
         binding.compute_2f(dd, tm[:2])
         torch.cuda.synchronize()
+
+
+def nearest_template(ds):
+    """Index of the template closest to the first injection, in units of the
+    bank's own spacing along each parameter that varies."""
+    inj = ds.injections[0]
+    tm = ds.templates
+    target = np.array([inj["alpha"], inj["delta"], 0.0, inj["f1dot"], 0.0,
+                       inj.get("asini", 0.0), inj.get("porb", 1.0), inj.get("tp", 0.0)])
+    cost = np.zeros(len(tm))
+    for c in (0, 1, 3, 5, 6, 7):
+        vals = np.unique(tm[:, c])
+        if len(vals) < 2:
+            continue
+        cost += np.abs(tm[:, c] - target[c]) / np.min(np.diff(vals))
+    return int(np.argmin(cost))
+
+
+def test_full_size_bench_workload_sampled(torch_dev):
+    """The benchmark workload at full size (2 detectors x 864 000 samples,
+    1000 templates, n_fft 2^21, full band), run as the benchmark runs it
+    (grouped search, 8 slots, default launch shapes): two whole templates
+    (2 097 152 bins each: the first one and the one nearest an injection)
+    against the oracle."""
+    from paper_2201_00451_amd import binding
+    ds = synth.config_sky_spindown()
+    dd = binding.DeviceData(ds)
+    sr = binding.Search(dd, ds.templates, slots=8)
+    tf = sr.run()
+    binding.sync_check()
+    pick = [0, nearest_template(ds)]
+    say(f"  full-size bench workload: templates {pick}")
+    ref = O.oracle_twoF(ds, ds.templates[pick])
+    for i, t in enumerate(pick):
+        assert_2f_parity(tf[t].cpu().numpy(), ref[i], f"bench workload template {t}")
+    assert ref[1].max() > 30.0
+
+
+def test_full_size_binary_workload_sampled(torch_dev):
+    """The binary workload at full size (2 detectors x 5 184 000 samples at 70%
+    duty, n_fft 2^23, full band): 32 lattice templates around the injection in
+    one batched call; the one nearest the injection against the oracle over
+    all 8 388 608 bins."""
+    from paper_2201_00451_amd import binding
+    ds = synth.config_binary()
+    t0 = nearest_template(ds)
+    lo = max(0, t0 - 16)
+    rows = ds.templates[lo:lo + 32]
+    dd = binding.DeviceData(ds, batch=8)
+    tf = binding.compute_2f_batched(dd, rows)
+    binding.sync_check()
+    say(f"  full-size binary workload: template {t0}")
+    ref = O.oracle_twoF(ds, ds.templates[[t0]])[0]
+    assert_2f_parity(tf[t0 - lo].cpu().numpy(), ref, f"binary workload template {t0}")
+    assert ref.max() > 30.0
+
+
+def test_autotuned_launch_shape(torch_dev):
+    """The autotuner returns a launch shape the plan accepts, and 2F computed
+    with it meets the bar against the oracle."""
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(**dict(CASES["two_det_gaps"], n=3000, n_fft=1 << 13, ntmpl=3))
+    tune, ms = binding.autotune(ds, ds.templates, batch=2)
+    say(f"  autotuned {tune} in {ms:.3f} ms")
+    assert ms > 0.0 and tune["tune_col_log_len"] in (6, 7) and tune["tune_fft_grid"] in (0, 1)
+    dd = binding.DeviceData(ds, tune=tune, batch=2)
+    got = binding.compute_2f_batched(dd, ds.templates).cpu().numpy()
+    binding.sync_check()
+    ref = O.oracle_twoF(ds)
+    for i in range(ds.ntmpl):
+        assert_2f_parity(got[i], ref[i], f"autotuned tmpl {i}")

@@ -187,3 +187,46 @@ def test_refinement_climbs_to_the_injection(torch_dev):
     say(f"  refinement: 2F start {tf_start:.3f} -> {vals[0]:.3f} (true parameters {tf_true:.3f})")
     assert tf_start < 0.9 * tf_true
     assert vals[0] >= 0.99 * tf_true
+
+
+def test_single_bin_path_matches_general_adjoint_and_oracle(torch_dev):
+    """The single-bin form (direct one-bin transform, adjoint series in closed
+    form) against the general adjoint with one-hot weights and against the FP64
+    oracle gradient; a bin outside the band gives NaN for that template only."""
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(seed=60, n=3000, n_fft=1 << 13, ndet=2, binary=True, gaps=True,
+                          ntmpl=3, rho=25, bin_lo=1000, n_bins=5000)
+    rows = np.array([displaced_row(ds) for _ in range(3)])
+    rows[1, 0] += 0.004
+    tf_ref = O.oracle_twoF(ds, rows)
+    bins = np.array([int(np.argmax(tf_ref[0])) + 2, int(np.argmax(tf_ref[1])), 17])
+    dd = binding.DeviceData(ds, batch=3)
+    g_bin, tf_bin = binding.compute_2f_grad_bin(dd, rows, bins)
+    onehot = np.zeros((3, ds.n_bins))
+    onehot[np.arange(3), bins] = 1.0
+    g_gen, tf_gen = binding.compute_2f_grad(dd, rows, onehot, want_twoF=True)
+    bad = bins.copy()
+    bad[1] = ds.n_bins
+    g_bad, tf_bad = binding.compute_2f_grad_bin(dd, rows, bad)
+    binding.sync_check()
+    g_bin, tf_bin = g_bin.cpu().numpy(), tf_bin.cpu().numpy()
+    g_gen, tf_gen = g_gen.cpu().numpy(), tf_gen.cpu().numpy()
+    for m in range(3):
+        ref2f = tf_ref[m, bins[m]]
+        got = tf_bin[m]
+        say(f"  template {m} bin {bins[m]}: 2F single-bin {got:.6f} fft {tf_gen[m, bins[m]]:.6f} "
+            f"oracle {ref2f:.6f}")
+        if ref2f >= 10.0:
+            assert abs(got - ref2f) <= 1e-4 * ref2f
+        else:
+            assert abs(got - ref2f) <= 1e-3
+        _, g_or = G.oracle_grad(ds, rows[m], onehot[m])
+        for i, name in enumerate(G.PARAMS):
+            say(f"    {name:6s} bin {g_bin[m, i]: .9e} general {g_gen[m, i]: .9e} "
+                f"oracle {g_or[i]: .9e}")
+            assert abs(g_bin[m, i] - g_or[i]) <= GRAD_RTOL * abs(g_or[i]), (m, name)
+            assert abs(g_bin[m, i] - g_gen[m, i]) <= GRAD_RTOL * abs(g_or[i]), (m, name)
+    g_bad, tf_bad = g_bad.cpu().numpy(), tf_bad.cpu().numpy()
+    assert np.all(np.isnan(g_bad[1])) and np.isnan(tf_bad[1])
+    assert np.array_equal(g_bad[[0, 2]], g_bin[[0, 2]])
+    assert np.array_equal(tf_bad[[0, 2]], tf_bin[[0, 2]])
