@@ -77,14 +77,18 @@ typedef struct {
    *     log2(n_fft) - tune_col_log_len; both must lie in [6, 12];
    *   tune_col_lines: columns per workgroup of the column pass;
    *   tune_row_lines: rows per workgroup of the row pass;
-   *   tune_fft_grid: 0 = persistent workgroups (as many as fit the device at
-   *     once, each looping over work items with the next item's loads in
-   *     flight), 1 = one workgroup per work item.
-   * Accepted line counts are the automatic value or half of it. */
+   *   tune_fft_grid: 1 = one workgroup per work item, 2 = persistent
+   *     workgroups (as many as fit the device at once, each looping over work
+   *     items with the next item's loads in flight);
+   *   tune_fft_radix: largest radix of a Stockham stage, 16 or 32.
+   * Accepted line counts are the largest (as many as fit 128 KiB of LDS, one
+   * 512-thread workgroup per compute unit) or half of it (256-thread
+   * workgroups, two per compute unit: the automatic choice). */
   int32_t tune_col_log_len;
   int32_t tune_col_lines;
   int32_t tune_row_lines;
   int32_t tune_fft_grid;
+  int32_t tune_fft_radix;
   uint32_t flags;                      /* reserved, must be 0 */
 } fstat_plan_desc;
 

@@ -46,7 +46,7 @@ class FstatPlanDesc(ctypes.Structure):
                 ("bin_lo", ctypes.c_int64), ("n_bins", ctypes.c_int64),
                 ("tune_col_log_len", ctypes.c_int32), ("tune_col_lines", ctypes.c_int32),
                 ("tune_row_lines", ctypes.c_int32), ("tune_fft_grid", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("tune_fft_radix", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class FstatInputs(ctypes.Structure):
@@ -432,7 +432,8 @@ def refine(dd: DeviceData, templates, bins, scales, steps=50, lr=0.5, free=None)
     return rows.numpy(), cur.numpy()
 
 
-TUNE_FIELDS = ("tune_col_log_len", "tune_col_lines", "tune_row_lines", "tune_fft_grid")
+TUNE_FIELDS = ("tune_col_log_len", "tune_col_lines", "tune_row_lines", "tune_fft_grid",
+               "tune_fft_radix")
 
 
 def autotune(ds, templates, batch=8, device="cuda:0", stream=None):

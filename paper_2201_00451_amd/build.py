@@ -13,6 +13,10 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions stay off: plain scalar/float2 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fuse per source expression only, the same way in every
+    # kernel that inlines a helper (the grouped and per-template paths give
+    # the same bits)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-fvisibility=hidden",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -25,6 +25,8 @@ struct fstat_plan {
   int log_n, log_rr, log_c;  // N = Rr * C
   int cols_lines, rows_lines;
   bool cols_half, rows_half;
+  int fft_mlr;       // largest stage radix 2^fft_mlr
+  bool fft_persist;  // persistent FFT workgroups
   int64_t k_pad, rows_act;
   double t_lo, t_hi;         // time range any timing evaluation may touch
 };
@@ -57,10 +59,10 @@ int ilog2(int64_t v) {
   return l;
 }
 
-// Lines per workgroup of the column pass (B) and rows per workgroup of the
-// row pass (RQ): by default as many as fit 128 KiB of LDS, capped for
-// coalescing; the tuning fields may halve them (then with half the threads,
-// so two workgroups share a CU).
+// Lines per workgroup of the column pass (NL) and rows per workgroup of the
+// row pass (RQ): at most as many as fit 128 KiB of LDS, capped for
+// coalescing, with 512 threads; or half of that with 256 threads, so that two
+// workgroups share a compute unit (the automatic choice).
 int cols_lines_max(int log_rr) { return std::min(64, 16384 >> log_rr); }
 int rows_lines_max(int log_c) { return std::min(32, 8192 >> log_c); }
 
@@ -77,54 +79,89 @@ struct FftVariant {
   int threads;
 };
 
-template <int LOGL, bool GROUPED>
+// Variant choice of an FFT pass: full or half line count (half: 256 threads),
+// largest stage radix 2^mlr (mlr 4 or 5; only line lengths 2^9 and 2^10 have
+// a different stage plan with 2^5), persistent or one workgroup per item.
+struct FftChoice {
+  bool half;
+  int mlr;
+  bool persist;
+};
+
+template <int LOGL, bool GROUPED, int MLR, bool PERSIST>
 FftVariant cols_variant(bool half) {
   if (half)
-    return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL> / 2, 256, GROUPED>),
+    return {reinterpret_cast<const void*>(
+                &k_fft_cols<LOGL, kColsMax<LOGL> / 2, 256, GROUPED, MLR, PERSIST>),
             256};
-  return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL>, 512, GROUPED>), 512};
+  return {reinterpret_cast<const void*>(
+              &k_fft_cols<LOGL, kColsMax<LOGL>, 512, GROUPED, MLR, PERSIST>),
+          512};
 }
-template <int LOGL, int MODE>
+template <int LOGL, int MODE, int MLR, bool PERSIST>
 FftVariant rows_variant(bool half) {
   if (half)
-    return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, kRowsMax<LOGL> / 2, 256, MODE>), 256};
-  return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, kRowsMax<LOGL>, 512, MODE>), 512};
+    return {reinterpret_cast<const void*>(
+                &k_fft_rows<LOGL, kRowsMax<LOGL> / 2, 256, MODE, MLR, PERSIST>),
+            256};
+  return {reinterpret_cast<const void*>(
+              &k_fft_rows<LOGL, kRowsMax<LOGL>, 512, MODE, MLR, PERSIST>),
+          512};
 }
 
-template <bool GROUPED>
-FftVariant pick_cols_g(int logl, bool half) {
+template <bool GROUPED, int MLR, bool PERSIST>
+FftVariant pick_cols_v(int logl, bool half) {
   switch (logl) {
-    case 6: return cols_variant<6, GROUPED>(half);
-    case 7: return cols_variant<7, GROUPED>(half);
-    case 8: return cols_variant<8, GROUPED>(half);
-    case 9: return cols_variant<9, GROUPED>(half);
-    case 10: return cols_variant<10, GROUPED>(half);
-    case 11: return cols_variant<11, GROUPED>(half);
-    case 12: return cols_variant<12, GROUPED>(half);
+    case 6: return cols_variant<6, GROUPED, 4, PERSIST>(half);
+    case 7: return cols_variant<7, GROUPED, 4, PERSIST>(half);
+    case 8: return cols_variant<8, GROUPED, 4, PERSIST>(half);
+    case 9: return cols_variant<9, GROUPED, MLR, PERSIST>(half);
+    case 10: return cols_variant<10, GROUPED, MLR, PERSIST>(half);
+    case 11: return cols_variant<11, GROUPED, 4, PERSIST>(half);
+    case 12: return cols_variant<12, GROUPED, 4, PERSIST>(half);
     default: return {nullptr, 0};
   }
 }
-FftVariant pick_cols(int logl, bool half, bool grouped) {
-  return grouped ? pick_cols_g<true>(logl, half) : pick_cols_g<false>(logl, half);
+template <bool GROUPED>
+FftVariant pick_cols_g(int logl, const FftChoice& c) {
+  if (c.mlr == 5)
+    return c.persist ? pick_cols_v<GROUPED, 5, true>(logl, c.half)
+                     : pick_cols_v<GROUPED, 5, false>(logl, c.half);
+  return c.persist ? pick_cols_v<GROUPED, 4, true>(logl, c.half)
+                   : pick_cols_v<GROUPED, 4, false>(logl, c.half);
+}
+FftVariant pick_cols(int logl, const FftChoice& c, bool grouped) {
+  return grouped ? pick_cols_g<true>(logl, c) : pick_cols_g<false>(logl, c);
+}
+template <int MODE, int MLR, bool PERSIST>
+FftVariant pick_rows_v(int logl, bool half) {
+  switch (logl) {
+    case 6: return rows_variant<6, MODE, 4, PERSIST>(half);
+    case 7: return rows_variant<7, MODE, 4, PERSIST>(half);
+    case 8: return rows_variant<8, MODE, 4, PERSIST>(half);
+    case 9: return rows_variant<9, MODE, MLR, PERSIST>(half);
+    case 10: return rows_variant<10, MODE, MLR, PERSIST>(half);
+    case 11: return rows_variant<11, MODE, 4, PERSIST>(half);
+    case 12: return rows_variant<12, MODE, 4, PERSIST>(half);
+    default: return {nullptr, 0};
+  }
 }
 template <int MODE>
-FftVariant pick_rows_m(int logl, bool half) {
-  switch (logl) {
-    case 6: return rows_variant<6, MODE>(half);
-    case 7: return rows_variant<7, MODE>(half);
-    case 8: return rows_variant<8, MODE>(half);
-    case 9: return rows_variant<9, MODE>(half);
-    case 10: return rows_variant<10, MODE>(half);
-    case 11: return rows_variant<11, MODE>(half);
-    case 12: return rows_variant<12, MODE>(half);
-    default: return {nullptr, 0};
-  }
+FftVariant pick_rows_m(int logl, const FftChoice& c) {
+  if (c.mlr == 5)
+    return c.persist ? pick_rows_v<MODE, 5, true>(logl, c.half)
+                     : pick_rows_v<MODE, 5, false>(logl, c.half);
+  return c.persist ? pick_rows_v<MODE, 4, true>(logl, c.half)
+                   : pick_rows_v<MODE, 4, false>(logl, c.half);
 }
-FftVariant pick_rows(int logl, bool half, int mode = kRow2F) {
-  return mode == kRowAdjoint ? pick_rows_m<kRowAdjoint>(logl, half)
-         : mode == kRowConj  ? pick_rows_m<kRowConj>(logl, half)
-                             : pick_rows_m<kRow2F>(logl, half);
+FftVariant pick_rows(int logl, const FftChoice& c, int mode = kRow2F) {
+  return mode == kRowAdjoint ? pick_rows_m<kRowAdjoint>(logl, c)
+         : mode == kRowConj  ? pick_rows_m<kRowConj>(logl, c)
+                             : pick_rows_m<kRow2F>(logl, c);
 }
+
+FftChoice cols_choice(const fstat_plan* p) { return {p->cols_half, p->fft_mlr, p->fft_persist}; }
+FftChoice rows_choice(const fstat_plan* p) { return {p->rows_half, p->fft_mlr, p->fft_persist}; }
 
 fstat_status check_hip(hipError_t e, const char* what) {
   if (e != hipSuccess) return fail(FSTAT_EHIP, "%s: %s", what, hipGetErrorString(e));
@@ -263,7 +300,7 @@ size_t lds_bytes_rows(const fstat_plan* p) { return fft_lds_bytes(p->log_c, 2 * 
 // per kernel, LDS size and device).
 unsigned fft_grid(const fstat_plan* p, const FftVariant& v, size_t lds, int64_t n_items) {
   if (n_items < 1) return 1;
-  if (p->desc.tune_fft_grid == 1) return unsigned(n_items);
+  if (!p->fft_persist) return unsigned(n_items);
   struct Entry {
     const void* fn;
     size_t lds;
@@ -369,8 +406,8 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
     hipLaunchKernelGGL(k_copy_series, dim3(256, n), dim3(256), 0, st, P, ws, map, y_out);
     return check_hip(hipGetLastError(), "resample launch");
   }
-  const FftVariant cv = pick_cols(p->log_rr, p->cols_half, grouped);
-  const FftVariant rv = pick_rows(p->log_c, p->rows_half);
+  const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), grouped);
+  const FftVariant rv = pick_rows(p->log_c, rows_choice(p));
   if ((s = tm.mark(2)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn)),
                      dim3(fft_grid(p, cv, lds_bytes_cols(p), cols_items(p, n))),
@@ -408,12 +445,12 @@ fstat_status finish_timer(KernelTimer& tm, hipStream_t st, float* kernel_ms, int
 fstat_status set_lds_limits(const fstat_plan* p) {
   hipError_t e = hipSuccess;
   for (bool grouped : {false, true}) {
-    e = hipFuncSetAttribute(pick_cols(p->log_rr, p->cols_half, grouped).fn,
+    e = hipFuncSetAttribute(pick_cols(p->log_rr, cols_choice(p), grouped).fn,
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_cols(p)));
     if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(cols)");
   }
   for (int mode : {int(kRow2F), int(kRowAdjoint), int(kRowConj)}) {
-    e = hipFuncSetAttribute(pick_rows(p->log_c, p->rows_half, mode).fn,
+    e = hipFuncSetAttribute(pick_rows(p->log_c, rows_choice(p), mode).fn,
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_rows(p)));
     if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(rows)");
   }
@@ -533,11 +570,11 @@ fstat_status launch_grad_chunk(const fstat_plan* p, const PlanConst& P, const do
   hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, ws);
   hipLaunchKernelGGL(resample_kernel(p->desc.sinc_halfwidth, false), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws, map, slots);
-  const FftVariant cv = pick_cols(p->log_rr, p->cols_half, false);
+  const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), false);
   const ColsFn cols = reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn));
   const dim3 cgrid(fft_grid(p, cv, lds_bytes_cols(p), cols_items(p, n)));
-  const FftVariant ra = pick_rows(p->log_c, p->rows_half, kRowAdjoint);
-  const FftVariant rc = pick_rows(p->log_c, p->rows_half, kRowConj);
+  const FftVariant ra = pick_rows(p->log_c, rows_choice(p), kRowAdjoint);
+  const FftVariant rc = pick_rows(p->log_c, rows_choice(p), kRowConj);
   const dim3 rgrid(fft_grid(p, ra, lds_bytes_rows(p), rows_items(p, n)));
   hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 0,
                      p->log_c, p->rows_act);
@@ -791,12 +828,20 @@ fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out) {
                 "tune_col_lines=%d / tune_row_lines=%d: accepted 0, %d or %d / 0, %d or %d", tc,
                 tr, cmax, cmax / 2, rmax, rmax / 2);
   }
-  if (desc->tune_fft_grid != 0 && desc->tune_fft_grid != 1) {
+  if (desc->tune_fft_grid < 0 || desc->tune_fft_grid > 2) {
     delete p;
-    return fail(FSTAT_EINVAL, "tune_fft_grid=%d: accepted 0 or 1", desc->tune_fft_grid);
+    return fail(FSTAT_EINVAL, "tune_fft_grid=%d: accepted 0, 1 or 2", desc->tune_fft_grid);
   }
-  p->cols_half = tc == cmax / 2 && cmax > 1;
-  p->rows_half = tr == rmax / 2 && rmax > 1;
+  if (desc->tune_fft_radix != 0 && desc->tune_fft_radix != 16 && desc->tune_fft_radix != 32) {
+    delete p;
+    return fail(FSTAT_EINVAL, "tune_fft_radix=%d: accepted 0, 16 or 32", desc->tune_fft_radix);
+  }
+  p->fft_persist = desc->tune_fft_grid == 2;
+  p->fft_mlr = desc->tune_fft_radix == 16 ? 4 : 5;
+  // automatic: the half line counts (256-thread workgroups, two per compute
+  // unit), measured faster than one 512-thread workgroup per unit
+  p->cols_half = (tc == 0 || tc == cmax / 2) && cmax > 1;
+  p->rows_half = (tr == 0 || tr == rmax / 2) && rmax > 1;
   p->cols_lines = p->cols_half ? cmax / 2 : cmax;
   p->rows_lines = p->rows_half ? rmax / 2 : rmax;
   // grid points that can be non-zero: up to the last sample plus the delay
@@ -916,12 +961,14 @@ fstat_status fstat_autotune(const fstat_plan_desc* desc, const fstat_inputs* in,
     if (lr < 6 || lr > 12 || lc < 6 || lc > 12) continue;
     for (int ch = 0; ch < 2; ++ch)
       for (int rh = 0; rh < 2; ++rh)
-        for (int grid = 0; grid < 2; ++grid) {
+        for (int grid = 1; grid <= 2; ++grid)
+          for (int radix = 16; radix <= 32; radix *= 2) {
           fstat_plan_desc d = *desc;
           d.tune_col_log_len = lr;
           d.tune_col_lines = ch ? cols_lines_max(lr) / 2 : 0;
           d.tune_row_lines = rh ? rows_lines_max(lc) / 2 : 0;
           d.tune_fft_grid = grid;
+          d.tune_fft_radix = radix;
           if ((ch && d.tune_col_lines < 1) || (rh && d.tune_row_lines < 1)) continue;
           fstat_plan* p = nullptr;
           if (fstat_plan_create(&d, &p) != FSTAT_OK) continue;

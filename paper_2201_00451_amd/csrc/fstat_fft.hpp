@@ -19,35 +19,35 @@
 
 namespace fstat {
 
-// cos(pi i / 8), sin(pi i / 8) for i = 0..7
-__host__ __device__ constexpr float c16(int i) {
-  return i == 0 ? 1.0f
-         : i == 1 ? 0.92387953251128674f
-         : i == 2 ? 0.70710678118654752f
-         : i == 3 ? 0.38268343236508977f
-         : i == 4 ? 0.0f
-         : i == 5 ? -0.38268343236508977f
-         : i == 6 ? -0.70710678118654752f
-                  : -0.92387953251128674f;
+// cos(pi i / 16), sin(pi i / 16) for i = 0..15 (32nd roots of unity)
+__host__ __device__ constexpr float c32(int i) {
+  constexpr float t[16] = {1.0f,
+                           0.98078528040323044913f,
+                           0.92387953251128675613f,
+                           0.83146961230254523708f,
+                           0.70710678118654752440f,
+                           0.55557023301960222474f,
+                           0.38268343236508977173f,
+                           0.19509032201612826785f,
+                           0.0f,
+                           -0.19509032201612826785f,
+                           -0.38268343236508977173f,
+                           -0.55557023301960222474f,
+                           -0.70710678118654752440f,
+                           -0.83146961230254523708f,
+                           -0.92387953251128675613f,
+                           -0.98078528040323044913f};
+  return t[i];
 }
-__host__ __device__ constexpr float s16(int i) {
-  return i == 0 ? 0.0f
-         : i == 1 ? 0.38268343236508977f
-         : i == 2 ? 0.70710678118654752f
-         : i == 3 ? 0.92387953251128674f
-         : i == 4 ? 1.0f
-         : i == 5 ? 0.92387953251128674f
-         : i == 6 ? 0.70710678118654752f
-                  : 0.38268343236508977f;
-}
+__host__ __device__ constexpr float s32(int i) { return i <= 8 ? c32(8 - i) : c32(i - 8); }
 
-// x * W_R^m, W_R = exp(-2 pi i / R), R <= 16, m < R/2
+// x * W_R^m, W_R = exp(-2 pi i / R), R <= 32, m < R/2
 template <int R>
 __device__ __forceinline__ float2 mul_wr(float2 x, int m) {
-  const int i = 16 / R * m;
+  const int i = 32 / R * m;
   if (i == 0) return x;
-  if (i == 4) return make_float2(x.y, -x.x);
-  const float c = c16(i), s = s16(i);
+  if (i == 8) return make_float2(x.y, -x.x);
+  const float c = c32(i), s = s32(i);
   return make_float2(x.x * c + x.y * s, x.y * c - x.x * s);
 }
 
@@ -77,13 +77,23 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
   }
 }
 
-// Radix plan: log2 L split into ceil(log2 L / 4) stages as evenly as possible.
-__host__ __device__ constexpr int stage_count(int logl) { return (logl + 3) / 4; }
-__host__ __device__ constexpr int stage_logr(int logl, int s) {
-  return s < logl % stage_count(logl) ? logl / stage_count(logl) + 1 : logl / stage_count(logl);
+// Radix plan: log2 L split into ceil(log2 L / MLR) stages as evenly as
+// possible (radix at most 2^MLR, MLR = 4 or 5).
+__host__ __device__ constexpr int stage_count(int logl, int mlr) { return (logl + mlr - 1) / mlr; }
+__host__ __device__ constexpr int stage_logr(int logl, int s, int mlr) {
+  return s < logl % stage_count(logl, mlr) ? logl / stage_count(logl, mlr) + 1
+                                            : logl / stage_count(logl, mlr);
 }
-__host__ __device__ constexpr int stage_logp(int logl, int s) {
-  return s == 0 ? 0 : stage_logp(logl, s - 1) + stage_logr(logl, s - 1);
+__host__ __device__ constexpr int stage_logp(int logl, int s, int mlr) {
+  return s == 0 ? 0 : stage_logp(logl, s - 1, mlr) + stage_logr(logl, s - 1, mlr);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs: give the ones an
+// XCD holds at the same time consecutive logical indices.
+__device__ inline uint32_t xcd_remap(uint32_t id, uint32_t total) {
+  const uint32_t full = total & ~7u;
+  if (id >= full) return id;
+  return (id & 7u) * (full >> 3) + (id >> 3);
 }
 
 // LDS layout of NL lines of length L: line-major with one pad element every
@@ -121,10 +131,10 @@ __device__ __forceinline__ void twiddle_dft(float2 (&v)[R], int k, const float2*
 // A middle Stockham stage (LDS to LDS) over NL lines.  Butterfly b covers
 // index i = b mod (L/R) of line b div (L/R); reads finish (barrier) before
 // the in-place writes, which finish (barrier) before the next stage.
-template <int LOGL, int NL, int NT, int S>
+template <int LOGL, int NL, int NT, int S, int MLR>
 __device__ __forceinline__ void fft_stage(float2* buf, const float2* twl) {
-  constexpr int LOGR = stage_logr(LOGL, S), R = 1 << LOGR;
-  constexpr int P = 1 << stage_logp(LOGL, S);
+  constexpr int LOGR = stage_logr(LOGL, S, MLR), R = 1 << LOGR;
+  constexpr int P = 1 << stage_logp(LOGL, S, MLR);
   constexpr int L = 1 << LOGL;
   constexpr int NBL = L / R;
   constexpr int NB = NL * NBL;
@@ -158,11 +168,11 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* twl) {
 }
 
 // Middle stages 1 .. last-1.
-template <int LOGL, int NL, int NT, int S>
+template <int LOGL, int NL, int NT, int S, int MLR>
 __device__ __forceinline__ void fft_middle(float2* buf, const float2* twl) {
-  if constexpr (S < stage_count(LOGL) - 1) {
-    fft_stage<LOGL, NL, NT, S>(buf, twl);
-    fft_middle<LOGL, NL, NT, S + 1>(buf, twl);
+  if constexpr (S < stage_count(LOGL, MLR) - 1) {
+    fft_stage<LOGL, NL, NT, S, MLR>(buf, twl);
+    fft_middle<LOGL, NL, NT, S + 1, MLR>(buf, twl);
   }
 }
 
@@ -190,14 +200,23 @@ __host__ __device__ constexpr size_t fft_lds_bytes(int logl, int nl) {
          sizeof(float2);
 }
 
-// Both passes are persistent: workgroup w transforms work items w, w + G,
-// w + 2G, ... (G = gridDim.x; with G = number of items every workgroup takes
-// one).  The first stage's HBM loads of the next item are issued before the
-// current item is transformed, so they are in flight during its LDS stages
-// and stores; the transform itself reads no global memory (stage twiddles
-// from LDS, four-step twiddles from sincospi), so nothing waits on them early.
-// Item order is template slot fastest: the templates of one sky/orbit group
-// read the same group series at about the same time.
+template <int LOGL, int MLR>
+constexpr int kR0 = 1 << stage_logr(LOGL, 0, MLR);
+template <int LOGL, int NL, int NT, int MLR>
+constexpr int kPer0 = (NL * ((1 << LOGL) / kR0<LOGL, MLR>) + NT - 1) / NT;
+
+// Work items.  PERSIST = false: one workgroup per item, line groups fastest
+// within a template, remapped so that the workgroups an XCD runs together
+// handle neighbouring line groups (the row pass writes 2F in runs of RQ
+// floats per row group; neighbouring groups complete each other's cache
+// lines in that XCD's L2 before write-back).  PERSIST = true: workgroup w
+// transforms items w, w + G, w + 2G, ... (G = gridDim.x), template slot
+// fastest (the templates of one sky/orbit group read the same group series
+// at about the same time), and the first-stage loads of the next item are
+// issued before the current item is transformed, so they are in flight during
+// its LDS stages and stores; the transform reads no global memory (stage
+// twiddles from LDS, four-step twiddles from sincospi), so nothing waits on
+// them early.
 
 struct ColItem {
   int live, g, arr;
@@ -215,23 +234,31 @@ struct ColItem {
 // GROUPED: the input is the unphased series of the slot's sky/orbit group;
 // stage 0 applies the template's spin-down phase while loading and the
 // output goes to the slot's own buffer.
-template <int LOGL, int NL, int NT, bool GROUPED>
+template <int LOGL, int NL, int NT, bool GROUPED, int MLR, bool PERSIST>
 __device__ __forceinline__ ColItem cols_fetch(const PlanConst& P, void* ws, const ChunkMap& map,
                                               int slots, int arr_base, int64_t C,
                                               int64_t rows_act, int item, int n_items,
-                                              float2 (&v)[((NL << LOGL) / (1 << stage_logr(LOGL, 0)) + NT - 1) / NT]
-                                                         [1 << stage_logr(LOGL, 0)]) {
+                                              float2 (&v)[kPer0<LOGL, NL, NT, MLR>]
+                                                         [kR0<LOGL, MLR>]) {
   constexpr int L = 1 << LOGL;
-  constexpr int R0 = 1 << stage_logr(LOGL, 0), NB0 = NL * (L / R0);
-  constexpr int PER = (NB0 + NT - 1) / NT;
+  constexpr int R0 = kR0<LOGL, MLR>, NB0 = NL * (L / R0);
+  constexpr int PER = kPer0<LOGL, NL, NT, MLR>;
   ColItem it;
   it.live = 0;
   if (item >= n_items) return it;
-  const int n = map.n_tmpl;
-  it.g = item % n;
-  const int rest = item / n;
-  it.arr = rest & 1;
-  it.c0 = int64_t(rest >> 1) * NL;
+  if (PERSIST) {
+    const int n = map.n_tmpl;
+    it.g = item % n;
+    const int rest = item / n;
+    it.arr = rest & 1;
+    it.c0 = int64_t(rest >> 1) * NL;
+  } else {
+    const int n_gx = int(C / NL);
+    it.c0 = int64_t(item % n_gx) * NL;
+    const int rest = item / n_gx;
+    it.arr = rest & 1;
+    it.g = rest >> 1;
+  }
   TmplParams* tpp = tmpl_params(ws, P, map, it.g);
   int32_t status = tpp->status;
   if (GROUPED) {
@@ -263,91 +290,110 @@ __device__ __forceinline__ ColItem cols_fetch(const PlanConst& P, void* ws, cons
   return it;
 }
 
-template <int LOGL, int NL, int NT, bool GROUPED>
+template <int LOGL, int NL, int NT, bool GROUPED, int MLR>
+__device__ __forceinline__ void cols_transform(const PlanConst& P, void* ws, const ColItem& it,
+                                               int arr_base, int64_t C, int64_t rows_act,
+                                               float2 (&v)[kPer0<LOGL, NL, NT, MLR>]
+                                                          [kR0<LOGL, MLR>],
+                                               float2* lds, const float2* twl) {
+  constexpr int L = 1 << LOGL;
+  constexpr int NS = stage_count(LOGL, MLR);
+  constexpr int R0 = kR0<LOGL, MLR>, NB0 = NL * (L / R0);
+  constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = NL * PL;
+  constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
+  using Lay = LdsLayout<L>;
+  const int tid = threadIdx.x;
+  const int64_t nmask = P.n_fft - 1;
+  const auto wr = buf_rsrc(slot_buf(ws, P, it.g, arr_base + it.arr),
+                           uint32_t(P.n_fft * int64_t(sizeof(float2))));
+  // stage 0: registers -> DFT -> LDS
+#pragma unroll
+  for (int s = 0; s < PER0; ++s) {
+    const int b = tid + s * NT;
+    if (NB0 % NT == 0 || b < NB0) {
+      const int line = b % NL, i = b / NL;
+      if (GROUPED) {
+#pragma unroll
+        for (int j = 0; j < R0; ++j) {
+          const int r = i + j * (L / R0);
+          if (r < rows_act)
+            v[s][j] = cmul_exact(v[s][j], spindown_rotation(P, it.f1dot, it.f2dot, it.df,
+                                                            int64_t(r) * C + it.c0 + line));
+        }
+      }
+      dft<R0>(v[s]);
+#pragma unroll
+      for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
+    }
+  }
+  __syncthreads();
+  fft_middle<LOGL, NL, NT, 1, MLR>(lds, twl);
+  // last stage: LDS -> registers -> DFT -> x W_N^{q c} -> HBM
+  constexpr int PER = (NBL + NT - 1) / NT;
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int b = tid + s * NT;
+    if (NBL % NT == 0 || b < NBL) {
+      const int line = b % NL, i = b / NL;
+      float2 u[RL];
+#pragma unroll
+      for (int j = 0; j < RL; ++j) u[j] = lds[Lay::at(i + j * PL, line)];
+      twiddle_dft<RL, PL, L>(u, i, twl);
+      const int64_t c = it.c0 + line;
+      // W_N^{c (i + m PL)} = W_N^{c i} (W_N^{c PL})^m
+      float2 w = tw_n((int64_t(i) * c) & nmask, P.n_fft);
+      const float2 step = tw_n((int64_t(PL) * c) & nmask, P.n_fft);
+      const uint32_t voff = uint32_t((int64_t(i) * C + c) * int64_t(sizeof(float2)));
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        buf_store2(cmul(u[m], w), wr, voff,
+                   uint32_t(int64_t(m) * PL * C * int64_t(sizeof(float2))));
+        w = cmul(w, step);
+      }
+    }
+  }
+}
+
+template <int LOGL, int NL, int NT, bool GROUPED, int MLR, bool PERSIST>
 __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap map, int slots,
                                                  int arr_base, int log_c, int64_t rows_act) {
   extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
-  constexpr int NS = stage_count(LOGL);
-  constexpr int R0 = 1 << stage_logr(LOGL, 0), NB0 = NL * (L / R0);
-  constexpr int RL = 1 << stage_logr(LOGL, NS - 1), PL = L / RL, NBL = NL * PL;
-  constexpr int PER0 = (NB0 + NT - 1) / NT;
-  using Lay = LdsLayout<L>;
-  float2* twl = lds + NL * Lay::pitch;
+  constexpr int R0 = kR0<LOGL, MLR>;
+  constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
+  float2* twl = lds + NL * LdsLayout<L>::pitch;
   const int tid = threadIdx.x;
   const int64_t C = int64_t(1) << log_c;
   const int n_items = int(C / NL) * 2 * map.n_tmpl;
-  const int64_t nmask = P.n_fft - 1;
   {
     const float2* __restrict__ tws = tw_stage(ws);
     for (int e = tid; e < L / 2; e += NT) twl[e] = tws[e * (kTwLen / L)];
   }
-  int item = blockIdx.x;
+  int item = PERSIST ? int(blockIdx.x) : int(xcd_remap(blockIdx.x, gridDim.x));
   float2 v[PER0][R0];
-  ColItem it = cols_fetch<LOGL, NL, NT, GROUPED>(P, ws, map, slots, arr_base, C, rows_act, item,
-                                                 n_items, v);
-  while (item < n_items) {
-    const int next = item + int(gridDim.x);
-    float2 vn[PER0][R0];
-    const ColItem nt = cols_fetch<LOGL, NL, NT, GROUPED>(P, ws, map, slots, arr_base, C,
-                                                         rows_act, next, n_items, vn);
-    if (it.live) {
-      const auto wr = buf_rsrc(slot_buf(ws, P, it.g, arr_base + it.arr),
-                               uint32_t(P.n_fft * int64_t(sizeof(float2))));
-      // stage 0: registers -> DFT -> LDS
-#pragma unroll
-      for (int s = 0; s < PER0; ++s) {
-        const int b = tid + s * NT;
-        if (NB0 % NT == 0 || b < NB0) {
-          const int line = b % NL, i = b / NL;
-          if (GROUPED) {
-#pragma unroll
-            for (int j = 0; j < R0; ++j) {
-              const int r = i + j * (L / R0);
-              if (r < rows_act)
-                v[s][j] = cmul_exact(v[s][j], spindown_rotation(P, it.f1dot, it.f2dot, it.df,
-                                                                int64_t(r) * C + it.c0 + line));
-            }
-          }
-          dft<R0>(v[s]);
-#pragma unroll
-          for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
-        }
+  ColItem it = cols_fetch<LOGL, NL, NT, GROUPED, MLR, PERSIST>(P, ws, map, slots, arr_base, C,
+                                                               rows_act, item, n_items, v);
+  if constexpr (!PERSIST) {
+    if (it.live)
+      cols_transform<LOGL, NL, NT, GROUPED, MLR>(P, ws, it, arr_base, C, rows_act, v, lds, twl);
+  } else {
+    while (item < n_items) {
+      const int next = item + int(gridDim.x);
+      float2 vn[PER0][R0];
+      const ColItem nt = cols_fetch<LOGL, NL, NT, GROUPED, MLR, PERSIST>(
+          P, ws, map, slots, arr_base, C, rows_act, next, n_items, vn);
+      if (it.live) {
+        cols_transform<LOGL, NL, NT, GROUPED, MLR>(P, ws, it, arr_base, C, rows_act, v, lds,
+                                                   twl);
+        __syncthreads();
       }
-      __syncthreads();
-      fft_middle<LOGL, NL, NT, 1>(lds, twl);
-      // last stage: LDS -> registers -> DFT -> x W_N^{q c} -> HBM
-      constexpr int PER = (NBL + NT - 1) / NT;
 #pragma unroll
-      for (int s = 0; s < PER; ++s) {
-        const int b = tid + s * NT;
-        if (NBL % NT == 0 || b < NBL) {
-          const int line = b % NL, i = b / NL;
-          float2 u[RL];
+      for (int s = 0; s < PER0; ++s)
 #pragma unroll
-          for (int j = 0; j < RL; ++j) u[j] = lds[Lay::at(i + j * PL, line)];
-          twiddle_dft<RL, PL, L>(u, i, twl);
-          const int64_t c = it.c0 + line;
-          // W_N^{c (i + m PL)} = W_N^{c i} (W_N^{c PL})^m
-          float2 w = tw_n((int64_t(i) * c) & nmask, P.n_fft);
-          const float2 step = tw_n((int64_t(PL) * c) & nmask, P.n_fft);
-          const uint32_t voff = uint32_t((int64_t(i) * C + c) * int64_t(sizeof(float2)));
-#pragma unroll
-          for (int m = 0; m < RL; ++m) {
-            buf_store2(cmul(u[m], w), wr, voff,
-                       uint32_t(int64_t(m) * PL * C * int64_t(sizeof(float2))));
-            w = cmul(w, step);
-          }
-        }
-      }
-      __syncthreads();
+        for (int j = 0; j < R0; ++j) v[s][j] = vn[s][j];
+      it = nt;
+      item = next;
     }
-#pragma unroll
-    for (int s = 0; s < PER0; ++s)
-#pragma unroll
-      for (int j = 0; j < R0; ++j) v[s][j] = vn[s][j];
-    it = nt;
-    item = next;
   }
 }
 
@@ -371,21 +417,27 @@ struct RowItem {
   float l11, l21, l22;
 };
 
-template <int LOGL, int RQ, int NT, int MODE>
+template <int LOGL, int RQ, int NT, int MODE, int MLR, bool PERSIST>
 __device__ __forceinline__ RowItem rows_fetch(const PlanConst& P, void* ws, const ChunkMap& map,
                                               int item, int n_items,
-                                              float2 (&v)[((2 * RQ << LOGL) / (1 << stage_logr(LOGL, 0)) + NT - 1) / NT]
-                                                         [1 << stage_logr(LOGL, 0)]) {
+                                              float2 (&v)[kPer0<LOGL, 2 * RQ, NT, MLR>]
+                                                         [kR0<LOGL, MLR>]) {
   constexpr int L = 1 << LOGL;
   constexpr int NL = 2 * RQ;
-  constexpr int R0 = 1 << stage_logr(LOGL, 0), NBL0 = L / R0, NB0 = NL * NBL0;
-  constexpr int PER = (NB0 + NT - 1) / NT;
+  constexpr int R0 = kR0<LOGL, MLR>, NBL0 = L / R0, NB0 = NL * NBL0;
+  constexpr int PER = kPer0<LOGL, NL, NT, MLR>;
   RowItem it;
   it.live = it.flagged = 0;
   if (item >= n_items) return it;
-  const int n = map.n_tmpl;
-  it.g = item % n;
-  it.q0 = int64_t(item / n) * RQ;
+  if (PERSIST) {
+    const int n = map.n_tmpl;
+    it.g = item % n;
+    it.q0 = int64_t(item / n) * RQ;
+  } else {
+    const int n_gx = n_items / map.n_tmpl;
+    it.q0 = int64_t(item % n_gx) * RQ;
+    it.g = item / n_gx;
+  }
   it.tmpl = map.tmpl[it.g];
   const TmplParams& tp = *tmpl_params(ws, P, map, it.g);
   if (tp.status != 0) {
@@ -415,24 +467,117 @@ __device__ __forceinline__ RowItem rows_fetch(const PlanConst& P, void* ws, cons
   return it;
 }
 
-template <int LOGL, int RQ, int NT, int MODE>
+template <int LOGL, int RQ, int NT, int MODE, int MLR>
+__device__ __forceinline__ void rows_transform(const PlanConst& P, void* ws, const RowItem& it,
+                                               int64_t Rr, float* __restrict__ twoF,
+                                               float2* fafb, const float* __restrict__ gin,
+                                               float2 (&v)[kPer0<LOGL, 2 * RQ, NT, MLR>]
+                                                          [kR0<LOGL, MLR>],
+                                               float2* lds, const float2* twl) {
+  constexpr int L = 1 << LOGL;
+  constexpr int NL = 2 * RQ;
+  constexpr int NS = stage_count(LOGL, MLR);
+  constexpr int R0 = kR0<LOGL, MLR>, NBL0 = L / R0, NB0 = NL * NBL0;
+  constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = RQ * PL;
+  constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
+  using Lay = LdsLayout<L>;
+  const int64_t N = P.n_fft;
+  const int tid = threadIdx.x;
+  // stage 0: registers -> DFT -> LDS
+#pragma unroll
+  for (int s = 0; s < PER0; ++s) {
+    const int b = tid + s * NT;
+    if (NB0 % NT == 0 || b < NB0) {
+      const int i = b % NBL0, line = b / NBL0;
+      dft<R0>(v[s]);
+#pragma unroll
+      for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
+    }
+  }
+  __syncthreads();
+  fft_middle<LOGL, NL, NT, 1, MLR>(lds, twl);
+  // last stage of both arrays + epilogue
+  constexpr int PER = (NBL + NT - 1) / NT;
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int b = tid + s * NT;
+    if (NBL % NT == 0 || b < NBL) {
+      const int ql = b % RQ, i = b / RQ;
+      float2 va[RL], vb[RL];
+#pragma unroll
+      for (int j = 0; j < RL; ++j) {
+        va[j] = lds[Lay::at(i + j * PL, ql)];
+        vb[j] = lds[Lay::at(i + j * PL, RQ + ql)];
+      }
+      twiddle_dft<RL, PL, L>(va, i, twl);
+      twiddle_dft<RL, PL, L>(vb, i, twl);
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        const int64_t nat = it.q0 + ql + Rr * int64_t(i + m * PL);
+        if (MODE == kRowConj) {
+          if (nat < P.k_pad) {
+            slot_buf(ws, P, it.g, 0)[nat] = make_float2(va[m].x, -va[m].y);
+            slot_buf(ws, P, it.g, 1)[nat] = make_float2(vb[m].x, -vb[m].y);
+          }
+          continue;
+        }
+        const int64_t ib = (nat + N / 2) & (N - 1);
+        const bool in_band = ib >= P.bin_lo && ib < P.bin_lo + P.n_bins;
+        const int64_t o = ib - P.bin_lo;
+        const float2 fa = va[m], fb = vb[m];
+        if (MODE == kRowAdjoint) {
+          const float gv = in_band ? gin[it.tmpl * P.n_bins + o] : 0.0f;
+          slot_buf(ws, P, it.g, 2)[nat] = make_float2(gv * fa.x, -gv * fa.y);
+          slot_buf(ws, P, it.g, 3)[nat] = make_float2(gv * fb.x, -gv * fb.y);
+        }
+        if (!in_band) continue;
+        if (twoF)
+          twoF[it.tmpl * P.n_bins + o] =
+              2.0f * ((fa.x * fa.x + fa.y * fa.y) + (fb.x * fb.x + fb.y * fb.y));
+        if (fafb) {
+          // undo the whitening: Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
+          fafb[(it.tmpl * 2 + 0) * P.n_bins + o] = cscale(fa, it.l11);
+          fafb[(it.tmpl * 2 + 1) * P.n_bins + o] =
+              make_float2(it.l21 * fa.x + it.l22 * fb.x, it.l21 * fa.y + it.l22 * fb.y);
+        }
+      }
+    }
+  }
+}
+
+// A flagged template: NaN in every bin the item owns.
+template <int LOGL, int RQ, int NT>
+__device__ __forceinline__ void rows_flagged(const PlanConst& P, const RowItem& it, int64_t Rr,
+                                             float* __restrict__ twoF, float2* fafb) {
+  constexpr int L = 1 << LOGL;
+  const int64_t N = P.n_fft;
+  const float qnan = __builtin_nanf("");
+  for (int e = threadIdx.x; e < L * RQ; e += NT) {
+    const int ql = e % RQ, p = e / RQ;
+    const int64_t i = (it.q0 + ql + Rr * p + N / 2) & (N - 1);
+    if (i < P.bin_lo || i >= P.bin_lo + P.n_bins) continue;
+    const int64_t o = i - P.bin_lo;
+    if (twoF) twoF[it.tmpl * P.n_bins + o] = qnan;
+    if (fafb) {
+      fafb[(it.tmpl * 2 + 0) * P.n_bins + o] = make_float2(qnan, qnan);
+      fafb[(it.tmpl * 2 + 1) * P.n_bins + o] = make_float2(qnan, qnan);
+    }
+  }
+}
+
+template <int LOGL, int RQ, int NT, int MODE, int MLR, bool PERSIST>
 __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap map, int slots,
                                                  int log_rr, float* __restrict__ twoF,
                                                  float2* fafb, const float* __restrict__ gin) {
   extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
   constexpr int NL = 2 * RQ;
-  constexpr int NS = stage_count(LOGL);
-  constexpr int R0 = 1 << stage_logr(LOGL, 0), NBL0 = L / R0, NB0 = NL * NBL0;
-  constexpr int RL = 1 << stage_logr(LOGL, NS - 1), PL = L / RL, NBL = RQ * PL;
-  constexpr int PER0 = (NB0 + NT - 1) / NT;
-  using Lay = LdsLayout<L>;
-  float2* twl = lds + NL * Lay::pitch;
+  constexpr int R0 = kR0<LOGL, MLR>;
+  constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
+  float2* twl = lds + NL * LdsLayout<L>::pitch;
   const int64_t Rr = int64_t(1) << log_rr;
-  const int64_t N = P.n_fft;
   const int tid = threadIdx.x;
   const int n_items = int(Rr / RQ) * map.n_tmpl;
-  const float qnan = __builtin_nanf("");
   // grouped path: every reader of the group buffers the next chunk resamples
   // has finished (column pass of this chunk), so their status words restart
   if (blockIdx.x == 0 && tid < map.n_reset) *group_status(ws, P, slots, map.reset_buf[tid]) = 0;
@@ -440,96 +585,31 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
     const float2* __restrict__ tws = tw_stage(ws);
     for (int e = tid; e < L / 2; e += NT) twl[e] = tws[e * (kTwLen / L)];
   }
-  int item = blockIdx.x;
+  int item = PERSIST ? int(blockIdx.x) : int(xcd_remap(blockIdx.x, gridDim.x));
   float2 v[PER0][R0];
-  RowItem it = rows_fetch<LOGL, RQ, NT, MODE>(P, ws, map, item, n_items, v);
-  while (item < n_items) {
-    const int next = item + int(gridDim.x);
-    float2 vn[PER0][R0];
-    const RowItem nt = rows_fetch<LOGL, RQ, NT, MODE>(P, ws, map, next, n_items, vn);
-    if (it.flagged && MODE != kRowConj) {
-      // flagged template: NaN in every bin this item owns
-      for (int e = tid; e < L * RQ; e += NT) {
-        const int ql = e % RQ, p = e / RQ;
-        const int64_t i = (it.q0 + ql + Rr * p + N / 2) & (N - 1);
-        if (i < P.bin_lo || i >= P.bin_lo + P.n_bins) continue;
-        const int64_t o = i - P.bin_lo;
-        if (twoF) twoF[it.tmpl * P.n_bins + o] = qnan;
-        if (fafb) {
-          fafb[(it.tmpl * 2 + 0) * P.n_bins + o] = make_float2(qnan, qnan);
-          fafb[(it.tmpl * 2 + 1) * P.n_bins + o] = make_float2(qnan, qnan);
-        }
+  RowItem it = rows_fetch<LOGL, RQ, NT, MODE, MLR, PERSIST>(P, ws, map, item, n_items, v);
+  if constexpr (!PERSIST) {
+    if (it.flagged && MODE != kRowConj) rows_flagged<LOGL, RQ, NT>(P, it, Rr, twoF, fafb);
+    if (it.live)
+      rows_transform<LOGL, RQ, NT, MODE, MLR>(P, ws, it, Rr, twoF, fafb, gin, v, lds, twl);
+  } else {
+    while (item < n_items) {
+      const int next = item + int(gridDim.x);
+      float2 vn[PER0][R0];
+      const RowItem nt = rows_fetch<LOGL, RQ, NT, MODE, MLR, PERSIST>(P, ws, map, next, n_items,
+                                                                      vn);
+      if (it.flagged && MODE != kRowConj) rows_flagged<LOGL, RQ, NT>(P, it, Rr, twoF, fafb);
+      if (it.live) {
+        rows_transform<LOGL, RQ, NT, MODE, MLR>(P, ws, it, Rr, twoF, fafb, gin, v, lds, twl);
+        __syncthreads();
       }
+#pragma unroll
+      for (int s = 0; s < PER0; ++s)
+#pragma unroll
+        for (int j = 0; j < R0; ++j) v[s][j] = vn[s][j];
+      it = nt;
+      item = next;
     }
-    if (it.live) {
-      // stage 0: registers -> DFT -> LDS
-#pragma unroll
-      for (int s = 0; s < PER0; ++s) {
-        const int b = tid + s * NT;
-        if (NB0 % NT == 0 || b < NB0) {
-          const int i = b % NBL0, line = b / NBL0;
-          dft<R0>(v[s]);
-#pragma unroll
-          for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
-        }
-      }
-      __syncthreads();
-      fft_middle<LOGL, NL, NT, 1>(lds, twl);
-      // last stage of both arrays + epilogue
-      constexpr int PER = (NBL + NT - 1) / NT;
-#pragma unroll
-      for (int s = 0; s < PER; ++s) {
-        const int b = tid + s * NT;
-        if (NBL % NT == 0 || b < NBL) {
-          const int ql = b % RQ, i = b / RQ;
-          float2 va[RL], vb[RL];
-#pragma unroll
-          for (int j = 0; j < RL; ++j) {
-            va[j] = lds[Lay::at(i + j * PL, ql)];
-            vb[j] = lds[Lay::at(i + j * PL, RQ + ql)];
-          }
-          twiddle_dft<RL, PL, L>(va, i, twl);
-          twiddle_dft<RL, PL, L>(vb, i, twl);
-#pragma unroll
-          for (int m = 0; m < RL; ++m) {
-            const int64_t nat = it.q0 + ql + Rr * int64_t(i + m * PL);
-            if (MODE == kRowConj) {
-              if (nat < P.k_pad) {
-                slot_buf(ws, P, it.g, 0)[nat] = make_float2(va[m].x, -va[m].y);
-                slot_buf(ws, P, it.g, 1)[nat] = make_float2(vb[m].x, -vb[m].y);
-              }
-              continue;
-            }
-            const int64_t ib = (nat + N / 2) & (N - 1);
-            const bool in_band = ib >= P.bin_lo && ib < P.bin_lo + P.n_bins;
-            const int64_t o = ib - P.bin_lo;
-            const float2 fa = va[m], fb = vb[m];
-            if (MODE == kRowAdjoint) {
-              const float gv = in_band ? gin[it.tmpl * P.n_bins + o] : 0.0f;
-              slot_buf(ws, P, it.g, 2)[nat] = make_float2(gv * fa.x, -gv * fa.y);
-              slot_buf(ws, P, it.g, 3)[nat] = make_float2(gv * fb.x, -gv * fb.y);
-            }
-            if (!in_band) continue;
-            if (twoF)
-              twoF[it.tmpl * P.n_bins + o] =
-                  2.0f * ((fa.x * fa.x + fa.y * fa.y) + (fb.x * fb.x + fb.y * fb.y));
-            if (fafb) {
-              // undo the whitening: Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
-              fafb[(it.tmpl * 2 + 0) * P.n_bins + o] = cscale(fa, it.l11);
-              fafb[(it.tmpl * 2 + 1) * P.n_bins + o] =
-                  make_float2(it.l21 * fa.x + it.l22 * fb.x, it.l21 * fa.y + it.l22 * fb.y);
-            }
-          }
-        }
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int s = 0; s < PER0; ++s)
-#pragma unroll
-      for (int j = 0; j < R0; ++j) v[s][j] = vn[s][j];
-    it = nt;
-    item = next;
   }
 }
 

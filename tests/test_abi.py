@@ -101,9 +101,10 @@ def test_plan_accepts_valid_setup(lib):
     p = B.Plan(d)
     # every documented tuning choice is accepted (n_fft = 2^13: columns 2^6 x rows 2^7 by default)
     for log_len, cl, rl in ((7, 64, 32), (7, 32, 16), (6, 64, 32), (6, 32, 16)):
-        for grid in (0, 1):
+        for grid, radix in ((0, 0), (1, 16), (1, 32), (2, 16), (2, 32)):
             d2 = B.make_plan_desc(ds, dict(tune_col_log_len=log_len, tune_col_lines=cl,
-                                           tune_row_lines=rl, tune_fft_grid=grid))
+                                           tune_row_lines=rl, tune_fft_grid=grid,
+                                           tune_fft_radix=radix))
             B.Plan(d2)
     k_pad, lc, lr = p.info()
     assert (lc, lr) == (6, 7) and k_pad % (1 << lr) == 0 and k_pad % 1024 == 0
@@ -137,7 +138,8 @@ def test_plan_accepts_valid_setup(lib):
     (lambda d: setattr(d, "tune_col_log_len", 13), "tune_col_log_len"),
     (lambda d: setattr(d, "tune_col_lines", 3), "tune_col_lines"),
     (lambda d: setattr(d, "tune_row_lines", 7), "tune_row_lines"),
-    (lambda d: setattr(d, "tune_fft_grid", 2), "tune_fft_grid"),
+    (lambda d: setattr(d, "tune_fft_grid", 3), "tune_fft_grid"),
+    (lambda d: setattr(d, "tune_fft_radix", 8), "tune_fft_radix"),
     (lambda d: (setattr(d, "n_fft", 1 << 12), setattr(d, "n_bins", 1 << 12),
                setattr(d.det[0], "n", 4000)), "too short"),
 ])
