@@ -34,9 +34,9 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # figures hold for the kernel sources, header and build flags with this
 # digest; for any other version the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "f56fd7634617d653edb3d9e51e5e58a901904f564e00b58c43a9225b4e1d6f1a",
-    "bytes_per_template": {"fft_columns": 13884597 + 33799691,
-                           "fft_rows_2f": 33569966 + 8592618},
+    "sources_sha256": "271a0457330808b1eae122c1cad213bc18d0226e3b098c75ace472f0ff1c3711",
+    "bytes_per_template": {"fft_columns": 13885207 + 33954990,
+                           "fft_rows_2f": 33598476 + 8613463},
 }
 
 
@@ -147,6 +147,9 @@ def main():
     ap.add_argument("--batch", type=int, default=32, help="templates in flight per launch")
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--graph-steps", type=int, default=5)
+    ap.add_argument("--cand-steps", type=int, default=5,
+                    help="timed steps of the candidate-retention epilogue (0: skip)")
+    ap.add_argument("--cand-threshold", type=float, default=40.0)
     ap.add_argument("--cpu-templates", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--refine-calls", type=int, default=10,
@@ -252,6 +255,19 @@ def main():
         graph = timed(run_graph, args.graph_steps)
         del srg
 
+    # the same search keeping only bins above a 2F threshold (and the loudest
+    # bin per template) instead of writing the full band
+    cand = None
+    if args.cand_steps > 0:
+        print("bench: candidate retention", file=sys.stderr, flush=True)
+        cap = 1 << 20
+        res = sr.run_candidates(args.cand_threshold, capacity=cap)
+        cand = timed(lambda: sr.run_candidates(args.cand_threshold, capacity=cap),
+                     args.cand_steps)
+        cand.update({"threshold": args.cand_threshold, "candidates": res["count"],
+                     "capacity": cap})
+        del res
+
     # every template resampled on its own, several templates per launch
     ungrouped = None
     plain = None
@@ -304,6 +320,7 @@ def main():
                    "position, spin-down phase applied in the FFT load",
                    "sky_orbit_groups": sr.ngroups},
         "graph_replay": graph,
+        "candidates": cand,
         "batched_ungrouped": ungrouped,
         "plain": plain,
         "batched_over_plain": round(value / plain["value"], 3) if plain else None,

@@ -75,22 +75,29 @@ typedef struct {
    * only how the work is laid out, never the result beyond FP32 rounding:
    *   tune_col_log_len: log2 of the column-pass FFT length, the row pass has
    *     log2(n_fft) - tune_col_log_len; both must lie in [6, 12];
-   *   tune_col_lines: columns per workgroup of the column pass;
-   *   tune_row_lines: rows per workgroup of the row pass;
-   *   tune_fft_grid: 1 = one workgroup per work item, 2 = persistent
-   *     workgroups (as many as fit the device at once, each looping over work
-   *     items with the next item's loads in flight);
-   *   tune_fft_radix: largest radix of a Stockham stage, 16 or 32.
-   * Accepted line counts are the largest (as many as fit 128 KiB of LDS, one
-   * 512-thread workgroup per compute unit) or half of it (256-thread
-   * workgroups, two per compute unit: the automatic choice). */
+   *   tune_col_lines: columns per workgroup of the column pass: the largest
+   *     count that fits 128 KiB of LDS (512 threads, one workgroup per compute
+   *     unit) or half of it (256 threads, two per unit: the automatic choice);
+   *   tune_row_lines: rows per workgroup of the row pass (the a and b rows
+   *     together): the largest count (512 threads: the automatic choice) or
+   *     half of it (256 threads);
+   *   tune_fft_radix: largest radix of a Stockham stage, 16 or 32 (automatic:
+   *     32, so lines of 2^9 and 2^10 points take two stages). */
   int32_t tune_col_log_len;
   int32_t tune_col_lines;
   int32_t tune_row_lines;
-  int32_t tune_fft_grid;
   int32_t tune_fft_radix;
   uint32_t flags;                      /* reserved, must be 0 */
 } fstat_plan_desc;
+
+/* A candidate of the search (device memory, written by
+ * fstat_search_run_candidates): template index, bin in the band, 2F. */
+typedef struct {
+  int32_t tmpl;
+  int32_t bin;
+  float twoF;
+  int32_t reserved;
+} fstat_candidate;
 
 /* Device-resident data, crossed to the device once (Sec. 3: the host-to-device
  * copy happens only between steps (ii) and (iii)). */
@@ -192,16 +199,23 @@ FSTAT_API fstat_status fstat_compute_2f_profiled(const fstat_plan* plan, const f
  *
  * fstat_search_create plans the bank from a HOST copy of the templates (the
  * same rows the device array will hold at run time, in the same order),
- * with `slots` (1..32) templates in flight per launch sequence; flags may be
- * FSTAT_SEARCH_GRAPH: fstat_search_run then captures its launch sequence in
- * a HIP graph on the first call and replays it while the pointers it was
- * captured with (inputs, templates, outputs, workspace) stay the same
- * (needs a non-null stream).  The search keeps a pointer to the plan, which
+ * with `slots` (1..32) templates in flight per launch sequence; flags may
+ * combine FSTAT_SEARCH_GRAPH: the run functions capture their launch sequence
+ * in a HIP graph on the first call and replay it while the arguments it was
+ * captured with (inputs, templates, outputs, threshold, workspace) stay the
+ * same (needs a non-null stream); and FSTAT_SEARCH_ACCUMULATE:
+ * fstat_search_run adds 2F to twoF instead of storing it, so that runs over
+ * several data segments with the same grid (dt, n_fft, f_het, t_ref, band)
+ * sum 2F over the segments on the device (the semi-coherent sum the paper's
+ * follow-up search uses; NaN stays NaN; the caller clears twoF before the
+ * first segment; fstat_search_run_candidates ignores the flag).  The search
+ * keeps a pointer to the plan, which
  * must outlive it.  fstat_search_info reports the workspace bytes, the
  * number of groups and of launch sequences.  fstat_search_run_profiled runs
  * without a graph and returns per-kernel device time like
  * fstat_compute_2f_profiled (synchronises the stream). */
 #define FSTAT_SEARCH_GRAPH 1u
+#define FSTAT_SEARCH_ACCUMULATE 2u
 typedef struct fstat_search fstat_search;  /* opaque, host memory owned by the library */
 FSTAT_API fstat_status fstat_search_create(const fstat_plan* plan, const double* templates_host,
                                            int64_t ntmpl, int32_t slots, uint32_t flags,
@@ -212,6 +226,21 @@ FSTAT_API fstat_status fstat_search_info(const fstat_search* search, size_t* ws_
 FSTAT_API fstat_status fstat_search_run(fstat_search* search, const fstat_inputs* in,
                                         const double* templates, float* twoF, void* fafb,
                                         void* workspace, size_t ws_bytes, void* stream);
+/* Candidate retention on the device instead of the full band: every bin
+ * whose 2F exceeds `threshold` is appended to cand (device fstat_candidate
+ * [capacity]) in no particular order; *count (device int64) receives the
+ * number of such bins, which may exceed capacity (then only capacity of them
+ * are stored).  best (nullable, device uint64 [ntmpl]) receives per template
+ * the largest 2F and its bin packed as (IEEE bits of 2F << 32) | bin (all
+ * ones for a flagged template; equal maxima resolve to the highest bin).
+ * Both are cleared by the call itself.  No 2F array is written.  Candidates
+ * of one run are unique; their order is not. */
+FSTAT_API fstat_status fstat_search_run_candidates(fstat_search* search, const fstat_inputs* in,
+                                                   const double* templates, float threshold,
+                                                   fstat_candidate* cand, int64_t capacity,
+                                                   int64_t* count, uint64_t* best,
+                                                   void* workspace, size_t ws_bytes,
+                                                   void* stream);
 FSTAT_API fstat_status fstat_search_run_profiled(fstat_search* search, const fstat_inputs* in,
                                                  const double* templates, float* twoF,
                                                  void* workspace, size_t ws_bytes, void* stream,
@@ -220,7 +249,7 @@ FSTAT_API fstat_status fstat_search_run_profiled(fstat_search* search, const fst
 /* Launch-shape autotuner: for the set-up *desc (its tune fields ignored),
  * times every FFT launch shape the plan accepts (both column/row splits of
  * n_fft around its square root, full or half line counts for each pass,
- * persistent or one-workgroup-per-item grids) by running the batched path
+ * radix-16 or radix-32 stage plans) by running the batched path
  * on the given sample of templates (device [ntmpl][8], ntmpl >= 1; twoF a
  * device [ntmpl][n_bins] scratch output) with the given workspace, once
  * untimed and once timed with HIP events, and returns the fastest

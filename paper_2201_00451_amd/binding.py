@@ -24,11 +24,13 @@ EXPORTED = ("fstat_plan_create", "fstat_plan_destroy", "fstat_workspace_size",
             "fstat_last_error", "fstat_version", "fstat_search_create", "fstat_search_destroy",
             "fstat_search_info", "fstat_search_run", "fstat_search_run_profiled",
             "fstat_grad_workspace_size", "fstat_compute_2f_grad", "fstat_plan_info",
-            "fstat_grad_bin_workspace_size", "fstat_compute_2f_grad_bin", "fstat_autotune")
+            "fstat_grad_bin_workspace_size", "fstat_compute_2f_grad_bin", "fstat_autotune",
+            "fstat_search_run_candidates")
 GRAD_PARAMS = ("df", "f1dot", "alpha", "delta", "asini", "porb", "tp")
 # template-row column of each gradient parameter
 GRAD_COLUMNS = (2, 3, 0, 1, 5, 6, 7)
 SEARCH_GRAPH = 1
+SEARCH_ACCUMULATE = 2
 
 
 class FstatDetector(ctypes.Structure):
@@ -45,8 +47,8 @@ class FstatPlanDesc(ctypes.Structure):
                 ("sid_rate", ctypes.c_double), ("n_fft", ctypes.c_int64),
                 ("bin_lo", ctypes.c_int64), ("n_bins", ctypes.c_int64),
                 ("tune_col_log_len", ctypes.c_int32), ("tune_col_lines", ctypes.c_int32),
-                ("tune_row_lines", ctypes.c_int32), ("tune_fft_grid", ctypes.c_int32),
-                ("tune_fft_radix", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("tune_row_lines", ctypes.c_int32), ("tune_fft_radix", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
 
 
 class FstatInputs(ctypes.Structure):
@@ -94,6 +96,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fstat_search_info.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64)]
     lib.fstat_search_run.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, vp, vp, vp, sz, vp]
+    lib.fstat_search_run_candidates.argtypes = [vp, ctypes.POINTER(FstatInputs), vp,
+                                                ctypes.c_float, vp, i64, vp, vp, vp, sz, vp]
     lib.fstat_search_run_profiled.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, vp, vp, sz, vp,
                                               ctypes.POINTER(ctypes.c_float),
                                               ctypes.POINTER(ctypes.c_int64)]
@@ -432,8 +436,7 @@ def refine(dd: DeviceData, templates, bins, scales, steps=50, lr=0.5, free=None)
     return rows.numpy(), cur.numpy()
 
 
-TUNE_FIELDS = ("tune_col_log_len", "tune_col_lines", "tune_row_lines", "tune_fft_grid",
-               "tune_fft_radix")
+TUNE_FIELDS = ("tune_col_log_len", "tune_col_lines", "tune_row_lines", "tune_fft_radix")
 
 
 def autotune(ds, templates, batch=8, device="cuda:0", stream=None):
@@ -463,7 +466,7 @@ class Search:
     sky position and orbit are resampled once.  ``templates`` is the bank in
     host memory; the same rows are copied to the device once."""
 
-    def __init__(self, dd: DeviceData, templates, slots=8, graph=False):
+    def __init__(self, dd: DeviceData, templates, slots=8, graph=False, accumulate=False):
         import torch
         lib = load_library()
         host = np.ascontiguousarray(np.asarray(templates, dtype=np.float64))
@@ -471,9 +474,9 @@ class Search:
             raise FstatError(FSTAT_EINVAL, "templates must have shape [n, 8]")
         self.dd, self.ntmpl = dd, host.shape[0]
         h = ctypes.c_void_p()
+        flags = (SEARCH_GRAPH if graph else 0) | (SEARCH_ACCUMULATE if accumulate else 0)
         _check(lib.fstat_search_create(dd.plan.handle, host.ctypes.data_as(ctypes.c_void_p),
-                                       self.ntmpl, int(slots), SEARCH_GRAPH if graph else 0,
-                                       ctypes.byref(h)))
+                                       self.ntmpl, int(slots), flags, ctypes.byref(h)))
         self.handle = h
         ws, ng, nc = ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib.fstat_search_info(h, ctypes.byref(ws), ctypes.byref(ng), ctypes.byref(nc)))
@@ -493,6 +496,31 @@ class Search:
                                                _ptr(self.templates), _ptr(tf), _ptr(fab),
                                                _ptr(self.ws), self.ws.numel(), _stream_ptr(stream)))
         return (tf, fab) if fafb else tf
+
+    def run_candidates(self, threshold, capacity=1 << 16, stream=None):
+        """Candidate retention (fstat_search_run_candidates): returns a dict with
+        the device tensors tmpl, bin (int32), twoF (float32) of the stored
+        candidates (unordered), the total count (a Python int: may exceed
+        capacity), and per template best_twoF (float32; NaN for a flagged
+        template) and best_bin (int64).  Synchronises the stream."""
+        import torch
+        dd = self.dd
+        cand = torch.empty((max(int(capacity), 1), 4), dtype=torch.int32, device=dd.device)
+        count = torch.empty(1, dtype=torch.int64, device=dd.device)
+        best = torch.empty(max(self.ntmpl, 1), dtype=torch.int64, device=dd.device)
+        _check(load_library().fstat_search_run_candidates(
+            self.handle, ctypes.byref(dd.inputs), _ptr(self.templates), float(threshold),
+            _ptr(cand), int(capacity), _ptr(count), _ptr(best), _ptr(self.ws), self.ws.numel(),
+            _stream_ptr(stream)))
+        n = int(count.item())
+        kept = cand[:min(n, int(capacity))]
+        flagged = best == -1
+        hi = (best >> 32) & 0xFFFFFFFF
+        best_twoF = hi.to(torch.int32).view(torch.float32).clone()
+        best_twoF[flagged] = float("nan")
+        return {"tmpl": kept[:, 0], "bin": kept[:, 1], "twoF": kept[:, 2].view(torch.float32),
+                "count": n, "best_twoF": best_twoF[:self.ntmpl],
+                "best_bin": (best & 0xFFFFFFFF)[:self.ntmpl]}
 
     def run_profiled(self, out=None, stream=None):
         import torch

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kResThreads) void k_grad(PlanConst P, void* ws) {
 #pragma unroll
   for (int i = 0; i < kResPerThread; ++i) {
     const int64_t k = k_s + tid + i * kResThreads;
-    const float2 e = spindown_rotation(P, tp.f1dot, tp.f2dot, tp.df, k);
+    const float2 e = spindown_rotation(tp.sd, k);
     if (ONEHOT) {
       const float2 tw = bin_twiddle(tp.bin_nat, k, P.n_fft);
       Wa[i] = cmul(cmul(make_float2(float(tp.hbin[0]), float(tp.hbin[1])), tw), e);

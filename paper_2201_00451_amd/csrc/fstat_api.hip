@@ -26,7 +26,6 @@ struct fstat_plan {
   int cols_lines, rows_lines;
   bool cols_half, rows_half;
   int fft_mlr;       // largest stage radix 2^fft_mlr
-  bool fft_persist;  // persistent FFT workgroups
   int64_t k_pad, rows_act;
   double t_lo, t_hi;         // time range any timing evaluation may touch
 };
@@ -67,7 +66,7 @@ int cols_lines_max(int log_rr) { return std::min(64, 16384 >> log_rr); }
 int rows_lines_max(int log_c) { return std::min(32, 8192 >> log_c); }
 
 using ColsFn = void (*)(PlanConst, void*, ChunkMap, int, int, int, int64_t);
-using RowsFn = void (*)(PlanConst, void*, ChunkMap, int, int, float*, float2*, const float*);
+using RowsFn = void (*)(PlanConst, void*, ChunkMap, int, int, RowOutput);
 
 template <int LOGL>
 constexpr int kColsMax = (16384 >> LOGL) < 64 ? (16384 >> LOGL) : 64;
@@ -79,80 +78,63 @@ struct FftVariant {
   int threads;
 };
 
-// Variant choice of an FFT pass: full or half line count (half: 256 threads),
-// largest stage radix 2^mlr (mlr 4 or 5; only line lengths 2^9 and 2^10 have
-// a different stage plan with 2^5), persistent or one workgroup per item.
+// Variant choice of the FFT passes: full or half line counts (512 or 256
+// threads), largest stage radix 2^mlr (mlr 4 or 5; only line lengths 2^9 and
+// 2^10 have a different stage plan with 2^5).
 struct FftChoice {
   bool half;
   int mlr;
-  bool persist;
 };
 
-template <int LOGL, bool GROUPED, int MLR, bool PERSIST>
+template <int LOGL, bool GROUPED, int MLR>
 FftVariant cols_variant(bool half) {
   if (half)
-    return {reinterpret_cast<const void*>(
-                &k_fft_cols<LOGL, kColsMax<LOGL> / 2, 256, GROUPED, MLR, PERSIST>),
+    return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL> / 2, 256, GROUPED, MLR>),
             256};
-  return {reinterpret_cast<const void*>(
-              &k_fft_cols<LOGL, kColsMax<LOGL>, 512, GROUPED, MLR, PERSIST>),
+  return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL>, 512, GROUPED, MLR>),
           512};
 }
-template <int LOGL, int MODE, int MLR, bool PERSIST>
+template <int LOGL, int MODE, int MLR>
 FftVariant rows_variant(bool half) {
   if (half)
-    return {reinterpret_cast<const void*>(
-                &k_fft_rows<LOGL, kRowsMax<LOGL> / 2, 256, MODE, MLR, PERSIST>),
+    return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, kRowsMax<LOGL> / 2, 256, MODE, MLR>),
             256};
-  return {reinterpret_cast<const void*>(
-              &k_fft_rows<LOGL, kRowsMax<LOGL>, 512, MODE, MLR, PERSIST>),
-          512};
+  return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, kRowsMax<LOGL>, 512, MODE, MLR>), 512};
 }
 
-template <bool GROUPED, int MLR, bool PERSIST>
+template <bool GROUPED, int MLR>
 FftVariant pick_cols_v(int logl, bool half) {
   switch (logl) {
-    case 6: return cols_variant<6, GROUPED, 4, PERSIST>(half);
-    case 7: return cols_variant<7, GROUPED, 4, PERSIST>(half);
-    case 8: return cols_variant<8, GROUPED, 4, PERSIST>(half);
-    case 9: return cols_variant<9, GROUPED, MLR, PERSIST>(half);
-    case 10: return cols_variant<10, GROUPED, MLR, PERSIST>(half);
-    case 11: return cols_variant<11, GROUPED, 4, PERSIST>(half);
-    case 12: return cols_variant<12, GROUPED, 4, PERSIST>(half);
+    case 6: return cols_variant<6, GROUPED, 4>(half);
+    case 7: return cols_variant<7, GROUPED, 4>(half);
+    case 8: return cols_variant<8, GROUPED, 4>(half);
+    case 9: return cols_variant<9, GROUPED, MLR>(half);
+    case 10: return cols_variant<10, GROUPED, MLR>(half);
+    case 11: return cols_variant<11, GROUPED, 4>(half);
+    case 12: return cols_variant<12, GROUPED, 4>(half);
     default: return {nullptr, 0};
   }
 }
-template <bool GROUPED>
-FftVariant pick_cols_g(int logl, const FftChoice& c) {
-  if (c.mlr == 5)
-    return c.persist ? pick_cols_v<GROUPED, 5, true>(logl, c.half)
-                     : pick_cols_v<GROUPED, 5, false>(logl, c.half);
-  return c.persist ? pick_cols_v<GROUPED, 4, true>(logl, c.half)
-                   : pick_cols_v<GROUPED, 4, false>(logl, c.half);
-}
 FftVariant pick_cols(int logl, const FftChoice& c, bool grouped) {
-  return grouped ? pick_cols_g<true>(logl, c) : pick_cols_g<false>(logl, c);
+  if (c.mlr == 5) return grouped ? pick_cols_v<true, 5>(logl, c.half) : pick_cols_v<false, 5>(logl, c.half);
+  return grouped ? pick_cols_v<true, 4>(logl, c.half) : pick_cols_v<false, 4>(logl, c.half);
 }
-template <int MODE, int MLR, bool PERSIST>
+template <int MODE, int MLR>
 FftVariant pick_rows_v(int logl, bool half) {
   switch (logl) {
-    case 6: return rows_variant<6, MODE, 4, PERSIST>(half);
-    case 7: return rows_variant<7, MODE, 4, PERSIST>(half);
-    case 8: return rows_variant<8, MODE, 4, PERSIST>(half);
-    case 9: return rows_variant<9, MODE, MLR, PERSIST>(half);
-    case 10: return rows_variant<10, MODE, MLR, PERSIST>(half);
-    case 11: return rows_variant<11, MODE, 4, PERSIST>(half);
-    case 12: return rows_variant<12, MODE, 4, PERSIST>(half);
+    case 6: return rows_variant<6, MODE, 4>(half);
+    case 7: return rows_variant<7, MODE, 4>(half);
+    case 8: return rows_variant<8, MODE, 4>(half);
+    case 9: return rows_variant<9, MODE, MLR>(half);
+    case 10: return rows_variant<10, MODE, MLR>(half);
+    case 11: return rows_variant<11, MODE, 4>(half);
+    case 12: return rows_variant<12, MODE, 4>(half);
     default: return {nullptr, 0};
   }
 }
 template <int MODE>
 FftVariant pick_rows_m(int logl, const FftChoice& c) {
-  if (c.mlr == 5)
-    return c.persist ? pick_rows_v<MODE, 5, true>(logl, c.half)
-                     : pick_rows_v<MODE, 5, false>(logl, c.half);
-  return c.persist ? pick_rows_v<MODE, 4, true>(logl, c.half)
-                   : pick_rows_v<MODE, 4, false>(logl, c.half);
+  return c.mlr == 5 ? pick_rows_v<MODE, 5>(logl, c.half) : pick_rows_v<MODE, 4>(logl, c.half);
 }
 FftVariant pick_rows(int logl, const FftChoice& c, int mode = kRow2F) {
   return mode == kRowAdjoint ? pick_rows_m<kRowAdjoint>(logl, c)
@@ -160,8 +142,8 @@ FftVariant pick_rows(int logl, const FftChoice& c, int mode = kRow2F) {
                              : pick_rows_m<kRow2F>(logl, c);
 }
 
-FftChoice cols_choice(const fstat_plan* p) { return {p->cols_half, p->fft_mlr, p->fft_persist}; }
-FftChoice rows_choice(const fstat_plan* p) { return {p->rows_half, p->fft_mlr, p->fft_persist}; }
+FftChoice cols_choice(const fstat_plan* p) { return {p->cols_half, p->fft_mlr}; }
+FftChoice rows_choice(const fstat_plan* p) { return {p->rows_half, p->fft_mlr}; }
 
 fstat_status check_hip(hipError_t e, const char* what) {
   if (e != hipSuccess) return fail(FSTAT_EHIP, "%s: %s", what, hipGetErrorString(e));
@@ -294,44 +276,9 @@ fstat_status validate_ws(const fstat_plan* p, void* ws, size_t ws_bytes, int64_t
 size_t lds_bytes_cols(const fstat_plan* p) { return fft_lds_bytes(p->log_rr, p->cols_lines); }
 size_t lds_bytes_rows(const fstat_plan* p) { return fft_lds_bytes(p->log_c, 2 * p->rows_lines); }
 
-// Workgroups of an FFT pass over n_items work items: one per item, or
-// (persistent, the default) as many as the device holds at once, from the
-// compute-unit count and the occupancy of that kernel at its LDS size (kept
-// per kernel, LDS size and device).
-unsigned fft_grid(const fstat_plan* p, const FftVariant& v, size_t lds, int64_t n_items) {
-  if (n_items < 1) return 1;
-  if (!p->fft_persist) return unsigned(n_items);
-  struct Entry {
-    const void* fn;
-    size_t lds;
-    int dev, blocks;
-  };
-  static std::mutex mu;
-  static std::vector<Entry> cache;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) {
-    (void)hipGetLastError();
-    return unsigned(n_items);
-  }
-  int blocks = 0;
-  {
-    std::lock_guard<std::mutex> lock(mu);
-    for (const Entry& e : cache)
-      if (e.fn == v.fn && e.lds == lds && e.dev == dev) blocks = e.blocks;
-  }
-  if (blocks == 0) {
-    int cus = 0, per = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, v.fn, v.threads, lds) != hipSuccess ||
-        cus < 1 || per < 1) {
-      (void)hipGetLastError();
-      return unsigned(n_items);
-    }
-    blocks = cus * per;
-    std::lock_guard<std::mutex> lock(mu);
-    cache.push_back({v.fn, lds, dev, blocks});
-  }
-  return unsigned(std::min<int64_t>(n_items, blocks));
+// One workgroup per FFT work item.
+unsigned fft_grid(const fstat_plan*, const FftVariant&, size_t, int64_t n_items) {
+  return unsigned(std::max<int64_t>(n_items, 1));
 }
 int64_t cols_items(const fstat_plan* p, int n) {
   return ((int64_t(1) << p->log_c) / p->cols_lines) * 2 * n;
@@ -383,8 +330,16 @@ struct KernelTimer {
 // chunk's map names the sky/orbit groups to resample (possibly none, when a
 // group continues from the previous chunk) and the group buffer every slot
 // reads.  y_out: diagnostic path (resampled series only, per template).
+RowOutput row_output(float* twoF, float2* fafb) {
+  RowOutput o;
+  std::memset(&o, 0, sizeof o);
+  o.twoF = twoF;
+  o.fafb = fafb;
+  return o;
+}
+
 fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double* templates,
-                          const ChunkMap& map, int slots, bool grouped, float* twoF, float2* fafb,
+                          const ChunkMap& map, int slots, bool grouped, const RowOutput& out,
                           float2* y_out, void* ws, hipStream_t st, KernelTimer& tm) {
   fstat_status s;
   const int n = map.n_tmpl;
@@ -417,8 +372,7 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
   if ((s = tm.mark(3)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rv.fn)),
                      dim3(fft_grid(p, rv, lds_bytes_rows(p), rows_items(p, n))),
-                     dim3(rv.threads), lds_bytes_rows(p), st, P, ws, map, slots, p->log_rr, twoF,
-                     fafb, static_cast<const float*>(nullptr));
+                     dim3(rv.threads), lds_bytes_rows(p), st, P, ws, map, slots, p->log_rr, out);
   if ((s = tm.mark(3)) != FSTAT_OK) return s;
   return check_hip(hipGetLastError(), "kernel launch");
 }
@@ -485,8 +439,9 @@ fstat_status run(const fstat_plan* p, const fstat_inputs* in, const double* temp
     std::memset(&map, 0, sizeof map);
     map.n_tmpl = int(std::min<int64_t>(slots, ntmpl - t));
     for (int i = 0; i < map.n_tmpl; ++i) map.tmpl[i] = t + i;
-    s = launch_chunk(p, P, templates, map, int(slots), false, twoF, static_cast<float2*>(fafb),
-                     static_cast<float2*>(y_out), ws, st, tm);
+    s = launch_chunk(p, P, templates, map, int(slots), false,
+                     row_output(twoF, static_cast<float2*>(fafb)), static_cast<float2*>(y_out),
+                     ws, st, tm);
     if (s != FSTAT_OK) return s;
   }
   return ok();
@@ -578,15 +533,15 @@ fstat_status launch_grad_chunk(const fstat_plan* p, const PlanConst& P, const do
   const dim3 rgrid(fft_grid(p, ra, lds_bytes_rows(p), rows_items(p, n)));
   hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 0,
                      p->log_c, p->rows_act);
+  RowOutput oa = row_output(twoF, nullptr);
+  oa.gin = gin;
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(ra.fn)), rgrid, dim3(ra.threads),
-                     lds_bytes_rows(p), st, P, ws, map, slots, p->log_rr, twoF,
-                     static_cast<float2*>(nullptr), gin);
+                     lds_bytes_rows(p), st, P, ws, map, slots, p->log_rr, oa);
   hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 2,
                      p->log_c, int64_t(1) << p->log_rr);
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rc.fn)), rgrid, dim3(rc.threads),
                      lds_bytes_rows(p), st, P, ws, map, slots, p->log_rr,
-                     static_cast<float*>(nullptr),
-                     static_cast<float2*>(nullptr), static_cast<const float*>(nullptr));
+                     row_output(nullptr, nullptr));
   hipLaunchKernelGGL(grad_kernel(p->desc.sinc_halfwidth, false), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws);
   hipLaunchKernelGGL(k_grad_final, dim3((n * kGradParams + 63) / 64), dim3(64), 0, st, P, ws, map,
@@ -604,9 +559,9 @@ struct fstat_search {
   int64_t ntmpl, ngroups;
   std::vector<ChunkMap> chunks;
   // captured launch sequence and the arguments it was captured with
+  static constexpr int kKey = 13;
   hipGraphExec_t exec = nullptr;
-  const void* key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  size_t key_ws = 0;
+  uint64_t key[kKey] = {};
   ~fstat_search() {
     if (exec) (void)hipGraphExecDestroy(exec);
   }
@@ -634,7 +589,7 @@ size_t search_ws_bytes(const fstat_search* sr) {
 }
 
 fstat_status search_launch(fstat_search* sr, const fstat_inputs* in, const double* templates,
-                           float* twoF, float2* fafb, void* ws, hipStream_t st, KernelTimer& tm) {
+                           const RowOutput& out, void* ws, hipStream_t st, KernelTimer& tm) {
   const fstat_plan* p = sr->plan;
   PlanConst P = make_const(p, in);
   P.params = static_cast<char*>(ws) + search_params_offset(sr);
@@ -643,20 +598,20 @@ fstat_status search_launch(fstat_search* sr, const fstat_inputs* in, const doubl
   if (s0 != FSTAT_OK) return s0;
   const int64_t nt = std::max<int64_t>(sr->ntmpl, sr->slots);
   hipLaunchKernelGGL(k_params, dim3(unsigned((nt + 63) / 64)), dim3(64), 0, st, P, templates,
-                     sr->ntmpl, ws, sr->slots);
+                     sr->ntmpl, ws, sr->slots, out);
   if ((s0 = tm.mark(0)) != FSTAT_OK) return s0;
   for (const ChunkMap& map : sr->chunks) {
-    fstat_status s =
-        launch_chunk(p, P, templates, map, sr->slots, true, twoF, fafb, nullptr, ws, st, tm);
+    fstat_status s = launch_chunk(p, P, templates, map, sr->slots, true, out, nullptr, ws, st, tm);
     if (s != FSTAT_OK) return s;
   }
   return FSTAT_OK;
 }
 
 fstat_status search_check(fstat_search* sr, const fstat_inputs* in, const double* templates,
-                          float* twoF, void* ws, size_t ws_bytes) {
+                          bool have_output, void* ws, size_t ws_bytes) {
   if (!sr) return fail(FSTAT_EINVAL, "search is NULL");
-  if (sr->ntmpl > 0 && (!templates || !twoF)) return fail(FSTAT_EINVAL, "templates or twoF is NULL");
+  if (sr->ntmpl > 0 && (!templates || !have_output))
+    return fail(FSTAT_EINVAL, "templates or output is NULL");
   fstat_status s = validate_inputs(sr->plan, in, true);
   if (s != FSTAT_OK) return s;
   if (!ws) return fail(FSTAT_EINVAL, "workspace is NULL");
@@ -666,6 +621,63 @@ fstat_status search_check(fstat_search* sr, const fstat_inputs* in, const double
     return fail(FSTAT_EWORKSPACE, "workspace %zu bytes < %zu for this search", ws_bytes,
                 search_ws_bytes(sr));
   return set_lds_limits(sr->plan);
+}
+
+// Run a checked search: directly, or (FSTAT_SEARCH_GRAPH) by replaying the
+// launch sequence captured for exactly these arguments.
+fstat_status search_run_out(fstat_search* search, const fstat_inputs* in,
+                            const double* templates, const RowOutput& out, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  if (search->ntmpl == 0) return ok();
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KernelTimer none;
+  none.st = st;
+  fstat_status s;
+  if (!(search->flags & FSTAT_SEARCH_GRAPH)) {
+    s = search_launch(search, in, templates, out, workspace, st, none);
+    return s == FSTAT_OK ? ok() : s;
+  }
+  if (!st) return fail(FSTAT_EINVAL, "graph replay needs a non-null stream");
+  uint32_t thr = 0;
+  std::memcpy(&thr, &out.threshold, sizeof thr);
+  const uint64_t key[fstat_search::kKey] = {
+      uint64_t(reinterpret_cast<uintptr_t>(in->x[0])),
+      uint64_t(reinterpret_cast<uintptr_t>(in->moments)),
+      uint64_t(reinterpret_cast<uintptr_t>(templates)),
+      uint64_t(reinterpret_cast<uintptr_t>(out.twoF)),
+      uint64_t(reinterpret_cast<uintptr_t>(out.fafb)),
+      uint64_t(reinterpret_cast<uintptr_t>(out.cand)),
+      uint64_t(reinterpret_cast<uintptr_t>(out.count)),
+      uint64_t(reinterpret_cast<uintptr_t>(out.best)),
+      uint64_t(out.cap),
+      uint64_t(thr) | (uint64_t(out.acc) << 32),
+      uint64_t(reinterpret_cast<uintptr_t>(workspace)),
+      uint64_t(ws_bytes),
+      1};
+  bool same = search->exec != nullptr;
+  for (int i = 0; i < fstat_search::kKey && same; ++i) same = key[i] == search->key[i];
+  if (!same) {
+    if (search->exec) {
+      (void)hipGraphExecDestroy(search->exec);
+      search->exec = nullptr;
+    }
+    s = check_hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (s != FSTAT_OK) return s;
+    fstat_status ls = search_launch(search, in, templates, out, workspace, st, none);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (ls != FSTAT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return ls;
+    }
+    if ((s = check_hip(e, "end capture")) != FSTAT_OK) return s;
+    e = hipGraphInstantiate(&search->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if ((s = check_hip(e, "graph instantiate")) != FSTAT_OK) return s;
+    for (int i = 0; i < fstat_search::kKey; ++i) search->key[i] = key[i];
+  }
+  s = check_hip(hipGraphLaunch(search->exec, st), "graph launch");
+  return s == FSTAT_OK ? ok() : s;
 }
 
 }  // namespace
@@ -680,7 +692,8 @@ fstat_status fstat_search_create(const fstat_plan* plan, const double* templates
   if (ntmpl < 0 || (ntmpl > 0 && !templates)) return fail(FSTAT_EINVAL, "templates / ntmpl invalid");
   if (slots < 1 || slots > kMaxSlots)
     return fail(FSTAT_EINVAL, "slots=%d outside [1, %d]", slots, kMaxSlots);
-  if (flags & ~uint32_t(FSTAT_SEARCH_GRAPH)) return fail(FSTAT_EINVAL, "unknown flags");
+  if (flags & ~uint32_t(FSTAT_SEARCH_GRAPH | FSTAT_SEARCH_ACCUMULATE))
+    return fail(FSTAT_EINVAL, "unknown flags");
   fstat_search* sr = new (std::nothrow) fstat_search;
   if (!sr) return fail(FSTAT_EINVAL, "host allocation failed");
   sr->plan = plan;
@@ -738,45 +751,30 @@ fstat_status fstat_search_info(const fstat_search* search, size_t* ws_bytes, int
 fstat_status fstat_search_run(fstat_search* search, const fstat_inputs* in,
                               const double* templates, float* twoF, void* fafb, void* workspace,
                               size_t ws_bytes, void* stream) {
-  fstat_status s = search_check(search, in, templates, twoF, workspace, ws_bytes);
+  fstat_status s = search_check(search, in, templates, twoF != nullptr, workspace, ws_bytes);
   if (s != FSTAT_OK) return s;
-  if (search->ntmpl == 0) return ok();
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  KernelTimer none;
-  none.st = st;
-  if (!(search->flags & FSTAT_SEARCH_GRAPH)) {
-    s = search_launch(search, in, templates, twoF, static_cast<float2*>(fafb), workspace, st,
-                      none);
-    return s == FSTAT_OK ? ok() : s;
-  }
-  if (!st) return fail(FSTAT_EINVAL, "graph replay needs a non-null stream");
-  const void* key[6] = {in->x[0], in->moments, templates, twoF, fafb, workspace};
-  bool same = search->exec && ws_bytes == search->key_ws;
-  for (int i = 0; i < 6 && same; ++i) same = key[i] == search->key[i];
-  if (!same) {
-    if (search->exec) {
-      (void)hipGraphExecDestroy(search->exec);
-      search->exec = nullptr;
-    }
-    s = check_hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
-    if (s != FSTAT_OK) return s;
-    fstat_status ls = search_launch(search, in, templates, twoF, static_cast<float2*>(fafb),
-                                    workspace, st, none);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(st, &graph);
-    if (ls != FSTAT_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return ls;
-    }
-    if ((s = check_hip(e, "end capture")) != FSTAT_OK) return s;
-    e = hipGraphInstantiate(&search->exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if ((s = check_hip(e, "graph instantiate")) != FSTAT_OK) return s;
-    for (int i = 0; i < 6; ++i) search->key[i] = key[i];
-    search->key_ws = ws_bytes;
-  }
-  s = check_hip(hipGraphLaunch(search->exec, st), "graph launch");
-  return s == FSTAT_OK ? ok() : s;
+  RowOutput out = row_output(twoF, static_cast<float2*>(fafb));
+  out.acc = (search->flags & FSTAT_SEARCH_ACCUMULATE) ? 1 : 0;
+  return search_run_out(search, in, templates, out, workspace, ws_bytes, stream);
+}
+
+fstat_status fstat_search_run_candidates(fstat_search* search, const fstat_inputs* in,
+                                         const double* templates, float threshold,
+                                         fstat_candidate* cand, int64_t capacity,
+                                         int64_t* count, uint64_t* best, void* workspace,
+                                         size_t ws_bytes, void* stream) {
+  if (!count) return fail(FSTAT_EINVAL, "count is NULL");
+  if (capacity < 0 || (capacity > 0 && !cand)) return fail(FSTAT_EINVAL, "cand / capacity invalid");
+  if (!std::isfinite(threshold)) return fail(FSTAT_EINVAL, "threshold must be finite");
+  fstat_status s = search_check(search, in, templates, true, workspace, ws_bytes);
+  if (s != FSTAT_OK) return s;
+  RowOutput out = row_output(nullptr, nullptr);
+  out.cand = cand;
+  out.cap = capacity;
+  out.count = reinterpret_cast<unsigned long long*>(count);
+  out.best = reinterpret_cast<unsigned long long*>(best);
+  out.threshold = threshold;
+  return search_run_out(search, in, templates, out, workspace, ws_bytes, stream);
 }
 
 fstat_status fstat_search_run_profiled(fstat_search* search, const fstat_inputs* in,
@@ -784,14 +782,16 @@ fstat_status fstat_search_run_profiled(fstat_search* search, const fstat_inputs*
                                        size_t ws_bytes, void* stream, float* kernel_ms,
                                        int64_t* launches) {
   if (!kernel_ms || !launches) return fail(FSTAT_EINVAL, "kernel_ms or launches is NULL");
-  fstat_status s = search_check(search, in, templates, twoF, workspace, ws_bytes);
+  fstat_status s = search_check(search, in, templates, twoF != nullptr, workspace, ws_bytes);
   if (s != FSTAT_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   KernelTimer tm;
   tm.on = true;
   tm.st = st;
   if (search->ntmpl > 0) {
-    s = search_launch(search, in, templates, twoF, nullptr, workspace, st, tm);
+    RowOutput out = row_output(twoF, nullptr);
+    out.acc = (search->flags & FSTAT_SEARCH_ACCUMULATE) ? 1 : 0;
+    s = search_launch(search, in, templates, out, workspace, st, tm);
     if (s != FSTAT_OK) return s;
   }
   return finish_timer(tm, st, kernel_ms, launches);
@@ -828,20 +828,15 @@ fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out) {
                 "tune_col_lines=%d / tune_row_lines=%d: accepted 0, %d or %d / 0, %d or %d", tc,
                 tr, cmax, cmax / 2, rmax, rmax / 2);
   }
-  if (desc->tune_fft_grid < 0 || desc->tune_fft_grid > 2) {
-    delete p;
-    return fail(FSTAT_EINVAL, "tune_fft_grid=%d: accepted 0, 1 or 2", desc->tune_fft_grid);
-  }
   if (desc->tune_fft_radix != 0 && desc->tune_fft_radix != 16 && desc->tune_fft_radix != 32) {
     delete p;
     return fail(FSTAT_EINVAL, "tune_fft_radix=%d: accepted 0, 16 or 32", desc->tune_fft_radix);
   }
-  p->fft_persist = desc->tune_fft_grid == 2;
   p->fft_mlr = desc->tune_fft_radix == 16 ? 4 : 5;
-  // automatic: the half line counts (256-thread workgroups, two per compute
-  // unit), measured faster than one 512-thread workgroup per unit
+  // automatic (measured): columns in the half line count (256-thread
+  // workgroups, two per compute unit), rows in the full count (512 threads)
   p->cols_half = (tc == 0 || tc == cmax / 2) && cmax > 1;
-  p->rows_half = (tr == 0 || tr == rmax / 2) && rmax > 1;
+  p->rows_half = tr == rmax / 2 && rmax > 1;
   p->cols_lines = p->cols_half ? cmax / 2 : cmax;
   p->rows_lines = p->rows_half ? rmax / 2 : rmax;
   // grid points that can be non-zero: up to the last sample plus the delay
@@ -961,15 +956,13 @@ fstat_status fstat_autotune(const fstat_plan_desc* desc, const fstat_inputs* in,
     if (lr < 6 || lr > 12 || lc < 6 || lc > 12) continue;
     for (int ch = 0; ch < 2; ++ch)
       for (int rh = 0; rh < 2; ++rh)
-        for (int grid = 1; grid <= 2; ++grid)
-          for (int radix = 16; radix <= 32; radix *= 2) {
+        for (int radix = 16; radix <= 32; radix *= 2) {
           fstat_plan_desc d = *desc;
           d.tune_col_log_len = lr;
-          d.tune_col_lines = ch ? cols_lines_max(lr) / 2 : 0;
-          d.tune_row_lines = rh ? rows_lines_max(lc) / 2 : 0;
-          d.tune_fft_grid = grid;
+          d.tune_col_lines = ch ? cols_lines_max(lr) / 2 : cols_lines_max(lr);
+          d.tune_row_lines = rh ? rows_lines_max(lc) / 2 : rows_lines_max(lc);
           d.tune_fft_radix = radix;
-          if ((ch && d.tune_col_lines < 1) || (rh && d.tune_row_lines < 1)) continue;
+          if (d.tune_col_lines < 1 || d.tune_row_lines < 1) continue;
           fstat_plan* p = nullptr;
           if (fstat_plan_create(&d, &p) != FSTAT_OK) continue;
           float ms = INFINITY;

@@ -64,6 +64,9 @@ struct PlanConst {
 struct TmplParams {
   double nhat[3];
   double df, f1dot, f2dot, asini, om_b, tp;
+  // spin-down and sub-bin phase in cycles as a cubic in the grid index k:
+  // Phi(k) = sd[0] + k (sd[1] + k (sd[2] + k sd[3]))
+  double sd[4];
   double alpha_cyc[kMaxDet];  // (alpha - lon - sidereal angle at 0) / 2 pi
   // Whitened, weighted antenna patterns: with M = [[A, C], [C, B]] = L L^T
   // (Cholesky), (a', b') = L^-1 (a, b) so that 2F = 2 (|Fa'|^2 + |Fb'|^2).
@@ -100,6 +103,23 @@ constexpr int32_t kStatusPhase = 16;    // non-finite spin-down or sub-bin param
 constexpr int32_t kStatusBin = 32;      // single-bin path: bin outside the band
 // Bits that concern the resampled series of a sky/orbit group.
 constexpr int32_t kStatusGroupMask = kStatusTiming | kStatusCoverage | kStatusWindow | kStatusNodes;
+
+// Where the row pass puts its results (passed by value).  twoF: full band
+// (stored, or added when acc is set); fafb: Fa and Fb; gin: adjoint weights;
+// cand/count/cap/threshold: bins with 2F above the threshold appended to a
+// list (count is the total, which may exceed cap); best: per template the
+// largest 2F and its bin packed as (float bits << 32) | bin.
+struct RowOutput {
+  float* twoF;
+  float2* fafb;
+  const float* gin;
+  fstat_candidate* cand;
+  unsigned long long* count;
+  unsigned long long* best;
+  int64_t cap;
+  float threshold;
+  int32_t acc;
+};
 
 // Template slots of one launch sequence and, for the grouped path, the
 // sky/orbit groups it resamples.  Passed by value to every kernel.
@@ -321,17 +341,25 @@ __device__ inline void split_u(double u, int64_t& j0, float& f) {
 __device__ inline float reduce_cycles(double c) { return static_cast<float>(c - rint(c)); }
 
 // exp(-i Phi_s(tau_k)) exp(-2 pi i df (tau_k - tau0)): the spin-down phase of
-// Sec. 2 about t_ref and the sub-bin frequency offset, FP64 cycles reduced to
+// Sec. 2 about t_ref and the sub-bin frequency offset, FP64 cycles evaluated
+// from the template's cubic in k (spindown_coefficients), reduced to
 // [-1/2, 1/2] before the FP32 rotation.  One definition for every kernel
-// that applies it, so the per-template and grouped paths agree bit for bit.
-// Evaluated without FMA contraction, so every kernel gets the same bits.
-__device__ inline float2 spindown_rotation(const PlanConst& P, double f1dot, double f2dot,
-                                           double df, int64_t k) {
+// that applies it, so the per-template and grouped paths agree bit for bit;
+// evaluated without FMA contraction, so every kernel gets the same bits.
+__host__ __device__ inline void spindown_coefficients(const PlanConst& P, double f1dot,
+                                                      double f2dot, double df, double sd[4]) {
+  // with d0 = tau0 - t_ref and s = dt k:
+  //   f1dot (d0 + s)^2 / 2 + f2dot (d0 + s)^3 / 6 + df s
+  const double d0 = P.tau0 - P.t_ref, dt = P.dt;
+  sd[0] = f1dot * d0 * d0 * 0.5 + f2dot * d0 * d0 * d0 * (1.0 / 6.0);
+  sd[1] = dt * (f1dot * d0 + f2dot * d0 * d0 * 0.5 + df);
+  sd[2] = dt * dt * (f1dot * 0.5 + f2dot * d0 * 0.5);
+  sd[3] = dt * dt * dt * f2dot * (1.0 / 6.0);
+}
+__device__ inline float2 spindown_rotation(const double sd[4], int64_t k) {
 #pragma clang fp contract(off)
-  const double tau = P.tau0 + P.dt * double(k);
-  const double dtr = tau - P.t_ref;
-  double cyc = f1dot * dtr * dtr * 0.5 + f2dot * dtr * dtr * dtr * (1.0 / 6.0);
-  cyc = cyc - rint(cyc) + df * (P.dt * double(k));
+  const double x = double(k);
+  const double cyc = sd[0] + x * (sd[1] + x * (sd[2] + x * sd[3]));
   const float c = reduce_cycles(cyc);
   float sn, cs;
   sincospif(2.0f * c, &sn, &cs);

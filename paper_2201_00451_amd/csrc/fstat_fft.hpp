@@ -205,23 +205,16 @@ constexpr int kR0 = 1 << stage_logr(LOGL, 0, MLR);
 template <int LOGL, int NL, int NT, int MLR>
 constexpr int kPer0 = (NL * ((1 << LOGL) / kR0<LOGL, MLR>) + NT - 1) / NT;
 
-// Work items.  PERSIST = false: one workgroup per item, line groups fastest
-// within a template, remapped so that the workgroups an XCD runs together
-// handle neighbouring line groups (the row pass writes 2F in runs of RQ
-// floats per row group; neighbouring groups complete each other's cache
-// lines in that XCD's L2 before write-back).  PERSIST = true: workgroup w
-// transforms items w, w + G, w + 2G, ... (G = gridDim.x), template slot
-// fastest (the templates of one sky/orbit group read the same group series
-// at about the same time), and the first-stage loads of the next item are
-// issued before the current item is transformed, so they are in flight during
-// its LDS stages and stores; the transform reads no global memory (stage
-// twiddles from LDS, four-step twiddles from sincospi), so nothing waits on
-// them early.
+// Work items: one workgroup per item, line groups fastest within a
+// template, and the block index remapped so that the workgroups an XCD runs
+// together take neighbouring line groups (the row pass writes 2F in runs of
+// RQ floats per row group; neighbouring groups complete each other's cache
+// lines in that XCD's L2 before write-back).
 
 struct ColItem {
   int live, g, arr;
   int64_t c0;
-  double f1dot, f2dot, df;
+  double sd[4];
 };
 
 // Column pass: lines are NL consecutive columns [c0, c0 + NL) of one array of
@@ -234,10 +227,10 @@ struct ColItem {
 // GROUPED: the input is the unphased series of the slot's sky/orbit group;
 // stage 0 applies the template's spin-down phase while loading and the
 // output goes to the slot's own buffer.
-template <int LOGL, int NL, int NT, bool GROUPED, int MLR, bool PERSIST>
+template <int LOGL, int NL, int NT, bool GROUPED, int MLR>
 __device__ __forceinline__ ColItem cols_fetch(const PlanConst& P, void* ws, const ChunkMap& map,
                                               int slots, int arr_base, int64_t C,
-                                              int64_t rows_act, int item, int n_items,
+                                              int64_t rows_act, int item,
                                               float2 (&v)[kPer0<LOGL, NL, NT, MLR>]
                                                          [kR0<LOGL, MLR>]) {
   constexpr int L = 1 << LOGL;
@@ -245,20 +238,11 @@ __device__ __forceinline__ ColItem cols_fetch(const PlanConst& P, void* ws, cons
   constexpr int PER = kPer0<LOGL, NL, NT, MLR>;
   ColItem it;
   it.live = 0;
-  if (item >= n_items) return it;
-  if (PERSIST) {
-    const int n = map.n_tmpl;
-    it.g = item % n;
-    const int rest = item / n;
-    it.arr = rest & 1;
-    it.c0 = int64_t(rest >> 1) * NL;
-  } else {
-    const int n_gx = int(C / NL);
-    it.c0 = int64_t(item % n_gx) * NL;
-    const int rest = item / n_gx;
-    it.arr = rest & 1;
-    it.g = rest >> 1;
-  }
+  const int n_gx = int(C / NL);
+  it.c0 = int64_t(item % n_gx) * NL;
+  const int rest = item / n_gx;
+  it.arr = rest & 1;
+  it.g = rest >> 1;
   TmplParams* tpp = tmpl_params(ws, P, map, it.g);
   int32_t status = tpp->status;
   if (GROUPED) {
@@ -268,9 +252,8 @@ __device__ __forceinline__ ColItem cols_fetch(const PlanConst& P, void* ws, cons
   }
   if (status != 0) return it;
   it.live = 1;
-  it.f1dot = tpp->f1dot;
-  it.f2dot = tpp->f2dot;
-  it.df = tpp->df;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) it.sd[q] = tpp->sd[q];
   const float2* src = GROUPED ? group_buf(ws, P, slots, map.tmpl_buf[it.g], it.arr)
                               : slot_buf(ws, P, it.g, arr_base + it.arr);
   // rows at or beyond rows_act lie past the descriptor's end and read as zero
@@ -291,18 +274,26 @@ __device__ __forceinline__ ColItem cols_fetch(const PlanConst& P, void* ws, cons
 }
 
 template <int LOGL, int NL, int NT, bool GROUPED, int MLR>
-__device__ __forceinline__ void cols_transform(const PlanConst& P, void* ws, const ColItem& it,
-                                               int arr_base, int64_t C, int64_t rows_act,
-                                               float2 (&v)[kPer0<LOGL, NL, NT, MLR>]
-                                                          [kR0<LOGL, MLR>],
-                                               float2* lds, const float2* twl) {
+__global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap map, int slots,
+                                                 int arr_base, int log_c, int64_t rows_act) {
+  extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
   constexpr int NS = stage_count(LOGL, MLR);
   constexpr int R0 = kR0<LOGL, MLR>, NB0 = NL * (L / R0);
   constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = NL * PL;
   constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
   using Lay = LdsLayout<L>;
+  float2* twl = lds + NL * Lay::pitch;
   const int tid = threadIdx.x;
+  const int64_t C = int64_t(1) << log_c;
+  {
+    const float2* __restrict__ tws = tw_stage(ws);
+    for (int e = tid; e < L / 2; e += NT) twl[e] = tws[e * (kTwLen / L)];
+  }
+  float2 v[PER0][R0];
+  const ColItem it = cols_fetch<LOGL, NL, NT, GROUPED, MLR>(
+      P, ws, map, slots, arr_base, C, rows_act, int(xcd_remap(blockIdx.x, gridDim.x)), v);
+  if (!it.live) return;
   const int64_t nmask = P.n_fft - 1;
   const auto wr = buf_rsrc(slot_buf(ws, P, it.g, arr_base + it.arr),
                            uint32_t(P.n_fft * int64_t(sizeof(float2))));
@@ -317,8 +308,7 @@ __device__ __forceinline__ void cols_transform(const PlanConst& P, void* ws, con
         for (int j = 0; j < R0; ++j) {
           const int r = i + j * (L / R0);
           if (r < rows_act)
-            v[s][j] = cmul_exact(v[s][j], spindown_rotation(P, it.f1dot, it.f2dot, it.df,
-                                                            int64_t(r) * C + it.c0 + line));
+            v[s][j] = cmul_exact(v[s][j], spindown_rotation(it.sd, int64_t(r) * C + it.c0 + line));
         }
       }
       dft<R0>(v[s]);
@@ -354,56 +344,13 @@ __device__ __forceinline__ void cols_transform(const PlanConst& P, void* ws, con
   }
 }
 
-template <int LOGL, int NL, int NT, bool GROUPED, int MLR, bool PERSIST>
-__global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap map, int slots,
-                                                 int arr_base, int log_c, int64_t rows_act) {
-  extern __shared__ float2 lds[];
-  constexpr int L = 1 << LOGL;
-  constexpr int R0 = kR0<LOGL, MLR>;
-  constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
-  float2* twl = lds + NL * LdsLayout<L>::pitch;
-  const int tid = threadIdx.x;
-  const int64_t C = int64_t(1) << log_c;
-  const int n_items = int(C / NL) * 2 * map.n_tmpl;
-  {
-    const float2* __restrict__ tws = tw_stage(ws);
-    for (int e = tid; e < L / 2; e += NT) twl[e] = tws[e * (kTwLen / L)];
-  }
-  int item = PERSIST ? int(blockIdx.x) : int(xcd_remap(blockIdx.x, gridDim.x));
-  float2 v[PER0][R0];
-  ColItem it = cols_fetch<LOGL, NL, NT, GROUPED, MLR, PERSIST>(P, ws, map, slots, arr_base, C,
-                                                               rows_act, item, n_items, v);
-  if constexpr (!PERSIST) {
-    if (it.live)
-      cols_transform<LOGL, NL, NT, GROUPED, MLR>(P, ws, it, arr_base, C, rows_act, v, lds, twl);
-  } else {
-    while (item < n_items) {
-      const int next = item + int(gridDim.x);
-      float2 vn[PER0][R0];
-      const ColItem nt = cols_fetch<LOGL, NL, NT, GROUPED, MLR, PERSIST>(
-          P, ws, map, slots, arr_base, C, rows_act, next, n_items, vn);
-      if (it.live) {
-        cols_transform<LOGL, NL, NT, GROUPED, MLR>(P, ws, it, arr_base, C, rows_act, v, lds,
-                                                   twl);
-        __syncthreads();
-      }
-#pragma unroll
-      for (int s = 0; s < PER0; ++s)
-#pragma unroll
-        for (int j = 0; j < R0; ++j) v[s][j] = vn[s][j];
-      it = nt;
-      item = next;
-    }
-  }
-}
-
 // Row pass with the 2F epilogue (eq. Fstat, normalised as 2F = 2 F^T M^-1 F,
-// which is 2 (|Fa'|^2 + |Fb'|^2) for the whitened antenna patterns).  Lines
-// 0..RQ-1 are rows q0..q0+RQ-1 of y_a', lines RQ..2RQ-1 the same rows of y_b';
-// line length C = 2^LOGL.  The first stage reads the rows straight from HBM
-// (contiguous across threads); the last stage transforms the a and b rows of
-// the same bins in one thread and writes 2F (rows fastest across threads:
-// RQ-element runs of the output).  Items: (Rr / RQ) row groups x template slots.
+// which is 2 (|Fa'|^2 + |Fb'|^2) for the whitened antenna patterns).  An item
+// is RQ rows q0..q0+RQ-1 of both y_a' and y_b' (line length C = 2^LOGL); the
+// first stage reads the rows straight from HBM (contiguous across threads),
+// the last stage leaves the a and b values of the same bins in one thread,
+// which writes 2F (rows fastest across threads: RQ-element runs of the
+// output).  Items: (Rr / RQ) row groups x template slots.
 // Row-pass epilogues: 2F (forward); the adjoint spectrum H = g conj(F') of
 // both arrays at every natural FFT index m (zero outside the band), written to
 // arrays 2 and 3 of the slot, with 2F if twoF is not null; or the complex
@@ -417,27 +364,13 @@ struct RowItem {
   float l11, l21, l22;
 };
 
-template <int LOGL, int RQ, int NT, int MODE, int MLR, bool PERSIST>
-__device__ __forceinline__ RowItem rows_fetch(const PlanConst& P, void* ws, const ChunkMap& map,
-                                              int item, int n_items,
-                                              float2 (&v)[kPer0<LOGL, 2 * RQ, NT, MLR>]
-                                                         [kR0<LOGL, MLR>]) {
-  constexpr int L = 1 << LOGL;
-  constexpr int NL = 2 * RQ;
-  constexpr int R0 = kR0<LOGL, MLR>, NBL0 = L / R0, NB0 = NL * NBL0;
-  constexpr int PER = kPer0<LOGL, NL, NT, MLR>;
+template <int MODE>
+__device__ __forceinline__ RowItem rows_item(const PlanConst& P, void* ws, const ChunkMap& map,
+                                             int item, int n_gx, int RQ) {
   RowItem it;
   it.live = it.flagged = 0;
-  if (item >= n_items) return it;
-  if (PERSIST) {
-    const int n = map.n_tmpl;
-    it.g = item % n;
-    it.q0 = int64_t(item / n) * RQ;
-  } else {
-    const int n_gx = n_items / map.n_tmpl;
-    it.q0 = int64_t(item % n_gx) * RQ;
-    it.g = item / n_gx;
-  }
+  it.q0 = int64_t(item % n_gx) * RQ;
+  it.g = item / n_gx;
   it.tmpl = map.tmpl[it.g];
   const TmplParams& tp = *tmpl_params(ws, P, map, it.g);
   if (tp.status != 0) {
@@ -448,13 +381,24 @@ __device__ __forceinline__ RowItem rows_fetch(const PlanConst& P, void* ws, cons
   it.l11 = tp.l11;
   it.l21 = tp.l21;
   it.l22 = tp.l22;
+  return it;
+}
+
+// First-stage inputs of butterflies s = S0 .. S0 + NSB - 1 (b = tid + s NT;
+// line b / (L / R0): lines 0..RQ-1 are the a rows, RQ..2RQ-1 the b rows).
+template <int LOGL, int RQ, int NT, int MODE, int MLR, int S0, int NSB>
+__device__ __forceinline__ void rows_load(const PlanConst& P, void* ws, const RowItem& it,
+                                          float2 (&v)[NSB][kR0<LOGL, MLR>]) {
+  constexpr int L = 1 << LOGL;
+  constexpr int NL = 2 * RQ;
+  constexpr int R0 = kR0<LOGL, MLR>, NBL0 = L / R0, NB0 = NL * NBL0;
   // arrays a and b of the slot are adjacent: one descriptor covers both
   const auto rs = buf_rsrc(slot_buf(ws, P, it.g, MODE == kRowConj ? 2 : 0),
                            uint32_t(2 * P.n_fft * int64_t(sizeof(float2))));
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int s = 0; s < PER; ++s) {
-    const int b = tid + s * NT;
+  for (int s = 0; s < NSB; ++s) {
+    const int b = tid + (S0 + s) * NT;
     if (NB0 % NT == 0 || b < NB0) {
       const int i = b % NBL0, line = b / NBL0;
       const int64_t e0 = (line < RQ ? 0 : P.n_fft) + (it.q0 + line % RQ) * L + i;
@@ -464,120 +408,88 @@ __device__ __forceinline__ RowItem rows_fetch(const PlanConst& P, void* ws, cons
         v[s][j] = buf_load2(rs, voff, uint32_t(j * NBL0 * int(sizeof(float2))));
     }
   }
-  return it;
 }
 
-template <int LOGL, int RQ, int NT, int MODE, int MLR>
-__device__ __forceinline__ void rows_transform(const PlanConst& P, void* ws, const RowItem& it,
-                                               int64_t Rr, float* __restrict__ twoF,
-                                               float2* fafb, const float* __restrict__ gin,
-                                               float2 (&v)[kPer0<LOGL, 2 * RQ, NT, MLR>]
-                                                          [kR0<LOGL, MLR>],
-                                               float2* lds, const float2* twl) {
-  constexpr int L = 1 << LOGL;
-  constexpr int NL = 2 * RQ;
-  constexpr int NS = stage_count(LOGL, MLR);
-  constexpr int R0 = kR0<LOGL, MLR>, NBL0 = L / R0, NB0 = NL * NBL0;
-  constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = RQ * PL;
-  constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
-  using Lay = LdsLayout<L>;
+// The row epilogue for one output element: natural index nat, a and b
+// values.  Returns 2F of an in-band bin (-1 otherwise) for the caller's
+// running maximum.
+template <int MODE>
+__device__ __forceinline__ float rows_out(const PlanConst& P, void* ws, const RowItem& it,
+                                          int64_t nat, float2 fa, float2 fb,
+                                          const RowOutput& out) {
   const int64_t N = P.n_fft;
-  const int tid = threadIdx.x;
-  // stage 0: registers -> DFT -> LDS
-#pragma unroll
-  for (int s = 0; s < PER0; ++s) {
-    const int b = tid + s * NT;
-    if (NB0 % NT == 0 || b < NB0) {
-      const int i = b % NBL0, line = b / NBL0;
-      dft<R0>(v[s]);
-#pragma unroll
-      for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
+  if (MODE == kRowConj) {
+    if (nat < P.k_pad) {
+      slot_buf(ws, P, it.g, 0)[nat] = make_float2(fa.x, -fa.y);
+      slot_buf(ws, P, it.g, 1)[nat] = make_float2(fb.x, -fb.y);
     }
+    return -1.0f;
   }
-  __syncthreads();
-  fft_middle<LOGL, NL, NT, 1, MLR>(lds, twl);
-  // last stage of both arrays + epilogue
-  constexpr int PER = (NBL + NT - 1) / NT;
-#pragma unroll
-  for (int s = 0; s < PER; ++s) {
-    const int b = tid + s * NT;
-    if (NBL % NT == 0 || b < NBL) {
-      const int ql = b % RQ, i = b / RQ;
-      float2 va[RL], vb[RL];
-#pragma unroll
-      for (int j = 0; j < RL; ++j) {
-        va[j] = lds[Lay::at(i + j * PL, ql)];
-        vb[j] = lds[Lay::at(i + j * PL, RQ + ql)];
-      }
-      twiddle_dft<RL, PL, L>(va, i, twl);
-      twiddle_dft<RL, PL, L>(vb, i, twl);
-#pragma unroll
-      for (int m = 0; m < RL; ++m) {
-        const int64_t nat = it.q0 + ql + Rr * int64_t(i + m * PL);
-        if (MODE == kRowConj) {
-          if (nat < P.k_pad) {
-            slot_buf(ws, P, it.g, 0)[nat] = make_float2(va[m].x, -va[m].y);
-            slot_buf(ws, P, it.g, 1)[nat] = make_float2(vb[m].x, -vb[m].y);
-          }
-          continue;
-        }
-        const int64_t ib = (nat + N / 2) & (N - 1);
-        const bool in_band = ib >= P.bin_lo && ib < P.bin_lo + P.n_bins;
-        const int64_t o = ib - P.bin_lo;
-        const float2 fa = va[m], fb = vb[m];
-        if (MODE == kRowAdjoint) {
-          const float gv = in_band ? gin[it.tmpl * P.n_bins + o] : 0.0f;
-          slot_buf(ws, P, it.g, 2)[nat] = make_float2(gv * fa.x, -gv * fa.y);
-          slot_buf(ws, P, it.g, 3)[nat] = make_float2(gv * fb.x, -gv * fb.y);
-        }
-        if (!in_band) continue;
-        if (twoF)
-          twoF[it.tmpl * P.n_bins + o] =
-              2.0f * ((fa.x * fa.x + fa.y * fa.y) + (fb.x * fb.x + fb.y * fb.y));
-        if (fafb) {
-          // undo the whitening: Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
-          fafb[(it.tmpl * 2 + 0) * P.n_bins + o] = cscale(fa, it.l11);
-          fafb[(it.tmpl * 2 + 1) * P.n_bins + o] =
-              make_float2(it.l21 * fa.x + it.l22 * fb.x, it.l21 * fa.y + it.l22 * fb.y);
-        }
-      }
-    }
+  const int64_t ib = (nat + N / 2) & (N - 1);
+  const bool in_band = ib >= P.bin_lo && ib < P.bin_lo + P.n_bins;
+  const int64_t o = ib - P.bin_lo;
+  if (MODE == kRowAdjoint) {
+    const float gv = in_band ? out.gin[it.tmpl * P.n_bins + o] : 0.0f;
+    slot_buf(ws, P, it.g, 2)[nat] = make_float2(gv * fa.x, -gv * fa.y);
+    slot_buf(ws, P, it.g, 3)[nat] = make_float2(gv * fb.x, -gv * fb.y);
   }
+  if (!in_band) return -1.0f;
+  const float v2 = 2.0f * ((fa.x * fa.x + fa.y * fa.y) + (fb.x * fb.x + fb.y * fb.y));
+  if (out.twoF) {
+    float* dst = out.twoF + it.tmpl * P.n_bins + o;
+    *dst = out.acc ? *dst + v2 : v2;
+  }
+  if (out.fafb) {
+    // undo the whitening: Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
+    out.fafb[(it.tmpl * 2 + 0) * P.n_bins + o] = cscale(fa, it.l11);
+    out.fafb[(it.tmpl * 2 + 1) * P.n_bins + o] =
+        make_float2(it.l21 * fa.x + it.l22 * fb.x, it.l21 * fa.y + it.l22 * fb.y);
+  }
+  if (out.cand && v2 > out.threshold) {
+    const unsigned long long idx = atomicAdd(out.count, 1ull);
+    if (idx < (unsigned long long)out.cap)
+      out.cand[idx] = fstat_candidate{int32_t(it.tmpl), int32_t(o), v2, 0};
+  }
+  return v2;
 }
 
-// A flagged template: NaN in every bin the item owns.
+// A flagged template: NaN in every bin the item owns (and the all-ones
+// marker in its best entry).
 template <int LOGL, int RQ, int NT>
 __device__ __forceinline__ void rows_flagged(const PlanConst& P, const RowItem& it, int64_t Rr,
-                                             float* __restrict__ twoF, float2* fafb) {
+                                             const RowOutput& out) {
   constexpr int L = 1 << LOGL;
   const int64_t N = P.n_fft;
   const float qnan = __builtin_nanf("");
+  if (out.best && threadIdx.x == 0) atomicMax(out.best + it.tmpl, ~0ull);
   for (int e = threadIdx.x; e < L * RQ; e += NT) {
     const int ql = e % RQ, p = e / RQ;
     const int64_t i = (it.q0 + ql + Rr * p + N / 2) & (N - 1);
     if (i < P.bin_lo || i >= P.bin_lo + P.n_bins) continue;
     const int64_t o = i - P.bin_lo;
-    if (twoF) twoF[it.tmpl * P.n_bins + o] = qnan;
-    if (fafb) {
-      fafb[(it.tmpl * 2 + 0) * P.n_bins + o] = make_float2(qnan, qnan);
-      fafb[(it.tmpl * 2 + 1) * P.n_bins + o] = make_float2(qnan, qnan);
+    if (out.twoF) out.twoF[it.tmpl * P.n_bins + o] = qnan;
+    if (out.fafb) {
+      out.fafb[(it.tmpl * 2 + 0) * P.n_bins + o] = make_float2(qnan, qnan);
+      out.fafb[(it.tmpl * 2 + 1) * P.n_bins + o] = make_float2(qnan, qnan);
     }
   }
 }
 
-template <int LOGL, int RQ, int NT, int MODE, int MLR, bool PERSIST>
+template <int LOGL, int RQ, int NT, int MODE, int MLR>
 __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap map, int slots,
-                                                 int log_rr, float* __restrict__ twoF,
-                                                 float2* fafb, const float* __restrict__ gin) {
+                                                 int log_rr, RowOutput out) {
   extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
-  constexpr int NL = 2 * RQ;
-  constexpr int R0 = kR0<LOGL, MLR>;
+  constexpr int NL = 2 * RQ;  // lines: the a rows then the b rows
+  constexpr int NS = stage_count(LOGL, MLR);
+  constexpr int R0 = kR0<LOGL, MLR>, NBL0 = L / R0;
+  constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = RQ * PL;
   constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
-  float2* twl = lds + NL * LdsLayout<L>::pitch;
+  constexpr int PER = (NBL + NT - 1) / NT;
+  using Lay = LdsLayout<L>;
+  float2* twl = lds + NL * Lay::pitch;
   const int64_t Rr = int64_t(1) << log_rr;
   const int tid = threadIdx.x;
-  const int n_items = int(Rr / RQ) * map.n_tmpl;
   // grouped path: every reader of the group buffers the next chunk resamples
   // has finished (column pass of this chunk), so their status words restart
   if (blockIdx.x == 0 && tid < map.n_reset) *group_status(ws, P, slots, map.reset_buf[tid]) = 0;
@@ -585,30 +497,63 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
     const float2* __restrict__ tws = tw_stage(ws);
     for (int e = tid; e < L / 2; e += NT) twl[e] = tws[e * (kTwLen / L)];
   }
-  int item = PERSIST ? int(blockIdx.x) : int(xcd_remap(blockIdx.x, gridDim.x));
-  float2 v[PER0][R0];
-  RowItem it = rows_fetch<LOGL, RQ, NT, MODE, MLR, PERSIST>(P, ws, map, item, n_items, v);
-  if constexpr (!PERSIST) {
-    if (it.flagged && MODE != kRowConj) rows_flagged<LOGL, RQ, NT>(P, it, Rr, twoF, fafb);
-    if (it.live)
-      rows_transform<LOGL, RQ, NT, MODE, MLR>(P, ws, it, Rr, twoF, fafb, gin, v, lds, twl);
-  } else {
-    while (item < n_items) {
-      const int next = item + int(gridDim.x);
-      float2 vn[PER0][R0];
-      const RowItem nt = rows_fetch<LOGL, RQ, NT, MODE, MLR, PERSIST>(P, ws, map, next, n_items,
-                                                                      vn);
-      if (it.flagged && MODE != kRowConj) rows_flagged<LOGL, RQ, NT>(P, it, Rr, twoF, fafb);
-      if (it.live) {
-        rows_transform<LOGL, RQ, NT, MODE, MLR>(P, ws, it, Rr, twoF, fafb, gin, v, lds, twl);
-        __syncthreads();
+  const RowItem it =
+      rows_item<MODE>(P, ws, map, int(xcd_remap(blockIdx.x, gridDim.x)), int(Rr / RQ), RQ);
+  if (it.flagged && MODE != kRowConj) rows_flagged<LOGL, RQ, NT>(P, it, Rr, out);
+  if (!it.live) return;
+  {
+    float2 v[PER0][R0];
+    rows_load<LOGL, RQ, NT, MODE, MLR, 0, PER0>(P, ws, it, v);
+    // stage 0 of both arrays: registers -> DFT -> LDS
+#pragma unroll
+    for (int s = 0; s < PER0; ++s) {
+      const int b = tid + s * NT;
+      if ((NL * NBL0) % NT == 0 || b < NL * NBL0) {
+        const int i = b % NBL0, line = b / NBL0;
+        dft<R0>(v[s]);
+#pragma unroll
+        for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
       }
+    }
+    __syncthreads();
+    fft_middle<LOGL, NL, NT, 1, MLR>(lds, twl);
+    float bmax = -1.0f;
+    int64_t bbin = 0;
 #pragma unroll
-      for (int s = 0; s < PER0; ++s)
+    for (int s = 0; s < PER; ++s) {
+      const int b = tid + s * NT;
+      if (NBL % NT == 0 || b < NBL) {
+        const int ql = b % RQ, i = b / RQ;
+        float2 va[RL], vb[RL];
 #pragma unroll
-        for (int j = 0; j < R0; ++j) v[s][j] = vn[s][j];
-      it = nt;
-      item = next;
+        for (int j = 0; j < RL; ++j) {
+          va[j] = lds[Lay::at(i + j * PL, ql)];
+          vb[j] = lds[Lay::at(i + j * PL, RQ + ql)];
+        }
+        twiddle_dft<RL, PL, L>(va, i, twl);
+        twiddle_dft<RL, PL, L>(vb, i, twl);
+#pragma unroll
+        for (int m = 0; m < RL; ++m) {
+          const int64_t nat = it.q0 + ql + Rr * int64_t(i + m * PL);
+          const float v2 = rows_out<MODE>(P, ws, it, nat, va[m], vb[m], out);
+          if (v2 > bmax) {
+            bmax = v2;
+            bbin = ((nat + P.n_fft / 2) & (P.n_fft - 1)) - P.bin_lo;
+          }
+        }
+      }
+    }
+    if (MODE == kRow2F && out.best) {
+      // largest 2F of the item: wavefront maximum, one atomic per wave
+      unsigned long long key =
+          bmax >= 0.0f ? (static_cast<unsigned long long>(__float_as_uint(bmax)) << 32) |
+                             static_cast<unsigned long long>(bbin)
+                       : 0ull;
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_down(key, off, 64);
+        key = o > key ? o : key;
+      }
+      if ((tid & 63) == 0 && key != 0ull) atomicMax(out.best + it.tmpl, key);
     }
   }
 }

@@ -145,6 +145,7 @@ __host__ __device__ inline void template_params(const PlanConst& P, const double
   if (tp.asini < 0.0 || (tp.asini != 0.0 && !(porb > 0.0))) status |= kStatusTiming;
   if (tp.asini > P.max_delay) status |= kStatusCoverage;
   tp.om_b = (tp.asini != 0.0 && porb > 0.0) ? 2.0 * kPi / porb : 0.0;
+  spindown_coefficients(P, tp.f1dot, tp.f2dot, tp.df, tp.sd);
   double sa, ca_, sd, cdl;
   sincos(alpha, &sa, &ca_);
   sincos(delta, &sd, &cdl);
@@ -290,13 +291,17 @@ __global__ __launch_bounds__(64) void k_prologue(PlanConst P, const double* __re
 }
 
 // Search path, once per run: the parameter blocks of all templates into the
-// per-template array P.params, and the status words of the group buffers
-// cleared for the first chunk.
+// per-template array P.params, the status words of the group buffers cleared
+// for the first chunk, and the candidate count and per-template maxima of
+// the run cleared (in a kernel, so that a captured graph needs no memset).
 __global__ __launch_bounds__(64) void k_params(PlanConst P, const double* __restrict__ templates,
-                                               int64_t ntmpl, void* ws, int slots) {
+                                               int64_t ntmpl, void* ws, int slots,
+                                               RowOutput out) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t < slots) *group_status(ws, P, slots, int(t)) = 0;
+  if (t == 0 && out.count) *out.count = 0ull;
   if (t >= ntmpl) return;
+  if (out.best) out.best[t] = 0ull;
   TmplParams tp;
   full_params(P, templates + t * FSTAT_TEMPLATE_STRIDE, tp);
   *reinterpret_cast<TmplParams*>(P.params + size_t(t) * kParamBytes) = tp;

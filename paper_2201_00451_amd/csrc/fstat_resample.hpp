@@ -284,7 +284,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws,
       yb[k] = acc_b[i];
     } else {
       // spin-down phase and sub-bin offset: y = acc * exp(-2 pi i cyc)
-      const float2 e = spindown_rotation(P, tp.f1dot, tp.f2dot, tp.df, k);
+      const float2 e = spindown_rotation(tp.sd, k);
       ya[k] = cmul_exact(acc_a[i], e);
       yb[k] = cmul_exact(acc_b[i], e);
     }
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample_bin(PlanConst P, void*
 #pragma unroll
   for (int i = 0; i < kResPerThread; ++i) {
     const int64_t k = k_s + tid + i * kResThreads;
-    const float2 e = cmul(spindown_rotation(P, tp.f1dot, tp.f2dot, tp.df, k),
+    const float2 e = cmul(spindown_rotation(tp.sd, k),
                           bin_twiddle(nat, k, P.n_fft));
     const float2 ya = cmul(acc_a[i], e), yb = cmul(acc_b[i], e);
     s[0] += double(ya.x);

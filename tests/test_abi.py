@@ -101,10 +101,9 @@ def test_plan_accepts_valid_setup(lib):
     p = B.Plan(d)
     # every documented tuning choice is accepted (n_fft = 2^13: columns 2^6 x rows 2^7 by default)
     for log_len, cl, rl in ((7, 64, 32), (7, 32, 16), (6, 64, 32), (6, 32, 16)):
-        for grid, radix in ((0, 0), (1, 16), (1, 32), (2, 16), (2, 32)):
+        for radix in (0, 16, 32):
             d2 = B.make_plan_desc(ds, dict(tune_col_log_len=log_len, tune_col_lines=cl,
-                                           tune_row_lines=rl, tune_fft_grid=grid,
-                                           tune_fft_radix=radix))
+                                           tune_row_lines=rl, tune_fft_radix=radix))
             B.Plan(d2)
     k_pad, lc, lr = p.info()
     assert (lc, lr) == (6, 7) and k_pad % (1 << lr) == 0 and k_pad % 1024 == 0
@@ -138,7 +137,7 @@ def test_plan_accepts_valid_setup(lib):
     (lambda d: setattr(d, "tune_col_log_len", 13), "tune_col_log_len"),
     (lambda d: setattr(d, "tune_col_lines", 3), "tune_col_lines"),
     (lambda d: setattr(d, "tune_row_lines", 7), "tune_row_lines"),
-    (lambda d: setattr(d, "tune_fft_grid", 3), "tune_fft_grid"),
+
     (lambda d: setattr(d, "tune_fft_radix", 8), "tune_fft_radix"),
     (lambda d: (setattr(d, "n_fft", 1 << 12), setattr(d, "n_bins", 1 << 12),
                setattr(d.det[0], "n", 4000)), "too short"),
@@ -254,8 +253,27 @@ def test_search_plan_groups_and_chunks(lib):
     h = vp()
     assert lib.fstat_search_create(p.handle, tm.ctypes.data_as(vp), len(tm), 33, 0,
                                    ctypes.byref(h)) == B.FSTAT_EINVAL
-    assert lib.fstat_search_create(p.handle, tm.ctypes.data_as(vp), len(tm), 4, 2,
+    assert lib.fstat_search_create(p.handle, tm.ctypes.data_as(vp), len(tm), 4, 4,
                                    ctypes.byref(h)) == B.FSTAT_EINVAL
+    # graph and accumulate flags together are accepted
+    assert lib.fstat_search_create(p.handle, tm.ctypes.data_as(vp), len(tm), 4,
+                                   B.SEARCH_GRAPH | B.SEARCH_ACCUMULATE, ctypes.byref(h)) == 0
+    # candidate retention: argument checks come before any launch
+    ws = ctypes.c_size_t()
+    assert lib.fstat_search_info(h, ctypes.byref(ws), None, None) == 0
+    inp = B.FstatInputs()
+    run = lib.fstat_search_run_candidates
+    assert run(h, ctypes.byref(inp), vp(4096), 70.0, vp(4096), 16, vp(0), vp(0), vp(4096),
+               ws.value, vp(0)) == B.FSTAT_EINVAL and "count" in B.last_error()
+    assert run(h, ctypes.byref(inp), vp(4096), 70.0, vp(0), 16, vp(4096), vp(0), vp(4096),
+               ws.value, vp(0)) == B.FSTAT_EINVAL
+    assert run(h, ctypes.byref(inp), vp(4096), 70.0, vp(4096), -1, vp(4096), vp(0), vp(4096),
+               ws.value, vp(0)) == B.FSTAT_EINVAL
+    assert run(h, ctypes.byref(inp), vp(4096), float("nan"), vp(4096), 16, vp(4096), vp(0),
+               vp(4096), ws.value, vp(0)) == B.FSTAT_EINVAL and "threshold" in B.last_error()
+    assert run(None, ctypes.byref(inp), vp(4096), 70.0, vp(4096), 16, vp(4096), vp(0),
+               vp(4096), ws.value, vp(0)) == B.FSTAT_EINVAL
+    lib.fstat_search_destroy(h)
 
 
 def test_autotune_checks_arguments_before_any_launch(lib):

@@ -174,12 +174,11 @@ def test_delay_bound_violation_gives_nan(torch_dev):
 
 
 @pytest.mark.parametrize("tune", [
-    dict(tune_col_lines=32, tune_row_lines=8),      # full line counts (512 threads): same arithmetic
-    dict(tune_fft_grid=2),                           # persistent workgroups: same arithmetic
-    dict(tune_col_lines=32, tune_row_lines=8, tune_fft_grid=2),
+    dict(tune_col_lines=32),                         # full column line count: same arithmetic
+    dict(tune_row_lines=4),                          # half row count: same arithmetic
     dict(tune_col_log_len=10),                       # other split of 2^19
     dict(tune_fft_radix=16),                         # 3-stage plans for 2^9 and 2^10 lines
-    dict(tune_fft_radix=16, tune_fft_grid=2),
+    dict(tune_fft_radix=16, tune_col_lines=32, tune_row_lines=4),
 ])
 def test_fft_launch_shapes(torch_dev, tune):
     """n_fft = 2^19 (columns 2^9 x rows 2^10 by default: both lengths where the
@@ -327,7 +326,7 @@ def test_autotuned_launch_shape(torch_dev):
     ds = synth.small_case(**dict(CASES["two_det_gaps"], n=3000, n_fft=1 << 13, ntmpl=3))
     tune, ms = binding.autotune(ds, ds.templates, batch=2)
     say(f"  autotuned {tune} in {ms:.3f} ms")
-    assert ms > 0.0 and tune["tune_col_log_len"] in (6, 7) and tune["tune_fft_grid"] in (1, 2)
+    assert ms > 0.0 and tune["tune_col_log_len"] in (6, 7)
     assert tune["tune_fft_radix"] in (16, 32)
     dd = binding.DeviceData(ds, tune=tune, batch=2)
     got = binding.compute_2f_batched(dd, ds.templates).cpu().numpy()

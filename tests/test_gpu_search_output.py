@@ -1,0 +1,192 @@
+"""Output modes of the grouped search, through the C ABI: candidate retention
+on the device (every bin above a 2F threshold, plus the loudest bin per
+template) and the accumulating epilogue that sums 2F over data segments with a
+common grid.
+
+Both are checked against the full-band 2F of the same search, which the parity
+tests pin to the FP64 oracle: candidates must be exactly the thresholded bins
+with bit-identical 2F, and the accumulated sum must equal the float32 sum of
+separate runs bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fstat_oracle as O
+from paper_2201_00451_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_2201_00451_amd import binding
+    binding.load_library()
+    return torch
+
+
+def bank(ds, nsky=3, nf1=5, binary_rows=2):
+    """Templates in sky groups with several spin-downs each, plus binary rows."""
+    base = ds.templates[0].copy()
+    rows = []
+    for s in range(nsky):
+        for j in range(nf1):
+            r = base.copy()
+            r[0] = base[0] + 0.01 * s
+            r[3] = base[3] + 2e-11 * (j - nf1 // 2)
+            rows.append(r)
+    for b in range(binary_rows):
+        r = base.copy()
+        r[5], r[6], r[7] = 0.2, 0.4 * 86400, 500.0 + 50.0 * b
+        rows.append(r)
+    return np.array(rows)
+
+
+def expected_candidates(full, thr):
+    t, b = np.nonzero(full > thr)
+    return set(zip(t.tolist(), b.tolist())), full[t, b]
+
+
+def check_best(res, full, flagged):
+    best = res["best_twoF"].cpu().numpy()
+    bbin = res["best_bin"].cpu().numpy()
+    for t in range(full.shape[0]):
+        if t in flagged:
+            assert np.isnan(best[t]), f"template {t}: flagged marker missing"
+            continue
+        m = np.max(full[t])
+        assert best[t] == m, f"template {t}: best {best[t]} vs {m}"
+        # equal maxima resolve to the highest bin
+        assert bbin[t] == np.nonzero(full[t] == m)[0].max()
+
+
+@pytest.mark.parametrize("slots", [2, 8])
+def test_candidates_equal_thresholded_band(torch_dev, slots):
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(seed=51, n=6000, n_fft=1 << 14, ndet=2, gaps=True, ntmpl=1,
+                          bin_lo=700, n_bins=9000)
+    tm = bank(ds)
+    tm[4, 3] = np.nan  # one flagged template: no candidates, NaN best
+    dd = binding.DeviceData(ds)
+    sr = binding.Search(dd, tm, slots=slots)
+    full = sr.run().cpu().numpy()
+    binding.sync_check()
+    assert np.all(np.isnan(full[4]))
+    ok = np.isfinite(full).all(axis=1)
+    thr = float(np.float32(np.quantile(full[ok], 0.999)))
+    res = sr.run_candidates(thr, capacity=1 << 14)
+    binding.sync_check()
+    want, _ = expected_candidates(np.where(np.isnan(full), -1.0, full), thr)
+    say(f"  slots {slots}: threshold {thr:.2f}, {res['count']} candidates, {len(want)} expected")
+    assert res["count"] == len(want) > 0
+    tt = res["tmpl"].cpu().numpy()
+    bb = res["bin"].cpu().numpy()
+    vv = res["twoF"].cpu().numpy()
+    got = set(zip(tt.tolist(), bb.tolist()))
+    assert len(got) == len(tt), "duplicate candidates"
+    assert got == want
+    np.testing.assert_array_equal(vv, full[tt, bb])
+    check_best(res, full, flagged={4})
+    # the stored 2F of the loudest template matches the oracle
+    t = int(np.argmax(np.nanmax(np.where(ok[:, None], full, -1.0), axis=1)))
+    ref = O.oracle_twoF(ds, tm[[t]])[0]
+    b = int(res["best_bin"][t])
+    assert abs(float(res["best_twoF"][t]) - ref[b]) <= 1e-4 * ref[b]
+
+
+def test_candidates_capacity_overflow_and_repeat(torch_dev):
+    """count reports every bin above the threshold when capacity is smaller;
+    the stored ones are distinct members of that set; a second call starts
+    from a cleared count and best array."""
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(seed=52, n=5000, n_fft=1 << 13, ndet=1, ntmpl=1)
+    tm = bank(ds, nsky=2, nf1=3, binary_rows=1)
+    dd = binding.DeviceData(ds)
+    sr = binding.Search(dd, tm, slots=4)
+    full = sr.run().cpu().numpy()
+    thr = float(np.float32(np.quantile(full, 0.99)))
+    want, _ = expected_candidates(full, thr)
+    for cap in (0, 17, len(want), len(want) + 5):
+        res = sr.run_candidates(thr, capacity=cap)
+        binding.sync_check()
+        assert res["count"] == len(want)
+        got = list(zip(res["tmpl"].cpu().numpy().tolist(), res["bin"].cpu().numpy().tolist()))
+        assert len(got) == min(cap, len(want)) and len(set(got)) == len(got)
+        assert set(got) <= want
+        check_best(res, full, flagged=set())
+    # a threshold above every bin: no candidates, best still reported
+    res = sr.run_candidates(float(np.float32(full.max() + 1.0)), capacity=64)
+    assert res["count"] == 0
+    check_best(res, full, flagged=set())
+
+
+def test_candidates_graph_replays(torch_dev):
+    import torch
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(seed=53, n=4000, n_fft=1 << 13, ndet=2, ntmpl=1)
+    tm = bank(ds, nsky=2, nf1=4, binary_rows=1)
+    dd = binding.DeviceData(ds)
+    full = binding.Search(dd, tm, slots=4).run().cpu().numpy()
+    torch.cuda.synchronize()
+    thr = float(np.float32(np.quantile(full, 0.995)))
+    want, _ = expected_candidates(full, thr)
+    sr = binding.Search(dd, tm, slots=4, graph=True)
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            res = sr.run_candidates(thr, capacity=4096, stream=s)
+        s.synchronize()
+        got = set(zip(res["tmpl"].cpu().numpy().tolist(), res["bin"].cpu().numpy().tolist()))
+        assert res["count"] == len(want) and got == want
+        check_best(res, full, flagged=set())
+        binding.compute_2f(dd, tm[:2])
+        torch.cuda.synchronize()
+
+
+def two_segments():
+    """Two data segments on one grid (same dt, n_fft, heterodyne, reference
+    time and band), from different noise and source draws."""
+    a = synth.small_case(seed=54, n=5000, n_fft=1 << 13, ndet=2, gaps=True, ntmpl=1)
+    b = synth.small_case(seed=55, n=5000, n_fft=1 << 13, ndet=2, gaps=True, ntmpl=1)
+    for k in ("dt", "f_het", "t_ref", "tau0", "n_fft", "bin_lo", "n_bins"):
+        assert getattr(a, k) == getattr(b, k), k
+    return a, b
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_accumulate_sums_segments(torch_dev, graph):
+    import torch
+    from paper_2201_00451_amd import binding
+    a, b = two_segments()
+    tm = bank(a, nsky=2, nf1=3, binary_rows=1)
+    tm[2, 3] = np.nan
+    dda, ddb = binding.DeviceData(a), binding.DeviceData(b)
+    sa = binding.Search(dda, tm, slots=4).run().cpu().numpy()
+    sb = binding.Search(ddb, tm, slots=4).run().cpu().numpy()
+    torch.cuda.synchronize()
+    acc_a = binding.Search(dda, tm, slots=4, graph=graph, accumulate=True)
+    acc_b = binding.Search(ddb, tm, slots=4, graph=graph, accumulate=True)
+    s = torch.cuda.Stream() if graph else None
+    out = torch.empty((tm.shape[0], a.n_bins), dtype=torch.float32, device=dda.device)
+    for rep in range(2):
+        out.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            acc_a.run(out=out, stream=s)
+            acc_b.run(out=out, stream=s)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        want = (sa.astype(np.float32) + sb.astype(np.float32)).astype(np.float32)
+        np.testing.assert_array_equal(got, want)
+        assert np.all(np.isnan(got[2])) and np.isfinite(np.delete(got, 2, axis=0)).all()
+        binding.compute_2f(dda, tm[:1])
+        torch.cuda.synchronize()
