@@ -205,10 +205,8 @@ __global__ __launch_bounds__(kResThreads) void k_grad(PlanConst P, void* ws) {
           sincos(om * (tsrc - tp.tp), &s2, &c2);
           invb = 1.0 / (1.0 + tp.asini * om * c2);
         }
-        const float c = reduce_cycles(P.f_het * (dr - r));
-        float sn, cs;
-        sincospif(2.0f * c, &sn, &cs);
-        z = make_float2(xv.x * cs + xv.y * sn, xv.y * cs - xv.x * sn);
+        const float2 e = cis_cycles(P.f_het * (dr - r));
+        z = make_float2(xv.x * e.x + xv.y * e.y, xv.y * e.x - xv.x * e.y);
         dz[0] = float(da * invb - tp.dshift[0]);
         dz[1] = float(ddl * invb - tp.dshift[1]);
         if (binary) {
@@ -231,9 +229,9 @@ __global__ __launch_bounds__(kResThreads) void k_grad(PlanConst P, void* ws) {
       float2 S[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) S[q] = make_float2(0.f, 0.f);
-      float sp, cp, ws_, wc_;
-      sincospif(f, &sp, &cp);
-      sincospif(f * (1.0f / float(D)), &ws_, &wc_);
+      const float2 pcs = cis_cycles_f32(0.5f * f);
+      const float2 wcs = cis_cycles_f32(f * (0.5f / float(D)));
+      const float sp = pcs.y, cp = pcs.x, ws_ = wcs.y, wc_ = wcs.x;
       const float inv_pi = 0.318309886183790671f;
 #pragma unroll 2
       for (int t = 0; t < 2 * D; ++t) {
@@ -269,9 +267,8 @@ __global__ __launch_bounds__(kResThreads) void k_grad(PlanConst P, void* ws) {
       }
       // antenna patterns and their x derivatives at T_k
       const double tau = tau_s + P.dt * double(tid + i * kResThreads);
-      const float xc = reduce_cycles(tp.alpha_cyc[X] - P.sid_rate_cyc * (tau + dly[i]));
-      float sx, cx;
-      sincospif(2.0f * xc, &sx, &cx);
+      const float2 ex = cis_cycles(tp.alpha_cyc[X] - P.sid_rate_cyc * (tau + dly[i]));
+      const float cx = ex.x, sx = ex.y;
       const float c2 = cx * cx - sx * sx, s2 = 2.0f * sx * cx;
       const float bas[5] = {1.0f, cx, sx, c2, s2};
       const float dbas[5] = {0.0f, -sx, cx, -2.0f * s2, 2.0f * c2};

@@ -76,6 +76,7 @@ constexpr int kRowsMax = (8192 >> LOGL) < 32 ? (8192 >> LOGL) : 32;
 struct FftVariant {
   const void* fn;
   int threads;
+  size_t lds;  // dynamic LDS bytes
 };
 
 // Variant choice of the FFT passes: full or half line counts (512 or 256
@@ -86,20 +87,27 @@ struct FftChoice {
   int mlr;
 };
 
+template <int LOGL, bool GROUPED, int MLR, int NL, int NT>
+FftVariant cols_variant_n() {
+  constexpr int R0 = kR0<LOGL, MLR>;
+  return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, NL, NT, GROUPED, MLR>), NT,
+          kLdsBytes<1 << LOGL, R0, NL, NL>};
+}
 template <int LOGL, bool GROUPED, int MLR>
 FftVariant cols_variant(bool half) {
-  if (half)
-    return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL> / 2, 256, GROUPED, MLR>),
-            256};
-  return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, kColsMax<LOGL>, 512, GROUPED, MLR>),
-          512};
+  if (half) return cols_variant_n<LOGL, GROUPED, MLR, kColsMax<LOGL> / 2, 256>();
+  return cols_variant_n<LOGL, GROUPED, MLR, kColsMax<LOGL>, 512>();
+}
+template <int LOGL, int MODE, int MLR, int RQ, int NT>
+FftVariant rows_variant_n() {
+  constexpr int R0 = kR0<LOGL, MLR>;
+  return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, RQ, NT, MODE, MLR>), NT,
+          kLdsBytes<1 << LOGL, R0, RQ, 2 * RQ>};
 }
 template <int LOGL, int MODE, int MLR>
 FftVariant rows_variant(bool half) {
-  if (half)
-    return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, kRowsMax<LOGL> / 2, 256, MODE, MLR>),
-            256};
-  return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, kRowsMax<LOGL>, 512, MODE, MLR>), 512};
+  if (half) return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL> / 2, 256>();
+  return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL>, 512>();
 }
 
 template <bool GROUPED, int MLR>
@@ -112,7 +120,7 @@ FftVariant pick_cols_v(int logl, bool half) {
     case 10: return cols_variant<10, GROUPED, MLR>(half);
     case 11: return cols_variant<11, GROUPED, 4>(half);
     case 12: return cols_variant<12, GROUPED, 4>(half);
-    default: return {nullptr, 0};
+    default: return {nullptr, 0, 0};
   }
 }
 FftVariant pick_cols(int logl, const FftChoice& c, bool grouped) {
@@ -129,7 +137,7 @@ FftVariant pick_rows_v(int logl, bool half) {
     case 10: return rows_variant<10, MODE, MLR>(half);
     case 11: return rows_variant<11, MODE, 4>(half);
     case 12: return rows_variant<12, MODE, 4>(half);
-    default: return {nullptr, 0};
+    default: return {nullptr, 0, 0};
   }
 }
 template <int MODE>
@@ -139,7 +147,12 @@ FftVariant pick_rows_m(int logl, const FftChoice& c) {
 FftVariant pick_rows(int logl, const FftChoice& c, int mode = kRow2F) {
   return mode == kRowAdjoint ? pick_rows_m<kRowAdjoint>(logl, c)
          : mode == kRowConj  ? pick_rows_m<kRowConj>(logl, c)
+         : mode == kRow2FExt ? pick_rows_m<kRow2FExt>(logl, c)
                              : pick_rows_m<kRow2F>(logl, c);
+}
+// The forward epilogue a RowOutput needs: plain 2F stores, or the extended one.
+int forward_row_mode(const RowOutput& out) {
+  return (out.twoF && !out.fafb && !out.cand && !out.best && !out.acc) ? kRow2F : kRow2FExt;
 }
 
 FftChoice cols_choice(const fstat_plan* p) { return {p->cols_half, p->fft_mlr}; }
@@ -273,8 +286,10 @@ fstat_status validate_ws(const fstat_plan* p, void* ws, size_t ws_bytes, int64_t
 }
 
 // LDS of a pass: NL lines at the padded pitch L + L/16 + 1 (see LdsLayout).
-size_t lds_bytes_cols(const fstat_plan* p) { return fft_lds_bytes(p->log_rr, p->cols_lines); }
-size_t lds_bytes_rows(const fstat_plan* p) { return fft_lds_bytes(p->log_c, 2 * p->rows_lines); }
+size_t lds_bytes_cols(const fstat_plan* p) {
+  return pick_cols(p->log_rr, cols_choice(p), false).lds;
+}
+size_t lds_bytes_rows(const fstat_plan* p) { return pick_rows(p->log_c, rows_choice(p)).lds; }
 
 // One workgroup per FFT work item.
 unsigned fft_grid(const fstat_plan*, const FftVariant&, size_t, int64_t n_items) {
@@ -362,7 +377,7 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
     return check_hip(hipGetLastError(), "resample launch");
   }
   const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), grouped);
-  const FftVariant rv = pick_rows(p->log_c, rows_choice(p));
+  const FftVariant rv = pick_rows(p->log_c, rows_choice(p), forward_row_mode(out));
   if ((s = tm.mark(2)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn)),
                      dim3(fft_grid(p, cv, lds_bytes_cols(p), cols_items(p, n))),
@@ -403,7 +418,7 @@ fstat_status set_lds_limits(const fstat_plan* p) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_cols(p)));
     if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(cols)");
   }
-  for (int mode : {int(kRow2F), int(kRowAdjoint), int(kRowConj)}) {
+  for (int mode : {int(kRow2F), int(kRowAdjoint), int(kRowConj), int(kRow2FExt)}) {
     e = hipFuncSetAttribute(pick_rows(p->log_c, rows_choice(p), mode).fn,
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_rows(p)));
     if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(rows)");

@@ -64,8 +64,8 @@ struct PlanConst {
 struct TmplParams {
   double nhat[3];
   double df, f1dot, f2dot, asini, om_b, tp;
-  // spin-down and sub-bin phase in cycles as a cubic in the grid index k:
-  // Phi(k) = sd[0] + k (sd[1] + k (sd[2] + k sd[3]))
+  // spin-down and sub-bin phase in quarter turns (4 x cycles) as a cubic in
+  // the grid index k: 4 Phi(k) = sd[0] + k (sd[1] + k (sd[2] + k sd[3]))
   double sd[4];
   double alpha_cyc[kMaxDet];  // (alpha - lon - sidereal angle at 0) / 2 pi
   // Whitened, weighted antenna patterns: with M = [[A, C], [C, B]] = L L^T
@@ -212,6 +212,10 @@ __device__ __forceinline__ void buf_store2(float2 x, __amdgpu_buffer_rsrc_t r, u
   using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), r, voff, soff, 0);
 }
+// One float; an offset at or past the descriptor's end drops the store.
+__device__ __forceinline__ void buf_store1(float x, __amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, voff, 0, 0);
+}
 
 // ---------------------------------------------------------------------------
 // FP64 timing (Sec. 2: t_b = t + t_m; binary: t_b = t_src + R(t_src)).
@@ -337,43 +341,90 @@ __device__ inline void split_u(double u, int64_t& j0, float& f) {
   }
 }
 
-// Reduce a phase given in cycles to [-1/2, 1/2] in FP64, then to float.
-__device__ inline float reduce_cycles(double c) { return static_cast<float>(c - rint(c)); }
+// (cos, sin) of (pi/2)(n + r) for an integer quarter-turn count n and a
+// remainder |r| <= 1/2.  sin((pi/2) r) = r P(r^2), cos((pi/2) r) = 1 + r^2 Q(r^2)
+// with P cubic and Q cubic, fitted for this file to the functions on
+// [0, 1/4] in r^2 (least squares on Chebyshev nodes, reweighted towards
+// equal ripple); evaluated with FMA in FP32 the results are within 9e-8 (sin)
+// and 6e-8 (cos) of the exact values.  The quadrant then swaps and negates.
+__device__ __forceinline__ float2 cis_quarter(int n, float r) {
+  const float u = r * r;
+  float ps = fmaf(u, -4.602177069e-03f, 7.968022674e-02f);
+  ps = fmaf(u, ps, -6.459634900e-01f);
+  ps = fmaf(u, ps, 1.570796371e+00f);
+  const float sn = r * ps;
+  float pc = fmaf(u, 9.040216682e-04f, -2.086028829e-02f);
+  pc = fmaf(u, pc, 2.536692321e-01f);
+  pc = fmaf(u, pc, -1.233700514e+00f);
+  const float cs = fmaf(u, pc, 1.0f);
+  const bool odd = (n & 1) != 0;
+  const float x = odd ? sn : cs, y = odd ? cs : sn;
+  // cos is negative in quadrants 1 and 2, sin in quadrants 2 and 3
+  const uint32_t sx = uint32_t((n + 1) & 2) << 30, sy = uint32_t(n & 2) << 30;
+  return make_float2(__uint_as_float(__float_as_uint(x) ^ sx),
+                     __uint_as_float(__float_as_uint(y) ^ sy));
+}
+
+// (cos 2 pi c, sin 2 pi c) for a phase c in FP64 cycles (|c| < 2^28): the
+// quarter-turn count and remainder are taken exactly in FP64, so only the
+// remainder is rounded to FP32.
+__device__ __forceinline__ float2 cis_cycles(double c) {
+  const double c4 = 4.0 * c;
+  const double q = rint(c4);
+  return cis_quarter(int(q), static_cast<float>(c4 - q));
+}
+
+// The same for a phase already in FP32 cycles (exact quarter-turn split).
+__device__ __forceinline__ float2 cis_cycles_f32(float c) {
+  const float c4 = 4.0f * c;
+  const float q = rintf(c4);
+  return cis_quarter(int(q), c4 - q);
+}
+
+// exp(-2 pi i e / n) for 0 <= e < n = 2^log_n <= 2^24: the quarter-turn
+// count and remainder of 4 e / n are split exactly in integers.
+__device__ __forceinline__ float2 cis_neg_frac(int64_t e, int log_n) {
+  const int64_t t = e << 2;
+  const int64_t q = (t + (int64_t(1) << (log_n - 1))) >> log_n;
+  const float r = ldexpf(float(int32_t(t - (q << log_n))), -log_n);
+  const float2 v = cis_quarter(int(q), r);
+  return make_float2(v.x, -v.y);
+}
 
 // exp(-i Phi_s(tau_k)) exp(-2 pi i df (tau_k - tau0)): the spin-down phase of
-// Sec. 2 about t_ref and the sub-bin frequency offset, FP64 cycles evaluated
-// from the template's cubic in k (spindown_coefficients), reduced to
-// [-1/2, 1/2] before the FP32 rotation.  One definition for every kernel
-// that applies it, so the per-template and grouped paths agree bit for bit;
-// evaluated without FMA contraction, so every kernel gets the same bits.
+// Sec. 2 about t_ref and the sub-bin frequency offset.  The template carries
+// the phase as a cubic in the grid index k in quarter turns
+// (spindown_coefficients); it is evaluated in FP64 with FMA, split into a
+// quarter-turn count and an FP32 remainder, and rotated with cis_quarter.
+// One definition for every kernel that applies it, so the per-template and
+// grouped paths agree bit for bit.
 __host__ __device__ inline void spindown_coefficients(const PlanConst& P, double f1dot,
                                                       double f2dot, double df, double sd[4]) {
-  // with d0 = tau0 - t_ref and s = dt k:
+  // with d0 = tau0 - t_ref and s = dt k, in cycles:
   //   f1dot (d0 + s)^2 / 2 + f2dot (d0 + s)^3 / 6 + df s
+  // stored times 4 (quarter turns; the scaling by 4 is exact)
   const double d0 = P.tau0 - P.t_ref, dt = P.dt;
-  sd[0] = f1dot * d0 * d0 * 0.5 + f2dot * d0 * d0 * d0 * (1.0 / 6.0);
-  sd[1] = dt * (f1dot * d0 + f2dot * d0 * d0 * 0.5 + df);
-  sd[2] = dt * dt * (f1dot * 0.5 + f2dot * d0 * 0.5);
-  sd[3] = dt * dt * dt * f2dot * (1.0 / 6.0);
+  sd[0] = 4.0 * (f1dot * d0 * d0 * 0.5 + f2dot * d0 * d0 * d0 * (1.0 / 6.0));
+  sd[1] = 4.0 * (dt * (f1dot * d0 + f2dot * d0 * d0 * 0.5 + df));
+  sd[2] = 4.0 * (dt * dt * (f1dot * 0.5 + f2dot * d0 * 0.5));
+  sd[3] = 4.0 * (dt * dt * dt * f2dot * (1.0 / 6.0));
 }
-__device__ inline float2 spindown_rotation(const double sd[4], int64_t k) {
-#pragma clang fp contract(off)
-  const double x = double(k);
-  const double cyc = sd[0] + x * (sd[1] + x * (sd[2] + x * sd[3]));
-  const float c = reduce_cycles(cyc);
-  float sn, cs;
-  sincospif(2.0f * c, &sn, &cs);
-  return make_float2(cs, -sn);
+// k < n_fft <= 2^24
+__device__ __forceinline__ float2 spindown_rotation(const double sd[4], int64_t k) {
+  const double x = double(int32_t(k));
+  const double c4 = fma(x, fma(x, fma(x, sd[3], sd[2]), sd[1]), sd[0]);
+  const double q = rint(c4);
+  const float2 e = cis_quarter(int(q), static_cast<float>(c4 - q));
+  return make_float2(e.x, -e.y);
 }
 
 __device__ inline float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-// Complex product without FMA contraction: applying the spin-down rotation
-// in different kernels must give the same bits.
+// Complex product with explicit FMA: applying the spin-down rotation in
+// different kernels must give the same bits whatever the compiler contracts.
 __device__ inline float2 cmul_exact(float2 a, float2 b) {
-#pragma clang fp contract(off)
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }

@@ -96,18 +96,28 @@ __device__ inline uint32_t xcd_remap(uint32_t id, uint32_t total) {
   return (id & 7u) * (full >> 3) + (id >> 3);
 }
 
-// LDS layout of NL lines of length L: line-major with one pad element every
-// 16 and an odd-ish pitch, addr(idx, line) = line * pitch + idx + idx / 16,
-// pitch = L + L / 16 + 1.  Consecutive butterflies of a stage, consecutive
-// elements of a line and the same element of consecutive lines all land in
-// different LDS banks (the radix-R decimation stride R becomes R + R/16).
-template <int L>
+// LDS layout of lines of length L: line-major, one pad element after every
+// PAD elements of a line, addr(idx, line) = line * pitch + idx + idx / PAD.
+// PAD is the first stage's radix R0, whose butterflies write idx = R0 i + m
+// across lanes: the pad turns that stride into R0 + 1, an odd number of bank
+// pairs.  The stages that face HBM run F lines fastest across lanes (F
+// lines times 16 / F consecutive butterflies in every 16 lanes); the pitch is
+// L + L / PAD rounded up to 16 / F modulo 16 (to 1 if F >= 16), so those 16
+// lanes touch 16 different 8-byte bank pairs.  The middle stages run one
+// line's butterflies across lanes.
+template <int L, int PAD, int F>
 struct LdsLayout {
-  static constexpr int pitch = L + L / 16 + 1;
+  static constexpr int kBank = F >= 16 ? 1 : 16 / F;
+  static constexpr int kBase = L + L / PAD;
+  static constexpr int pitch = kBase + ((kBank - kBase % 16) % 16 + 16) % 16;
   __device__ static __forceinline__ int at(int idx, int line) {
-    return line * pitch + idx + (idx >> 4);
+    return line * pitch + idx + idx / PAD;
   }
 };
+// Bytes of LDS of a pass: NL padded lines and the half twiddle table.
+template <int L, int PAD, int F, int NL>
+constexpr size_t kLdsBytes = (size_t(NL) * LdsLayout<L, PAD, F>::pitch + size_t(L / 2)) *
+                             sizeof(float2);
 
 // W_L^e from the LDS half table T[e] = W_L^e, e < L/2 (W_L^{e+L/2} = -W_L^e).
 template <int L>
@@ -131,7 +141,7 @@ __device__ __forceinline__ void twiddle_dft(float2 (&v)[R], int k, const float2*
 // A middle Stockham stage (LDS to LDS) over NL lines.  Butterfly b covers
 // index i = b mod (L/R) of line b div (L/R); reads finish (barrier) before
 // the in-place writes, which finish (barrier) before the next stage.
-template <int LOGL, int NL, int NT, int S, int MLR>
+template <int LOGL, int NL, int NT, int S, int MLR, class Lay>
 __device__ __forceinline__ void fft_stage(float2* buf, const float2* twl) {
   constexpr int LOGR = stage_logr(LOGL, S, MLR), R = 1 << LOGR;
   constexpr int P = 1 << stage_logp(LOGL, S, MLR);
@@ -139,7 +149,6 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* twl) {
   constexpr int NBL = L / R;
   constexpr int NB = NL * NBL;
   constexpr int PER = (NB + NT - 1) / NT;
-  using Lay = LdsLayout<L>;
   const int tid = threadIdx.x;
   float2 v[PER][R];
 #pragma unroll
@@ -168,11 +177,11 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* twl) {
 }
 
 // Middle stages 1 .. last-1.
-template <int LOGL, int NL, int NT, int S, int MLR>
+template <int LOGL, int NL, int NT, int S, int MLR, class Lay>
 __device__ __forceinline__ void fft_middle(float2* buf, const float2* twl) {
   if constexpr (S < stage_count(LOGL, MLR) - 1) {
-    fft_stage<LOGL, NL, NT, S, MLR>(buf, twl);
-    fft_middle<LOGL, NL, NT, S + 1, MLR>(buf, twl);
+    fft_stage<LOGL, NL, NT, S, MLR, Lay>(buf, twl);
+    fft_middle<LOGL, NL, NT, S + 1, MLR, Lay>(buf, twl);
   }
 }
 
@@ -186,18 +195,9 @@ __global__ void k_twiddles(void* ws) {
   tw_stage(ws)[e] = make_float2(float(c), float(s));
 }
 
-// W_N^e for 0 <= e < N <= 2^24 (e / N is exact in FP32).
+// W_N^e for 0 <= e < N <= 2^24.
 __device__ __forceinline__ float2 tw_n(int64_t e, int64_t n_fft) {
-  float s, c;
-  sincospif(-2.0f * (float(e) / float(n_fft)), &s, &c);
-  return make_float2(c, s);
-}
-
-// Bytes of LDS a pass with NL lines of 2^LOGL uses: the padded lines plus the
-// half twiddle table.
-__host__ __device__ constexpr size_t fft_lds_bytes(int logl, int nl) {
-  return (size_t(nl) * size_t((1 << logl) + (1 << logl) / 16 + 1) + size_t(1 << logl) / 2) *
-         sizeof(float2);
+  return cis_neg_frac(e, __builtin_ctzll(uint64_t(n_fft)));
 }
 
 template <int LOGL, int MLR>
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
   constexpr int R0 = kR0<LOGL, MLR>, NB0 = NL * (L / R0);
   constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = NL * PL;
   constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
-  using Lay = LdsLayout<L>;
+  using Lay = LdsLayout<L, R0, NL>;
   float2* twl = lds + NL * Lay::pitch;
   const int tid = threadIdx.x;
   const int64_t C = int64_t(1) << log_c;
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
     }
   }
   __syncthreads();
-  fft_middle<LOGL, NL, NT, 1, MLR>(lds, twl);
+  fft_middle<LOGL, NL, NT, 1, MLR, Lay>(lds, twl);
   // last stage: LDS -> registers -> DFT -> x W_N^{q c} -> HBM
   constexpr int PER = (NBL + NT - 1) / NT;
 #pragma unroll
@@ -356,7 +356,16 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
 // arrays 2 and 3 of the slot, with 2F if twoF is not null; or the complex
 // transform itself, conjugated, written to arrays 0 and 1 at the natural
 // index for indices below k_pad (the inverse transform of the adjoint).
-enum RowMode { kRow2F = 0, kRowAdjoint = 1, kRowConj = 2 };
+// kRow2F stores 2F only (the plain full-band output); kRow2FExt is the same
+// transform with every optional output of RowOutput (Fa/Fb, accumulation,
+// candidates, loudest bin).
+enum RowMode { kRow2F = 0, kRowAdjoint = 1, kRowConj = 2, kRow2FExt = 3 };
+
+// 2F = 2 (|Fa'|^2 + |Fb'|^2) with explicit FMA, so that every epilogue gives
+// the same bits.
+__device__ __forceinline__ float two_f(float2 fa, float2 fb) {
+  return 2.0f * (fmaf(fa.x, fa.x, fa.y * fa.y) + fmaf(fb.x, fb.x, fb.y * fb.y));
+}
 
 struct RowItem {
   int live, flagged, g;
@@ -434,7 +443,7 @@ __device__ __forceinline__ float rows_out(const PlanConst& P, void* ws, const Ro
     slot_buf(ws, P, it.g, 3)[nat] = make_float2(gv * fb.x, -gv * fb.y);
   }
   if (!in_band) return -1.0f;
-  const float v2 = 2.0f * ((fa.x * fa.x + fa.y * fa.y) + (fb.x * fb.x + fb.y * fb.y));
+  const float v2 = two_f(fa, fb);
   if (out.twoF) {
     float* dst = out.twoF + it.tmpl * P.n_bins + o;
     *dst = out.acc ? *dst + v2 : v2;
@@ -486,7 +495,7 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
   constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = RQ * PL;
   constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
   constexpr int PER = (NBL + NT - 1) / NT;
-  using Lay = LdsLayout<L>;
+  using Lay = LdsLayout<L, R0, RQ>;
   float2* twl = lds + NL * Lay::pitch;
   const int64_t Rr = int64_t(1) << log_rr;
   const int tid = threadIdx.x;
@@ -516,9 +525,16 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
       }
     }
     __syncthreads();
-    fft_middle<LOGL, NL, NT, 1, MLR>(lds, twl);
+    fft_middle<LOGL, NL, NT, 1, MLR, Lay>(lds, twl);
     float bmax = -1.0f;
     int64_t bbin = 0;
+    // plain 2F: band offsets o = ((nat + N/2) mod N) - bin_lo in 32 bits; the
+    // descriptor spans this template's n_bins floats, so the store of a bin
+    // outside the band (o >= n_bins, also when the subtraction wraps) is dropped
+    const auto tf = buf_rsrc(MODE == kRow2F ? out.twoF + it.tmpl * P.n_bins : nullptr,
+                             MODE == kRow2F ? uint32_t(P.n_bins * int64_t(sizeof(float))) : 0u);
+    const uint32_t nmask = uint32_t(P.n_fft - 1), lo = uint32_t(P.bin_lo);
+    const uint32_t ostep = uint32_t(Rr * PL);
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
       const int b = tid + s * NT;
@@ -532,6 +548,15 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
         }
         twiddle_dft<RL, PL, L>(va, i, twl);
         twiddle_dft<RL, PL, L>(vb, i, twl);
+        if (MODE == kRow2F) {
+          const uint32_t o0 = uint32_t(it.q0 + ql + Rr * i) + uint32_t(P.n_fft / 2);
+#pragma unroll
+          for (int m = 0; m < RL; ++m) {
+            const uint32_t o = ((o0 + uint32_t(m) * ostep) & nmask) - lo;
+            buf_store1(two_f(va[m], vb[m]), tf, o * uint32_t(sizeof(float)));
+          }
+          continue;
+        }
 #pragma unroll
         for (int m = 0; m < RL; ++m) {
           const int64_t nat = it.q0 + ql + Rr * int64_t(i + m * PL);
@@ -543,7 +568,7 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
         }
       }
     }
-    if (MODE == kRow2F && out.best) {
+    if (MODE == kRow2FExt && out.best) {
       // largest 2F of the item: wavefront maximum, one atomic per wave
       unsigned long long key =
           bmax >= 0.0f ? (static_cast<unsigned long long>(__float_as_uint(bmax)) << 32) |

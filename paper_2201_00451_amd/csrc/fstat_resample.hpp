@@ -190,11 +190,9 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
       if (j >= 0 && j < d.n) {
         float2 xv = d.x[j];
         double dl = sample_delay(re, tp, d.t0 + P.dt * double(j), oob);
-        float c = reduce_cycles(P.f_het * dl);
-        float sn, cs;
-        sincospif(2.0f * c, &sn, &cs);
-        // x * exp(-2 pi i c)
-        z = make_float2(xv.x * cs + xv.y * sn, xv.y * cs - xv.x * sn);
+        const float2 e = cis_cycles(P.f_het * dl);
+        // x * exp(-2 pi i f_h dl)
+        z = make_float2(xv.x * e.x + xv.y * e.y, xv.y * e.x - xv.x * e.y);
       }
       zs[w] = z;
     }
@@ -212,8 +210,9 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
       if (f == 0.0f) {
         zh = zp[D - 1];
       } else {
-        float ws_, wc_;
-        sincospif(f * (1.0f / float(D)), &ws_, &wc_);
+        // window phase pi f / D and sinc numerator sin(pi f), in cycles
+        const float2 wcs = cis_cycles_f32(f * (0.5f / float(D)));
+        const float ws_ = wcs.y, wc_ = wcs.x;
         float sx = 0.f, sy = 0.f;
 #pragma unroll
         for (int t = 0; t < 2 * D; ++t) {
@@ -223,14 +222,13 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
           sx = fmaf(h, zv.x, sx);
           sy = fmaf(h, zv.y, sy);
         }
-        const float sp = sinpif(f);
+        const float sp = cis_cycles_f32(0.5f * f).y;
         zh = make_float2(sx * sp, sy * sp);
       }
       // antenna patterns at T_k: x = alpha - phi(T_k), in cycles
       const double tau = tau_s + P.dt * double(tid + i * kResThreads);
-      const float xc = reduce_cycles(tp.alpha_cyc[X] - P.sid_rate_cyc * (tau + dly[i]));
-      float sx, cx;
-      sincospif(2.0f * xc, &sx, &cx);
+      const float2 ex = cis_cycles(tp.alpha_cyc[X] - P.sid_rate_cyc * (tau + dly[i]));
+      const float cx = ex.x, sx = ex.y;
       const float c2 = cx * cx - sx * sx, s2 = 2.0f * sx * cx;
       const float a = tp.ca[X][0] + tp.ca[X][1] * cx + tp.ca[X][2] * sx + tp.ca[X][3] * c2 +
                       tp.ca[X][4] * s2;
@@ -293,10 +291,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample(PlanConst P, void* ws,
 
 // exp(-2 pi i nat k / N) with the product reduced exactly in integers.
 __device__ inline float2 bin_twiddle(int64_t nat, int64_t k, int64_t n_fft) {
-  const int64_t r = (nat * k) & (n_fft - 1);
-  float s, c;
-  sincospif(2.0f * float(r) / float(n_fft), &s, &c);
-  return make_float2(c, -s);
+  return cis_neg_frac((nat * k) & (n_fft - 1), __builtin_ctzll(uint64_t(n_fft)));
 }
 
 // Natural FFT index of band bin i (bins ascend in frequency from bin_lo of

@@ -469,14 +469,19 @@ def config_refine(seed=5, ndays=30.0, dt=1.0, n_fft=1 << 22, f_het=400.0, band=0
 
 def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmpl=4, D=8,
                rho=15.0, noise=True, binary=False, gaps=False, noise_vars=None, f_inj=None,
-               bin_lo=0, n_bins=None, keep_f64=False, model=None, sites=None, f1dot=None):
-    """Small search (a few hours of data) for oracle pins and quick parity."""
+               bin_lo=0, n_bins=None, keep_f64=False, model=None, sites=None, f1dot=None,
+               t0=0.0, noise_seed=None):
+    """Small search (a few hours of data) for oracle pins and quick parity.
+
+    t0 shifts the data (and the computed grid) in time with the reference time
+    kept at 0, so that cases with the same seed and different t0 are segments
+    of one source; noise_seed (default: seed) draws their noise independently."""
     ss = np.random.SeedSequence(seed)
     s_par, s_gap = ss.spawn(2)
     rng = np.random.default_rng(s_par)
     sites = sites or ["H", "L", "H", "L"][:ndet]
     nv = noise_vars or [1.0] * ndet
-    dets = [make_detector(s, 0.0, n, v, name=f"{s}{i}") for i, (s, v) in enumerate(zip(sites, nv))]
+    dets = [make_detector(s, t0, n, v, name=f"{s}{i}") for i, (s, v) in enumerate(zip(sites, nv))]
     band = 0.5 / dt
     inj = dict(alpha=float(rng.uniform(0, 2 * math.pi)), delta=float(rng.uniform(-1.2, 1.2)),
                f=f_het + (f_inj if f_inj is not None else float(rng.uniform(-0.6, 0.6) * band)),
@@ -491,8 +496,8 @@ def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmp
         rg = np.random.default_rng(s_gap)
         g = [random_gaps(rg, n, dt, 2, 600.0) for _ in dets]
     model = dict(model or EPHEM_MODEL)
-    xs, vs = make_data(dets, dt, f_het, 0.0, [inj], seed, gaps=g, noise=noise, keep_f64=keep_f64,
-                       model=model)
+    xs, vs = make_data(dets, dt, f_het, 0.0, [inj], seed if noise_seed is None else noise_seed,
+                       gaps=g, noise=noise, keep_f64=keep_f64, model=model)
     tm = np.zeros((ntmpl, 8))
     tm[:, 0] = inj["alpha"] + 0.02 * np.arange(ntmpl)
     tm[:, 1] = inj["delta"]
@@ -502,7 +507,7 @@ def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmp
         tm[:, 5], tm[:, 6], tm[:, 7] = inj["asini"], inj["porb"], inj["tp"]
     margin = 512.0 + (inj.get("asini", 0.0) if binary else 0.0)
     nb = n_fft if n_bins is None else n_bins
-    ds = Dataset("small", dt, f_het, 0.0, grid_origin(0.0, dt, margin), n_fft, D, bin_lo, nb,
+    ds = Dataset("small", dt, f_het, 0.0, grid_origin(t0, dt, margin), n_fft, D, bin_lo, nb,
                  dets, xs, vs, tm, ephem_model=model, injections=[inj])
     return finish(ds)
 
