@@ -61,7 +61,7 @@ int ilog2(int64_t v) {
 // Lines per workgroup of the column pass (NL) and rows per workgroup of the
 // row pass (RQ): at most as many as fit 128 KiB of LDS, capped for
 // coalescing, with 512 threads; or half of that with 256 threads, so that two
-// workgroups share a compute unit (the automatic choice).
+// workgroups share a compute unit.
 int cols_lines_max(int log_rr) { return std::min(64, 16384 >> log_rr); }
 int rows_lines_max(int log_c) { return std::min(32, 8192 >> log_c); }
 
@@ -77,6 +77,7 @@ struct FftVariant {
   const void* fn;
   int threads;
   size_t lds;  // dynamic LDS bytes
+  int lines;   // columns (column pass) or rows of each array (row pass) per item
 };
 
 // Variant choice of the FFT passes: full or half line counts (512 or 256
@@ -91,7 +92,7 @@ template <int LOGL, bool GROUPED, int MLR, int NL, int NT>
 FftVariant cols_variant_n() {
   constexpr int R0 = kR0<LOGL, MLR>;
   return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, NL, NT, GROUPED, MLR>), NT,
-          kLdsBytes<1 << LOGL, R0, NL, NL>};
+          kLdsBytes<1 << LOGL, R0, NL, NL>, NL};
 }
 template <int LOGL, bool GROUPED, int MLR>
 FftVariant cols_variant(bool half) {
@@ -102,12 +103,19 @@ template <int LOGL, int MODE, int MLR, int RQ, int NT>
 FftVariant rows_variant_n() {
   constexpr int R0 = kR0<LOGL, MLR>;
   return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, RQ, NT, MODE, MLR>), NT,
-          kLdsBytes<1 << LOGL, R0, RQ, 2 * RQ>};
+          kLdsBytes<1 << LOGL, R0, RQ, 2 * RQ>, RQ};
 }
+// The adjoint, conjugate and extended epilogues of a radix-32 plan exceed 256
+// VGPRs at the full count: they take the half count (the same arithmetic per
+// point, so the same bits as the full-count plain 2F kernel).
 template <int LOGL, int MODE, int MLR>
 FftVariant rows_variant(bool half) {
-  if (half) return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL> / 2, 256>();
-  return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL>, 512>();
+  if constexpr (MODE != kRow2F && kR0<LOGL, MLR> == 32) {
+    return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL> / 2, 256>();
+  } else {
+    if (half) return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL> / 2, 256>();
+    return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL>, 512>();
+  }
 }
 
 template <bool GROUPED, int MLR>
@@ -120,7 +128,7 @@ FftVariant pick_cols_v(int logl, bool half) {
     case 10: return cols_variant<10, GROUPED, MLR>(half);
     case 11: return cols_variant<11, GROUPED, 4>(half);
     case 12: return cols_variant<12, GROUPED, 4>(half);
-    default: return {nullptr, 0, 0};
+    default: return {nullptr, 0, 0, 1};
   }
 }
 FftVariant pick_cols(int logl, const FftChoice& c, bool grouped) {
@@ -137,7 +145,7 @@ FftVariant pick_rows_v(int logl, bool half) {
     case 10: return rows_variant<10, MODE, MLR>(half);
     case 11: return rows_variant<11, MODE, 4>(half);
     case 12: return rows_variant<12, MODE, 4>(half);
-    default: return {nullptr, 0, 0};
+    default: return {nullptr, 0, 0, 1};
   }
 }
 template <int MODE>
@@ -285,21 +293,15 @@ fstat_status validate_ws(const fstat_plan* p, void* ws, size_t ws_bytes, int64_t
   return FSTAT_OK;
 }
 
-// LDS of a pass: NL lines at the padded pitch L + L/16 + 1 (see LdsLayout).
-size_t lds_bytes_cols(const fstat_plan* p) {
-  return pick_cols(p->log_rr, cols_choice(p), false).lds;
-}
-size_t lds_bytes_rows(const fstat_plan* p) { return pick_rows(p->log_c, rows_choice(p)).lds; }
-
 // One workgroup per FFT work item.
-unsigned fft_grid(const fstat_plan*, const FftVariant&, size_t, int64_t n_items) {
+unsigned fft_grid(int64_t n_items) {
   return unsigned(std::max<int64_t>(n_items, 1));
 }
-int64_t cols_items(const fstat_plan* p, int n) {
-  return ((int64_t(1) << p->log_c) / p->cols_lines) * 2 * n;
+int64_t cols_items(const fstat_plan* p, const FftVariant& v, int n) {
+  return ((int64_t(1) << p->log_c) / v.lines) * 2 * n;
 }
-int64_t rows_items(const fstat_plan* p, int n) {
-  return ((int64_t(1) << p->log_rr) / p->rows_lines) * n;
+int64_t rows_items(const fstat_plan* p, const FftVariant& v, int n) {
+  return ((int64_t(1) << p->log_rr) / v.lines) * n;
 }
 
 // Resampling kernel for a supported interpolation half-width.
@@ -380,14 +382,14 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
   const FftVariant rv = pick_rows(p->log_c, rows_choice(p), forward_row_mode(out));
   if ((s = tm.mark(2)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn)),
-                     dim3(fft_grid(p, cv, lds_bytes_cols(p), cols_items(p, n))),
-                     dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 0, p->log_c,
+                     dim3(fft_grid(cols_items(p, cv, n))), dim3(cv.threads), cv.lds, st, P, ws, map,
+                     slots, 0, p->log_c,
                      p->rows_act);
   if ((s = tm.mark(2)) != FSTAT_OK) return s;
   if ((s = tm.mark(3)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rv.fn)),
-                     dim3(fft_grid(p, rv, lds_bytes_rows(p), rows_items(p, n))),
-                     dim3(rv.threads), lds_bytes_rows(p), st, P, ws, map, slots, p->log_rr, out);
+                     dim3(fft_grid(rows_items(p, rv, n))), dim3(rv.threads), rv.lds, st, P, ws, map,
+                     slots, p->log_rr, out);
   if ((s = tm.mark(3)) != FSTAT_OK) return s;
   return check_hip(hipGetLastError(), "kernel launch");
 }
@@ -414,13 +416,13 @@ fstat_status finish_timer(KernelTimer& tm, hipStream_t st, float* kernel_ms, int
 fstat_status set_lds_limits(const fstat_plan* p) {
   hipError_t e = hipSuccess;
   for (bool grouped : {false, true}) {
-    e = hipFuncSetAttribute(pick_cols(p->log_rr, cols_choice(p), grouped).fn,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_cols(p)));
+    const FftVariant v = pick_cols(p->log_rr, cols_choice(p), grouped);
+    e = hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(v.lds));
     if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(cols)");
   }
   for (int mode : {int(kRow2F), int(kRowAdjoint), int(kRowConj), int(kRow2FExt)}) {
-    e = hipFuncSetAttribute(pick_rows(p->log_c, rows_choice(p), mode).fn,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes_rows(p)));
+    const FftVariant v = pick_rows(p->log_c, rows_choice(p), mode);
+    e = hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(v.lds));
     if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(rows)");
   }
   return FSTAT_OK;
@@ -542,20 +544,20 @@ fstat_status launch_grad_chunk(const fstat_plan* p, const PlanConst& P, const do
                      dim3(kResThreads), 0, st, P, ws, map, slots);
   const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), false);
   const ColsFn cols = reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn));
-  const dim3 cgrid(fft_grid(p, cv, lds_bytes_cols(p), cols_items(p, n)));
+  const dim3 cgrid(fft_grid(cols_items(p, cv, n)));
   const FftVariant ra = pick_rows(p->log_c, rows_choice(p), kRowAdjoint);
   const FftVariant rc = pick_rows(p->log_c, rows_choice(p), kRowConj);
-  const dim3 rgrid(fft_grid(p, ra, lds_bytes_rows(p), rows_items(p, n)));
-  hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 0,
+  const dim3 rgrid_a(fft_grid(rows_items(p, ra, n))), rgrid_c(fft_grid(rows_items(p, rc, n)));
+  hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), cv.lds, st, P, ws, map, slots, 0,
                      p->log_c, p->rows_act);
   RowOutput oa = row_output(twoF, nullptr);
   oa.gin = gin;
-  hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(ra.fn)), rgrid, dim3(ra.threads),
-                     lds_bytes_rows(p), st, P, ws, map, slots, p->log_rr, oa);
-  hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), lds_bytes_cols(p), st, P, ws, map, slots, 2,
+  hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(ra.fn)), rgrid_a, dim3(ra.threads),
+                     ra.lds, st, P, ws, map, slots, p->log_rr, oa);
+  hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), cv.lds, st, P, ws, map, slots, 2,
                      p->log_c, int64_t(1) << p->log_rr);
-  hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rc.fn)), rgrid, dim3(rc.threads),
-                     lds_bytes_rows(p), st, P, ws, map, slots, p->log_rr,
+  hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rc.fn)), rgrid_c, dim3(rc.threads),
+                     rc.lds, st, P, ws, map, slots, p->log_rr,
                      row_output(nullptr, nullptr));
   hipLaunchKernelGGL(grad_kernel(p->desc.sinc_halfwidth, false), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws);

@@ -224,3 +224,34 @@ def test_semicoherent_segments_against_oracle(torch_dev):
         assert np.all(err <= tol)
     # the source adds up: the loudest bin of the summed band beats each segment's
     assert ref[0].max() > max(ra[0].max(), rb[0].max()) + 50.0
+
+
+def test_optional_outputs_bitwise_at_radix32_rows(torch_dev):
+    """At n_fft = 2^20 the row pass runs two radix-32 stages; the epilogues
+    with optional outputs (candidates, Fa/Fb, the adjoint's 2F) run with a
+    different line count there and must still give the plain 2F bit for bit."""
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(seed=60, n=20000, n_fft=1 << 20, ndet=2, ntmpl=1, rho=20.0)
+    tm = bank(ds, nsky=1, nf1=3, binary_rows=1)
+    dd = binding.DeviceData(ds, batch=4)
+    assert dd.plan.info()[2] == 10
+    plain = binding.compute_2f(dd, tm).cpu().numpy()
+    sr = binding.Search(dd, tm, slots=4)
+    full = sr.run().cpu().numpy()
+    np.testing.assert_array_equal(full, plain)
+    thr = float(np.float32(np.quantile(full, 0.9999)))
+    res = sr.run_candidates(thr, capacity=1 << 12)
+    tt, bb = res["tmpl"].cpu().numpy(), res["bin"].cpu().numpy()
+    assert res["count"] == int(np.sum(full > thr)) == len(tt)
+    np.testing.assert_array_equal(res["twoF"].cpu().numpy(), full[tt, bb])
+    check_best(res, full, flagged=set())
+    tf, fab = binding.compute_2f(dd, tm, fafb=True)
+    np.testing.assert_array_equal(tf.cpu().numpy(), plain)
+    w = np.ones((tm.shape[0], ds.n_bins))
+    g, tfg = binding.compute_2f_grad(dd, tm, w, want_twoF=True, batch=2)
+    binding.sync_check()
+    np.testing.assert_array_equal(tfg.cpu().numpy(), plain)
+    assert np.isfinite(g.cpu().numpy()).all()
+    ref = O.oracle_twoF(ds, tm[[1]])[0]
+    err = np.abs(plain[1].astype(np.float64) - ref)
+    assert np.all(err <= np.maximum(1e-4 * ref, 1e-3))
