@@ -34,9 +34,9 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # figures hold for the kernel sources, header and build flags with this
 # digest; for any other version the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "271a0457330808b1eae122c1cad213bc18d0226e3b098c75ace472f0ff1c3711",
-    "bytes_per_template": {"fft_columns": 13885207 + 33954990,
-                           "fft_rows_2f": 33598476 + 8613463},
+    "sources_sha256": "959d53e35aa874ad9943e78d7b5cff5259de027d2f83a213944296ab7f1a4387",
+    "bytes_per_template": {"fft_columns": 13880906 + 33911975,
+                           "fft_rows_2f": 33586685 + 8672862},
 }
 
 
