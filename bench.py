@@ -139,6 +139,53 @@ def refinement_leg(steps, refine_steps):
             "min_2F_end_over_true": round(float(np.min(vals / tf_true)), 4)}
 
 
+def uneven_leg(n_search, steps):
+    """Independent searches of uneven span, band, FFT length and detector
+    count (spans log-uniform in 1-30 d, dt in {0.5, 1, 2, 5} s, n_fft 2^16 to
+    2^22, 8-64 templates each), run one after the other and as one captured
+    batch over 4 branches."""
+    import torch
+    from paper_2201_00451_amd import binding, synth
+    dss = synth.config_uneven(seed=4, n_search=n_search)
+    srs = [binding.Search(binding.DeviceData(ds), ds.templates, slots=8) for ds in dss]
+    outs = [torch.empty((sr.ntmpl, ds.n_bins), dtype=torch.float32, device="cuda")
+            for sr, ds in zip(srs, dss)]
+    ntmpl = sum(sr.ntmpl for sr in srs)
+    nbins = sum(sr.ntmpl * ds.n_bins for sr, ds in zip(srs, dss))
+    batch = binding.Batch(srs, lanes=4)
+    st = torch.cuda.Stream()
+
+    def run_seq():
+        with torch.cuda.stream(st):
+            for sr, o in zip(srs, outs):
+                sr.run(out=o, stream=st)
+
+    def run_batch():
+        batch.run(outs, stream=st)
+
+    res = {}
+    for name, fn in (("sequential", run_seq), ("batch", run_batch)):
+        fn()
+        st.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            fn()
+        e1.record(st)
+        st.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = {"ms_per_step": round(ms, 3), "templates_per_s": round(ntmpl / (ms / 1e3), 1),
+                     "bins_per_s": float(f"{nbins / (ms / 1e3):.4g}")}
+    binding.sync_check()
+    return {"workload": f"{n_search} searches: spans log-uniform 1-30 d, dt in 0.5-5 s, "
+                        "1 or 2 detectors, n_fft 2^16-2^22, full band, 8-64 templates each",
+            "searches": n_search, "templates": ntmpl, "n_fft_range": [min(d.n_fft for d in dss),
+                                                                      max(d.n_fft for d in dss)],
+            "steps": steps, **res,
+            "batch_over_sequential": round(res["sequential"]["ms_per_step"] /
+                                           res["batch"]["ms_per_step"], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +197,10 @@ def main():
     ap.add_argument("--cand-steps", type=int, default=5,
                     help="timed steps of the candidate-retention epilogue (0: skip)")
     ap.add_argument("--cand-threshold", type=float, default=40.0)
+    ap.add_argument("--uneven-searches", type=int, default=64,
+                    help="independent searches of uneven shape run as one captured batch "
+                         "(0: skip)")
+    ap.add_argument("--uneven-steps", type=int, default=3)
     ap.add_argument("--cpu-templates", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--refine-calls", type=int, default=10,
@@ -298,6 +349,12 @@ def main():
         refine = refinement_leg(args.refine_calls, args.refine_steps)
         binding.sync_check()
 
+    uneven = None
+    if args.uneven_searches > 0:
+        print(f"bench: {args.uneven_searches} uneven searches, sequential and batched",
+              file=sys.stderr, flush=True)
+        uneven = uneven_leg(args.uneven_searches, args.uneven_steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: FP64 oracle on the host", file=sys.stderr, flush=True)
@@ -329,6 +386,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "refinement": refine,
+        "uneven_batch": uneven,
         "wall_s_timed": round(wall, 3),
     }
     if calib:

@@ -246,6 +246,32 @@ FSTAT_API fstat_status fstat_search_run_profiled(fstat_search* search, const fst
                                                  void* workspace, size_t ws_bytes, void* stream,
                                                  float* kernel_ms, int64_t* launches);
 
+/* Several independent searches run as one unit (searches of uneven span,
+ * band, FFT length and detector count, each with its own plan, data,
+ * template bank, output and workspace).  fstat_batch_create takes `n` search
+ * handles (host array; the searches and their plans must outlive the batch)
+ * and spreads them over `lanes` (1..16) concurrent branches, the longest
+ * first onto the least loaded branch (work ~ templates x n_fft).
+ * fstat_batch_run takes host arrays of length n: inputs, device template
+ * arrays, device 2F outputs [ntmpl][n_bins] (added to for searches created
+ * with FSTAT_SEARCH_ACCUMULATE), workspaces of at least fstat_search_info's
+ * size, and their sizes.  The first call captures every search's launch
+ * sequence into one HIP graph (fork on `stream`, one branch per lane, join
+ * back on `stream`) and later calls with the same pointers replay it; other
+ * pointers recapture.  Each search's FSTAT_SEARCH_GRAPH flag is not used
+ * here.  Needs a non-null stream; runs asynchronously on it.  Each output is
+ * the one fstat_search_run gives for that search alone, bit for bit.
+ * Searches of one batch must not share a workspace or an output. */
+#define FSTAT_MAX_BATCH_LANES 16
+typedef struct fstat_batch fstat_batch;  /* opaque, host memory owned by the library */
+FSTAT_API fstat_status fstat_batch_create(fstat_search* const* searches, int32_t n,
+                                          int32_t lanes, fstat_batch** out);
+FSTAT_API void fstat_batch_destroy(fstat_batch* batch);
+FSTAT_API fstat_status fstat_batch_run(fstat_batch* batch, const fstat_inputs* const* in,
+                                       const double* const* templates, float* const* twoF,
+                                       void* const* workspace, const size_t* ws_bytes,
+                                       void* stream);
+
 /* Launch-shape autotuner: for the set-up *desc (its tune fields ignored),
  * times every FFT launch shape the plan accepts (both column/row splits of
  * n_fft around its square root, full or half line counts for each pass,

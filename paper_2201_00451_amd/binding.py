@@ -25,7 +25,8 @@ EXPORTED = ("fstat_plan_create", "fstat_plan_destroy", "fstat_workspace_size",
             "fstat_search_info", "fstat_search_run", "fstat_search_run_profiled",
             "fstat_grad_workspace_size", "fstat_compute_2f_grad", "fstat_plan_info",
             "fstat_grad_bin_workspace_size", "fstat_compute_2f_grad_bin", "fstat_autotune",
-            "fstat_search_run_candidates")
+            "fstat_search_run_candidates", "fstat_batch_create", "fstat_batch_destroy",
+            "fstat_batch_run")
 GRAD_PARAMS = ("df", "f1dot", "alpha", "delta", "asini", "porb", "tp")
 # template-row column of each gradient parameter
 GRAD_COLUMNS = (2, 3, 0, 1, 5, 6, 7)
@@ -112,6 +113,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                               vp, vp, sz, vp]
     lib.fstat_compute_2f_grad.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, i64, vp, vp, vp,
                                           vp, sz, vp]
+    lib.fstat_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(vp)]
+    lib.fstat_batch_destroy.argtypes = [vp]
+    lib.fstat_batch_destroy.restype = None
+    lib.fstat_batch_run.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(FstatInputs)),
+                                    ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                    ctypes.POINTER(sz), vp]
     lib.fstat_sync_check.argtypes = [vp]
     lib.fstat_last_error.restype = ctypes.c_char_p
     lib.fstat_last_error.argtypes = []
@@ -119,7 +127,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fstat_version.argtypes = []
     for name in EXPORTED:
         if name not in ("fstat_plan_destroy", "fstat_last_error", "fstat_version",
-                        "fstat_search_destroy"):
+                        "fstat_search_destroy", "fstat_batch_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -537,4 +545,51 @@ class Search:
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.fstat_search_destroy(self.handle)
+            self.handle = None
+
+
+class Batch:
+    """Independent searches run as one captured graph (fstat_batch_*): each
+    search keeps its own plan, data, templates, output and workspace; `lanes`
+    concurrent branches.  run() returns the list of 2F outputs."""
+
+    def __init__(self, searches, lanes=4):
+        lib = load_library()
+        self.searches = list(searches)
+        arr = (ctypes.c_void_p * len(self.searches))(*[s.handle for s in self.searches])
+        h = ctypes.c_void_p()
+        _check(lib.fstat_batch_create(arr, len(self.searches), int(lanes), ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, outs=None, stream=None):
+        import torch
+        n = len(self.searches)
+        if outs is None:
+            outs = [torch.empty((s.ntmpl, s.dd.n_bins), dtype=torch.float32, device=s.dd.device)
+                    for s in self.searches]
+        ins = (ctypes.POINTER(FstatInputs) * n)(*[ctypes.pointer(s.dd.inputs)
+                                                  for s in self.searches])
+        vp = ctypes.c_void_p
+        tm = (vp * n)(*[_ptr(s.templates) for s in self.searches])
+        tf = (vp * n)(*[_ptr(o) for o in outs])
+        ws = (vp * n)(*[_ptr(s.ws) for s in self.searches])
+        wb = (ctypes.c_size_t * n)(*[s.ws.numel() for s in self.searches])
+        # the graph is launched on a stream of its own (a capture needs a
+        # non-null stream), ordered after and before the caller's stream
+        cur = torch.cuda.current_stream()
+        if stream is None:
+            if getattr(self, "stream", None) is None:
+                self.stream = torch.cuda.Stream()
+            st = self.stream
+            st.wait_stream(cur)
+        else:
+            st = stream
+        _check(load_library().fstat_batch_run(self.handle, ins, tm, tf, ws, wb, _stream_ptr(st)))
+        if stream is None:
+            cur.wait_stream(st)
+        return outs
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fstat_batch_destroy(self.handle)
             self.handle = None

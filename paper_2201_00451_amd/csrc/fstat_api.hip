@@ -584,6 +584,26 @@ struct fstat_search {
   }
 };
 
+// Independent searches captured together: one HIP graph whose branches
+// (lanes) run the searches' launch sequences concurrently.
+struct fstat_batch {
+  std::vector<fstat_search*> searches;
+  std::vector<int> lane_of;  // lane of each search (balanced by estimated work)
+  int lanes = 1;
+  int device = -1;
+  std::vector<hipStream_t> lane_st;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uint64_t> key;
+  ~fstat_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (hipStream_t s : lane_st) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : join) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+  }
+};
+
 namespace {
 
 // Templates with the same sky position and orbit share the resampled series;
@@ -814,6 +834,130 @@ fstat_status fstat_search_run_profiled(fstat_search* search, const fstat_inputs*
   return finish_timer(tm, st, kernel_ms, launches);
 }
 
+
+fstat_status fstat_batch_create(fstat_search* const* searches, int32_t n, int32_t lanes,
+                                fstat_batch** out) {
+  if (!out) return fail(FSTAT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || !searches) return fail(FSTAT_EINVAL, "searches / n invalid");
+  if (lanes < 1 || lanes > FSTAT_MAX_BATCH_LANES)
+    return fail(FSTAT_EINVAL, "lanes=%d outside [1, %d]", lanes, FSTAT_MAX_BATCH_LANES);
+  for (int32_t i = 0; i < n; ++i)
+    if (!searches[i]) return fail(FSTAT_EINVAL, "search %d is NULL", i);
+  fstat_batch* b = new (std::nothrow) fstat_batch;
+  if (!b) return fail(FSTAT_EINVAL, "host allocation failed");
+  b->searches.assign(searches, searches + n);
+  b->lanes = std::min<int32_t>(lanes, n);
+  // longest first onto the least loaded lane; work ~ templates x FFT length
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto cost = [&](int i) {
+    return double(searches[i]->ntmpl) * double(searches[i]->plan->desc.n_fft);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost(a) > cost(c); });
+  std::vector<double> load(b->lanes, 0.0);
+  b->lane_of.assign(n, 0);
+  for (int i : order) {
+    const int l = int(std::min_element(load.begin(), load.end()) - load.begin());
+    b->lane_of[i] = l;
+    load[l] += cost(i);
+  }
+  *out = b;
+  return ok();
+}
+
+void fstat_batch_destroy(fstat_batch* batch) { delete batch; }
+
+fstat_status fstat_batch_run(fstat_batch* b, const fstat_inputs* const* in,
+                             const double* const* templates, float* const* twoF,
+                             void* const* workspace, const size_t* ws_bytes, void* stream) {
+  if (!b) return fail(FSTAT_EINVAL, "batch is NULL");
+  if (!in || !templates || !twoF || !workspace || !ws_bytes)
+    return fail(FSTAT_EINVAL, "argument arrays must not be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!st) return fail(FSTAT_EINVAL, "a batch runs from a graph: it needs a non-null stream");
+  const int n = int(b->searches.size());
+  std::vector<uint64_t> key;
+  key.reserve(size_t(n) * 6);
+  for (int i = 0; i < n; ++i) {
+    if (!in[i]) return fail(FSTAT_EINVAL, "inputs %d is NULL", i);
+    fstat_status s = search_check(b->searches[i], in[i], templates[i], twoF[i] != nullptr,
+                                  workspace[i], ws_bytes[i]);
+    if (s != FSTAT_OK) return s;
+    key.push_back(uint64_t(reinterpret_cast<uintptr_t>(in[i]->x[0])));
+    key.push_back(uint64_t(reinterpret_cast<uintptr_t>(in[i]->moments)));
+    key.push_back(uint64_t(reinterpret_cast<uintptr_t>(templates[i])));
+    key.push_back(uint64_t(reinterpret_cast<uintptr_t>(twoF[i])));
+    key.push_back(uint64_t(reinterpret_cast<uintptr_t>(workspace[i])));
+    key.push_back(uint64_t(ws_bytes[i]));
+  }
+  int dev = 0;
+  fstat_status s = check_hip(hipGetDevice(&dev), "get device");
+  if (s != FSTAT_OK) return s;
+  if (b->device != dev) {
+    // lane streams and events belong to the device current at first use
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    for (hipStream_t x : b->lane_st) (void)hipStreamDestroy(x);
+    for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    b->lane_st.assign(b->lanes, nullptr);
+    b->join.assign(b->lanes, nullptr);
+    b->fork = nullptr;
+    b->device = -1;
+    for (int l = 0; l < b->lanes; ++l) {
+      if ((s = check_hip(hipStreamCreateWithFlags(&b->lane_st[l], hipStreamNonBlocking),
+                         "lane stream")) != FSTAT_OK)
+        return s;
+      if ((s = check_hip(hipEventCreateWithFlags(&b->join[l], hipEventDisableTiming),
+                         "lane event")) != FSTAT_OK)
+        return s;
+    }
+    if ((s = check_hip(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "fork event")) !=
+        FSTAT_OK)
+      return s;
+    b->device = dev;
+  }
+  if (!b->exec || key != b->key) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    if ((s = check_hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal),
+                       "begin capture")) != FSTAT_OK)
+      return s;
+    hipError_t e = hipEventRecord(b->fork, st);
+    for (int l = 0; l < b->lanes && e == hipSuccess; ++l)
+      e = hipStreamWaitEvent(b->lane_st[l], b->fork, 0);
+    fstat_status ls = check_hip(e, "fork");
+    KernelTimer none;
+    for (int i = 0; i < n && ls == FSTAT_OK; ++i) {
+      fstat_search* sr = b->searches[i];
+      if (sr->ntmpl == 0) continue;
+      RowOutput out = row_output(twoF[i], nullptr);
+      out.acc = (sr->flags & FSTAT_SEARCH_ACCUMULATE) ? 1 : 0;
+      hipStream_t ls_st = b->lane_st[b->lane_of[i]];
+      none.st = ls_st;
+      ls = search_launch(sr, in[i], templates[i], out, workspace[i], ls_st, none);
+    }
+    for (int l = 0; l < b->lanes && ls == FSTAT_OK; ++l) {
+      e = hipEventRecord(b->join[l], b->lane_st[l]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join[l], 0);
+      ls = check_hip(e, "join");
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st, &graph);
+    if (ls != FSTAT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return ls;
+    }
+    if ((s = check_hip(e, "end capture")) != FSTAT_OK) return s;
+    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if ((s = check_hip(e, "graph instantiate")) != FSTAT_OK) return s;
+    b->key = key;
+  }
+  s = check_hip(hipGraphLaunch(b->exec, st), "graph launch");
+  return s == FSTAT_OK ? ok() : s;
+}
 
 const char* fstat_version(void) { return "fstat-gfx950 0.1"; }
 

@@ -512,6 +512,58 @@ def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmp
     return finish(ds)
 
 
+def config_uneven(seed=4, n_search=256, days=(1.0, 30.0), dts=(0.5, 1.0, 2.0, 5.0),
+                  max_log_n=22, ntmpl=(8, 64), f_het=(50.0, 1000.0), D=8, noise=True):
+    """Independent searches of uneven shape for batched serving: per search a
+    span log-uniform in `days`, dt from `dts`, one or two detectors, a
+    heterodyne frequency uniform in `f_het`, n_fft the power of two >= twice
+    the samples (span and dt redrawn while n_fft > 2^max_log_n), full band,
+    one injection (rho U(10, 30)) and a template count uniform in `ntmpl`:
+    even searches a spin-down grid at the injection's sky position, odd ones
+    a circular-binary lattice around the injection's orbit.  Returns a list of
+    Datasets."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    out = []
+    for k in range(n_search):
+        while True:
+            span = math.exp(rng.uniform(math.log(days[0]), math.log(days[1]))) * DAY
+            dt = float(rng.choice(dts))
+            n = int(round(span / dt))
+            n_fft = 1 << max(12, int(math.ceil(math.log2(2 * n))))
+            if n_fft <= (1 << max_log_n):
+                break
+        ndet = int(rng.integers(1, 3))
+        fh = float(rng.uniform(*f_het))
+        nt = int(rng.integers(ntmpl[0], ntmpl[1] + 1))
+        binary = k % 2 == 1
+        dets = [make_detector(site, 0.0, n, float(rng.uniform(0.8, 1.2)))
+                for site in ("H", "L")[:ndet]]
+        inj = dict(alpha=float(rng.uniform(0, 2 * math.pi)), delta=float(rng.uniform(-1.2, 1.2)),
+                   f=fh + float(rng.uniform(-0.3, 0.3)) * 0.5 / dt, f1dot=0.0,
+                   cosi=float(rng.uniform(-1, 1)), psi=float(rng.uniform(-0.7, 0.7)),
+                   phi0=float(rng.uniform(0, 2 * math.pi)), rho=float(rng.uniform(10, 30)))
+        tm = np.zeros((nt, 8))
+        tm[:, 0], tm[:, 1] = inj["alpha"], inj["delta"]
+        max_a = 0.0
+        if binary:
+            inj.update(asini=float(rng.uniform(0.01, 0.2)),
+                       porb=float(rng.uniform(0.5, 2.0)) * DAY, tp=float(rng.uniform(0, 1e4)))
+            side = int(math.ceil(nt ** (1.0 / 3.0)))
+            lat = binary_lattice(inj["f"], inj["asini"], inj["porb"], inj["tp"], n * dt,
+                                 shape=(side, side, side), limit=nt)
+            tm[:, 5:8] = lat
+            max_a = float(np.max(lat[:, 0]))
+        else:
+            inj["f1dot"] = float(rng.uniform(-1e-10, 1e-10))
+            tm[:, 3] = inj["f1dot"] + 2e-11 * (np.arange(nt) - (nt - 1) / 2.0)
+            tm[:, 6] = 1.0
+        xs, vs = make_data(dets, dt, fh, 0.0, [inj], seed * 1000 + k, noise=noise)
+        ds = Dataset(f"uneven{k}", dt, fh, 0.0, grid_origin(0.0, dt, 512.0 + max_a), n_fft, D, 0,
+                     n_fft, dets, xs, vs, tm, injections=[inj])
+        out.append(finish(ds))
+    return out
+
+
 CONFIGS = {
     "tiny": config_tiny,
     "sky_spindown": config_sky_spindown,

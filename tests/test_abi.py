@@ -294,3 +294,35 @@ def test_autotune_checks_arguments_before_any_launch(lib):
     bad.ndet = 0
     assert tune(ctypes.byref(bad), ctypes.byref(inp), vp(4096), 1, vp(4096), vp(4096), 1 << 30,
                 vp(0), ctypes.byref(best), ctypes.byref(ms)) == B.FSTAT_EINVAL
+
+
+def test_batch_checks_arguments_before_any_launch(lib):
+    """fstat_batch_create/run validate every argument on the host."""
+    vp = ctypes.c_void_p
+    p = B.Plan(good_desc()[1])
+    tm = np.zeros((3, 8))
+    tm[:, 6] = 1.0
+    h = vp()
+    assert lib.fstat_search_create(p.handle, tm.ctypes.data_as(vp), 3, 2, 0, ctypes.byref(h)) == 0
+    arr = (vp * 1)(h)
+    b = vp()
+    assert lib.fstat_batch_create(None, 1, 2, ctypes.byref(b)) == B.FSTAT_EINVAL
+    assert lib.fstat_batch_create(arr, 0, 2, ctypes.byref(b)) == B.FSTAT_EINVAL
+    assert lib.fstat_batch_create(arr, 1, 0, ctypes.byref(b)) == B.FSTAT_EINVAL
+    assert lib.fstat_batch_create(arr, 1, 17, ctypes.byref(b)) == B.FSTAT_EINVAL
+    assert "lanes" in B.last_error()
+    assert lib.fstat_batch_create((vp * 1)(None), 1, 2, ctypes.byref(b)) == B.FSTAT_EINVAL
+    assert lib.fstat_batch_create(arr, 1, 2, None) == B.FSTAT_EINVAL
+    assert lib.fstat_batch_create(arr, 1, 4, ctypes.byref(b)) == B.FSTAT_OK
+    ins = (ctypes.POINTER(B.FstatInputs) * 1)(ctypes.pointer(B.FstatInputs()))
+    ptrs = (vp * 1)(4096)
+    sizes = (ctypes.c_size_t * 1)(1 << 30)
+    run = lib.fstat_batch_run
+    assert run(None, ins, ptrs, ptrs, ptrs, sizes, vp(4096)) == B.FSTAT_EINVAL
+    assert run(b, None, ptrs, ptrs, ptrs, sizes, vp(4096)) == B.FSTAT_EINVAL
+    assert run(b, ins, ptrs, ptrs, ptrs, sizes, vp(0)) == B.FSTAT_EINVAL
+    assert "stream" in B.last_error()
+    # invalid inputs of a member search are reported before any launch
+    assert run(b, ins, ptrs, ptrs, ptrs, sizes, vp(4096)) == B.FSTAT_EINVAL
+    lib.fstat_batch_destroy(b)
+    lib.fstat_search_destroy(h)

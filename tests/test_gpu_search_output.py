@@ -255,3 +255,47 @@ def test_optional_outputs_bitwise_at_radix32_rows(torch_dev):
     ref = O.oracle_twoF(ds, tm[[1]])[0]
     err = np.abs(plain[1].astype(np.float64) - ref)
     assert np.all(err <= np.maximum(1e-4 * ref, 1e-3))
+
+
+def uneven_searches():
+    from paper_2201_00451_amd import binding
+    dss = synth.config_uneven(seed=41, n_search=6, days=(0.05, 0.5), max_log_n=16,
+                              ntmpl=(3, 8))
+    srs = []
+    for ds in dss:
+        dd = binding.DeviceData(ds)
+        srs.append(binding.Search(dd, ds.templates, slots=4))
+    return dss, srs
+
+
+def test_batch_of_uneven_searches(torch_dev):
+    """Searches of different spans, bands, FFT lengths and detector counts run
+    as one captured graph over 3 branches: every output equals the search run
+    alone, bit for bit, on every replay and after a recapture."""
+    import torch
+    from paper_2201_00451_amd import binding
+    dss, srs = uneven_searches()
+    assert len({ds.n_fft for ds in dss}) > 2 and len({ds.ndet for ds in dss}) == 2
+    alone = [sr.run().cpu().numpy() for sr in srs]
+    torch.cuda.synchronize()
+    batch = binding.Batch(srs, lanes=3)
+    outs = [torch.full((sr.ntmpl, ds.n_bins), -1.0, device="cuda") for sr, ds in zip(srs, dss)]
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-1.0)
+        batch.run(outs)
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            np.testing.assert_array_equal(o.cpu().numpy(), alone[i], err_msg=f"search {i}")
+        srs[0].run()
+        torch.cuda.synchronize()
+    fresh = batch.run()
+    torch.cuda.synchronize()
+    for i, o in enumerate(fresh):
+        np.testing.assert_array_equal(o.cpu().numpy(), alone[i])
+    binding.sync_check()
+    # one search against the oracle
+    i = int(np.argmax([ds.n_fft for ds in dss]))
+    ref = O.oracle_twoF(dss[i], dss[i].templates[:1])[0]
+    err = np.abs(alone[i][0].astype(np.float64) - ref)
+    assert np.all(err <= np.maximum(1e-4 * ref, 1e-3))
