@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kResThreads) void k_grad(PlanConst P, void* ws) {
       re3(tau + dly[i], rv, rd, ra, rdl, oob);
       const double inv = 1.0 - rd * (1.0 - rd * (1.0 - rd));
       double sb = 0.0, cb = 0.0;
-      if (binary) sincos(om * (tau - tp.tp), &sb, &cb);
+      if (binary) sincos_cycles((tau - tp.tp) * tp.nu_b, sb, cb);
       dT[i][0] = float(-ra * inv);
       dT[i][1] = float(-rdl * inv);
       dT[i][2] = float(sb * inv);
@@ -196,13 +196,13 @@ __global__ __launch_bounds__(kResThreads) void k_grad(PlanConst P, void* ws) {
         double r = 0.0, invb = 1.0, s2 = 0.0, c2 = 0.0, tsrc = t;
         if (binary) {
           const double tb = t + dr;
-          const double r0 = tp.asini * sin(om * (tb - tp.tp));
+          const double r0 = binary_delay(tp, tb);
           double s, c;
-          sincos(om * (tb - r0 - tp.tp), &s, &c);
+          sincos_cycles((tb - r0 - tp.tp) * tp.nu_b, s, c);
           const double hh = r0 - tp.asini * s;
           r = r0 - hh / (1.0 + tp.asini * om * c);
           tsrc = tb - r;
-          sincos(om * (tsrc - tp.tp), &s2, &c2);
+          sincos_cycles((tsrc - tp.tp) * tp.nu_b, s2, c2);
           invb = 1.0 / (1.0 + tp.asini * om * c2);
         }
         const float2 e = cis_cycles(P.f_het * (dr - r));

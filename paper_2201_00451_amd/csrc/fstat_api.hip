@@ -105,6 +105,17 @@ FftVariant rows_variant_n() {
   return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, RQ, NT, MODE, MLR>), NT,
           kLdsBytes<1 << LOGL, R0, RQ, 2 * RQ>, RQ};
 }
+// The plain 2F pass at the full row count holds one array at a time in LDS
+// (k_fft_rows_split), so two 512-thread workgroups share a compute unit; with
+// radix-32 stages that does not fit 128 VGPRs, and with fewer than 4 rows per
+// item (lines of 2^12) the shorter 2F runs cost more than the occupancy
+// gains (measured): there the pass keeps both arrays.
+template <int LOGL, int MLR>
+FftVariant rows_split_variant() {
+  constexpr int RQ = kRowsMax<LOGL>, R0 = kR0<LOGL, MLR>;
+  return {reinterpret_cast<const void*>(&k_fft_rows_split<LOGL, RQ, 512, MLR>), 512,
+          kLdsBytes<1 << LOGL, R0, RQ, RQ>, RQ};
+}
 // The adjoint, conjugate and extended epilogues of a radix-32 plan exceed 256
 // VGPRs at the full count: they take the half count (the same arithmetic per
 // point, so the same bits as the full-count plain 2F kernel).
@@ -114,6 +125,8 @@ FftVariant rows_variant(bool half) {
     return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL> / 2, 256>();
   } else {
     if (half) return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL> / 2, 256>();
+    if constexpr (MODE == kRow2F && kR0<LOGL, MLR> <= 16 && kRowsMax<LOGL> >= 4)
+      return rows_split_variant<LOGL, MLR>();
     return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL>, 512>();
   }
 }

@@ -64,6 +64,7 @@ struct PlanConst {
 struct TmplParams {
   double nhat[3];
   double df, f1dot, f2dot, asini, om_b, tp;
+  double nu_b;  // orbital frequency 1 / porb (0 for an isolated source)
   // spin-down and sub-bin phase in quarter turns (4 x cycles) as a cubic in
   // the grid index k: 4 Phi(k) = sd[0] + k (sd[1] + k (sd[2] + k sd[3]))
   double sd[4];
@@ -273,6 +274,43 @@ struct NodeRoemer {
   }
 };
 
+// sin and cos of 2 pi c for a phase c in FP64 cycles (|c| < 2^28): the
+// quarter-turn count and remainder are split exactly in FP64, then the
+// Taylor polynomials of sin and cos in x = (pi/2) r, |x| <= pi/4, through x^13
+// and x^14 (truncation below 3e-14), and a quadrant swap.
+__device__ inline void sincos_cycles(double c, double& sn, double& cs) {
+  const double c4 = 4.0 * c;
+  const double q = rint(c4);
+  const double x = (c4 - q) * 1.57079632679489661923;
+  const double u = x * x;
+  double ps = fma(u, -1.0 / 6227020800.0, 1.0 / 39916800.0);
+  ps = fma(u, ps, -1.0 / 362880.0);
+  ps = fma(u, ps, 1.0 / 5040.0);
+  ps = fma(u, ps, -1.0 / 120.0);
+  ps = fma(u, ps, 1.0 / 6.0);
+  const double s0 = fma(-x * u, ps, x);
+  double pc = fma(u, 1.0 / 87178291200.0, -1.0 / 479001600.0);
+  pc = fma(u, pc, 1.0 / 3628800.0);
+  pc = fma(u, pc, -1.0 / 40320.0);
+  pc = fma(u, pc, 1.0 / 720.0);
+  pc = fma(u, pc, -1.0 / 24.0);
+  pc = fma(u, pc, 0.5);
+  const double c0 = fma(-u, pc, 1.0);
+  const int n = int(q) & 3;
+  const double x1 = (n & 1) ? s0 : c0, y1 = (n & 1) ? c0 : s0;
+  cs = (n == 1 || n == 2) ? -x1 : x1;
+  sn = (n & 2) ? -y1 : y1;
+}
+
+// Binary Roemer delay R(tau) = asini sin(2 pi (tau - tp) / porb) of the
+// source (0 for an isolated source).
+__device__ inline double binary_delay(const TmplParams& tp, double tau) {
+  if (tp.asini == 0.0) return 0.0;
+  double s, c;
+  sincos_cycles((tau - tp.tp) * tp.nu_b, s, c);
+  return tp.asini * s;
+}
+
 // Step (iv): for the source-frame time tau return T - tau, where the detector
 // time T satisfies T + roemer(T) = tau + R(tau).  One fixed-point step from
 // T = t_b then one Newton step; 1/(1 + roemer') by its series to third order
@@ -280,8 +318,7 @@ struct NodeRoemer {
 template <class RoemerFn, class... Flag>
 __device__ inline double grid_delay(const RoemerFn& roemer, const TmplParams& tp, double tau,
                                     Flag&... oob) {
-  double rb = 0.0;
-  if (tp.asini != 0.0) rb = tp.asini * sin(tp.om_b * (tau - tp.tp));
+  const double rb = binary_delay(tp, tau);
   double d0, dd0;
   roemer(tau + rb, d0, dd0, oob...);
   double dl = rb - d0;
@@ -291,10 +328,6 @@ __device__ inline double grid_delay(const RoemerFn& roemer, const TmplParams& tp
   return dl - g * (1.0 - x * (1.0 - x * (1.0 - x)));
 }
 
-// Binary Roemer delay R(tau) of the source (0 for an isolated source).
-__device__ inline double binary_delay(const TmplParams& tp, double tau) {
-  return tp.asini != 0.0 ? tp.asini * sin(tp.om_b * (tau - tp.tp)) : 0.0;
-}
 
 // Step (iv) from a prediction: one Newton step on T + roemer(T) = tau + rb
 // (rb = R(tau)) started at T = tau + guess.  The caller predicts from a
@@ -320,9 +353,9 @@ __device__ inline double sample_delay(const RoemerFn& roemer, const TmplParams& 
   double r = 0.0;
   if (tp.asini != 0.0) {
     double tb = t + dr;
-    double r0 = tp.asini * sin(tp.om_b * (tb - tp.tp));
+    double r0 = binary_delay(tp, tb);
     double s, c;
-    sincos(tp.om_b * (tb - r0 - tp.tp), &s, &c);
+    sincos_cycles((tb - r0 - tp.tp) * tp.nu_b, s, c);
     double h = r0 - tp.asini * s;
     r = r0 - h / (1.0 + tp.asini * tp.om_b * c);
   }

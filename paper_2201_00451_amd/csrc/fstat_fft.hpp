@@ -583,6 +583,100 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
   }
 }
 
+// Plain 2F row pass holding one array at a time: the RQ rows of y_a' are
+// transformed and |Fa'|^2 of every bin the thread owns is kept in registers,
+// then the same rows of y_b' reuse the LDS lines and the thread writes
+// 2F = 2 (|Fa'|^2 + |Fb'|^2) (the same arithmetic, so the same bits, as
+// k_fft_rows).  With RQ lines of LDS instead of 2 RQ, two workgroups share a
+// compute unit (the launch bound asks for registers to match) while the 2F
+// runs stay RQ floats long.
+template <int LOGL, int RQ, int NT, int MLR>
+__global__ __launch_bounds__(NT, NT / 128) void k_fft_rows_split(PlanConst P, void* ws,
+                                                                  ChunkMap map, int slots,
+                                                                  int log_rr, RowOutput out) {
+  extern __shared__ float2 lds[];
+  constexpr int L = 1 << LOGL;
+  constexpr int NS = stage_count(LOGL, MLR);
+  constexpr int R0 = kR0<LOGL, MLR>, NBL0 = L / R0, NB0 = RQ * NBL0;
+  constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = RQ * PL;
+  constexpr int PER0 = (NB0 + NT - 1) / NT;
+  constexpr int PER = (NBL + NT - 1) / NT;
+  using Lay = LdsLayout<L, R0, RQ>;
+  float2* twl = lds + RQ * Lay::pitch;
+  const int64_t Rr = int64_t(1) << log_rr;
+  const int tid = threadIdx.x;
+  // grouped path: every reader of the group buffers the next chunk resamples
+  // has finished (column pass of this chunk), so their status words restart
+  if (blockIdx.x == 0 && tid < map.n_reset) *group_status(ws, P, slots, map.reset_buf[tid]) = 0;
+  {
+    const float2* __restrict__ tws = tw_stage(ws);
+    for (int e = tid; e < L / 2; e += NT) twl[e] = tws[e * (kTwLen / L)];
+  }
+  const RowItem it =
+      rows_item<kRow2F>(P, ws, map, int(xcd_remap(blockIdx.x, gridDim.x)), int(Rr / RQ), RQ);
+  if (it.flagged) rows_flagged<LOGL, RQ, NT>(P, it, Rr, out);
+  if (!it.live) return;
+  const auto tf = buf_rsrc(out.twoF + it.tmpl * P.n_bins,
+                           uint32_t(P.n_bins * int64_t(sizeof(float))));
+  const uint32_t nmask = uint32_t(P.n_fft - 1), lo = uint32_t(P.bin_lo);
+  const uint32_t ostep = uint32_t(Rr * PL);
+  float pa[PER][RL];
+#pragma unroll
+  for (int arr = 0; arr < 2; ++arr) {
+    // the a pass's last stage has finished reading the lines
+    if (arr == 1) __syncthreads();
+    const auto rs = buf_rsrc(slot_buf(ws, P, it.g, arr),
+                             uint32_t(P.n_fft * int64_t(sizeof(float2))));
+    float2 v[PER0][R0];
+#pragma unroll
+    for (int s = 0; s < PER0; ++s) {
+      const int b = tid + s * NT;
+      if (NB0 % NT == 0 || b < NB0) {
+        const int i = b % NBL0, line = b / NBL0;
+        const uint32_t voff = uint32_t(((it.q0 + line) * L + i) * int64_t(sizeof(float2)));
+#pragma unroll
+        for (int j = 0; j < R0; ++j)
+          v[s][j] = buf_load2(rs, voff, uint32_t(j * NBL0 * int(sizeof(float2))));
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < PER0; ++s) {
+      const int b = tid + s * NT;
+      if (NB0 % NT == 0 || b < NB0) {
+        const int i = b % NBL0, line = b / NBL0;
+        dft<R0>(v[s]);
+#pragma unroll
+        for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
+      }
+    }
+    __syncthreads();
+    fft_middle<LOGL, RQ, NT, 1, MLR, Lay>(lds, twl);
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int b = tid + s * NT;
+      if (NBL % NT == 0 || b < NBL) {
+        const int ql = b % RQ, i = b / RQ;
+        float2 u[RL];
+#pragma unroll
+        for (int j = 0; j < RL; ++j) u[j] = lds[Lay::at(i + j * PL, ql)];
+        twiddle_dft<RL, PL, L>(u, i, twl);
+        if (arr == 0) {
+#pragma unroll
+          for (int m = 0; m < RL; ++m) pa[s][m] = fmaf(u[m].x, u[m].x, u[m].y * u[m].y);
+        } else {
+          const uint32_t o0 = uint32_t(it.q0 + ql + Rr * i) + uint32_t(P.n_fft / 2);
+#pragma unroll
+          for (int m = 0; m < RL; ++m) {
+            const uint32_t o = ((o0 + uint32_t(m) * ostep) & nmask) - lo;
+            const float v2 = 2.0f * (pa[s][m] + fmaf(u[m].x, u[m].x, u[m].y * u[m].y));
+            buf_store1(v2, tf, o * uint32_t(sizeof(float)));
+          }
+        }
+      }
+    }
+  }
+}
+
 // Copy of the resampled series for the diagnostic entry point: y_a, y_b of
 // slot g into out[t][2][n_fft], zero beyond the computed grid, with the
 // whitening undone (y_a = l11 y_a', y_b = l21 y_a' + l22 y_b').

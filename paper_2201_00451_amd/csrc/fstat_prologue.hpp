@@ -145,6 +145,7 @@ __host__ __device__ inline void template_params(const PlanConst& P, const double
   if (tp.asini < 0.0 || (tp.asini != 0.0 && !(porb > 0.0))) status |= kStatusTiming;
   if (tp.asini > P.max_delay) status |= kStatusCoverage;
   tp.om_b = (tp.asini != 0.0 && porb > 0.0) ? 2.0 * kPi / porb : 0.0;
+  tp.nu_b = (tp.asini != 0.0 && porb > 0.0) ? 1.0 / porb : 0.0;
   spindown_coefficients(P, tp.f1dot, tp.f2dot, tp.df, tp.sd);
   double sa, ca_, sd, cdl;
   sincos(alpha, &sa, &ca_);

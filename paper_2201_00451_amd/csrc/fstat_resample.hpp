@@ -138,6 +138,12 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
   n_count = n_count > kNodeCap ? kNodeCap : (n_count < 2 ? 2 : n_count);
   const NodeRoemer re{nodes, n_count, P.eph_t0 + double(n_lo) * P.eph_dt, P.eph_dt, P.inv_eph_dt};
   const double tau_s = P.tau0 + P.dt * double(k_s);
+  // the binary delay depends on the grid point only: once for all detectors
+  const double rb0 = binary_delay(tp, tau_s);
+  double rbk[kResPerThread];
+#pragma unroll
+  for (int i = 0; i < kResPerThread; ++i)
+    rbk[i] = binary_delay(tp, tau_s + P.dt * double(tid + i * kResThreads));
 
   for (int X = 0; X < P.ndet; ++X) {
     const DetConst& d = P.det[X];
@@ -152,7 +158,6 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
     // Newton steps), the rest by one Newton step from a prediction that
     // carries the exact binary delay and linearises the Roemer delay about
     // the first point: T ~ T_s + (t_b - t_b,s) / (1 + roemer'(T_s)).
-    const double rb0 = binary_delay(tp, tau_s);
     double x0;
     double d0 = grid_delay(re, tp, tau_s, oob);
     d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
@@ -166,7 +171,7 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
       const int64_t kk = tid + i * kResThreads;
       const double dtau = P.dt * double(kk);
       const double tau = tau_s + dtau;
-      const double rb = binary_delay(tp, tau);
+      const double rb = rbk[i];
       const double guess = d0 + (dtau + rb - rb0) * inv0 - dtau;
       double x;
       dly[i] = grid_delay_newton(re, tau, rb, guess, x, oob);
