@@ -196,11 +196,8 @@ __global__ __launch_bounds__(kResThreads) void k_grad(PlanConst P, void* ws) {
         double r = 0.0, invb = 1.0, s2 = 0.0, c2 = 0.0, tsrc = t;
         if (binary) {
           const double tb = t + dr;
-          const double r0 = binary_delay(tp, tb);
           double s, c;
-          sincos_cycles((tb - r0 - tp.tp) * tp.nu_b, s, c);
-          const double hh = r0 - tp.asini * s;
-          r = r0 - hh / (1.0 + tp.asini * om * c);
+          r = binary_inverse(tp, tb, s, c);
           tsrc = tb - r;
           sincos_cycles((tsrc - tp.tp) * tp.nu_b, s2, c2);
           invb = 1.0 / (1.0 + tp.asini * om * c2);

@@ -342,6 +342,28 @@ __device__ inline double grid_delay_newton(const RoemerFn& roemer, double tau, d
   return guess - (guess + d1 - rb) * (1.0 - x * (1.0 - x * (1.0 - x)));
 }
 
+// The source-frame delay R(t_src) of the emission that reaches the
+// barycentre at tb (t_src + R(t_src) = tb): one Newton step from R(tb).  The
+// phase at t_src is the phase at tb minus om_b r0, an angle below
+// asini om_b < 1e-2 rad, so its sine and cosine follow from the ones at tb by
+// angle addition with short series (truncation below 1e-17), and the Newton
+// denominator 1 / (1 + asini om_b cos) is its series to third order
+// (residual < 1e-12 s).  s and c receive the sine and cosine of the orbital
+// phase at tb - R(tb), the first iterate of t_src.
+__device__ inline double binary_inverse(const TmplParams& tp, double tb, double& s, double& c) {
+  double s0, c0;
+  sincos_cycles((tb - tp.tp) * tp.nu_b, s0, c0);
+  const double r0 = tp.asini * s0;
+  const double e = tp.om_b * r0, e2 = e * e;
+  const double ce = fma(e2, fma(e2, 1.0 / 24.0, -0.5), 1.0);
+  const double se = e * fma(e2, -1.0 / 6.0, 1.0);
+  s = fma(s0, ce, -c0 * se);
+  c = fma(c0, ce, s0 * se);
+  const double h = r0 - tp.asini * s;
+  const double g = tp.asini * tp.om_b * c;
+  return r0 - h * fma(g, fma(g, 1.0 - g, -1.0), 1.0);
+}
+
 // Step (iii): for the detector sample time t return t_src - t, where
 // t_src + R(t_src) = t + roemer(t).  R is found by one Newton step from
 // R(t_b) (contraction asini * om_b < 1e-2: residual < 1e-12 s).
@@ -352,12 +374,8 @@ __device__ inline double sample_delay(const RoemerFn& roemer, const TmplParams& 
   roemer(t, dr, ddr, oob...);
   double r = 0.0;
   if (tp.asini != 0.0) {
-    double tb = t + dr;
-    double r0 = binary_delay(tp, tb);
     double s, c;
-    sincos_cycles((tb - r0 - tp.tp) * tp.nu_b, s, c);
-    double h = r0 - tp.asini * s;
-    r = r0 - h / (1.0 + tp.asini * tp.om_b * c);
+    r = binary_inverse(tp, t + dr, s, c);
   }
   return dr - r;
 }
