@@ -34,9 +34,9 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # figures hold for the kernel sources, header and build flags with this
 # digest; for any other version the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "959d53e35aa874ad9943e78d7b5cff5259de027d2f83a213944296ab7f1a4387",
-    "bytes_per_template": {"fft_columns": 13880906 + 33911975,
-                           "fft_rows_2f": 33586685 + 8672862},
+    "sources_sha256": "cf43d0027d360b6765856ec556b4d1c9a7f6b3860d2e544bfaf1a22d0f948a11",
+    "bytes_per_template": {"fft_columns": 13881390 + 33915784,
+                           "fft_rows_2f": 34619804 + 9975214},
 }
 
 
