@@ -336,23 +336,30 @@ ResFn resample_kernel(int D, bool grouped) {
 }
 
 // Optional per-kernel timing: events recorded before and after each launch.
+// Per-kernel device time from HIP events on the launch stream: open(k)
+// records an event where kernel k starts, which also ends the kernel opened
+// before it (launches follow one another on the stream); close() ends the
+// last one.  One event per launch boundary.
 struct KernelTimer {
   static constexpr int kKernels = 4;
-  std::vector<hipEvent_t> ev[kKernels];
+  std::vector<hipEvent_t> ev;
+  std::vector<int> who;  // kernel that starts at ev[i] (-1: none)
   bool on = false;
   hipStream_t st = nullptr;
-  fstat_status mark(int k) {
+  fstat_status record(int k) {
     if (!on) return FSTAT_OK;
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
     if (r == hipSuccess) r = hipEventRecord(e, st);
     if (r != hipSuccess) return check_hip(r, "timing event");
-    ev[k].push_back(e);
+    ev.push_back(e);
+    who.push_back(k);
     return FSTAT_OK;
   }
+  fstat_status open(int k) { return record(k); }
+  fstat_status close() { return record(-1); }
   ~KernelTimer() {
-    for (auto& v : ev)
-      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
 };
 
@@ -375,52 +382,54 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
   const int n = map.n_tmpl;
   if (!grouped) {
     // the grouped (search) path computed every parameter block up front
-    if ((s = tm.mark(0)) != FSTAT_OK) return s;
+    if ((s = tm.open(0)) != FSTAT_OK) return s;
     hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, ws);
-    if ((s = tm.mark(0)) != FSTAT_OK) return s;
   }
   const int n_res = grouped ? map.n_grp : n;
   if (n_res > 0) {
-    if ((s = tm.mark(1)) != FSTAT_OK) return s;
+    if ((s = tm.open(1)) != FSTAT_OK) return s;
     hipLaunchKernelGGL(resample_kernel(p->desc.sinc_halfwidth, grouped),
                        dim3(unsigned(p->k_pad / kResTile), n_res), dim3(kResThreads), 0, st, P,
                        ws, map, slots);
-    if ((s = tm.mark(1)) != FSTAT_OK) return s;
   }
   if (y_out) {
+    if ((s = tm.close()) != FSTAT_OK) return s;
     hipLaunchKernelGGL(k_copy_series, dim3(256, n), dim3(256), 0, st, P, ws, map, y_out);
     return check_hip(hipGetLastError(), "resample launch");
   }
   const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), grouped);
   const FftVariant rv = pick_rows(p->log_c, rows_choice(p), forward_row_mode(out));
-  if ((s = tm.mark(2)) != FSTAT_OK) return s;
+  if ((s = tm.open(2)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn)),
                      dim3(fft_grid(cols_items(p, cv, n))), dim3(cv.threads), cv.lds, st, P, ws, map,
                      slots, 0, p->log_c,
                      p->rows_act);
-  if ((s = tm.mark(2)) != FSTAT_OK) return s;
-  if ((s = tm.mark(3)) != FSTAT_OK) return s;
+  if ((s = tm.open(3)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rv.fn)),
                      dim3(fft_grid(rows_items(p, rv, n))), dim3(rv.threads), rv.lds, st, P, ws, map,
                      slots, p->log_rr, out);
-  if ((s = tm.mark(3)) != FSTAT_OK) return s;
   return check_hip(hipGetLastError(), "kernel launch");
 }
 
-// Wait for the stream, then sum each kernel's event intervals.
+// End the last kernel, wait for the stream, then sum each kernel's event
+// intervals.
 fstat_status finish_timer(KernelTimer& tm, hipStream_t st, float* kernel_ms, int64_t* launches) {
-  fstat_status s = check_hip(hipStreamSynchronize(st), "timing synchronise");
+  fstat_status s = tm.close();
+  if (s != FSTAT_OK) return s;
+  s = check_hip(hipStreamSynchronize(st), "timing synchronise");
   if (s != FSTAT_OK) return s;
   for (int k = 0; k < KernelTimer::kKernels; ++k) {
-    float total = 0.f;
-    for (size_t i = 0; i + 1 < tm.ev[k].size(); i += 2) {
-      float ms = 0.f;
-      s = check_hip(hipEventElapsedTime(&ms, tm.ev[k][i], tm.ev[k][i + 1]), "event time");
-      if (s != FSTAT_OK) return s;
-      total += ms;
-    }
-    kernel_ms[k] = total;
-    launches[k] = int64_t(tm.ev[k].size() / 2);
+    kernel_ms[k] = 0.f;
+    launches[k] = 0;
+  }
+  for (size_t i = 0; i + 1 < tm.ev.size(); ++i) {
+    const int k = tm.who[i];
+    if (k < 0) continue;
+    float ms = 0.f;
+    s = check_hip(hipEventElapsedTime(&ms, tm.ev[i], tm.ev[i + 1]), "event time");
+    if (s != FSTAT_OK) return s;
+    kernel_ms[k] += ms;
+    launches[k] += 1;
   }
   g_err.clear();
   return FSTAT_OK;
@@ -644,12 +653,11 @@ fstat_status search_launch(fstat_search* sr, const fstat_inputs* in, const doubl
   PlanConst P = make_const(p, in);
   P.params = static_cast<char*>(ws) + search_params_offset(sr);
   hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, ws);
-  fstat_status s0 = tm.mark(0);
+  fstat_status s0 = tm.open(0);
   if (s0 != FSTAT_OK) return s0;
   const int64_t nt = std::max<int64_t>(sr->ntmpl, sr->slots);
   hipLaunchKernelGGL(k_params, dim3(unsigned((nt + 63) / 64)), dim3(64), 0, st, P, templates,
                      sr->ntmpl, ws, sr->slots, out);
-  if ((s0 = tm.mark(0)) != FSTAT_OK) return s0;
   for (const ChunkMap& map : sr->chunks) {
     fstat_status s = launch_chunk(p, P, templates, map, sr->slots, true, out, nullptr, ws, st, tm);
     if (s != FSTAT_OK) return s;
