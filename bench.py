@@ -186,6 +186,56 @@ def uneven_leg(n_search, steps):
                                            res["batch"]["ms_per_step"], 3)}
 
 
+def workload_leg(name):
+    """Other workloads of the grouped search.  tiny: one timed step after an
+    untimed one, full-band 2F.  binary: the full bank with candidate
+    retention on the device (threshold 70, the paper's pilot search; the
+    full band of 10^4 templates at 2^23 bins would take 335 GB), one timed
+    step after an untimed one, plus the per-kernel split from a profiled
+    full-band run of the first 256 templates."""
+    import torch
+    from paper_2201_00451_amd import binding, synth
+    ds = {"tiny": synth.config_tiny, "binary": synth.config_binary}[name]()
+    dd = binding.DeviceData(ds, batch=1)
+    slots = min(32, ds.ntmpl)
+    sr = binding.Search(dd, ds.templates, slots=slots)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {"templates": ds.ntmpl, "n_fft": ds.n_fft, "detectors": ds.ndet,
+           "samples_per_detector": ds.detectors[0].n, "sky_orbit_groups": sr.ngroups,
+           "slots": slots}
+    if name == "binary":
+        sr.run_candidates(70.0, capacity=1 << 20)
+        torch.cuda.synchronize()
+        e0.record(st)
+        c = sr.run_candidates(70.0, capacity=1 << 20)
+        e1.record(st)
+        torch.cuda.synchronize()
+        res["output"] = "candidates 2F > 70"
+        res["candidates"] = c["count"]
+        sub = binding.Search(dd, ds.templates[:256], slots=slots)
+        out = torch.empty((256, ds.n_bins), dtype=torch.float32, device=dd.device)
+        sub.run_profiled(out=out)
+        _, kt = sub.run_profiled(out=out)
+        nk = 256
+        del out, sub
+    else:
+        out = torch.empty((ds.ntmpl, ds.n_bins), dtype=torch.float32, device=dd.device)
+        sr.run_profiled(out=out)
+        torch.cuda.synchronize()
+        e0.record(st)
+        _, kt = sr.run_profiled(out=out)
+        e1.record(st)
+        torch.cuda.synchronize()
+        res["output"] = "full band"
+        nk = ds.ntmpl
+    ms = e0.elapsed_time(e1)
+    binding.sync_check()
+    res.update({"ms_per_step": round(ms, 3), "templates_per_s": round(ds.ntmpl / (ms / 1e3), 1),
+                "us_per_template": {k: round(v[0] * 1e3 / nk, 3) for k, v in kt.items()}})
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +251,9 @@ def main():
                     help="independent searches of uneven shape run as one captured batch "
                          "(0: skip)")
     ap.add_argument("--uneven-steps", type=int, default=3)
+    ap.add_argument("--other-workloads", type=int, default=1,
+                    help="also time the tiny (1 detector, 1 d, 2^17) and binary (2 detectors, "
+                         "120 d, 2^23, 10^4 orbits) workloads, one step each (0: skip)")
     ap.add_argument("--cpu-templates", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--refine-calls", type=int, default=10,
@@ -349,6 +402,14 @@ def main():
         refine = refinement_leg(args.refine_calls, args.refine_steps)
         binding.sync_check()
 
+    others = None
+    if args.other_workloads:
+        others = {}
+        for name in ("tiny", "binary"):
+            print(f"bench: {name} workload", file=sys.stderr, flush=True)
+            others[name] = workload_leg(name)
+            torch.cuda.empty_cache()
+
     uneven = None
     if args.uneven_searches > 0:
         print(f"bench: {args.uneven_searches} uneven searches, sequential and batched",
@@ -387,6 +448,7 @@ def main():
         "cpu_baseline": cpu,
         "refinement": refine,
         "uneven_batch": uneven,
+        "other_workloads": others,
         "wall_s_timed": round(wall, 3),
     }
     if calib:
