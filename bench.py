@@ -265,7 +265,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the whole search on a single "
+        print("bench.py measures one GPU only: the library runs the whole search on a single "
               "MI355X (templates would shard across GPUs with no exchange step); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)

@@ -36,7 +36,7 @@ extern "C" {
 typedef enum {
   FSTAT_OK = 0,
   FSTAT_EINVAL = -1,       /* an argument is invalid (null, out of range, inconsistent) */
-  FSTAT_EUNSUPPORTED = -2, /* valid, but outside what this build implements */
+  FSTAT_EUNSUPPORTED = -2, /* valid, but outside what this library implements */
   FSTAT_EWORKSPACE = -3,   /* workspace smaller than fstat_workspace_size() */
   FSTAT_EHIP = -4          /* the HIP runtime reported an error */
 } fstat_status;

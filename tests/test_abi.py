@@ -276,6 +276,26 @@ def test_search_plan_groups_and_chunks(lib):
     lib.fstat_search_destroy(h)
 
 
+def test_search_chunks_keep_groups_whole(lib):
+    """A sky group that fits a launch sequence is not split over two: 10
+    groups of 10 spin-downs with 25 slots give 5 sequences of 2 groups; a
+    group larger than the slots fills whole sequences."""
+    ds, d = good_desc()
+    p = B.Plan(d)
+    vp = ctypes.c_void_p
+    rows = [[1.0 + 0.01 * g, -0.5, 0, 1e-11 * k, 0, 0, 1.0, 0] for g in range(10) for k in range(10)]
+    for tm, slots, want in ((np.array(rows), 25, 5), (np.array(rows), 30, 4),
+                            (np.array(rows[:10] * 1), 4, 3)):
+        tm = np.ascontiguousarray(tm, dtype=np.float64)
+        h = vp()
+        assert lib.fstat_search_create(p.handle, tm.ctypes.data_as(vp), len(tm), slots, 0,
+                                       ctypes.byref(h)) == 0
+        ng, nc = ctypes.c_int64(), ctypes.c_int64()
+        assert lib.fstat_search_info(h, None, ctypes.byref(ng), ctypes.byref(nc)) == 0
+        assert nc.value == want, (slots, nc.value)
+        lib.fstat_search_destroy(h)
+
+
 def test_autotune_checks_arguments_before_any_launch(lib):
     ds, d = good_desc()
     vp = ctypes.c_void_p
