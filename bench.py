@@ -34,9 +34,9 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # figures hold for the kernel sources, header and build flags with this
 # digest; for any other version the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "cf43d0027d360b6765856ec556b4d1c9a7f6b3860d2e544bfaf1a22d0f948a11",
-    "bytes_per_template": {"fft_columns": 13881390 + 33915784,
-                           "fft_rows_2f": 34619804 + 9975214},
+    "sources_sha256": "fb71a26f892b04054891bd65411cc370000d8abcb606b4536082b5bd5e1d17cc",
+    "bytes_per_template": {"fft_columns": 13882740 + 33633610,
+                           "fft_rows_2f": 34622190 + 9939000},
 }
 
 
