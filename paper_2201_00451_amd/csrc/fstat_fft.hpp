@@ -113,6 +113,18 @@ struct LdsLayout {
   __device__ static __forceinline__ int at(int idx, int line) {
     return line * pitch + idx + idx / PAD;
   }
+  // at(i + j STEP, line) for STEP a multiple of PAD: the pad of the strided
+  // part is a constant stride, so the unrolled accesses of one thread differ
+  // by compile-time offsets (one address register per butterfly)
+  template <int STEP>
+  __device__ static __forceinline__ int at_step(int i, int j, int line) {
+    static_assert(STEP % PAD == 0, "stride must be a multiple of the pad period");
+    return line * pitch + i + i / PAD + j * (STEP + STEP / PAD);
+  }
+  // at(i PAD + m, line) for m < PAD (a first-stage butterfly's outputs)
+  __device__ static __forceinline__ int at_block(int i, int m, int line) {
+    return line * pitch + i * (PAD + 1) + m;
+  }
 };
 // Bytes of LDS of a pass: NL padded lines and the half twiddle table.
 template <int L, int PAD, int F, int NL>
@@ -156,7 +168,7 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* twl, int ti
     if (NB % NT == 0 || b < NB) {
       const int i = b % NBL, line = b / NBL;
 #pragma unroll
-      for (int j = 0; j < R; ++j) v[s][j] = buf[Lay::at(i + j * NBL, line)];
+      for (int j = 0; j < R; ++j) v[s][j] = buf[Lay::template at_step<NBL>(i, j, line)];
     }
   }
   __syncthreads();
@@ -169,7 +181,7 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* twl, int ti
       twiddle_dft<R, P, L>(v[s], k, twl);
       const int base = (i - k) * R + k;
 #pragma unroll
-      for (int m = 0; m < R; ++m) buf[Lay::at(base + m * P, line)] = v[s][m];
+      for (int m = 0; m < R; ++m) buf[Lay::template at_step<P>(base, m, line)] = v[s][m];
     }
   }
   __syncthreads();
@@ -312,7 +324,7 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
       }
       dft<R0>(v[s]);
 #pragma unroll
-      for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
+      for (int m = 0; m < R0; ++m) lds[Lay::at_block(i, m, line)] = v[s][m];
     }
   }
   __syncthreads();
@@ -326,7 +338,7 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
       const int line = b % NL, i = b / NL;
       float2 u[RL];
 #pragma unroll
-      for (int j = 0; j < RL; ++j) u[j] = lds[Lay::at(i + j * PL, line)];
+      for (int j = 0; j < RL; ++j) u[j] = lds[Lay::template at_step<PL>(i, j, line)];
       twiddle_dft<RL, PL, L>(u, i, twl);
       const int64_t c = it.c0 + line;
       // W_N^{c (i + m PL)} = W_N^{c i} (W_N^{c PL})^m
@@ -520,7 +532,7 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
         const int i = b % NBL0, line = b / NBL0;
         dft<R0>(v[s]);
 #pragma unroll
-        for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
+        for (int m = 0; m < R0; ++m) lds[Lay::at_block(i, m, line)] = v[s][m];
       }
     }
     __syncthreads();
@@ -542,8 +554,8 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
         float2 va[RL], vb[RL];
 #pragma unroll
         for (int j = 0; j < RL; ++j) {
-          va[j] = lds[Lay::at(i + j * PL, ql)];
-          vb[j] = lds[Lay::at(i + j * PL, RQ + ql)];
+          va[j] = lds[Lay::template at_step<PL>(i, j, ql)];
+          vb[j] = lds[Lay::template at_step<PL>(i, j, RQ + ql)];
         }
         twiddle_dft<RL, PL, L>(va, i, twl);
         twiddle_dft<RL, PL, L>(vb, i, twl);
@@ -647,7 +659,7 @@ __global__ __launch_bounds__(NT, NT / 128) void k_fft_rows_split(PlanConst P, vo
         const int i = b % NBL0, line = b / NBL0;
         dft<R0>(v[s]);
 #pragma unroll
-        for (int m = 0; m < R0; ++m) lds[Lay::at(i * R0 + m, line)] = v[s][m];
+        for (int m = 0; m < R0; ++m) lds[Lay::at_block(i, m, line)] = v[s][m];
       }
     }
     __syncthreads();
@@ -659,7 +671,7 @@ __global__ __launch_bounds__(NT, NT / 128) void k_fft_rows_split(PlanConst P, vo
         const int ql = b % RQ, i = b / RQ;
         float2 u[RL];
 #pragma unroll
-        for (int j = 0; j < RL; ++j) u[j] = lds[Lay::at(i + j * PL, ql)];
+        for (int j = 0; j < RL; ++j) u[j] = lds[Lay::template at_step<PL>(i, j, ql)];
         twiddle_dft<RL, PL, L>(u, i, twl);
         if (arr == 0) {
 #pragma unroll
