@@ -5,14 +5,16 @@
 //   Column pass: for each column c, an Rr-point FFT over r, then the twiddle
 //     W_N^{q c}; written back in place (each workgroup owns whole columns).
 //   Row pass: for each row q, a C-point FFT over c gives X[q + Rr p].  The
-//     same workgroup transforms rows of y_a' and y_b', so it holds Fa' and
-//     Fb' of every bin it produces and writes 2F directly (ascending
+//     same workgroup transforms the rows of y_a' and y_b', so it holds Fa'
+//     and Fb' of every bin it produces and writes 2F directly (ascending
 //     frequency: output index (m + N/2) mod N).
 // Inside a pass, lines are transformed in LDS by a mixed-radix Stockham
-// autosort: every thread holds whole radix-R butterflies (R <= 16) in
-// registers.  Stage twiddles come from an FP32 table written from FP64 once
-// per call and copied to LDS; the four-step twiddles from sincospi.  The HBM
-// traffic is one read and one write of the series per pass.
+// autosort: every thread holds whole radix-R butterflies (R <= 32) in
+// registers; the first stage reads HBM and the last one writes it.  Stage
+// twiddles come from an FP32 table written from FP64 once per call and
+// copied to LDS; the four-step twiddles from the exact quarter-turn split of
+// their exponent and the rotation polynomials.  The HBM traffic is one read
+// and one write of the series per pass.
 #pragma once
 
 #include "fstat_common.hpp"

@@ -11,8 +11,9 @@
 //      solution extrapolated along dT/dtau; T_k is monotonic in k, so the
 //      tile's first and last points bound the input samples it touches;
 //   3. stages those samples in LDS after the step (iii) heterodyne correction
-//      z_j = x_j exp(-2 pi i f_h (t_src,j - t_j)) (FP64 delay, reduced to
-//      [-1/2, 1/2] cycles, FP32 rotation): each input sample is read from HBM
+//      z_j = x_j exp(-2 pi i f_h (t_src,j - t_j)) (FP64 delay, split
+//      exactly into quarter turns and an FP32 remainder, polynomial
+//      rotation): each input sample is read from HBM
 //      and corrected once per tile;
 //   4. interpolates z at T_k with the 2D-tap Hann-windowed sinc
 //      h(s) = sinc(s) (1 + cos(pi s / D)) / 2 (the paper leaves the kernel of
