@@ -285,7 +285,8 @@ def main():
 
     sr = binding.Search(dd, ds.templates, slots=args.batch)
     print(f"bench: {ds.ntmpl} templates in {sr.ngroups} sky/orbit groups, "
-          f"{sr.nchunks} launch sequences of {args.batch} slots", file=sys.stderr, flush=True)
+          f"{sr.nchunks} launch sequences of at most {args.batch} templates (whole groups)",
+          file=sys.stderr, flush=True)
 
     print("bench: warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -434,6 +435,7 @@ def main():
                    "n_bins": ds.n_bins, "detectors": ds.ndet,
                    "samples_per_detector": ds.detectors[0].n,
                    "sinc_halfwidth": ds.sinc_halfwidth, "slots": args.batch,
+                   "launch_sequences": sr.nchunks,
                    "timing_dtype": "f64", "path": "grouped: one resampled series per sky "
                    "position, spin-down phase applied in the FFT load",
                    "sky_orbit_groups": sr.ngroups},
