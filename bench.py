@@ -34,9 +34,9 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # figures hold for the kernel sources, header and build flags with this
 # digest; for any other version the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "fb71a26f892b04054891bd65411cc370000d8abcb606b4536082b5bd5e1d17cc",
-    "bytes_per_template": {"fft_columns": 13882740 + 33633610,
-                           "fft_rows_2f": 34622190 + 9939000},
+    "sources_sha256": "5547a37bfae306b404896ceabccc9aed9cd4b7a8873e96775a77bb7e131f7fc5",
+    "bytes_per_template": {"fft_columns": 13882300 + 33777016,
+                           "fft_rows_2f": 33571009 + 9078755},
 }
 
 
