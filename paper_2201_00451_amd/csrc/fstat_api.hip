@@ -1027,8 +1027,11 @@ fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out) {
   }
   p->fft_mlr = desc->tune_fft_radix == 16 ? 4 : 5;
   // automatic (measured): columns in the half line count (256-thread
-  // workgroups, two per compute unit), rows in the full count (512 threads)
-  p->cols_half = (tc == 0 || tc == cmax / 2) && cmax > 1;
+  // workgroups, two per compute unit) while that still gives 8 columns
+  // (64-byte runs per row; at 2^11-point columns the 4-column half count ran
+  // the pass 24 % slower than 8 columns in one workgroup), rows in the full
+  // count (512 threads)
+  p->cols_half = (tc == 0 ? cmax / 2 >= 8 : tc == cmax / 2) && cmax > 1;
   p->rows_half = tr == rmax / 2 && rmax > 1;
   p->cols_lines = p->cols_half ? cmax / 2 : cmax;
   p->rows_lines = p->rows_half ? rmax / 2 : rmax;
