@@ -34,9 +34,9 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # figures hold for the kernel sources, header and build flags with this
 # digest; for any other version the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "c09cbdb9e5a1d6115358ffc405e01f0d7ac89b14cf9481ea1b6aec51b74e603f",
-    "bytes_per_template": {"fft_columns": 13881649 + 33768751,
-                           "fft_rows_2f": 33568717 + 9053235},
+    "sources_sha256": "8446bcb52b8cc0a830e4d095f0469800722be8871a97ec067fec610077fef671",
+    "bytes_per_template": {"fft_columns": 13881470 + 33745906,
+                           "fft_rows_2f": 33563436 + 8418103},
 }
 
 

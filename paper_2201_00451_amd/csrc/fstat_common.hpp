@@ -208,6 +208,16 @@ __device__ __forceinline__ float2 buf_load2(__amdgpu_buffer_rsrc_t r, uint32_t v
                                             uint32_t soff) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
+// Streaming read (non-temporal cache policy): for data read exactly once, so
+// that it does not evict lines other loads and stores still use from L2 (the
+// row passes read the intermediate once; meanwhile their partial 2F lines
+// wait in L2 for their neighbours).
+__device__ __forceinline__ float2 buf_load2_stream(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                   uint32_t soff) {
+  constexpr int kNonTemporal = 2;
+  return __builtin_bit_cast(float2,
+                            __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kNonTemporal));
+}
 __device__ __forceinline__ void buf_store2(float2 x, __amdgpu_buffer_rsrc_t r, uint32_t voff,
                                            uint32_t soff) {
   using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));

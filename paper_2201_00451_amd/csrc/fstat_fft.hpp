@@ -425,9 +425,13 @@ __device__ __forceinline__ void rows_load(const PlanConst& P, void* ws, const Ro
       const int i = b % NBL0, line = b / NBL0;
       const int64_t e0 = (line < RQ ? 0 : P.n_fft) + (it.q0 + line % RQ) * L + i;
       const uint32_t voff = uint32_t(e0 * int64_t(sizeof(float2)));
+      // streaming reads pay off with the plain 2F epilogue (its partial 2F
+      // lines stay in L2); with the extended epilogue they cost 2 % (measured)
 #pragma unroll
-      for (int j = 0; j < R0; ++j)
-        v[s][j] = buf_load2(rs, voff, uint32_t(j * NBL0 * int(sizeof(float2))));
+      for (int j = 0; j < R0; ++j) {
+        const uint32_t soff = uint32_t(j * NBL0 * int(sizeof(float2)));
+        v[s][j] = MODE == kRow2F ? buf_load2_stream(rs, voff, soff) : buf_load2(rs, voff, soff);
+      }
     }
   }
 }
@@ -651,7 +655,7 @@ __global__ __launch_bounds__(NT, NT / 128) void k_fft_rows_split(PlanConst P, vo
         const uint32_t voff = uint32_t(((it.q0 + line) * L + i) * int64_t(sizeof(float2)));
 #pragma unroll
         for (int j = 0; j < R0; ++j)
-          v[s][j] = buf_load2(rs, voff, uint32_t(j * NBL0 * int(sizeof(float2))));
+          v[s][j] = buf_load2_stream(rs, voff, uint32_t(j * NBL0 * int(sizeof(float2))));
       }
     }
 #pragma unroll
