@@ -110,23 +110,30 @@ FftVariant rows_variant_n() {
 // radix-32 stages that does not fit 128 VGPRs, and with fewer than 4 rows per
 // item (lines of 2^12) the shorter 2F runs cost more than the occupancy
 // gains (measured): there the pass keeps both arrays.
-template <int LOGL, int MLR>
+template <int LOGL, int MLR, int MODE>
 FftVariant rows_split_variant() {
   constexpr int RQ = kRowsMax<LOGL>, R0 = kR0<LOGL, MLR>;
-  return {reinterpret_cast<const void*>(&k_fft_rows_split<LOGL, RQ, 512, MLR>), 512,
+  return {reinterpret_cast<const void*>(&k_fft_rows_split<LOGL, RQ, 512, MLR, MODE>), 512,
           kLdsBytes<1 << LOGL, R0, RQ, RQ>, RQ};
 }
 // The adjoint, conjugate and extended epilogues of a radix-32 plan exceed 256
 // VGPRs at the full count: they take the half count (the same arithmetic per
 // point, so the same bits as the full-count plain 2F kernel).
+// Candidates and loudest bin only: the split pass where the plain 2F pass
+// takes it (no 2F array is written), else the extended epilogue.
 template <int LOGL, int MODE, int MLR>
 FftVariant rows_variant(bool half) {
-  if constexpr (MODE != kRow2F && kR0<LOGL, MLR> == 32) {
+  if constexpr (MODE == kRowCand) {
+    if constexpr (kR0<LOGL, MLR> <= 16 && kRowsMax<LOGL> >= 4) {
+      if (!half) return rows_split_variant<LOGL, MLR, kRowCand>();
+    }
+    return rows_variant<LOGL, kRow2FExt, MLR>(half);
+  } else if constexpr (MODE != kRow2F && kR0<LOGL, MLR> == 32) {
     return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL> / 2, 256>();
   } else {
     if (half) return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL> / 2, 256>();
     if constexpr (MODE == kRow2F && kR0<LOGL, MLR> <= 16 && kRowsMax<LOGL> >= 4)
-      return rows_split_variant<LOGL, MLR>();
+      return rows_split_variant<LOGL, MLR, kRow2F>();
     return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL>, 512>();
   }
 }
@@ -169,11 +176,15 @@ FftVariant pick_rows(int logl, const FftChoice& c, int mode = kRow2F) {
   return mode == kRowAdjoint ? pick_rows_m<kRowAdjoint>(logl, c)
          : mode == kRowConj  ? pick_rows_m<kRowConj>(logl, c)
          : mode == kRow2FExt ? pick_rows_m<kRow2FExt>(logl, c)
+         : mode == kRowCand  ? pick_rows_m<kRowCand>(logl, c)
                              : pick_rows_m<kRow2F>(logl, c);
 }
-// The forward epilogue a RowOutput needs: plain 2F stores, or the extended one.
+// The forward epilogue a RowOutput needs: plain 2F stores, candidates and
+// loudest bin without a 2F array, or the extended one.
 int forward_row_mode(const RowOutput& out) {
-  return (out.twoF && !out.fafb && !out.cand && !out.best && !out.acc) ? kRow2F : kRow2FExt;
+  if (out.twoF && !out.fafb && !out.cand && !out.best && !out.acc) return kRow2F;
+  if (!out.twoF && !out.fafb && !out.acc && (out.cand || out.best)) return kRowCand;
+  return kRow2FExt;
 }
 
 FftChoice cols_choice(const fstat_plan* p) { return {p->cols_half, p->fft_mlr}; }
@@ -442,7 +453,7 @@ fstat_status set_lds_limits(const fstat_plan* p) {
     e = hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(v.lds));
     if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(cols)");
   }
-  for (int mode : {int(kRow2F), int(kRowAdjoint), int(kRowConj), int(kRow2FExt)}) {
+  for (int mode : {int(kRow2F), int(kRowAdjoint), int(kRowConj), int(kRow2FExt), int(kRowCand)}) {
     const FftVariant v = pick_rows(p->log_c, rows_choice(p), mode);
     e = hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(v.lds));
     if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(rows)");

@@ -372,7 +372,10 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
 // kRow2F stores 2F only (the plain full-band output); kRow2FExt is the same
 // transform with every optional output of RowOutput (Fa/Fb, accumulation,
 // candidates, loudest bin).
-enum RowMode { kRow2F = 0, kRowAdjoint = 1, kRowConj = 2, kRow2FExt = 3 };
+// Row epilogues: plain 2F stores; the adjoint's two; the extended forward one
+// (Fa/Fb, accumulation, candidates, loudest bin); candidates and loudest bin
+// only (no 2F array).
+enum RowMode { kRow2F = 0, kRowAdjoint = 1, kRowConj = 2, kRow2FExt = 3, kRowCand = 4 };
 
 // 2F = 2 (|Fa'|^2 + |Fb'|^2) with explicit FMA, so that every epilogue gives
 // the same bits.
@@ -385,6 +388,34 @@ struct RowItem {
   int64_t q0, tmpl;
   float l11, l21, l22;
 };
+
+// A bin above the threshold joins the candidate list (slots past the
+// capacity are counted, not stored).
+__device__ __forceinline__ void keep_candidate(const RowOutput& out, int64_t tmpl, int64_t o,
+                                               float v2) {
+  if (out.cand && v2 > out.threshold) {
+    const unsigned long long idx = atomicAdd(out.count, 1ull);
+    if (idx < (unsigned long long)out.cap)
+      out.cand[idx] = fstat_candidate{int32_t(tmpl), int32_t(o), v2, 0};
+  }
+}
+// Loudest-bin key: 2F's bits (2F >= 0, so unsigned order is float order)
+// above the band offset, so the largest key is the loudest bin and equal 2F
+// resolve to the highest bin.
+__device__ __forceinline__ unsigned long long best_key(float v2, int64_t o) {
+  return (static_cast<unsigned long long>(__float_as_uint(v2)) << 32) |
+         static_cast<unsigned long long>(o);
+}
+// The workgroup's keys into the template's entry: wavefront maximum, one
+// atomic per wave.
+__device__ __forceinline__ void best_to_global(const RowOutput& out, int64_t tmpl,
+                                               unsigned long long key) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_down(key, off, 64);
+    key = o > key ? o : key;
+  }
+  if ((threadIdx.x & 63) == 0 && key != 0ull) atomicMax(out.best + tmpl, key);
+}
 
 template <int MODE>
 __device__ __forceinline__ RowItem rows_item(const PlanConst& P, void* ws, const ChunkMap& map,
@@ -471,11 +502,7 @@ __device__ __forceinline__ float rows_out(const PlanConst& P, void* ws, const Ro
     out.fafb[(it.tmpl * 2 + 1) * P.n_bins + o] =
         make_float2(it.l21 * fa.x + it.l22 * fb.x, it.l21 * fa.y + it.l22 * fb.y);
   }
-  if (out.cand && v2 > out.threshold) {
-    const unsigned long long idx = atomicAdd(out.count, 1ull);
-    if (idx < (unsigned long long)out.cap)
-      out.cand[idx] = fstat_candidate{int32_t(it.tmpl), int32_t(o), v2, 0};
-  }
+  keep_candidate(out, it.tmpl, o, v2);
   return v2;
 }
 
@@ -543,8 +570,7 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
     }
     __syncthreads();
     fft_middle<LOGL, NL, NT, 1, MLR, Lay>(lds, twl, tid);
-    float bmax = -1.0f;
-    int64_t bbin = 0;
+    unsigned long long bkey = 0ull;
     // plain 2F: band offsets o = ((nat + N/2) mod N) - bin_lo in 32 bits; the
     // descriptor spans this template's n_bins floats, so the store of a bin
     // outside the band (o >= n_bins, also when the subtraction wraps) is dropped
@@ -578,25 +604,15 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
         for (int m = 0; m < RL; ++m) {
           const int64_t nat = it.q0 + ql + Rr * int64_t(i + m * PL);
           const float v2 = rows_out<MODE>(P, ws, it, nat, va[m], vb[m], out);
-          if (v2 > bmax) {
-            bmax = v2;
-            bbin = ((nat + P.n_fft / 2) & (P.n_fft - 1)) - P.bin_lo;
+          if (v2 >= 0.0f) {
+            const unsigned long long key =
+                best_key(v2, ((nat + P.n_fft / 2) & (P.n_fft - 1)) - P.bin_lo);
+            bkey = key > bkey ? key : bkey;
           }
         }
       }
     }
-    if (MODE == kRow2FExt && out.best) {
-      // largest 2F of the item: wavefront maximum, one atomic per wave
-      unsigned long long key =
-          bmax >= 0.0f ? (static_cast<unsigned long long>(__float_as_uint(bmax)) << 32) |
-                             static_cast<unsigned long long>(bbin)
-                       : 0ull;
-      for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_down(key, off, 64);
-        key = o > key ? o : key;
-      }
-      if ((tid & 63) == 0 && key != 0ull) atomicMax(out.best + it.tmpl, key);
-    }
+    if (MODE == kRow2FExt && out.best) best_to_global(out, it.tmpl, bkey);
   }
 }
 
@@ -604,12 +620,13 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
 // transformed and |Fa'|^2 of every bin the thread owns is kept in registers,
 // then the same rows of y_b' reuse the LDS lines and the thread writes
 // 2F = 2 (|Fa'|^2 + |Fb'|^2) (the same arithmetic, so the same bits, as
-// k_fft_rows).  With RQ lines of LDS instead of 2 RQ, two workgroups share a
+// k_fft_rows), or, with MODE kRowCand, keeps the bins above the threshold and
+// the loudest bin instead of writing 2F.  With RQ lines of LDS instead of 2 RQ, two workgroups share a
 // compute unit (the launch bound asks for registers to match) while the 2F
 // runs stay RQ floats long.  At lines of 2^11 the compiler keeps two LDS
 // offsets in scratch; recomputing the offsets in each pass instead measured
 // 3 % slower.
-template <int LOGL, int RQ, int NT, int MLR>
+template <int LOGL, int RQ, int NT, int MLR, int MODE>
 __global__ __launch_bounds__(NT, NT / 128) void k_fft_rows_split(PlanConst P, void* ws,
                                                                   ChunkMap map, int slots,
                                                                   int log_rr, RowOutput out) {
@@ -632,11 +649,11 @@ __global__ __launch_bounds__(NT, NT / 128) void k_fft_rows_split(PlanConst P, vo
     for (int e = tid; e < L / 2; e += NT) twl[e] = tws[e * (kTwLen / L)];
   }
   const RowItem it =
-      rows_item<kRow2F>(P, ws, map, int(xcd_remap(blockIdx.x, gridDim.x)), int(Rr / RQ), RQ);
+      rows_item<MODE>(P, ws, map, int(xcd_remap(blockIdx.x, gridDim.x)), int(Rr / RQ), RQ);
   if (it.flagged) rows_flagged<LOGL, RQ, NT>(P, it, Rr, out);
   if (!it.live) return;
-  const auto tf = buf_rsrc(out.twoF + it.tmpl * P.n_bins,
-                           uint32_t(P.n_bins * int64_t(sizeof(float))));
+  const auto tf = buf_rsrc(MODE == kRow2F ? out.twoF + it.tmpl * P.n_bins : nullptr,
+                           MODE == kRow2F ? uint32_t(P.n_bins * int64_t(sizeof(float))) : 0u);
   const uint32_t nmask = uint32_t(P.n_fft - 1), lo = uint32_t(P.bin_lo);
   const uint32_t ostep = uint32_t(Rr * PL);
   float pa[PER][RL];
@@ -688,11 +705,38 @@ __global__ __launch_bounds__(NT, NT / 128) void k_fft_rows_split(PlanConst P, vo
           for (int m = 0; m < RL; ++m) {
             const uint32_t o = ((o0 + uint32_t(m) * ostep) & nmask) - lo;
             const float v2 = 2.0f * (pa[s][m] + fmaf(u[m].x, u[m].x, u[m].y * u[m].y));
-            buf_store1(v2, tf, o * uint32_t(sizeof(float)));
+            if constexpr (MODE == kRow2F) {
+              buf_store1(v2, tf, o * uint32_t(sizeof(float)));
+            } else {
+              pa[s][m] = v2;
+            }
           }
         }
       }
     }
+  }
+  if constexpr (MODE == kRowCand) {
+    // after the transforms, so the candidate code does not compete with
+    // them for registers
+    unsigned long long bkey = 0ull;
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int b = tid + s * NT;
+      if (NBL % NT == 0 || b < NBL) {
+        const int ql = b % RQ, i = b / RQ;
+        const uint32_t o0 = uint32_t(it.q0 + ql + Rr * i) + uint32_t(P.n_fft / 2);
+#pragma unroll
+        for (int m = 0; m < RL; ++m) {
+          const uint32_t o = ((o0 + uint32_t(m) * ostep) & nmask) - lo;
+          if (o < uint32_t(P.n_bins)) {
+            keep_candidate(out, it.tmpl, o, pa[s][m]);
+            const unsigned long long key = best_key(pa[s][m], o);
+            bkey = key > bkey ? key : bkey;
+          }
+        }
+      }
+    }
+    if (out.best) best_to_global(out, it.tmpl, bkey);
   }
 }
 
