@@ -264,9 +264,41 @@ struct GlobalRoemer {
   }
 };
 
-// The same from nodes already projected on the sky (n.r, n.v) and staged in
-// LDS: node i sits at t0 + i h.  An evaluation outside the staged nodes is
-// clamped (memory-safe) and raises `oob`.
+// The same cubic per interval, staged in LDS as its power-series
+// coefficients in u = (t - t_i) / h: interval i holds (c0, c1), (c2, c3) with
+// c0 = p0, c1 = h v0, c2 = 3 (p1 - p0) - h (2 v0 + v1),
+// c3 = 2 (p0 - p1) + h (v0 + v1) of the projected nodes i, i + 1, so an
+// evaluation is three FMAs for the delay and three for its slope.  count is
+// the number of nodes (intervals + 1); an evaluation outside them is clamped
+// (memory-safe) and raises `oob`.
+struct CubicRoemer {
+  const double2* coef;
+  int count;
+  double t0, inv_h;
+  __device__ void operator()(double t, double& d, double& dd, bool& oob) const {
+    const double s = (t - t0) * inv_h;
+    int i = static_cast<int>(fmin(fmax(floor(s), -1.0), double(count)));
+    if (i < 0 || i > count - 2) {
+      oob = true;
+      i = i < 0 ? 0 : count - 2;
+    }
+    const double u = s - static_cast<double>(i);
+    const double2 a = coef[2 * i], b = coef[2 * i + 1];
+    d = fma(fma(fma(b.y, u, b.x), u, a.y), u, a.x);
+    dd = fma(fma(3.0 * b.y, u, 2.0 * b.x), u, a.y) * inv_h;
+  }
+};
+// Interval coefficients of CubicRoemer from projected positions p and
+// velocities v of two neighbouring nodes h apart.
+__device__ inline void cubic_interval(double p0, double v0, double p1, double v1, double h,
+                                      double2& lo, double2& hi) {
+  lo = make_double2(p0, h * v0);
+  hi = make_double2(3.0 * (p1 - p0) - h * (2.0 * v0 + v1), 2.0 * (p0 - p1) + h * (v0 + v1));
+}
+
+// The Hermite form from nodes already projected on the sky (n.r, n.v) and
+// staged in LDS: node i sits at t0 + i h.  An evaluation outside the staged
+// nodes is clamped (memory-safe) and raises `oob`.
 struct NodeRoemer {
   const double2* nodes;
   int count;

@@ -2,9 +2,10 @@
 //
 // One workgroup owns kResTile consecutive points of the regular source-frame
 // grid tau_k = tau0 + k dt of one template.  For each detector it
-//   1. stages the ephemeris nodes the tile can touch in LDS, projected on the
-//      sky direction once per node (n.r, n.v), so every later delay
-//      evaluation is a cubic Hermite on LDS data;
+//   1. stages the ephemeris intervals the tile can touch in LDS: the cubic
+//      Hermite of each interval, from its two nodes projected on the sky
+//      direction (n.r, n.v), as power-series coefficients, so every later
+//      delay evaluation is three FMAs on LDS data;
 //   2. solves the detector epochs T_k of step (iv) for the thread's own grid
 //      points (FP64): the tile's first point by a fixed-point and a Newton
 //      step, every other point by one Newton step from the first point's
@@ -116,7 +117,7 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
                                      float2 (&acc_b)[kResPerThread]) {
   const int tid = threadIdx.x;
   __shared__ float2 zs[kResWcap];
-  __shared__ double2 nodes[kNodeCap];
+  __shared__ double2 coef[2 * kNodeCap];
   __shared__ int64_t win_lo, win_hi;
   __shared__ int bad;
 
@@ -137,7 +138,7 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
   n_hi = n_hi > P.n_eph - 1 ? P.n_eph - 1 : n_hi;
   int n_count = int(n_hi - n_lo + 1);
   n_count = n_count > kNodeCap ? kNodeCap : (n_count < 2 ? 2 : n_count);
-  const NodeRoemer re{nodes, n_count, P.eph_t0 + double(n_lo) * P.eph_dt, P.eph_dt, P.inv_eph_dt};
+  const CubicRoemer re{coef, n_count, P.eph_t0 + double(n_lo) * P.eph_dt, P.inv_eph_dt};
   const double tau_s = P.tau0 + P.dt * double(k_s);
   // the binary delay depends on the grid point only: once for all detectors
   const double rb0 = binary_delay(tp, tau_s);
@@ -148,11 +149,14 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
 
   for (int X = 0; X < P.ndet; ++X) {
     const DetConst& d = P.det[X];
-    // 1. projected ephemeris nodes
-    for (int i = tid; i < n_count; i += kResThreads) {
+    // 1. interval coefficients from the projected nodes i and i + 1
+    for (int i = tid; i < n_count - 1; i += kResThreads) {
       const double* e = d.ephem + 6 * (n_lo + i);
-      nodes[i] = make_double2(tp.nhat[0] * e[0] + tp.nhat[1] * e[1] + tp.nhat[2] * e[2],
-                              tp.nhat[0] * e[3] + tp.nhat[1] * e[4] + tp.nhat[2] * e[5]);
+      const double p0 = tp.nhat[0] * e[0] + tp.nhat[1] * e[1] + tp.nhat[2] * e[2];
+      const double v0 = tp.nhat[0] * e[3] + tp.nhat[1] * e[4] + tp.nhat[2] * e[5];
+      const double p1 = tp.nhat[0] * e[6] + tp.nhat[1] * e[7] + tp.nhat[2] * e[8];
+      const double v1 = tp.nhat[0] * e[9] + tp.nhat[1] * e[10] + tp.nhat[2] * e[11];
+      cubic_interval(p0, v0, p1, v1, P.eph_dt, coef[2 * i], coef[2 * i + 1]);
     }
     __syncthreads();
     // 2. detector epochs: the tile's first point in full (fixed point, two
