@@ -34,9 +34,9 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # figures hold for the kernel sources, header and build flags with this
 # digest; for any other version the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "bfe0d577671340d9debaf218615c85c2deca002cfd6a7965a64f1e549530a02e",
-    "bytes_per_template": {"fft_columns": 13881378 + 33753007,
-                           "fft_rows_2f": 33563468 + 8417632},
+    "sources_sha256": "b3e4756cced3d056b429362ae8adba94261d366587cac560985c818495d5add0",
+    "bytes_per_template": {"fft_columns": 13881424 + 33759698,
+                           "fft_rows_2f": 33563484 + 8416371},
 }
 
 

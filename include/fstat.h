@@ -331,7 +331,7 @@ FSTAT_API fstat_status fstat_compute_2f_grad(const fstat_plan* plan, const fstat
  * direct sum Fa'(m), Fb'(m) over the grid (step (vi) for one output bin), and
  * the gradient kernel forms the adjoint series in closed form
  * X_k = conj(F'(m)) exp(-2 pi i m k / N).  Two passes over the input data per
- * template, and a workspace of about 1 KiB plus 64 bytes per 1024 grid points
+ * template, and a workspace of about 1 KiB plus 64 bytes per 512 grid points
  * per template in flight (fstat_grad_bin_workspace_size; up to 32 per
  * launch).  Outputs: twoF (nullable) device float [ntmpl] = 2F at the bin;
  * grad device double [ntmpl][7] as in fstat_compute_2f_grad.  A flagged

@@ -67,8 +67,7 @@ constexpr int kGradParams = 7;  // df, f1dot, alpha, delta, asini, porb, tp
 // and 1 hold conj(X)).  ONEHOT = true (single-bin path): L = 2F(m) at one bin
 // m, so H is non-zero only at m and X_k = H_m exp(-2 pi i m k / N) in closed
 // form; the slot holds no arrays.
-// Two waves per SIMD: the kernel's 435 registers, cut to 256 with spills,
-// still ran the single-bin adjoint 6 % faster than one wave (measured).
+// Two waves per SIMD (249 registers at two outputs per thread, no spills).
 template <int D, bool ONEHOT>
 __global__ __launch_bounds__(kResThreads, 2) void k_grad(PlanConst P, void* ws) {
   const int slot = blockIdx.y;

@@ -15,8 +15,13 @@ constexpr int kMaxDet = FSTAT_MAX_DET;
 constexpr double kPi = 3.14159265358979323846;
 
 // Resampling tile: outputs per workgroup, threads, and the staged-sample
-// capacity (tile + 1/16 drift allowance + 2D taps for D <= 32 + slack).
-constexpr int kResTile = 1024;
+// capacity (tile + 1/16 drift allowance + 2D taps for D <= 32 + slack).  Two
+// outputs per thread keep the resampling kernel at 115 registers and the
+// adjoint at 249, so four and two waves per SIMD fit without spills
+// (measured against 1024-point tiles: single-bin gradients 1800 to 2370 per
+// second, resampling 4 % faster on sky positions, 1 % slower on binary
+// orbits).
+constexpr int kResTile = 512;
 constexpr int kResThreads = 256;
 constexpr int kResPerThread = kResTile / kResThreads;
 constexpr int kResWcap = kResTile + kResTile / 16 + 64 + 8;

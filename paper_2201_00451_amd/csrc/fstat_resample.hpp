@@ -268,11 +268,12 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
 // the spin-down phase to the group's buffer, which every template of the
 // group reads (the reuse of the sky-dependent barycentring across spin-down
 // templates that Sec. 4.1 measures).
-// Three waves per SIMD (at most 168 registers, no spills): the timing's
-// FP64 and LDS latency chains hide better than at two (measured: 11 % on
-// sky positions, 17 % on binary orbits).
+// Four waves per SIMD (at most 128 registers, no spills at two outputs per
+// thread): the timing's FP64 and LDS latency chains hide better with more
+// waves (measured at 1024-point tiles: three waves against two, 11 % on sky
+// positions and 17 % on binary orbits).
 template <int D, bool GROUPED>
-__global__ __launch_bounds__(kResThreads, 3) void k_resample(PlanConst P, void* ws, ChunkMap map,
+__global__ __launch_bounds__(kResThreads, 4) void k_resample(PlanConst P, void* ws, ChunkMap map,
                                                          int slots) {
   const int gi = blockIdx.y;
   const int slot = GROUPED ? map.grp_slot[gi] : gi;
@@ -318,7 +319,7 @@ __host__ __device__ inline int64_t band_bin_nat(const PlanConst& P, int64_t i) {
 // (step (vi) restricted to one output bin), reduced per tile into the slot's
 // partials (Fa'.re, Fa'.im, Fb'.re, Fb'.im in FP64).
 template <int D>
-__global__ __launch_bounds__(kResThreads, 3) void k_resample_bin(PlanConst P, void* ws, ChunkMap map,
+__global__ __launch_bounds__(kResThreads, 4) void k_resample_bin(PlanConst P, void* ws, ChunkMap map,
                                                              const int64_t* __restrict__ bins) {
   const int slot = blockIdx.y;
   TmplParams* tpp = slot_params(ws, P, slot);

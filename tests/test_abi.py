@@ -106,7 +106,7 @@ def test_plan_accepts_valid_setup(lib):
                                            tune_row_lines=rl, tune_fft_radix=radix))
             B.Plan(d2)
     k_pad, lc, lr = p.info()
-    assert (lc, lr) == (6, 7) and k_pad % (1 << lr) == 0 and k_pad % 1024 == 0
+    assert (lc, lr) == (6, 7) and k_pad % (1 << lr) == 0 and k_pad % 512 == 0
     assert k_pad >= ds.detectors[0].n and k_pad <= ds.n_fft
     # header + one slot of two n_fft complex64 arrays
     assert p.workspace_size(1) >= 2 * 8 * ds.n_fft
