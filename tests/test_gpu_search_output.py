@@ -103,6 +103,36 @@ def test_candidates_equal_thresholded_band(torch_dev, slots):
     assert abs(float(res["best_twoF"][t]) - ref[b]) <= 1e-4 * ref[b]
 
 
+def test_candidates_split_row_pass_at_2e21(torch_dev):
+    """At n_fft = 2^21 the rows are 2^11 points and candidate retention runs in
+    the one-array-at-a-time row pass (the launch shape of the benchmark
+    workload): the candidates are exactly the thresholded bins of the full
+    band with the same 2F bits, a flagged template keeps none and reports the
+    NaN marker, and the loudest bins match."""
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(seed=61, n=20000, n_fft=1 << 21, ndet=2, ntmpl=1, rho=20.0)
+    tm = bank(ds, nsky=2, nf1=3, binary_rows=1)
+    tm[1, 3] = np.nan
+    dd = binding.DeviceData(ds, batch=4)
+    assert dd.plan.info()[2] == 11
+    sr = binding.Search(dd, tm, slots=4)
+    full = sr.run().cpu().numpy()
+    binding.sync_check()
+    assert np.all(np.isnan(full[1]))
+    ok = np.isfinite(full).all(axis=1)
+    thr = float(np.float32(np.quantile(full[ok], 0.99999)))
+    res = sr.run_candidates(thr, capacity=1 << 14)
+    binding.sync_check()
+    want, _ = expected_candidates(np.where(np.isnan(full), -1.0, full), thr)
+    say(f"  2^21: threshold {thr:.2f}, {res['count']} candidates, {len(want)} expected")
+    assert res["count"] == len(want) > 0
+    tt, bb = res["tmpl"].cpu().numpy(), res["bin"].cpu().numpy()
+    got = set(zip(tt.tolist(), bb.tolist()))
+    assert len(got) == len(tt) and got == want
+    np.testing.assert_array_equal(res["twoF"].cpu().numpy(), full[tt, bb])
+    check_best(res, full, flagged={1})
+
+
 def test_candidates_capacity_overflow_and_repeat(torch_dev):
     """count reports every bin above the threshold when capacity is smaller;
     the stored ones are distinct members of that set; a second call starts
