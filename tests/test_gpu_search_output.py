@@ -103,18 +103,20 @@ def test_candidates_equal_thresholded_band(torch_dev, slots):
     assert abs(float(res["best_twoF"][t]) - ref[b]) <= 1e-4 * ref[b]
 
 
-def test_candidates_split_row_pass_at_2e21(torch_dev):
+@pytest.mark.parametrize("log_n", [21, 23])
+def test_candidates_split_row_pass(torch_dev, log_n):
     """At n_fft = 2^21 the rows are 2^11 points and candidate retention runs in
-    the one-array-at-a-time row pass (the launch shape of the benchmark
-    workload): the candidates are exactly the thresholded bins of the full
+    the one-array-at-a-time row pass; at 2^23 (rows of 2^12, two per item) in
+    the extended epilogue (the launch shapes of the benchmark and binary
+    workloads): the candidates are exactly the thresholded bins of the full
     band with the same 2F bits, a flagged template keeps none and reports the
     NaN marker, and the loudest bins match."""
     from paper_2201_00451_amd import binding
-    ds = synth.small_case(seed=61, n=20000, n_fft=1 << 21, ndet=2, ntmpl=1, rho=20.0)
+    ds = synth.small_case(seed=61, n=20000, n_fft=1 << log_n, ndet=2, ntmpl=1, rho=20.0)
     tm = bank(ds, nsky=2, nf1=3, binary_rows=1)
     tm[1, 3] = np.nan
     dd = binding.DeviceData(ds, batch=4)
-    assert dd.plan.info()[2] == 11
+    assert dd.plan.info()[2] == log_n - log_n // 2
     sr = binding.Search(dd, tm, slots=4)
     full = sr.run().cpu().numpy()
     binding.sync_check()
@@ -124,7 +126,7 @@ def test_candidates_split_row_pass_at_2e21(torch_dev):
     res = sr.run_candidates(thr, capacity=1 << 14)
     binding.sync_check()
     want, _ = expected_candidates(np.where(np.isnan(full), -1.0, full), thr)
-    say(f"  2^21: threshold {thr:.2f}, {res['count']} candidates, {len(want)} expected")
+    say(f"  2^{log_n}: threshold {thr:.2f}, {res['count']} candidates, {len(want)} expected")
     assert res["count"] == len(want) > 0
     tt, bb = res["tmpl"].cpu().numpy(), res["bin"].cpu().numpy()
     got = set(zip(tt.tolist(), bb.tolist()))
