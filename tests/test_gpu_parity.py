@@ -283,13 +283,14 @@ def nearest_template(ds):
 def test_full_size_bench_workload_sampled(torch_dev):
     """The benchmark workload at full size (2 detectors x 864 000 samples,
     1000 templates, n_fft 2^21, full band), run as the benchmark runs it
-    (grouped search, 8 slots, default launch shapes): two whole templates
+    (grouped search, 32 slots: launch sequences of 30, default launch
+    shapes): two whole templates
     (2 097 152 bins each: the first one and the one nearest an injection)
     against the oracle."""
     from paper_2201_00451_amd import binding
     ds = synth.config_sky_spindown()
     dd = binding.DeviceData(ds)
-    sr = binding.Search(dd, ds.templates, slots=8)
+    sr = binding.Search(dd, ds.templates, slots=32)
     tf = sr.run()
     binding.sync_check()
     pick = [0, nearest_template(ds)]
