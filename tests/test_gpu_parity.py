@@ -318,6 +318,22 @@ def test_full_size_binary_workload_sampled(torch_dev):
     ref = O.oracle_twoF(ds, ds.templates[[t0]])[0]
     assert_2f_parity(tf[t0 - lo].cpu().numpy(), ref, f"binary workload template {t0}")
     assert ref.max() > 30.0
+    # as the benchmark runs it: grouped search (32 slots) keeping the bins
+    # above a threshold and the loudest bin, equal to the thresholded band bit
+    # for bit
+    import torch
+    thr = float(np.float32(0.5 * float(tf.max())))
+    sr = binding.Search(dd, rows, slots=32)
+    res = sr.run_candidates(thr, capacity=1 << 16)
+    binding.sync_check()
+    want = torch.nonzero(tf > thr)
+    assert res["count"] == want.shape[0] > 0
+    got = set(zip(res["tmpl"].cpu().numpy().tolist(), res["bin"].cpu().numpy().tolist()))
+    assert got == set(map(tuple, want.cpu().numpy().tolist()))
+    best, arg = torch.max(tf, dim=1)
+    assert torch.equal(res["best_twoF"], best)
+    np.testing.assert_array_equal(res["twoF"].cpu().numpy(),
+                                  tf[res["tmpl"].long(), res["bin"].long()].cpu().numpy())
 
 
 def test_autotuned_launch_shape(torch_dev):
