@@ -470,12 +470,14 @@ def config_refine(seed=5, ndays=30.0, dt=1.0, n_fft=1 << 22, f_het=400.0, band=0
 def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmpl=4, D=8,
                rho=15.0, noise=True, binary=False, gaps=False, noise_vars=None, f_inj=None,
                bin_lo=0, n_bins=None, keep_f64=False, model=None, sites=None, f1dot=None,
-               t0=0.0, noise_seed=None):
+               t0=0.0, noise_seed=None, f2dot=0.0):
     """Small search (a few hours of data) for oracle pins and quick parity.
 
     t0 shifts the data (and the computed grid) in time with the reference time
     kept at 0, so that cases with the same seed and different t0 are segments
-    of one source; noise_seed (default: seed) draws their noise independently."""
+    of one source; noise_seed (default: seed) draws their noise independently.
+    f2dot is the injection's second frequency derivative (the templates carry
+    it too)."""
     ss = np.random.SeedSequence(seed)
     s_par, s_gap = ss.spawn(2)
     rng = np.random.default_rng(s_par)
@@ -487,7 +489,8 @@ def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmp
                f=f_het + (f_inj if f_inj is not None else float(rng.uniform(-0.6, 0.6) * band)),
                f1dot=float(rng.uniform(-2e-9, 2e-9)) if f1dot is None else f1dot,
                cosi=float(rng.uniform(-1, 1)),
-               psi=float(rng.uniform(-0.7, 0.7)), phi0=float(rng.uniform(0, 6.28)), rho=rho)
+               psi=float(rng.uniform(-0.7, 0.7)), phi0=float(rng.uniform(0, 6.28)), rho=rho,
+               f2dot=float(f2dot))
     if binary:
         inj.update(asini=float(rng.uniform(0.05, 0.5)), porb=float(rng.uniform(0.2, 1.0)) * DAY,
                    tp=float(rng.uniform(0, 1e4)))
@@ -502,6 +505,7 @@ def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmp
     tm[:, 0] = inj["alpha"] + 0.02 * np.arange(ntmpl)
     tm[:, 1] = inj["delta"]
     tm[:, 3] = inj["f1dot"]
+    tm[:, 4] = inj["f2dot"]
     tm[:, 6] = 1.0
     if binary:
         tm[:, 5], tm[:, 6], tm[:, 7] = inj["asini"], inj["porb"], inj["tp"]

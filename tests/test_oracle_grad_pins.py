@@ -21,14 +21,18 @@ def fd_grad(ds, row, w, name):
             np.sum(w * O.oracle_twoF(ds, rm[None])[0])) / (2 * h)
 
 
-@pytest.mark.parametrize("binary", [False, True])
-def test_gradient_oracle_matches_oracle_and_finite_differences(binary):
+@pytest.mark.parametrize("binary,asini,f2dot", [(False, None, 0.0), (True, None, 0.0),
+                                               (True, 2e-3, 0.0), (False, None, 4e-12)])
+def test_gradient_oracle_matches_oracle_and_finite_differences(binary, asini, f2dot):
+    """asini = 2e-3 ls: a barely binary template, where the orbit derivatives
+    are real and small; f2dot != 0: the held-fixed second spin-down term
+    enters the phase the derivatives are taken through."""
     ds = synth.small_case(seed=51, n=3000, n_fft=1 << 13, ndet=2, binary=binary, gaps=True,
-                          rho=20)
+                          rho=20, f2dot=f2dot)
     row = ds.templates[0].copy()
     row[0] += 0.002
     if binary:
-        row[5] *= 1.001
+        row[5] = asini if asini is not None else row[5] * 1.001
     tf_np = O.oracle_twoF(ds, row[None])[0]
     w = np.zeros(ds.n_bins)
     ipk = int(np.argmax(tf_np))
@@ -42,3 +46,5 @@ def test_gradient_oracle_matches_oracle_and_finite_differences(binary):
             continue
         fd = fd_grad(ds, row, w, name)
         assert abs(g[i] - fd) <= 1e-4 * abs(fd) + 1e-9, (name, g[i], fd)
+        if asini is not None and name == "asini":
+            assert abs(fd) > 1e-2   # a real, non-vanishing derivative

@@ -253,6 +253,57 @@ def test_spindown_reference_time_shift():
     np.testing.assert_allclose(moved[shift_bins:], ref[:-shift_bins], rtol=1e-8, atol=1e-8)
 
 
+def test_second_spindown_term_noiseless_rho2():
+    """Phi_s carries the second frequency derivative as f2dot (tau - t_ref)^3 / 6
+    (Sec. 2: Phi_s is the Taylor series in the f^(k)).  The generator injects
+    a source whose cubic term moves its phase by about 1.7 cycles over the
+    data; at the injected parameters the noiseless direct sum recovers the
+    optimal rho^2 exactly, which a wrong Taylor factor (or a dropped cubic)
+    does not."""
+    ds = synth.small_case(seed=61, n=5000, n_fft=1 << 14, ndet=2, noise=False, keep_f64=True,
+                          f2dot=1e-11, gaps=True)
+    inj = ds.injections[0]
+    tm = O.template_dict(ds.templates[0])
+    assert tm["f2dot"] == 1e-11
+    v = O.direct_twoF(ds, tm, [inj["f"]])[0]
+    assert abs(v / inj["rho2"] - 1) < 1e-11
+    # the resampled series recovers it too (interpolation loss only)
+    tm["df"], ipk = on_bin(ds, inj["f"])
+    Fa, Fb = O.fa_fb(ds, tm)
+    A, B, C = O.antenna_matrix(ds.ephem_model, ds.detectors, ds.valid, tm["alpha"], tm["delta"],
+                               ds.dt)
+    tf = O.two_f(Fa, Fb, A, B, C)
+    assert int(np.argmax(tf)) == ipk
+    assert abs(tf[ipk] / inj["rho2"] - 1.0) < 5e-3
+    # without the cubic term the template loses most of the signal
+    tm0 = dict(tm, f2dot=0.0)
+    assert O.direct_twoF(ds, tm0, [inj["f"]])[0] < 0.5 * inj["rho2"]
+
+
+def test_spindown_reference_time_shift_with_f2dot():
+    """Re-expanding the Taylor series about t_ref + s: with x = tau - t_ref - s,
+    f1dot (x + s)^2 / 2 + f2dot (x + s)^3 / 6 = f2dot x^3 / 6
+    + (f1dot + f2dot s) x^2 / 2 + (f1dot s + f2dot s^2 / 2) x + const, so the
+    template (f1dot + f2dot s, f2dot) about t_ref + s sees the spectrum of
+    (f1dot, f2dot) about t_ref moved up by f1dot s + f2dot s^2 / 2 in
+    frequency (closed form; s is chosen to make that a whole number of bins)."""
+    ds = synth.small_case(seed=62, n=3000, n_fft=1 << 13, noise=True, f1dot=0.0)
+    f1, f2 = 2.0e-10, 1.2e-11
+    m = 7
+    width = 1.0 / (ds.n_fft * ds.dt)
+    # f1 s + f2 s^2 / 2 = m width
+    s = (-f1 + math.sqrt(f1 * f1 + 2.0 * f2 * m * width)) / f2
+    assert f2 * s * (ds.detectors[0].n * ds.dt) ** 2 > 1.0   # the cubic matters
+    row = ds.templates[0].copy()
+    row[3], row[4] = f1, f2
+    ref = O.oracle_twoF(ds, row[None])[0]
+    row2 = row.copy()
+    row2[3] = f1 + f2 * s
+    ds.t_ref += s
+    moved = O.oracle_twoF(ds, row2[None])[0]
+    np.testing.assert_allclose(moved[m:], ref[:-m], rtol=1e-8, atol=1e-8)
+
+
 def test_detector_permutation_and_duplication():
     ds = synth.small_case(seed=28, n=3000, n_fft=1 << 13, ndet=2, noise=True, noise_vars=[0.8, 1.1])
     ref = O.oracle_twoF(ds, ds.templates[:1])[0]
