@@ -38,7 +38,9 @@ typedef enum {
   FSTAT_EINVAL = -1,       /* an argument is invalid (null, out of range, inconsistent) */
   FSTAT_EUNSUPPORTED = -2, /* valid, but outside what this library implements */
   FSTAT_EWORKSPACE = -3,   /* workspace smaller than fstat_workspace_size() */
-  FSTAT_EHIP = -4          /* the HIP runtime reported an error */
+  FSTAT_EHIP = -4,         /* the HIP runtime reported an error */
+  FSTAT_EINTERNAL = -5     /* an inconsistency inside the library (no kernel for a shape
+                              the plan accepted); nothing was launched */
 } fstat_status;
 
 /* One detector: its site (for a(t), b(t) of Sec. 2 and the Roemer delay t_m)
@@ -202,8 +204,10 @@ FSTAT_API fstat_status fstat_compute_2f_profiled(const fstat_plan* plan, const f
  * with `slots` (1..32) templates in flight per launch sequence; flags may
  * combine FSTAT_SEARCH_GRAPH: the run functions capture their launch sequence
  * in a HIP graph on the first call and replay it while the arguments it was
- * captured with (inputs, templates, outputs, threshold, workspace) stay the
- * same (needs a non-null stream); and FSTAT_SEARCH_ACCUMULATE:
+ * captured with stay the same (needs a non-null stream): every device
+ * pointer and scalar of the inputs that the plan's detectors use (x, valid,
+ * ephem, n_eph, eph_t0, eph_dt, moments), the templates, outputs, threshold
+ * and workspace; any other value captures again; and FSTAT_SEARCH_ACCUMULATE:
  * fstat_search_run adds 2F to twoF instead of storing it, so that runs over
  * several data segments with the same grid (dt, n_fft, f_het, t_ref, band)
  * sum 2F over the segments on the device (the semi-coherent sum the paper's
@@ -257,8 +261,9 @@ FSTAT_API fstat_status fstat_search_run_profiled(fstat_search* search, const fst
  * with FSTAT_SEARCH_ACCUMULATE), workspaces of at least fstat_search_info's
  * size, and their sizes.  The first call captures every search's launch
  * sequence into one HIP graph (fork on `stream`, one branch per lane, join
- * back on `stream`) and later calls with the same pointers replay it; other
- * pointers recapture.  Each search's FSTAT_SEARCH_GRAPH flag is not used
+ * back on `stream`) and later calls with the same arguments (every pointer
+ * and scalar of every search's inputs, as for FSTAT_SEARCH_GRAPH, and the
+ * templates, outputs and workspaces) replay it; any other value recaptures.  Each search's FSTAT_SEARCH_GRAPH flag is not used
  * here.  Needs a non-null stream; runs asynchronously on it.  Each output is
  * the one fstat_search_run gives for that search alone, bit for bit.
  * Searches of one batch must not share a workspace or an output. */
@@ -342,6 +347,20 @@ FSTAT_API fstat_status fstat_compute_2f_grad_bin(const fstat_plan* plan, const f
                                                  const double* templates, int64_t ntmpl,
                                                  const int64_t* bins, float* twoF, double* grad,
                                                  void* workspace, size_t ws_bytes, void* stream);
+
+/* Templates whose outputs the last call on `workspace` set to NaN (any
+ * status bit: parameters not finite or out of range, delays beyond
+ * max_delay, a tile's input window beyond the staging capacity, a bin
+ * outside the band).  Every compute call clears the count in its first
+ * kernel and counts each such template once: fstat_compute_2f, _batched,
+ * _profiled, fstat_search_run, _run_candidates, _run_profiled, each
+ * search's own workspace after fstat_batch_run, fstat_compute_2f_grad and
+ * fstat_compute_2f_grad_bin.  (The paper's problem statement has one 2F per
+ * template and bin; a NaN row is this library's report of a template it
+ * cannot evaluate.)  Waits for the stream, then writes the count to the host
+ * int64 *count. */
+FSTAT_API fstat_status fstat_flagged_count(const void* workspace, size_t ws_bytes, void* stream,
+                                           int64_t* count);
 
 /* Wait for the stream and report any asynchronous HIP error as FSTAT_EHIP. */
 FSTAT_API fstat_status fstat_sync_check(void* stream);

@@ -309,6 +309,24 @@ def oracle_twoF(ds, templates=None, return_fafb=False):
     return (out, fafb) if return_fafb else out
 
 
+def twoF_at_bin(ds, row, i):
+    """2F of one template at band bin i only: steps (iii)-(v) as in
+    resampled_series, then step (vi) restricted to that one output bin, the
+    DFT sum F[m] = sum_k y_k exp(-2 pi i m k / n_fft) at the natural index m
+    of band bin i (no FFT), then eq. Fstat.  Cost O(n_fft) after the
+    resampling, for checks at sizes where a full transform per evaluation is
+    not wanted."""
+    tm = template_dict(row)
+    ya, yb = resampled_series(ds, tm)
+    m = (ds.bin_lo + int(i) + ds.n_fft // 2) % ds.n_fft
+    k = np.arange(ds.n_fft)
+    e = np.exp(-1j * TWO_PI * ((m * k) % ds.n_fft) / ds.n_fft)
+    Fa, Fb = np.sum(ya * e), np.sum(yb * e)
+    A, B, C = antenna_matrix(ds.ephem_model, ds.detectors, ds.valid, tm["alpha"], tm["delta"],
+                             ds.dt)
+    return float(two_f(Fa, Fb, A, B, C))
+
+
 # ----------------------------------------------------------------------------
 # Direct sum: eqs. Fa_DET, Fb_DET of Sec. 2 discretised over the samples
 # ----------------------------------------------------------------------------

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfstat.so
 MAX_DET = 4
 TEMPLATE_STRIDE = 8
 
-FSTAT_OK, FSTAT_EINVAL, FSTAT_EUNSUPPORTED, FSTAT_EWORKSPACE, FSTAT_EHIP = 0, -1, -2, -3, -4
+FSTAT_OK, FSTAT_EINVAL, FSTAT_EUNSUPPORTED, FSTAT_EWORKSPACE, FSTAT_EHIP, FSTAT_EINTERNAL = \
+    0, -1, -2, -3, -4, -5
 
 EXPORTED = ("fstat_plan_create", "fstat_plan_destroy", "fstat_workspace_size",
             "fstat_antenna_moments", "fstat_compute_2f", "fstat_compute_2f_batched",
@@ -26,7 +27,7 @@ EXPORTED = ("fstat_plan_create", "fstat_plan_destroy", "fstat_workspace_size",
             "fstat_grad_workspace_size", "fstat_compute_2f_grad", "fstat_plan_info",
             "fstat_grad_bin_workspace_size", "fstat_compute_2f_grad_bin", "fstat_autotune",
             "fstat_search_run_candidates", "fstat_batch_create", "fstat_batch_destroy",
-            "fstat_batch_run")
+            "fstat_batch_run", "fstat_flagged_count")
 GRAD_PARAMS = ("df", "f1dot", "alpha", "delta", "asini", "porb", "tp")
 # template-row column of each gradient parameter
 GRAD_COLUMNS = (2, 3, 0, 1, 5, 6, 7)
@@ -120,6 +121,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fstat_batch_run.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(FstatInputs)),
                                     ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.POINTER(sz), vp]
+    lib.fstat_flagged_count.argtypes = [vp, sz, vp, ctypes.POINTER(i64)]
     lib.fstat_sync_check.argtypes = [vp]
     lib.fstat_last_error.restype = ctypes.c_char_p
     lib.fstat_last_error.argtypes = []
@@ -463,6 +465,15 @@ def autotune(ds, templates, batch=8, device="cuda:0", stream=None):
                                          _stream_ptr(stream), ctypes.byref(best),
                                          ctypes.byref(ms)))
     return {k: int(getattr(best, k)) for k in TUNE_FIELDS}, float(ms.value)
+
+
+def flagged_count(ws, stream=None) -> int:
+    """Templates whose outputs the last call on workspace tensor ``ws`` set
+    to NaN (fstat_flagged_count; synchronises the stream)."""
+    n = ctypes.c_int64()
+    _check(load_library().fstat_flagged_count(_ptr(ws), ws.numel(), _stream_ptr(stream),
+                                              ctypes.byref(n)))
+    return int(n.value)
 
 
 def sync_check(stream=None):

@@ -397,6 +397,11 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
     hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, ws);
   }
   const int n_res = grouped ? map.n_grp : n;
+  const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), grouped);
+  const FftVariant rv = pick_rows(p->log_c, rows_choice(p), forward_row_mode(out));
+  if (!resample_kernel(p->desc.sinc_halfwidth, grouped) || !cv.fn || !rv.fn)
+    return fail(FSTAT_EINTERNAL, "no kernel for D=%d, FFT lines 2^%d x 2^%d",
+                p->desc.sinc_halfwidth, p->log_rr, p->log_c);
   if (n_res > 0) {
     if ((s = tm.open(1)) != FSTAT_OK) return s;
     hipLaunchKernelGGL(resample_kernel(p->desc.sinc_halfwidth, grouped),
@@ -408,8 +413,6 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
     hipLaunchKernelGGL(k_copy_series, dim3(256, n), dim3(256), 0, st, P, ws, map, y_out);
     return check_hip(hipGetLastError(), "resample launch");
   }
-  const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), grouped);
-  const FftVariant rv = pick_rows(p->log_c, rows_choice(p), forward_row_mode(out));
   if ((s = tm.open(2)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn)),
                      dim3(fft_grid(cols_items(p, cv, n))), dim3(cv.threads), cv.lds, st, P, ws, map,
@@ -450,11 +453,13 @@ fstat_status set_lds_limits(const fstat_plan* p) {
   hipError_t e = hipSuccess;
   for (bool grouped : {false, true}) {
     const FftVariant v = pick_cols(p->log_rr, cols_choice(p), grouped);
+    if (!v.fn) return fail(FSTAT_EINTERNAL, "no column kernel for lines of 2^%d", p->log_rr);
     e = hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(v.lds));
     if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(cols)");
   }
   for (int mode : {int(kRow2F), int(kRowAdjoint), int(kRowConj), int(kRow2FExt), int(kRowCand)}) {
     const FftVariant v = pick_rows(p->log_c, rows_choice(p), mode);
+    if (!v.fn) return fail(FSTAT_EINTERNAL, "no row kernel for lines of 2^%d", p->log_c);
     e = hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(v.lds));
     if (e != hipSuccess) return check_hip(e, "hipFuncSetAttribute(rows)");
   }
@@ -609,9 +614,8 @@ struct fstat_search {
   int64_t ntmpl, ngroups;
   std::vector<ChunkMap> chunks;
   // captured launch sequence and the arguments it was captured with
-  static constexpr int kKey = 13;
   hipGraphExec_t exec = nullptr;
-  uint64_t key[kKey] = {};
+  std::vector<uint64_t> key;
   ~fstat_search() {
     if (exec) (void)hipGraphExecDestroy(exec);
   }
@@ -638,6 +642,27 @@ struct fstat_batch {
 };
 
 namespace {
+
+uint64_t key_ptr(const void* q) { return uint64_t(reinterpret_cast<uintptr_t>(q)); }
+uint64_t key_f64(double v) {
+  uint64_t b;
+  std::memcpy(&b, &v, sizeof b);
+  return b;
+}
+// Everything of the inputs that a captured launch sequence bakes into its
+// kernel arguments (make_const): the device pointers and ephemeris scalars
+// of the plan's detectors and the moments.
+void inputs_key(const fstat_plan* p, const fstat_inputs* in, std::vector<uint64_t>& key) {
+  for (int X = 0; X < p->desc.ndet; ++X) {
+    key.push_back(key_ptr(in->x[X]));
+    key.push_back(key_ptr(in->valid[X]));
+    key.push_back(key_ptr(in->ephem[X]));
+  }
+  key.push_back(uint64_t(in->n_eph));
+  key.push_back(key_f64(in->eph_t0));
+  key.push_back(key_f64(in->eph_dt));
+  key.push_back(key_ptr(in->moments));
+}
 
 // Templates with the same sky position and orbit share the resampled series;
 // an isolated source (asini = 0) ignores porb and tp.
@@ -709,23 +734,14 @@ fstat_status search_run_out(fstat_search* search, const fstat_inputs* in,
   if (!st) return fail(FSTAT_EINVAL, "graph replay needs a non-null stream");
   uint32_t thr = 0;
   std::memcpy(&thr, &out.threshold, sizeof thr);
-  const uint64_t key[fstat_search::kKey] = {
-      uint64_t(reinterpret_cast<uintptr_t>(in->x[0])),
-      uint64_t(reinterpret_cast<uintptr_t>(in->moments)),
-      uint64_t(reinterpret_cast<uintptr_t>(templates)),
-      uint64_t(reinterpret_cast<uintptr_t>(out.twoF)),
-      uint64_t(reinterpret_cast<uintptr_t>(out.fafb)),
-      uint64_t(reinterpret_cast<uintptr_t>(out.cand)),
-      uint64_t(reinterpret_cast<uintptr_t>(out.count)),
-      uint64_t(reinterpret_cast<uintptr_t>(out.best)),
-      uint64_t(out.cap),
-      uint64_t(thr) | (uint64_t(out.acc) << 32),
-      uint64_t(reinterpret_cast<uintptr_t>(workspace)),
-      uint64_t(ws_bytes),
-      1};
-  bool same = search->exec != nullptr;
-  for (int i = 0; i < fstat_search::kKey && same; ++i) same = key[i] == search->key[i];
-  if (!same) {
+  std::vector<uint64_t> key;
+  inputs_key(search->plan, in, key);
+  for (uint64_t v : {key_ptr(templates), key_ptr(out.twoF), key_ptr(out.fafb), key_ptr(out.cand),
+                     key_ptr(out.count), key_ptr(out.best), uint64_t(out.cap),
+                     uint64_t(thr) | (uint64_t(out.acc) << 32), key_ptr(workspace),
+                     uint64_t(ws_bytes)})
+    key.push_back(v);
+  if (!search->exec || key != search->key) {
     if (search->exec) {
       (void)hipGraphExecDestroy(search->exec);
       search->exec = nullptr;
@@ -743,7 +759,7 @@ fstat_status search_run_out(fstat_search* search, const fstat_inputs* in,
     e = hipGraphInstantiate(&search->exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if ((s = check_hip(e, "graph instantiate")) != FSTAT_OK) return s;
-    for (int i = 0; i < fstat_search::kKey; ++i) search->key[i] = key[i];
+    search->key = key;
   }
   s = check_hip(hipGraphLaunch(search->exec, st), "graph launch");
   return s == FSTAT_OK ? ok() : s;
@@ -921,17 +937,16 @@ fstat_status fstat_batch_run(fstat_batch* b, const fstat_inputs* const* in,
   if (!st) return fail(FSTAT_EINVAL, "a batch runs from a graph: it needs a non-null stream");
   const int n = int(b->searches.size());
   std::vector<uint64_t> key;
-  key.reserve(size_t(n) * 6);
+  key.reserve(size_t(n) * 24);
   for (int i = 0; i < n; ++i) {
     if (!in[i]) return fail(FSTAT_EINVAL, "inputs %d is NULL", i);
     fstat_status s = search_check(b->searches[i], in[i], templates[i], twoF[i] != nullptr,
                                   workspace[i], ws_bytes[i]);
     if (s != FSTAT_OK) return s;
-    key.push_back(uint64_t(reinterpret_cast<uintptr_t>(in[i]->x[0])));
-    key.push_back(uint64_t(reinterpret_cast<uintptr_t>(in[i]->moments)));
-    key.push_back(uint64_t(reinterpret_cast<uintptr_t>(templates[i])));
-    key.push_back(uint64_t(reinterpret_cast<uintptr_t>(twoF[i])));
-    key.push_back(uint64_t(reinterpret_cast<uintptr_t>(workspace[i])));
+    inputs_key(b->searches[i]->plan, in[i], key);
+    key.push_back(key_ptr(templates[i]));
+    key.push_back(key_ptr(twoF[i]));
+    key.push_back(key_ptr(workspace[i]));
     key.push_back(uint64_t(ws_bytes[i]));
   }
   int dev = 0;
@@ -1289,6 +1304,8 @@ fstat_status fstat_compute_2f_grad_bin(const fstat_plan* plan, const fstat_input
   P.slot_stride = int64_t(sb);
   P.part_offset = int64_t(kParamBytes);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  // (clears the flagged-template counter)
+  hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, workspace);
   for (int64_t t = 0; t < ntmpl; t += slots) {
     ChunkMap map;
     std::memset(&map, 0, sizeof map);
@@ -1298,6 +1315,23 @@ fstat_status fstat_compute_2f_grad_bin(const fstat_plan* plan, const fstat_input
                               st);
     if (s != FSTAT_OK) return s;
   }
+  return ok();
+}
+
+fstat_status fstat_flagged_count(const void* workspace, size_t ws_bytes, void* stream,
+                                 int64_t* count) {
+  if (!workspace || !count) return fail(FSTAT_EINVAL, "workspace or count is NULL");
+  if (ws_bytes < kHeaderBytes)
+    return fail(FSTAT_EWORKSPACE, "workspace %zu bytes < %zu", ws_bytes, kHeaderBytes);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned long long v = 0;
+  fstat_status s = check_hip(
+      hipMemcpyAsync(&v, flag_counter(const_cast<void*>(workspace)), sizeof v,
+                     hipMemcpyDeviceToHost, st),
+      "flagged count copy");
+  if (s == FSTAT_OK) s = check_hip(hipStreamSynchronize(st), "flagged count synchronise");
+  if (s != FSTAT_OK) return s;
+  *count = int64_t(v);
   return ok();
 }
 

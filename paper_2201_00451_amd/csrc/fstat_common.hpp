@@ -153,6 +153,13 @@ constexpr size_t kHeaderBytes = kTwOffset + 3 * kTwLen * sizeof(float2) + 4096;
 __host__ __device__ inline float2* tw_stage(void* ws) {
   return reinterpret_cast<float2*>(static_cast<char*>(ws) + kTwOffset);
 }
+// In the reserved space: the number of templates of the current call whose
+// outputs are NaN (cleared by the first kernel of every call, counted once
+// per template by the row pass or the single-bin reduction).
+constexpr size_t kFlagOffset = kTwOffset + 3 * kTwLen * sizeof(float2);
+__host__ __device__ inline unsigned long long* flag_counter(void* ws) {
+  return reinterpret_cast<unsigned long long*>(static_cast<char*>(ws) + kFlagOffset);
+}
 
 // Workspace: header (moment partials, twiddles), then template slots of
 // [TmplParams | narr arrays of n_fft float2 | extra bytes], narr = 2 for the
@@ -501,8 +508,11 @@ __host__ __device__ inline void spindown_coefficients(const PlanConst& P, double
   // with d0 = tau0 - t_ref and s = dt k, in cycles:
   //   f1dot (d0 + s)^2 / 2 + f2dot (d0 + s)^3 / 6 + df s
   // stored times 4 (quarter turns; the scaling by 4 is exact)
+  // The constant term is reduced modulo one turn (exactly: fmod rounds
+  // nothing), so that the quarter-turn count of the evaluated cubic stays far
+  // inside 32 bits even for a reference time years away from the grid.
   const double d0 = P.tau0 - P.t_ref, dt = P.dt;
-  sd[0] = 4.0 * (f1dot * d0 * d0 * 0.5 + f2dot * d0 * d0 * d0 * (1.0 / 6.0));
+  sd[0] = fmod(4.0 * (f1dot * d0 * d0 * 0.5 + f2dot * d0 * d0 * d0 * (1.0 / 6.0)), 4.0);
   sd[1] = 4.0 * (dt * (f1dot * d0 + f2dot * d0 * d0 * 0.5 + df));
   sd[2] = 4.0 * (dt * dt * (f1dot * 0.5 + f2dot * d0 * 0.5));
   sd[3] = 4.0 * (dt * dt * dt * f2dot * (1.0 / 6.0));

@@ -200,8 +200,10 @@ __device__ __forceinline__ void fft_middle(float2* buf, const float2* twl, int t
 
 // FP32 stage twiddle table W_4096^e from FP64, written at the start of every
 // call; each FFT workgroup copies the W_L^e, e < L/2, it needs into LDS.
+// It also clears the call's flagged-template counter.
 __global__ void k_twiddles(void* ws) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) *flag_counter(ws) = 0ull;
   if (e >= kTwLen) return;
   double s, c;
   sincospi(-2.0 * double(e) / double(kTwLen), &s, &c);
@@ -507,13 +509,14 @@ __device__ __forceinline__ float rows_out(const PlanConst& P, void* ws, const Ro
 }
 
 // A flagged template: NaN in every bin the item owns (and the all-ones
-// marker in its best entry).
+// marker in its best entry); the template's first row group counts it.
 template <int LOGL, int RQ, int NT>
-__device__ __forceinline__ void rows_flagged(const PlanConst& P, const RowItem& it, int64_t Rr,
-                                             const RowOutput& out) {
+__device__ __forceinline__ void rows_flagged(const PlanConst& P, void* ws, const RowItem& it,
+                                             int64_t Rr, const RowOutput& out) {
   constexpr int L = 1 << LOGL;
   const int64_t N = P.n_fft;
   const float qnan = __builtin_nanf("");
+  if (it.q0 == 0 && threadIdx.x == 0) atomicAdd(flag_counter(ws), 1ull);
   if (out.best && threadIdx.x == 0) atomicMax(out.best + it.tmpl, ~0ull);
   for (int e = threadIdx.x; e < L * RQ; e += NT) {
     const int ql = e % RQ, p = e / RQ;
@@ -552,7 +555,7 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
   }
   const RowItem it =
       rows_item<MODE>(P, ws, map, int(xcd_remap(blockIdx.x, gridDim.x)), int(Rr / RQ), RQ);
-  if (it.flagged && MODE != kRowConj) rows_flagged<LOGL, RQ, NT>(P, it, Rr, out);
+  if (it.flagged && MODE != kRowConj) rows_flagged<LOGL, RQ, NT>(P, ws, it, Rr, out);
   if (!it.live) return;
   {
     float2 v[PER0][R0];
@@ -650,7 +653,7 @@ __global__ __launch_bounds__(NT, NT / 128) void k_fft_rows_split(PlanConst P, vo
   }
   const RowItem it =
       rows_item<MODE>(P, ws, map, int(xcd_remap(blockIdx.x, gridDim.x)), int(Rr / RQ), RQ);
-  if (it.flagged) rows_flagged<LOGL, RQ, NT>(P, it, Rr, out);
+  if (it.flagged) rows_flagged<LOGL, RQ, NT>(P, ws, it, Rr, out);
   if (!it.live) return;
   const auto tf = buf_rsrc(MODE == kRow2F ? out.twoF + it.tmpl * P.n_bins : nullptr,
                            MODE == kRow2F ? uint32_t(P.n_bins * int64_t(sizeof(float))) : 0u);

@@ -136,8 +136,10 @@ __host__ __device__ inline void template_params(const PlanConst& P, const double
   double porb = row[6];
   tp.tp = row[7];
   int status = 0;
+  // porb and tp describe the orbit only when asini != 0: an isolated
+  // source (asini = 0) ignores them, whatever they hold
   if (!__builtin_isfinite(alpha) || !__builtin_isfinite(delta) || !__builtin_isfinite(tp.asini) ||
-      !__builtin_isfinite(porb) || !__builtin_isfinite(tp.tp))
+      (tp.asini != 0.0 && (!__builtin_isfinite(porb) || !__builtin_isfinite(tp.tp))))
     status |= kStatusTiming;
   if (!__builtin_isfinite(tp.df) || !__builtin_isfinite(tp.f1dot) ||
       !__builtin_isfinite(tp.f2dot))

@@ -285,7 +285,17 @@ __global__ __launch_bounds__(kResThreads, 4) void k_resample(PlanConst P, void* 
   float2* yb = GROUPED ? group_buf(ws, P, slots, map.grp_buf[gi], 1)
                        : slot_buf(ws, P, slot, 1);
   const int64_t k_s = int64_t(blockIdx.x) * kResTile;
-  if ((GROUPED ? (tp.status & kStatusGroupMask) : tp.status) != 0) return;
+  if (GROUPED) {
+    // a leader whose sky or orbit is invalid invalidates the whole group:
+    // its status word tells every member's column pass not to read the buffer
+    const int32_t gflag = tp.status & kStatusGroupMask;
+    if (gflag != 0) {
+      if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(status_word, gflag);
+      return;
+    }
+  } else if (tp.status != 0) {
+    return;
+  }
   float2 acc_a[kResPerThread], acc_b[kResPerThread];
   if (!resample_tile<D>(P, tp, status_word, k_s, acc_a, acc_b)) return;
 #pragma unroll
@@ -372,6 +382,7 @@ __global__ void k_bin_final(PlanConst P, void* ws, ChunkMap map, int64_t ntiles,
   const double* part = slot_partials(ws, P, slot);
   const int64_t bin = bins[map.tmpl[slot]];
   if (bin < 0 || bin >= P.n_bins) tp.status |= kStatusBin;
+  if (tp.status != 0) atomicAdd(flag_counter(ws), 1ull);
   double f[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t b = 0; b < ntiles; ++b)
     for (int q = 0; q < 4; ++q) f[q] += part[b * 8 + q];

@@ -517,7 +517,8 @@ def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmp
 
 
 def config_uneven(seed=4, n_search=256, days=(1.0, 30.0), dts=(0.5, 1.0, 2.0, 5.0),
-                  max_log_n=22, ntmpl=(8, 64), f_het=(50.0, 1000.0), D=8, noise=True):
+                  max_log_n=22, ntmpl=(8, 64), f_het=(50.0, 1000.0), D=8, noise=True,
+                  pick=None):
     """Independent searches of uneven shape for batched serving: per search a
     span log-uniform in `days`, dt from `dts`, one or two detectors, a
     heterodyne frequency uniform in `f_het`, n_fft the power of two >= twice
@@ -525,7 +526,9 @@ def config_uneven(seed=4, n_search=256, days=(1.0, 30.0), dts=(0.5, 1.0, 2.0, 5.
     one injection (rho U(10, 30)) and a template count uniform in `ntmpl`:
     even searches a spin-down grid at the injection's sky position, odd ones
     a circular-binary lattice around the injection's orbit.  Returns a list of
-    Datasets."""
+    Datasets; with ``pick`` (indices) only those searches are built, the same
+    as in the full list (every search's parameters are still drawn in order
+    and its data has a seed of its own)."""
     rng = np.random.default_rng(np.random.SeedSequence(seed))
     out = []
     for k in range(n_search):
@@ -561,6 +564,8 @@ def config_uneven(seed=4, n_search=256, days=(1.0, 30.0), dts=(0.5, 1.0, 2.0, 5.
             inj["f1dot"] = float(rng.uniform(-1e-10, 1e-10))
             tm[:, 3] = inj["f1dot"] + 2e-11 * (np.arange(nt) - (nt - 1) / 2.0)
             tm[:, 6] = 1.0
+        if pick is not None and k not in pick:
+            continue
         xs, vs = make_data(dets, dt, fh, 0.0, [inj], seed * 1000 + k, noise=noise)
         ds = Dataset(f"uneven{k}", dt, fh, 0.0, grid_origin(0.0, dt, 512.0 + max_a), n_fft, D, 0,
                      n_fft, dets, xs, vs, tm, injections=[inj])

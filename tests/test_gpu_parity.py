@@ -70,6 +70,13 @@ CASES = {
     "n_fft_2e12": dict(seed=37, n=1200, n_fft=1 << 12, ndet=1, dt=2.0),
     "n_fft_2e16": dict(seed=38, n=20000, n_fft=1 << 16, ndet=2, dt=2.0),
     "three_det": dict(seed=39, n=3000, n_fft=1 << 13, ndet=3, noise_vars=[1.0, 0.7, 1.4]),
+    # the other accepted interpolation half-widths
+    "d6": dict(seed=61, n=5000, n_fft=1 << 13, ndet=1, D=6),
+    "d10": dict(seed=62, n=5000, n_fft=1 << 13, ndet=2, D=10, binary=True, gaps=True),
+    "d16": dict(seed=63, n=5000, n_fft=1 << 14, ndet=2, D=16, gaps=True),
+    # the second spin-down term: f2dot T^3 / 6 is about 5 cycles over the data
+    "f2dot": dict(seed=64, n=7000, n_fft=1 << 14, ndet=2, gaps=True, f2dot=1.1e-11),
+    "f2dot_binary": dict(seed=65, n=7000, n_fft=1 << 14, ndet=2, binary=True, f2dot=-1.1e-11),
 }
 
 
@@ -351,3 +358,30 @@ def test_autotuned_launch_shape(torch_dev):
     ref = O.oracle_twoF(ds)
     for i in range(ds.ntmpl):
         assert_2f_parity(got[i], ref[i], f"autotuned tmpl {i}")
+
+
+def test_second_spindown_term_grouped_and_peak(torch_dev):
+    """f2dot moving the phase by several cycles over the data: a sky group of
+    templates that differ only in f2dot (one shared resampled series, each
+    template's cubic spin-down phase applied as the column pass loads it)
+    equals the per-template path bit for bit and the oracle to the bar, and
+    the template at the injected f2dot recovers the injection."""
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(**dict(CASES["f2dot"], ntmpl=1))
+    inj = ds.injections[0]
+    T = ds.detectors[0].n * ds.dt
+    rows = np.repeat(ds.templates[:1], 5, axis=0)
+    rows[:, 4] = inj["f2dot"] + (np.arange(5) - 2) * 6.0 / T ** 3
+    dd = binding.DeviceData(ds)
+    plain = binding.compute_2f(dd, rows).cpu().numpy()
+    sr = binding.Search(dd, rows, slots=4)
+    assert sr.ngroups == 1
+    got = sr.run().cpu().numpy()
+    binding.sync_check()
+    np.testing.assert_array_equal(got, plain)
+    ref = O.oracle_twoF(ds, rows[[0, 2]])
+    assert_2f_parity(got[0], ref[0], "f2dot off by -12 cycles T^-3")
+    assert_2f_parity(got[2], ref[1], "f2dot at the injection")
+    say(f"  peak 2F by f2dot offset: {np.round(got.max(axis=1), 2)}; rho^2 {inj['rho2']:.1f}")
+    assert int(np.argmax(got.max(axis=1))) == 2
+    assert got[2].max() > 0.8 * inj["rho2"]

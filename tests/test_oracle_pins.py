@@ -382,3 +382,14 @@ def test_accuracy_metrics_closed_forms():
     assert O.rel_err([1.0, 2.0], [1.0, 2.0], 2) == 0.0
     assert abs(O.rel_err([3.0, 0.0], [0.0, 4.0], 1) - 2 * 7.0 / 7.0) < 1e-15
     assert abs(O.rel_err([3.0, 0.0], [0.0, 4.0], 2) - 2 * 5.0 / 7.0) < 1e-15
+
+
+def test_single_bin_2f_equals_full_transform():
+    """2F at one bin from the DFT sum at that bin equals the FFT band's bin
+    (two different evaluations of step (vi)), also in a sub-band."""
+    ds = synth.small_case(seed=17, n=2000, n_fft=1 << 12, ndet=2, binary=True, gaps=True,
+                          ntmpl=1, bin_lo=700, n_bins=1500)
+    row = ds.templates[0]
+    full = O.oracle_twoF(ds, row[None])[0]
+    for i in (0, 3, int(np.argmax(full)), ds.n_bins - 1):
+        assert abs(O.twoF_at_bin(ds, row, i) - full[i]) <= 1e-9 * max(1.0, full[i])
