@@ -18,8 +18,9 @@ light-seconds):
 
 * Roemer delay (Sec. 2, t_b = t + t_m): t_b = t + r_X(t) . n, with r_X the
   detector position and n the unit vector towards the source.
-* Circular binary (reading: e = 0, Roemer term only): t_b = t_src + R(t_src),
-  R(t') = asini sin(2 pi (t' - tp) / porb).
+* Binary (reading: Roemer term only): t_b = t_src + R(t_src), circular
+  R(t') = asini sin(2 pi (t' - tp) / porb), or Keplerian with eccentricity
+  and argument of periapsis (binary_delay).
 * Spin-down phase (Sec. 2, Phi_s is a Taylor series in f^(k), k >= 1):
   Phi_s(tau) = 2 pi [f1dot (tau - t_ref)^2 / 2 + f2dot (tau - t_ref)^3 / 6].
 * Output bin i in [0, n_fft) has frequency f_het + df + (i - n_fft/2)/(n_fft dt).
@@ -36,6 +37,49 @@ import math
 import numpy as np
 
 TWO_PI = 2.0 * math.pi
+
+
+# ----------------------------------------------------------------------------
+# Steps (i)-(ii) of Sec. 3: SFTs to the heterodyned, downsampled series
+# ----------------------------------------------------------------------------
+
+def sfts_to_series(sfts, present, k0, t_sft, t_start):
+    """x_h(t) on t = t_start + n dt from short Fourier transforms (reading of
+    steps (i)-(ii), which the paper leaves to existing code).
+
+    SFT s covers [t_s, t_s + t_sft), t_s = t_start + s t_sft, and holds the K
+    bins k = k0 .. k0 + K - 1 (frequency k / t_sft) of the segment's DFT with
+    the time-step normalisation X_s[k] = dt_raw sum_n r(t_s + n dt_raw)
+    exp(-2 pi i k n / N_sft).  Combining the SFTs into one transform of the
+    whole span and keeping the band [k0, k0 + K) / t_sft is the low-pass of
+    step (ii); with f_h = (k0 + K/2) / t_sft at the band's centre and
+    dt = t_sft / K, the inverse transform over the band, heterodyned by
+    exp(-2 pi i f_h t), is, sample by sample,
+
+      x_h(t_s + j dt) = (1 / t_sft) sum_q X_s[k0 + q]
+                        exp(2 pi i (k0 + q) j / K) exp(-2 pi i f_h (t_s + j dt)),
+
+    which this function evaluates literally (a K x K sum per SFT, phases
+    reduced exactly: (k0 + q) j mod K and f_h t mod 1 in float64).  Missing
+    SFTs (present = 0) give zeros and valid = 0.  Returns (x complex128
+    [n_sft K], valid uint8, f_h, dt)."""
+    sfts = np.asarray(sfts, dtype=np.complex128)
+    n_sft, K = sfts.shape
+    f_h = (k0 + K / 2) / t_sft
+    dt = t_sft / K
+    j = np.arange(K)
+    q = np.arange(K)
+    E = np.exp(2j * np.pi * (((k0 + q)[None, :] * j[:, None]) % K) / K)
+    x = np.zeros(n_sft * K, dtype=np.complex128)
+    valid = np.zeros(n_sft * K, dtype=np.uint8)
+    for s in range(n_sft):
+        if not present[s]:
+            continue
+        t = t_start + s * t_sft + j * dt
+        het = np.exp(-2j * np.pi * np.mod(f_h * t, 1.0))
+        x[s * K:(s + 1) * K] = (E @ sfts[s]) * het / t_sft
+        valid[s * K:(s + 1) * K] = 1
+    return x, valid, f_h, dt
 
 
 # ----------------------------------------------------------------------------
@@ -79,18 +123,49 @@ def roemer_delay(model, det, nhat, t):
 # O3: circular binary Roemer delay (reading of the orbit model varied in Sec. 4.2)
 # ----------------------------------------------------------------------------
 
+def eccentric_anomaly(mean_anomaly, ecc):
+    """E solving Kepler's equation E - e sin E = M: M is reduced to
+    [-pi, pi] by whole turns, then Newton's iteration from E = M + e sin M
+    runs until the update is at the rounding level."""
+    M = np.asarray(mean_anomaly, dtype=np.float64)
+    turns = np.round(M / TWO_PI)
+    Mr = M - TWO_PI * turns
+    E = Mr + ecc * np.sin(Mr)
+    for _ in range(100):
+        step = (E - ecc * np.sin(E) - Mr) / (1.0 - ecc * np.cos(E))
+        E = E - step
+        if np.max(np.abs(step), initial=0.0) < 1e-15:
+            return E + TWO_PI * turns
+    raise RuntimeError("Kepler's equation did not converge")
+
+
 def binary_delay(tm, t_src):
+    """R(t') of the source's orbit (Roemer term only).  Circular orbit
+    (ecc = argp = 0): asini sin(2 pi (t' - tp) / porb), tp the time of the
+    ascending node.  Eccentric orbit (reading of the orbital elements the
+    paper's binary searches vary, the period among them, Sec. 4.2): mean
+    anomaly M = 2 pi (t' - tp) / porb with tp the time of periapsis, E from
+    Kepler's equation, and
+    R = asini [sin(argp) (cos E - ecc) + cos(argp) sqrt(1 - ecc^2) sin E],
+    which for ecc = argp = 0 is the circular form."""
     asini, porb, tp = tm["asini"], tm["porb"], tm["tp"]
     if asini == 0.0:
         return np.zeros_like(np.asarray(t_src, dtype=np.float64))
-    return asini * np.sin(TWO_PI * (np.asarray(t_src) - tp) / porb)
+    ecc, argp = tm.get("ecc", 0.0), tm.get("argp", 0.0)
+    M = TWO_PI * (np.asarray(t_src, dtype=np.float64) - tp) / porb
+    if ecc == 0.0 and argp == 0.0:
+        return asini * np.sin(M)
+    E = eccentric_anomaly(M, ecc)
+    return asini * (math.sin(argp) * (np.cos(E) - ecc) +
+                    math.cos(argp) * math.sqrt(1.0 - ecc * ecc) * np.sin(E))
 
 
 def emission_time_delay(tm, t_b):
     """Return R(t_src) where t_src solves t_src + R(t_src) = t_b.
 
     Plain fixed-point iteration t_src <- t_b - R(t_src); the map contracts with
-    factor asini * 2 pi / porb < 1e-2 for every orbit considered."""
+    factor max|R'| (asini * 2 pi / porb for a circular orbit) < 1e-2 for every
+    orbit considered."""
     t_b = np.asarray(t_b, dtype=np.float64)
     r = np.zeros_like(t_b)
     if tm["asini"] == 0.0:
@@ -250,8 +325,14 @@ def two_f(Fa, Fb, A, B, C):
 # ----------------------------------------------------------------------------
 
 def template_dict(row):
-    return dict(alpha=float(row[0]), delta=float(row[1]), df=float(row[2]), f1dot=float(row[3]),
-                f2dot=float(row[4]), asini=float(row[5]), porb=float(row[6]), tp=float(row[7]))
+    """Template row: (alpha, delta, df, f1dot, f2dot, asini, porb, tp) and, in
+    rows of ten, the eccentricity and the argument of periapsis."""
+    tm = dict(alpha=float(row[0]), delta=float(row[1]), df=float(row[2]), f1dot=float(row[3]),
+              f2dot=float(row[4]), asini=float(row[5]), porb=float(row[6]), tp=float(row[7]),
+              ecc=0.0, argp=0.0)
+    if len(row) >= 10:
+        tm["ecc"], tm["argp"] = float(row[8]), float(row[9])
+    return tm
 
 
 def resampled_series(ds, tm):

@@ -48,7 +48,18 @@ def roemer(model, det, nhat, t):
 
 
 def binary_delay(p, t_src):
-    return p["asini"] * torch.sin(TWO_PI * (t_src - p["tp"]) / p["porb"])
+    """R(t'): circular, or Keplerian with p["ecc"], p["argp"] (held fixed;
+    E from Newton's iteration on Kepler's equation run to convergence inside
+    the graph, so its derivative is the converged map's)."""
+    M = TWO_PI * (t_src - p["tp"]) / p["porb"]
+    ecc, argp = float(p.get("ecc", 0.0)), float(p.get("argp", 0.0))
+    if ecc == 0.0 and argp == 0.0:
+        return p["asini"] * torch.sin(M)
+    E = M + ecc * torch.sin(M)
+    for _ in range(40):
+        E = E - (E - ecc * torch.sin(E) - M) / (1.0 - ecc * torch.cos(E))
+    return p["asini"] * (math.sin(argp) * (torch.cos(E) - ecc) +
+                         math.cos(argp) * math.sqrt(1.0 - ecc * ecc) * torch.sin(E))
 
 
 def emission_delay(p, t_b, iters=60):
@@ -155,7 +166,10 @@ def twoF_torch(ds, p):
 
 def template_params(row):
     names = ("alpha", "delta", "df", "f1dot", "f2dot", "asini", "porb", "tp")
-    return {n: _t(float(v)) for n, v in zip(names, row)}
+    p = {n: _t(float(v)) for n, v in zip(names, row)}
+    if len(row) >= 10:
+        p["ecc"], p["argp"] = float(row[8]), float(row[9])
+    return p
 
 
 def oracle_grad(ds, row, weights):

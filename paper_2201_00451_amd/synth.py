@@ -188,16 +188,38 @@ def tensor_response(model, det, alpha, delta, psi, t):
     return fp, fx
 
 
-def source_emission_time(t_b, asini, porb, tp):
-    """Solve t_src + asini sin(2 pi (t_src - tp)/porb) = t_b by Newton steps."""
+def orbit_delay(t_src, asini, porb, tp, ecc=0.0, argp=0.0):
+    """Roemer delay of the source in its orbit and its time derivative.
+    Keplerian elements: tp is the time of periapsis (of the ascending node
+    for a circular orbit, argp = 0).  The eccentric anomaly comes from a
+    Halley iteration on E - ecc sin E = mean anomaly (then the delay is
+    asini (sin argp (cos E - ecc) + cos argp sqrt(1 - ecc^2) sin E))."""
+    om = 2.0 * math.pi / porb
+    M = om * (np.asarray(t_src, dtype=np.float64) - tp)
+    if ecc == 0.0:
+        s_, c_ = np.sin(M + argp), np.cos(M + argp)
+        return asini * s_, asini * om * c_
+    E = M.copy()
+    for _ in range(12):
+        f0 = E - ecc * np.sin(E) - M
+        f1 = 1.0 - ecc * np.cos(E)
+        f2 = ecc * np.sin(E)
+        E = E - 2.0 * f0 * f1 / (2.0 * f1 * f1 - f0 * f2)
+    sq = math.sqrt(1.0 - ecc * ecc)
+    r = asini * (math.sin(argp) * (np.cos(E) - ecc) + math.cos(argp) * sq * np.sin(E))
+    dr_dE = asini * (-math.sin(argp) * np.sin(E) + math.cos(argp) * sq * np.cos(E))
+    return r, dr_dE * om / (1.0 - ecc * np.cos(E))
+
+
+def source_emission_time(t_b, asini, porb, tp, ecc=0.0, argp=0.0):
+    """Solve t_src + R(t_src) = t_b by Newton steps."""
     t_b = np.asarray(t_b, dtype=np.float64)
     if asini == 0.0:
         return t_b.copy()
-    om = 2.0 * math.pi / porb
-    ts = t_b - asini * np.sin(om * (t_b - tp))
+    ts = t_b - orbit_delay(t_b, asini, porb, tp, ecc, argp)[0]
     for _ in range(8):
-        g = ts + asini * np.sin(om * (ts - tp)) - t_b
-        ts = ts - g / (1.0 + asini * om * np.cos(om * (ts - tp)))
+        r, dr = orbit_delay(ts, asini, porb, tp, ecc, argp)
+        ts = ts - (ts + r - t_b) / (1.0 + dr)
     return ts
 
 
@@ -207,10 +229,12 @@ def signal_series(model, det, t, inj, f_het, t_ref):
     pos, _ = detector_pos_vel(model, det, t)
     roemer = nhat @ pos
     t_b = t + roemer
-    t_src = source_emission_time(t_b, inj.get("asini", 0.0), inj.get("porb", 1.0), inj.get("tp", 0.0))
+    orbit = (inj.get("asini", 0.0), inj.get("porb", 1.0), inj.get("tp", 0.0),
+             inj.get("ecc", 0.0), inj.get("argp", 0.0))
+    t_src = source_emission_time(t_b, *orbit)
     # delay t_src - t formed from small numbers
-    if inj.get("asini", 0.0) != 0.0:
-        delay = roemer - inj["asini"] * np.sin(2.0 * math.pi / inj["porb"] * (t_src - inj["tp"]))
+    if orbit[0] != 0.0:
+        delay = roemer - orbit_delay(t_src, *orbit)[0]
     else:
         delay = roemer
     tau = t_src - t_ref
@@ -470,14 +494,16 @@ def config_refine(seed=5, ndays=30.0, dt=1.0, n_fft=1 << 22, f_het=400.0, band=0
 def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmpl=4, D=8,
                rho=15.0, noise=True, binary=False, gaps=False, noise_vars=None, f_inj=None,
                bin_lo=0, n_bins=None, keep_f64=False, model=None, sites=None, f1dot=None,
-               t0=0.0, noise_seed=None, f2dot=0.0):
+               t0=0.0, noise_seed=None, f2dot=0.0, ecc=None, argp=None):
     """Small search (a few hours of data) for oracle pins and quick parity.
 
     t0 shifts the data (and the computed grid) in time with the reference time
     kept at 0, so that cases with the same seed and different t0 are segments
     of one source; noise_seed (default: seed) draws their noise independently.
     f2dot is the injection's second frequency derivative (the templates carry
-    it too)."""
+    it too).  ecc and argp (binary only) make the orbit Keplerian; the
+    templates then have ten columns (eccentricity and argument of periapsis
+    last)."""
     ss = np.random.SeedSequence(seed)
     s_par, s_gap = ss.spawn(2)
     rng = np.random.default_rng(s_par)
@@ -494,6 +520,9 @@ def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmp
     if binary:
         inj.update(asini=float(rng.uniform(0.05, 0.5)), porb=float(rng.uniform(0.2, 1.0)) * DAY,
                    tp=float(rng.uniform(0, 1e4)))
+    kepler = binary and (ecc is not None or argp is not None)
+    if kepler:
+        inj.update(ecc=float(ecc or 0.0), argp=float(argp or 0.0))
     g = None
     if gaps:
         rg = np.random.default_rng(s_gap)
@@ -501,7 +530,7 @@ def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmp
     model = dict(model or EPHEM_MODEL)
     xs, vs = make_data(dets, dt, f_het, 0.0, [inj], seed if noise_seed is None else noise_seed,
                        gaps=g, noise=noise, keep_f64=keep_f64, model=model)
-    tm = np.zeros((ntmpl, 8))
+    tm = np.zeros((ntmpl, 10 if kepler else 8))
     tm[:, 0] = inj["alpha"] + 0.02 * np.arange(ntmpl)
     tm[:, 1] = inj["delta"]
     tm[:, 3] = inj["f1dot"]
@@ -509,6 +538,8 @@ def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmp
     tm[:, 6] = 1.0
     if binary:
         tm[:, 5], tm[:, 6], tm[:, 7] = inj["asini"], inj["porb"], inj["tp"]
+    if kepler:
+        tm[:, 8], tm[:, 9] = inj["ecc"], inj["argp"]
     margin = 512.0 + (inj.get("asini", 0.0) if binary else 0.0)
     nb = n_fft if n_bins is None else n_bins
     ds = Dataset("small", dt, f_het, 0.0, grid_origin(t0, dt, margin), n_fft, D, bin_lo, nb,
@@ -571,6 +602,89 @@ def config_uneven(seed=4, n_search=256, days=(1.0, 30.0), dts=(0.5, 1.0, 2.0, 5.
                      n_fft, dets, xs, vs, tm, injections=[inj])
         out.append(finish(ds))
     return out
+
+
+def make_sfts(det, t_start, t_sft, n_sft, f_raw, k0, K, injections, f_het, t_ref, seed,
+              drop_p=0.0, noise_var=1.0, model=None, noise=True):
+    """Short Fourier transforms of a real detector strain, the input of steps
+    (i)-(ii): the strain r(t) = 2 Re[s(t) exp(2 pi i f_het t)] + real white
+    noise sampled at f_raw over n_sft contiguous t_sft-second segments, where
+    s is the complex heterodyned signal of the injections (their h0 already
+    set); each segment's DFT with the time-step normalisation
+    X[k] = (1/f_raw) sum_n r_n exp(-2 pi i k n / N) keeps bins k0 .. k0+K-1.
+    Segments are dropped independently with probability drop_p.  The noise
+    variance is set so that the heterodyned series has E|n|^2 = noise_var.
+    Returns (sfts complex64 [n_sft, K], present uint8 [n_sft])."""
+    model = model or EPHEM_MODEL
+    ss = seed if isinstance(seed, np.random.SeedSequence) else np.random.SeedSequence(seed)
+    s_noise, s_drop = ss.spawn(2)
+    rng_n = np.random.default_rng(s_noise)
+    present = (np.random.default_rng(s_drop).random(n_sft) >= drop_p).astype(np.uint8)
+    n_seg = int(round(t_sft * f_raw))
+    sd = math.sqrt(noise_var * f_raw * t_sft / K)
+    out = np.zeros((n_sft, K), dtype=np.complex64)
+    for s_ in range(n_sft):
+        t = t_start + s_ * t_sft + np.arange(n_seg) / f_raw
+        r = np.zeros(n_seg)
+        for inj in injections:
+            sig = signal_series(model, det, t, inj, f_het, t_ref) * inj["h0"]
+            r += 2.0 * np.real(sig * np.exp(2j * np.pi * np.mod(f_het * t, 1.0)))
+        if noise:
+            r += sd * rng_n.standard_normal(n_seg)
+        if present[s_]:
+            out[s_] = (np.fft.rfft(r)[k0:k0 + K] / f_raw).astype(np.complex64)
+    return out, present
+
+
+def sft_case(seed=81, t_sft=300.0, n_sft=40, f_raw=256.0, dt=2.0, f_het=30007.0 / 300.0, ndet=2,
+             rho=20.0, drop_p=0.15, ntmpl=3, binary=False, noise=True):
+    """A search whose input comes as SFTs: per detector make_sfts output, and a
+    Dataset with everything but the series (x and valid are None: steps
+    (i)-(ii) fill them).  Band of K = t_sft / dt bins centred on f_het (f_het
+    t_sft an integer; the default puts f_het dt off whole and half cycles);
+    one injection at rho over the SFT span."""
+    K = int(round(t_sft / dt))
+    kc = int(round(f_het * t_sft))
+    assert abs(kc - f_het * t_sft) < 1e-6 and K % 2 == 0
+    f_het = kc / t_sft
+    k0 = kc - K // 2
+    ss = np.random.SeedSequence(seed)
+    s_par, s_sft = ss.spawn(2)
+    rng = np.random.default_rng(s_par)
+    n = n_sft * K
+    dets = [make_detector(site, 0.0, n, 1.0, name=f"{site}{i}")
+            for i, site in enumerate(["H", "L", "H", "L"][:ndet])]
+    inj = dict(alpha=float(rng.uniform(0, 2 * math.pi)), delta=float(rng.uniform(-1.2, 1.2)),
+               f=f_het + float(rng.uniform(-0.15, 0.15)) / dt,
+               f1dot=float(rng.uniform(-1e-9, 1e-9)), cosi=float(rng.uniform(-1, 1)),
+               psi=float(rng.uniform(-0.7, 0.7)), phi0=float(rng.uniform(0, 6.28)), rho=rho)
+    if binary:
+        inj.update(asini=float(rng.uniform(0.05, 0.3)), porb=float(rng.uniform(0.2, 1.0)) * DAY,
+                   tp=float(rng.uniform(0, 1e4)))
+    # h0 for the target rho, from the heterodyned signal on the output grid
+    # (all SFTs present)
+    rho2 = 0.0
+    for det in dets:
+        t = det.t0 + dt * np.arange(n)
+        rho2 += 2.0 * np.sum(np.abs(signal_series(EPHEM_MODEL, det, t, inj, f_het, 0.0)) ** 2)
+    inj["h0"] = rho / math.sqrt(rho2)
+    inj["rho2"] = rho * rho
+    seeds = s_sft.spawn(ndet)
+    sfts = [make_sfts(det, 0.0, t_sft, n_sft, f_raw, k0, K, [inj], f_het, 0.0, seeds[i],
+                      drop_p=drop_p, noise=noise) for i, det in enumerate(dets)]
+    tm = np.zeros((ntmpl, 8))
+    tm[:, 0] = inj["alpha"] + 0.01 * np.arange(ntmpl)
+    tm[:, 1] = inj["delta"]
+    tm[:, 3] = inj["f1dot"]
+    tm[:, 6] = 1.0
+    if binary:
+        tm[:, 5], tm[:, 6], tm[:, 7] = inj["asini"], inj["porb"], inj["tp"]
+    n_fft = 1 << int(math.ceil(math.log2(n + 1024)))
+    ds = Dataset("sft", dt, f_het, 0.0, grid_origin(0.0, dt, 512.0 + inj.get("asini", 0.0)),
+                 n_fft, 8, 0, n_fft, dets, None, None, tm, injections=[inj])
+    ds = finish(ds)
+    ds.sft = dict(t_start=0.0, t_sft=t_sft, k0=k0, K=K, f_raw=f_raw)
+    return ds, sfts
 
 
 CONFIGS = {

@@ -48,3 +48,22 @@ def test_gradient_oracle_matches_oracle_and_finite_differences(binary, asini, f2
         assert abs(g[i] - fd) <= 1e-4 * abs(fd) + 1e-9, (name, g[i], fd)
         if asini is not None and name == "asini":
             assert abs(fd) > 1e-2   # a real, non-vanishing derivative
+
+
+def test_gradient_oracle_keplerian_orbit():
+    """The gradient oracle with a Keplerian orbit (eccentricity and argument
+    of periapsis held fixed) against central differences of the numpy oracle."""
+    ds = synth.small_case(seed=52, n=3000, n_fft=1 << 13, ndet=2, binary=True, gaps=True,
+                          rho=20, ecc=0.3, argp=0.9)
+    row = ds.templates[0].copy()
+    row[0] += 0.002
+    row[5] *= 1.001
+    tf_np = O.oracle_twoF(ds, row[None])[0]
+    w = np.zeros(ds.n_bins)
+    ipk = int(np.argmax(tf_np))
+    w[ipk - 3:ipk + 4] = 1.0
+    tf_t, g = G.oracle_grad(ds, row, w)
+    np.testing.assert_allclose(tf_t, tf_np, rtol=1e-10, atol=1e-10)
+    for i, name in enumerate(G.PARAMS):
+        fd = fd_grad(ds, row, w, name)
+        assert abs(g[i] - fd) <= 1e-4 * abs(fd) + 1e-9, (name, g[i], fd)

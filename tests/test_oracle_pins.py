@@ -393,3 +393,170 @@ def test_single_bin_2f_equals_full_transform():
     full = O.oracle_twoF(ds, row[None])[0]
     for i in (0, 3, int(np.argmax(full)), ds.n_bins - 1):
         assert abs(O.twoF_at_bin(ds, row, i) - full[i]) <= 1e-9 * max(1.0, full[i])
+
+
+# --------------------------------------------------------------------------
+# Keplerian (eccentric) orbits
+# --------------------------------------------------------------------------
+
+def test_kepler_solution_and_orbit_closed_forms():
+    """E solves Kepler's equation; at periapsis (M = 0) and apoapsis (M = pi)
+    the delay takes its closed forms asini sin(argp) (1 -+ e); ecc = 0 with an
+    argument of periapsis is the circular orbit with tp moved by argp P / 2pi."""
+    M = np.linspace(-20.0, 20.0, 4001)
+    for e in (0.0, 0.1, 0.5, 0.9):
+        E = O.eccentric_anomaly(M, e)
+        assert np.abs(E - e * np.sin(E) - M).max() < 1e-13
+    P, a, tp, w, e = 0.7 * 86400.0, 0.6, 1234.0, 0.8, 0.35
+    tm = dict(asini=a, porb=P, tp=tp, ecc=e, argp=w)
+    r = O.binary_delay(tm, np.array([tp, tp + 0.5 * P, tp + 3 * P]))
+    np.testing.assert_allclose(r, a * math.sin(w) * np.array([1 - e, -1 - e, 1 - e]),
+                               rtol=0, atol=1e-14)
+    t = np.linspace(0, 5 * 86400, 1001)
+    circ = O.binary_delay(dict(asini=a, porb=P, tp=tp - w * P / (2 * math.pi), ecc=0.0,
+                               argp=0.0), t)
+    np.testing.assert_allclose(O.binary_delay(dict(tm, ecc=0.0), t), circ, rtol=0, atol=1e-12)
+    # ecc = 0 and argp = 0 is the circular form itself
+    np.testing.assert_array_equal(O.binary_delay(dict(tm, ecc=0.0, argp=0.0), t),
+                                  a * np.sin(2 * math.pi * (t - tp) / P))
+
+
+@pytest.mark.parametrize("ecc,argp", [(0.3, 1.1), (0.6, -2.0)])
+def test_eccentric_noiseless_direct_sum_equals_rho2(ecc, argp):
+    """The generator's independent Keplerian timing and the oracle's agree:
+    at the injected orbit the direct-sum 2F is rho^2; a wrong element does not."""
+    ds = synth.small_case(seed=27, n=5000, n_fft=1 << 14, ndet=2, noise=False, binary=True,
+                          keep_f64=True, ecc=ecc, argp=argp)
+    inj = ds.injections[0]
+    tm = O.template_dict(ds.templates[0])
+    assert tm["ecc"] == ecc and tm["argp"] == argp
+    v = O.direct_twoF(ds, tm, [inj["f"]])[0]
+    assert abs(v / inj["rho2"] - 1) < 1e-10
+    off = O.direct_twoF(ds, dict(tm, argp=argp + 0.3), [inj["f"]])[0]
+    assert off < 0.9 * inj["rho2"]
+
+
+def test_eccentric_resampled_matches_direct_sum():
+    ds = synth.small_case(seed=28, n=6000, n_fft=1 << 14, ndet=2, noise=False, binary=True,
+                          gaps=True, f_inj=0.05, ecc=0.4, argp=0.7)
+    inj = ds.injections[0]
+    tm = O.template_dict(ds.templates[0])
+    tm["df"], ipk = on_bin(ds, inj["f"])
+    Fa, Fb = O.fa_fb(ds, tm)
+    A, B, C = O.antenna_matrix(ds.ephem_model, ds.detectors, ds.valid, tm["alpha"], tm["delta"],
+                               ds.dt)
+    tf = O.two_f(Fa, Fb, A, B, C)
+    assert int(np.argmax(tf)) == ipk
+    assert abs(tf[ipk] / inj["rho2"] - 1.0) < 5e-3
+    idx = np.arange(ipk - 30, ipk + 31)
+    dFa, dFb = O.direct_fa_fb(ds, tm, ds.bin_frequencies(tm["df"])[idx])
+    assert O.rel_err(Fa[idx], dFa, 2) < 3e-3
+
+
+def test_eccentric_detector_epoch_residual():
+    m = synth.EPHEM_MODEL
+    det = synth.make_detector("H", 0, 10, 1.0)
+    tm = dict(alpha=2.0, delta=0.3, df=0, f1dot=0, f2dot=0, asini=0.8, porb=0.25 * 86400,
+              tp=1234.5, ecc=0.5, argp=2.5)
+    tau = np.linspace(-600, 20 * 86400, 5001)
+    n = O.sky_vector(tm["alpha"], tm["delta"])
+    T, _ = O.detector_epochs(m, det, n, tm, tau)
+    t_b = tau + O.binary_delay(tm, tau)
+    assert np.abs(T + O.roemer_delay(m, det, n, T) - t_b).max() < 1e-9
+    rb = O.emission_time_delay(tm, t_b)
+    np.testing.assert_allclose(t_b - rb, tau, atol=1e-8)
+
+
+# --------------------------------------------------------------------------
+# Steps (i)-(ii): SFTs to the heterodyned series
+# --------------------------------------------------------------------------
+
+def _tone_sfts(freqs, amps, t_sft, n_sft, f_raw, k0, K, t_start):
+    """SFTs (time-step normalised DFT bins k0..k0+K-1) of the real strain
+    r = 2 Re sum_m A_m exp(2 pi i f_m t), written out here."""
+    n = int(t_sft * f_raw)
+    out = np.zeros((n_sft, K), dtype=np.complex128)
+    for s in range(n_sft):
+        t = t_start + s * t_sft + np.arange(n) / f_raw
+        r = np.zeros(n)
+        for f, a in zip(freqs, amps):
+            r += 2.0 * np.real(a * np.exp(2j * np.pi * f * t))
+        out[s] = np.fft.rfft(r)[k0:k0 + K] / f_raw
+    return out
+
+
+def test_sft_series_exact_for_on_grid_tones():
+    """Tones on the SFT frequency grid inside the band come out as the exact
+    heterodyned tones A exp(2 pi i (f - f_h) t); a missing SFT gives zeros."""
+    t_sft, K, f_raw, n_sft, t0 = 60.0, 30, 64.0, 5, 1234.0
+    kc = 607                      # f_h = 10.1167 Hz: f_h dt is not a whole number
+    k0 = kc - K // 2
+    freqs = [(k0 + 3) / t_sft, (k0 + 17) / t_sft, (k0 + 29) / t_sft]
+    amps = [0.7 - 0.2j, 1.3j, -0.4]
+    sfts = _tone_sfts(freqs, amps, t_sft, n_sft, f_raw, k0, K, t0)
+    present = np.array([1, 1, 0, 1, 1], dtype=np.uint8)
+    x, v, f_h, dt = O.sfts_to_series(sfts, present, k0, t_sft, t0)
+    assert f_h == kc / t_sft and dt == 2.0
+    t = t0 + dt * np.arange(n_sft * K)
+    want = sum(a * np.exp(2j * np.pi * (f - f_h) * t) for f, a in zip(freqs, amps))
+    want = want * np.repeat(present, K)
+    np.testing.assert_allclose(x, want, rtol=0, atol=1e-10)
+    np.testing.assert_array_equal(v, np.repeat(present, K))
+
+
+def test_sft_series_parseval_and_cw_signal():
+    """Per SFT, sum |x_h|^2 = K / t_sft^2 sum |X|^2 (unitary up to the
+    normalisation); for a Doppler-modulated CW signal the series matches the
+    generator's heterodyned signal away from SFT edges (per-SFT band
+    limiting rings only near the edges)."""
+    ds, sfts = synth.sft_case(seed=82, noise=False, drop_p=0.0, ndet=1)
+    sf = ds.sft
+    S, pres = sfts[0]
+    x, v, f_h, dt = O.sfts_to_series(S, pres, sf["k0"], sf["t_sft"], sf["t_start"])
+    K = sf["K"]
+    for s in range(3):
+        lhs = np.sum(np.abs(x[s * K:(s + 1) * K]) ** 2)
+        rhs = K / sf["t_sft"] ** 2 * np.sum(np.abs(S[s].astype(np.complex128)) ** 2)
+        assert abs(lhs / rhs - 1) < 1e-12
+    det = ds.detectors[0]
+    t = det.t0 + ds.dt * np.arange(det.n)
+    inj = ds.injections[0]
+    ref = synth.signal_series(ds.ephem_model, det, t, inj, ds.f_het, 0.0) * inj["h0"]
+    j = np.arange(det.n) % K
+    mid = (j > K // 3) & (j < 2 * K // 3)
+    assert np.abs(x - ref)[mid].max() < 1e-2 * np.abs(ref).max()
+    assert np.abs(x - ref).max() > 3e-2 * np.abs(ref).max()   # the edges ring
+
+
+def test_sft_pipeline_recovers_rho2_and_chi2_noise():
+    """Steps (i)-(vii) from SFTs: noiseless, 2F at the injection is rho^2
+    within the per-SFT edge loss; in noise alone the mean of 2F is 4 (the
+    series' noise normalisation E|n|^2 = 1)."""
+    ds, sfts = synth.sft_case(seed=83, noise=False, drop_p=0.1, ndet=2, rho=20.0)
+    sf = ds.sft
+    xs, vs = [], []
+    for S, pres in sfts:
+        x, v, _, _ = O.sfts_to_series(S, pres, sf["k0"], sf["t_sft"], sf["t_start"])
+        xs.append(x)
+        vs.append(v)
+    ds.x, ds.valid = xs, vs
+    inj = ds.injections[0]
+    tm = O.template_dict(ds.templates[0])
+    tm["df"], ipk = on_bin(ds, inj["f"])
+    Fa, Fb = O.fa_fb(ds, tm)
+    A, B, C = O.antenna_matrix(ds.ephem_model, ds.detectors, ds.valid, tm["alpha"], tm["delta"],
+                               ds.dt)
+    tf = O.two_f(Fa, Fb, A, B, C)
+    # rho^2 was set with every SFT present; the dropped ones remove their share
+    kept = np.mean([v.mean() for v in vs])
+    assert int(np.argmax(tf)) == ipk
+    assert 0.9 * kept * inj["rho2"] < tf[ipk] < 1.02 * inj["rho2"]
+    dn, sn = synth.sft_case(seed=84, noise=True, drop_p=0.1, ndet=1, rho=0.0)
+    S, pres = sn[0]
+    x, v, _, _ = O.sfts_to_series(S, pres, dn.sft["k0"], dn.sft["t_sft"], dn.sft["t_start"])
+    dn.x, dn.valid = [x], [v]
+    var = np.mean(np.abs(x[v == 1]) ** 2)
+    assert abs(var - 1.0) < 0.05
+    tf = O.oracle_twoF(dn, dn.templates[:1])[0]
+    inner = tf[dn.n_fft // 10: -dn.n_fft // 10]
+    assert abs(inner.mean() - 4.0) < 0.15
