@@ -32,6 +32,17 @@ extern "C" {
 
 #define FSTAT_MAX_DET 4
 #define FSTAT_TEMPLATE_STRIDE 8
+/* Plan flag: Keplerian (eccentric) source orbits.  Template rows then hold
+ * FSTAT_TEMPLATE_STRIDE_KEPLER doubles: the eight of a circular row and the
+ * eccentricity (0 <= ecc < 1) and argument of periapsis argp (rad), with tp
+ * the time of periapsis.  The orbit's Roemer delay is
+ *   R(t') = asini [sin(argp) (cos E - ecc) + cos(argp) sqrt(1 - ecc^2) sin E],
+ * E - ecc sin E = 2 pi (t' - tp) / porb (Kepler's equation); with ecc = 0 and
+ * argp = 0 it is the circular asini sin(2 pi (t' - tp) / porb).  (The paper's
+ * binary searches vary the orbital elements, Sec. 4.2 the period among them;
+ * its own searches assume circular orbits.) */
+#define FSTAT_PLAN_KEPLER 1u
+#define FSTAT_TEMPLATE_STRIDE_KEPLER 10
 
 typedef enum {
   FSTAT_OK = 0,
@@ -89,7 +100,7 @@ typedef struct {
   int32_t tune_col_lines;
   int32_t tune_row_lines;
   int32_t tune_fft_radix;
-  uint32_t flags;                      /* reserved, must be 0 */
+  uint32_t flags;                      /* 0 or FSTAT_PLAN_KEPLER */
 } fstat_plan_desc;
 
 /* A candidate of the search (device memory, written by
@@ -118,11 +129,50 @@ typedef struct {
 
 typedef struct fstat_plan fstat_plan;  /* opaque, host memory owned by the library */
 
+/* Short Fourier transforms of one detector's strain (the input of Sec. 3,
+ * steps (i)-(ii)): n_sft contiguous slots of length t_sft starting at
+ * t_start (slot s covers [t_start + s t_sft, t_start + (s+1) t_sft)); each
+ * holds n_bins bins k0 .. k0 + n_bins - 1 (frequency k / t_sft) of its
+ * segment's DFT normalised by the raw time step,
+ *   X_s[k] = dt_raw sum_n r(t_s + n dt_raw) exp(-2 pi i k n / N_s). */
+typedef struct {
+  double t_start;
+  double t_sft;
+  int64_t n_sft;
+  int64_t k0;
+  int32_t n_bins;   /* K: even, 2..4096, prime factors 2, 3 and 5 only */
+  int32_t reserved; /* must be 0 */
+} fstat_sft_desc;
+
+/* Steps (i)-(ii) of Sec. 3: the SFTs combined into one transform, low-passed
+ * to their band, heterodyned at the band's centre f_h = (k0 + K/2) / t_sft
+ * and transformed back, which gives the complex series x_h at
+ * t_start + n dt, dt = t_sft / K, n < n_sft K:
+ *   x_h(t_s + j dt) = (1/t_sft) sum_q X_s[k0 + q] exp(2 pi i (k0 + q) j / K)
+ *                     exp(-2 pi i f_h (t_s + j dt)),
+ * one K-point inverse DFT per SFT (the band of each SFT carries its segment
+ * only; nothing of the raw series outside the band is needed).
+ *   sfts:    device float2 [n_sft][K];
+ *   present: device uint8 [n_sft], nullable (= all present); a missing SFT
+ *            gives K zeros;
+ *   x:       device float2 [n_sft K] (output, fstat_inputs.x of a plan with
+ *            dt, f_het as above and detector t0 = t_start, n = n_sft K);
+ *   valid:   device uint8 [n_sft K] (output, nullable): 1 where an SFT was present.
+ * Fails with FSTAT_EINVAL for a null pointer, t_sft not positive and finite,
+ * n_sft < 1, k0 < 0 or a non-zero reserved field, and FSTAT_EUNSUPPORTED for
+ * K outside 2..4096, odd, or with a prime factor above 5. */
+FSTAT_API fstat_status fstat_sfts_to_series(const fstat_sft_desc* desc, const void* sfts,
+                                            const uint8_t* present, void* x, uint8_t* valid,
+                                            void* stream);
+
 /* Validate a set-up and build a plan.  Fails with FSTAT_EINVAL when: ndet out of
  * range; dt, noise_var or sid_rate not positive and finite; n_fft not a power of
  * two in [2^12, 2^24]; the band [bin_lo, bin_lo+n_bins) not inside [0, n_fft) or
  * empty; D not one of 4, 6, 8, 10, 12, 16; the source-frame grid [tau0, tau0 + n_fft*dt) does not
- * cover every sample's source time widened by max_delay; flags != 0. */
+ * cover every sample's source time widened by max_delay; flags other than
+ * FSTAT_PLAN_KEPLER.  Template rows of a plan are FSTAT_TEMPLATE_STRIDE
+ * doubles, or FSTAT_TEMPLATE_STRIDE_KEPLER with FSTAT_PLAN_KEPLER (every
+ * `templates` argument below and fstat_search_create's host rows). */
 FSTAT_API fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out);
 FSTAT_API void fstat_plan_destroy(fstat_plan* plan);
 
@@ -276,6 +326,20 @@ FSTAT_API fstat_status fstat_batch_run(fstat_batch* batch, const fstat_inputs* c
                                        const double* const* templates, float* const* twoF,
                                        void* const* workspace, const size_t* ws_bytes,
                                        void* stream);
+
+/* The interpolation half-width for an accuracy bound (the paper leaves the
+ * step (v) kernel open; D sets its accuracy, so it is chosen by accuracy,
+ * not time): the smallest D of 4, 6, 8, 10, 12, 16 for which a tone anywhere
+ * in the central band_fraction of the band (|nu| <= band_fraction / 2 cycles
+ * per sample), interpolated at any fractional offset, has its power (its 2F)
+ * within tol_2f of what the same kernel with D = 32 gives (the worst case
+ * over a grid of 65 frequencies and 32 offsets, evaluated on the host).  For
+ * tol_2f = 1e-3: D = 10 for the central 30 % of the band, 12 for the
+ * central half.  *err_2f (nullable) receives the worst error of the D
+ * returned.  FSTAT_EUNSUPPORTED (with *D = 16) when even D = 16 misses the
+ * bound. */
+FSTAT_API fstat_status fstat_sinc_halfwidth_for(double band_fraction, double tol_2f, int32_t* D,
+                                                double* err_2f);
 
 /* Launch-shape autotuner: for the set-up *desc (its tune fields ignored),
  * times every FFT launch shape the plan accepts (both column/row splits of

@@ -15,6 +15,8 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfstat.so")
 MAX_DET = 4
 TEMPLATE_STRIDE = 8
+TEMPLATE_STRIDE_KEPLER = 10
+PLAN_KEPLER = 1
 
 FSTAT_OK, FSTAT_EINVAL, FSTAT_EUNSUPPORTED, FSTAT_EWORKSPACE, FSTAT_EHIP, FSTAT_EINTERNAL = \
     0, -1, -2, -3, -4, -5
@@ -27,7 +29,8 @@ EXPORTED = ("fstat_plan_create", "fstat_plan_destroy", "fstat_workspace_size",
             "fstat_grad_workspace_size", "fstat_compute_2f_grad", "fstat_plan_info",
             "fstat_grad_bin_workspace_size", "fstat_compute_2f_grad_bin", "fstat_autotune",
             "fstat_search_run_candidates", "fstat_batch_create", "fstat_batch_destroy",
-            "fstat_batch_run", "fstat_flagged_count")
+            "fstat_batch_run", "fstat_flagged_count", "fstat_sfts_to_series",
+            "fstat_sinc_halfwidth_for")
 GRAD_PARAMS = ("df", "f1dot", "alpha", "delta", "asini", "porb", "tp")
 # template-row column of each gradient parameter
 GRAD_COLUMNS = (2, 3, 0, 1, 5, 6, 7)
@@ -58,6 +61,12 @@ class FstatInputs(ctypes.Structure):
                 ("ephem", ctypes.c_void_p * MAX_DET), ("n_eph", ctypes.c_int64),
                 ("eph_t0", ctypes.c_double), ("eph_dt", ctypes.c_double),
                 ("moments", ctypes.c_void_p)]
+
+
+class FstatSftDesc(ctypes.Structure):
+    _fields_ = [("t_start", ctypes.c_double), ("t_sft", ctypes.c_double),
+                ("n_sft", ctypes.c_int64), ("k0", ctypes.c_int64), ("n_bins", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class FstatError(RuntimeError):
@@ -122,6 +131,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.POINTER(sz), vp]
     lib.fstat_flagged_count.argtypes = [vp, sz, vp, ctypes.POINTER(i64)]
+    lib.fstat_sinc_halfwidth_for.argtypes = [ctypes.c_double, ctypes.c_double,
+                                             ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_double)]
+    lib.fstat_sfts_to_series.argtypes = [ctypes.POINTER(FstatSftDesc), vp, vp, vp, vp, vp]
     lib.fstat_sync_check.argtypes = [vp]
     lib.fstat_last_error.restype = ctypes.c_char_p
     lib.fstat_last_error.argtypes = []
@@ -160,7 +173,10 @@ def make_plan_desc(ds, tune=None) -> FstatPlanDesc:
     d.max_delay = ds.max_delay
     d.sid_angle0 = ds.ephem_model["sidereal_angle0_rad"]
     d.sid_rate = ds.ephem_model["sidereal_rate_rad_s"]
-    d.n_fft, d.bin_lo, d.n_bins, d.flags = ds.n_fft, ds.bin_lo, ds.n_bins, 0
+    d.n_fft, d.bin_lo, d.n_bins = ds.n_fft, ds.bin_lo, ds.n_bins
+    # rows of ten: Keplerian orbits (eccentricity, argument of periapsis)
+    kepler = np.asarray(ds.templates).shape[1] == TEMPLATE_STRIDE_KEPLER
+    d.flags = PLAN_KEPLER if kepler else 0
     for k, v in (tune or {}).items():
         setattr(d, k, int(v))
     return d
@@ -226,6 +242,8 @@ class DeviceData:
             raise FstatError(FSTAT_EUNSUPPORTED, "no HIP device visible to torch")
         self.device = torch.device(device)
         self.plan = Plan(make_plan_desc(ds, tune))
+        self.stride = (TEMPLATE_STRIDE_KEPLER if self.plan.desc.flags & PLAN_KEPLER
+                       else TEMPLATE_STRIDE)
         self.ndet = len(ds.detectors)
         self.n_fft, self.n_bins = int(ds.n_fft), int(ds.n_bins)
         dev = self.device
@@ -264,8 +282,8 @@ def antenna_moments(dd: DeviceData, stream=None):
 def _templates(dd, templates):
     import torch
     t = torch.as_tensor(templates, dtype=torch.float64)
-    if t.dim() != 2 or t.shape[1] != TEMPLATE_STRIDE:
-        raise FstatError(FSTAT_EINVAL, "templates must have shape [n, 8]")
+    if t.dim() != 2 or t.shape[1] != dd.stride:
+        raise FstatError(FSTAT_EINVAL, f"templates must have shape [n, {dd.stride}]")
     return t.to(dd.device).contiguous()
 
 
@@ -360,15 +378,19 @@ def compute_2f_grad_bin(dd: DeviceData, templates, bins, batch=32, stream=None):
     return grad, tf
 
 
-def template_rows(params, f2dot=None):
-    """Template rows [n, 8] from params [n, 7] in GRAD_PARAMS order (float64)."""
+def template_rows(params, f2dot=None, kepler=None):
+    """Template rows from params [n, 7] in GRAD_PARAMS order (float64): [n, 8],
+    or [n, 10] with kepler = (ecc, argp) per row ([n, 2]) for Keplerian plans."""
     import torch
     p = torch.as_tensor(params, dtype=torch.float64)
-    rows = torch.zeros((p.shape[0], TEMPLATE_STRIDE), dtype=torch.float64, device=p.device)
+    width = TEMPLATE_STRIDE if kepler is None else TEMPLATE_STRIDE_KEPLER
+    rows = torch.zeros((p.shape[0], width), dtype=torch.float64, device=p.device)
     for i, c in enumerate(GRAD_COLUMNS):
         rows[:, c] = p[:, i]
     if f2dot is not None:
         rows[:, 4] = torch.as_tensor(f2dot, dtype=torch.float64, device=p.device)
+    if kepler is not None:
+        rows[:, 8:10] = torch.as_tensor(kepler, dtype=torch.float64, device=p.device)
     return rows
 
 
@@ -467,6 +489,33 @@ def autotune(ds, templates, batch=8, device="cuda:0", stream=None):
     return {k: int(getattr(best, k)) for k in TUNE_FIELDS}, float(ms.value)
 
 
+def sfts_to_series(sfts, present, k0, t_sft, t_start=0.0, device="cuda:0", stream=None):
+    """Steps (i)-(ii) on the GPU (fstat_sfts_to_series): SFTs [n_sft, K]
+    complex64 (host or device) and their presence flags [n_sft] to the
+    heterodyned series x [n_sft K] complex64 and its validity [n_sft K] uint8,
+    both on the device; also returns (f_het, dt) of the series."""
+    import torch
+    X = torch.as_tensor(sfts).to(device=device, dtype=torch.complex64).contiguous()
+    n_sft, K = X.shape
+    pr = None if present is None else torch.as_tensor(
+        np.asarray(present, dtype=np.uint8)).to(device).contiguous()
+    x = torch.empty(n_sft * K, dtype=torch.complex64, device=device)
+    v = torch.empty(n_sft * K, dtype=torch.uint8, device=device)
+    d = FstatSftDesc(float(t_start), float(t_sft), int(n_sft), int(k0), int(K), 0)
+    _check(load_library().fstat_sfts_to_series(ctypes.byref(d), _ptr(X), _ptr(pr), _ptr(x),
+                                                _ptr(v), _stream_ptr(stream)))
+    return x, v, (k0 + K / 2) / t_sft, t_sft / K
+
+
+def sinc_halfwidth_for(band_fraction, tol_2f=1e-3):
+    """fstat_sinc_halfwidth_for: (D, worst 2F error) for an accuracy bound."""
+    D = ctypes.c_int32()
+    err = ctypes.c_double()
+    _check(load_library().fstat_sinc_halfwidth_for(float(band_fraction), float(tol_2f),
+                                                    ctypes.byref(D), ctypes.byref(err)))
+    return int(D.value), float(err.value)
+
+
 def flagged_count(ws, stream=None) -> int:
     """Templates whose outputs the last call on workspace tensor ``ws`` set
     to NaN (fstat_flagged_count; synchronises the stream)."""
@@ -480,17 +529,37 @@ def sync_check(stream=None):
     _check(load_library().fstat_sync_check(_stream_ptr(stream)))
 
 
+def search_workspace_size(dd: DeviceData, templates, slots=8) -> int:
+    """Workspace bytes fstat_search_info reports for this bank (host-only:
+    plans the bank and destroys the handle)."""
+    lib = load_library()
+    host = np.ascontiguousarray(np.asarray(templates, dtype=np.float64))
+    h = ctypes.c_void_p()
+    _check(lib.fstat_search_create(dd.plan.handle, host.ctypes.data_as(ctypes.c_void_p),
+                                   host.shape[0], int(slots), 0, ctypes.byref(h)))
+    ws = ctypes.c_size_t()
+    try:
+        _check(lib.fstat_search_info(h, ctypes.byref(ws), None, None))
+    finally:
+        lib.fstat_search_destroy(h)
+    return int(ws.value)
+
+
 class Search:
     """Grouped path for a template bank (fstat_search_*): templates sharing a
     sky position and orbit are resampled once.  ``templates`` is the bank in
     host memory; the same rows are copied to the device once."""
 
-    def __init__(self, dd: DeviceData, templates, slots=8, graph=False, accumulate=False):
+    def __init__(self, dd: DeviceData, templates, slots=8, graph=False, accumulate=False,
+                 workspace=None):
+        """workspace: optional device uint8 tensor of at least ws_bytes to use
+        instead of a workspace of the search's own (searches run one after
+        another on one stream may share one)."""
         import torch
         lib = load_library()
         host = np.ascontiguousarray(np.asarray(templates, dtype=np.float64))
-        if host.ndim != 2 or host.shape[1] != TEMPLATE_STRIDE:
-            raise FstatError(FSTAT_EINVAL, "templates must have shape [n, 8]")
+        if host.ndim != 2 or host.shape[1] != dd.stride:
+            raise FstatError(FSTAT_EINVAL, f"templates must have shape [n, {dd.stride}]")
         self.dd, self.ntmpl = dd, host.shape[0]
         h = ctypes.c_void_p()
         flags = (SEARCH_GRAPH if graph else 0) | (SEARCH_ACCUMULATE if accumulate else 0)
@@ -501,7 +570,13 @@ class Search:
         _check(lib.fstat_search_info(h, ctypes.byref(ws), ctypes.byref(ng), ctypes.byref(nc)))
         self.ws_bytes, self.ngroups, self.nchunks = int(ws.value), int(ng.value), int(nc.value)
         self.templates = torch.from_numpy(host).to(dd.device)
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dd.device)
+        if workspace is not None:
+            if workspace.numel() < self.ws_bytes:
+                raise FstatError(FSTAT_EWORKSPACE,
+                                 f"workspace {workspace.numel()} bytes < {self.ws_bytes}")
+            self.ws = workspace
+        else:
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dd.device)
         self.graph = graph
 
     def run(self, out=None, fafb=False, stream=None):

@@ -68,7 +68,7 @@ constexpr int kGradParams = 7;  // df, f1dot, alpha, delta, asini, porb, tp
 // m, so H is non-zero only at m and X_k = H_m exp(-2 pi i m k / N) in closed
 // form; the slot holds no arrays.
 // Two waves per SIMD (249 registers at two outputs per thread, no spills).
-template <int D, bool ONEHOT>
+template <int D, bool ONEHOT, bool KEP>
 __global__ __launch_bounds__(kResThreads, 2) void k_grad(PlanConst P, void* ws) {
   const int slot = blockIdx.y;
   const TmplParams& tp = *slot_params(ws, P, slot);
@@ -90,7 +90,6 @@ __global__ __launch_bounds__(kResThreads, 2) void k_grad(PlanConst P, void* ws) 
   if (tid == 0) bad = 0;
   bool oob = false;
   const bool binary = tp.asini != 0.0;
-  const double om = tp.om_b;
 
   // adjoint weights W_k = X_k E_k (the conjugate pass stored conj(X))
   float2 Wa[kResPerThread], Wb[kResPerThread];
@@ -143,9 +142,9 @@ __global__ __launch_bounds__(kResThreads, 2) void k_grad(PlanConst P, void* ws) 
     }
     __syncthreads();
     // epochs of the grid points (as the forward kernel) and their derivatives
-    const double rb0 = binary_delay(tp, tau_s);
+    const double rb0 = binary_delay<KEP>(tp, tau_s);
     double x0;
-    double d0 = grid_delay(re, tp, tau_s, oob);
+    double d0 = grid_delay<KEP>(re, tp, tau_s, oob);
     d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
     d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
     const double inv0 = 1.0 - x0 * (1.0 - x0 * (1.0 - x0));
@@ -158,7 +157,7 @@ __global__ __launch_bounds__(kResThreads, 2) void k_grad(PlanConst P, void* ws) 
       const int64_t kk = tid + i * kResThreads;
       const double dtau = P.dt * double(kk);
       const double tau = tau_s + dtau;
-      const double rb = binary_delay(tp, tau);
+      const double rb = binary_delay<KEP>(tp, tau);
       const double guess = d0 + (dtau + rb - rb0) * inv0 - dtau;
       double x;
       dly[i] = grid_delay_newton(re, tau, rb, guess, x, oob);
@@ -166,13 +165,15 @@ __global__ __launch_bounds__(kResThreads, 2) void k_grad(PlanConst P, void* ws) 
       double rv, rd, ra, rdl;
       re3(tau + dly[i], rv, rd, ra, rdl, oob);
       const double inv = 1.0 - rd * (1.0 - rd * (1.0 - rd));
-      double sb = 0.0, cb = 0.0;
-      if (binary) sincos_cycles((tau - tp.tp) * tp.nu_b, sb, cb);
+      // the orbit's delay R and rate R' at tau: dR/d asini = R / asini,
+      // dR/d porb = -R' (tau - tp) / porb, dR/d tp = -R' (circular or Keplerian)
+      double rbv = 0.0, rbp = 0.0;
+      if (binary) orbit_delay<KEP>(tp, tau, rbv, rbp);
       dT[i][0] = float(-ra * inv);
       dT[i][1] = float(-rdl * inv);
-      dT[i][2] = float(sb * inv);
-      dT[i][3] = float(-tp.asini * cb * om * (tau - tp.tp) / tp.porb * inv);
-      dT[i][4] = float(-tp.asini * om * cb * inv);
+      dT[i][2] = float(binary ? rbv / tp.asini * inv : 0.0);
+      dT[i][3] = float(-rbp * (tau - tp.tp) / tp.porb * inv);
+      dT[i][4] = float(-rbp * inv);
     }
     if (tid == 0) win_lo = j0[0] - D + 1;
     if (tid == kResThreads - 1) win_hi = j0[kResPerThread - 1] + D;
@@ -194,23 +195,22 @@ __global__ __launch_bounds__(kResThreads, 2) void k_grad(PlanConst P, void* ws) 
         const double t = d.t0 + P.dt * double(j);
         double dr, ddr, da, ddl;
         re3(t, dr, ddr, da, ddl, oob);
-        double r = 0.0, invb = 1.0, s2 = 0.0, c2 = 0.0, tsrc = t;
+        double r = 0.0, invb = 1.0, rs = 0.0, rsp = 0.0, tsrc = t;
         if (binary) {
           const double tb = t + dr;
-          double s, c;
-          r = binary_inverse(tp, tb, s, c);
+          r = orbit_inverse<KEP>(tp, tb);
           tsrc = tb - r;
-          sincos_cycles((tsrc - tp.tp) * tp.nu_b, s2, c2);
-          invb = 1.0 / (1.0 + tp.asini * om * c2);
+          orbit_delay<KEP>(tp, tsrc, rs, rsp);
+          invb = 1.0 / (1.0 + rsp);
         }
         const float2 e = cis_cycles(P.f_het * (dr - r));
         z = make_float2(xv.x * e.x + xv.y * e.y, xv.y * e.x - xv.x * e.y);
         dz[0] = float(da * invb - tp.dshift[0]);
         dz[1] = float(ddl * invb - tp.dshift[1]);
         if (binary) {
-          dz[2] = float(-s2 * invb);
-          dz[3] = float(tp.asini * c2 * om * (tsrc - tp.tp) / tp.porb * invb);
-          dz[4] = float(tp.asini * om * c2 * invb);
+          dz[2] = float(-rs / tp.asini * invb);
+          dz[3] = float(rsp * (tsrc - tp.tp) / tp.porb * invb);
+          dz[4] = float(rsp * invb);
         }
       }
       zs[w] = z;

@@ -17,6 +17,7 @@
 #include "fstat_prologue.hpp"
 #include "fstat_resample.hpp"
 #include "fstat_adjoint.hpp"
+#include "fstat_sft.hpp"
 
 using namespace fstat;
 
@@ -76,8 +77,8 @@ constexpr int kRowsMax = (8192 >> LOGL) < 32 ? (8192 >> LOGL) : 32;
 struct FftVariant {
   const void* fn;
   int threads;
-  size_t lds;  // dynamic LDS bytes
-  int lines;   // columns (column pass) or rows of each array (row pass) per item
+  size_t lds;    // dynamic LDS bytes
+  int lines;     // columns (column pass) or rows of each array (row pass) per item
 };
 
 // Variant choice of the FFT passes: full or half line counts (512 or 256
@@ -91,8 +92,8 @@ struct FftChoice {
 template <int LOGL, bool GROUPED, int MLR, int NL, int NT>
 FftVariant cols_variant_n() {
   constexpr int R0 = kR0<LOGL, MLR>;
-  return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, NL, NT, GROUPED, MLR>), NT,
-          kLdsBytes<1 << LOGL, R0, NL, NL>, NL};
+  constexpr size_t lds = kLdsBytes<1 << LOGL, R0, NL, NL>;
+  return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, NL, NT, GROUPED, MLR>), NT, lds, NL};
 }
 template <int LOGL, bool GROUPED, int MLR>
 FftVariant cols_variant(bool half) {
@@ -102,8 +103,8 @@ FftVariant cols_variant(bool half) {
 template <int LOGL, int MODE, int MLR, int RQ, int NT>
 FftVariant rows_variant_n() {
   constexpr int R0 = kR0<LOGL, MLR>;
-  return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, RQ, NT, MODE, MLR>), NT,
-          kLdsBytes<1 << LOGL, R0, RQ, 2 * RQ>, RQ};
+  constexpr size_t lds = kLdsBytes<1 << LOGL, R0, RQ, 2 * RQ>;
+  return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, RQ, NT, MODE, MLR>), NT, lds, RQ};
 }
 // The plain 2F pass at the full row count holds one array at a time in LDS
 // (k_fft_rows_split), so two 512-thread workgroups share a compute unit; with
@@ -197,7 +198,8 @@ fstat_status check_hip(hipError_t e, const char* what) {
 
 fstat_status validate_desc(const fstat_plan_desc* d) {
   if (!d) return fail(FSTAT_EINVAL, "desc is NULL");
-  if (d->flags != 0) return fail(FSTAT_EINVAL, "flags must be 0");
+  if (d->flags & ~FSTAT_PLAN_KEPLER)
+    return fail(FSTAT_EINVAL, "flags: only FSTAT_PLAN_KEPLER is defined");
   if (d->ndet < 1 || d->ndet > FSTAT_MAX_DET)
     return fail(FSTAT_EINVAL, "ndet=%d outside [1, %d]", d->ndet, FSTAT_MAX_DET);
   if (d->sinc_halfwidth != 4 && d->sinc_halfwidth != 6 && d->sinc_halfwidth != 8 &&
@@ -234,12 +236,19 @@ fstat_status validate_desc(const fstat_plan_desc* d) {
   return FSTAT_OK;
 }
 
+// Doubles per template row of a plan.
+int tmpl_stride(const fstat_plan* p) {
+  return (p->desc.flags & FSTAT_PLAN_KEPLER) ? FSTAT_TEMPLATE_STRIDE_KEPLER
+                                             : FSTAT_TEMPLATE_STRIDE;
+}
+
 PlanConst make_const(const fstat_plan* p, const fstat_inputs* in) {
   const fstat_plan_desc& d = p->desc;
   PlanConst P;
   std::memset(&P, 0, sizeof P);
   P.ndet = d.ndet;
   P.D = d.sinc_halfwidth;
+  P.tmpl_stride = tmpl_stride(p);
   P.dt = d.dt;
   P.inv_dt = 1.0 / d.dt;
   P.f_het = d.f_het;
@@ -292,7 +301,8 @@ fstat_status validate_inputs(const fstat_plan* p, const fstat_inputs* in, bool n
   if (!finite_pos(in->eph_dt) || !std::isfinite(in->eph_t0) || in->n_eph < 4)
     return fail(FSTAT_EINVAL, "ephemeris: need eph_dt > 0, finite eph_t0, n_eph >= 4");
   const fstat_plan_desc& d = p->desc;
-  const double span = kResTile * d.dt + 2.0 * (d.max_delay + (d.sinc_halfwidth + 2) * d.dt);
+  const double span = kResTile * d.dt +
+                      2.0 * (d.max_delay + (d.sinc_halfwidth + 2 + (1 << kKnotLogMax)) * d.dt);
   if (span / in->eph_dt + 4.0 > double(kNodeCap))
     return fail(FSTAT_EINVAL,
                 "ephemeris spacing %.6g s too fine: a resampling tile spans %.6g s and stages at "
@@ -318,7 +328,7 @@ fstat_status validate_ws(const fstat_plan* p, void* ws, size_t ws_bytes, int64_t
 }
 
 // One workgroup per FFT work item.
-unsigned fft_grid(int64_t n_items) {
+unsigned fft_grid(const FftVariant&, int64_t n_items) {
   return unsigned(std::max<int64_t>(n_items, 1));
 }
 int64_t cols_items(const fstat_plan* p, const FftVariant& v, int n) {
@@ -330,20 +340,25 @@ int64_t rows_items(const fstat_plan* p, const FftVariant& v, int n) {
 
 // Resampling kernel for a supported interpolation half-width.
 using ResFn = void (*)(PlanConst, void*, ChunkMap, int);
-template <bool GROUPED>
+template <bool GROUPED, bool KEP>
 ResFn resample_kernel_g(int D) {
   switch (D) {
-    case 4: return &k_resample<4, GROUPED>;
-    case 6: return &k_resample<6, GROUPED>;
-    case 8: return &k_resample<8, GROUPED>;
-    case 10: return &k_resample<10, GROUPED>;
-    case 12: return &k_resample<12, GROUPED>;
-    case 16: return &k_resample<16, GROUPED>;
+    case 4: return &k_resample<4, GROUPED, KEP>;
+    case 6: return &k_resample<6, GROUPED, KEP>;
+    case 8: return &k_resample<8, GROUPED, KEP>;
+    case 10: return &k_resample<10, GROUPED, KEP>;
+    case 12: return &k_resample<12, GROUPED, KEP>;
+    case 16: return &k_resample<16, GROUPED, KEP>;
     default: return nullptr;
   }
 }
-ResFn resample_kernel(int D, bool grouped) {
-  return grouped ? resample_kernel_g<true>(D) : resample_kernel_g<false>(D);
+// Plans with Keplerian rows take the kernels that carry the Kepler solver.
+bool kepler_plan(const fstat_plan* p) { return (p->desc.flags & FSTAT_PLAN_KEPLER) != 0; }
+ResFn resample_kernel(const fstat_plan* p, bool grouped) {
+  const int D = p->desc.sinc_halfwidth;
+  if (kepler_plan(p))
+    return grouped ? resample_kernel_g<true, true>(D) : resample_kernel_g<false, true>(D);
+  return grouped ? resample_kernel_g<true, false>(D) : resample_kernel_g<false, false>(D);
 }
 
 // Optional per-kernel timing: events recorded before and after each launch.
@@ -399,12 +414,12 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
   const int n_res = grouped ? map.n_grp : n;
   const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), grouped);
   const FftVariant rv = pick_rows(p->log_c, rows_choice(p), forward_row_mode(out));
-  if (!resample_kernel(p->desc.sinc_halfwidth, grouped) || !cv.fn || !rv.fn)
+  if (!resample_kernel(p, grouped) || !cv.fn || !rv.fn)
     return fail(FSTAT_EINTERNAL, "no kernel for D=%d, FFT lines 2^%d x 2^%d",
                 p->desc.sinc_halfwidth, p->log_rr, p->log_c);
   if (n_res > 0) {
     if ((s = tm.open(1)) != FSTAT_OK) return s;
-    hipLaunchKernelGGL(resample_kernel(p->desc.sinc_halfwidth, grouped),
+    hipLaunchKernelGGL(resample_kernel(p, grouped),
                        dim3(unsigned(p->k_pad / kResTile), n_res), dim3(kResThreads), 0, st, P,
                        ws, map, slots);
   }
@@ -415,12 +430,12 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
   }
   if ((s = tm.open(2)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn)),
-                     dim3(fft_grid(cols_items(p, cv, n))), dim3(cv.threads), cv.lds, st, P, ws, map,
+                     dim3(fft_grid(cv, cols_items(p, cv, n))), dim3(cv.threads), cv.lds, st, P, ws, map,
                      slots, 0, p->log_c,
                      p->rows_act);
   if ((s = tm.open(3)) != FSTAT_OK) return s;
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rv.fn)),
-                     dim3(fft_grid(rows_items(p, rv, n))), dim3(rv.threads), rv.lds, st, P, ws, map,
+                     dim3(fft_grid(rv, rows_items(p, rv, n))), dim3(rv.threads), rv.lds, st, P, ws, map,
                      slots, p->log_rr, out);
   return check_hip(hipGetLastError(), "kernel launch");
 }
@@ -511,33 +526,41 @@ size_t grad_slot_bytes(const fstat_plan* p) {
 }
 
 using GradFn = void (*)(PlanConst, void*);
-template <bool ONEHOT>
+template <bool ONEHOT, bool KEP>
 GradFn grad_kernel_o(int D) {
   switch (D) {
-    case 4: return &k_grad<4, ONEHOT>;
-    case 6: return &k_grad<6, ONEHOT>;
-    case 8: return &k_grad<8, ONEHOT>;
-    case 10: return &k_grad<10, ONEHOT>;
-    case 12: return &k_grad<12, ONEHOT>;
-    case 16: return &k_grad<16, ONEHOT>;
+    case 4: return &k_grad<4, ONEHOT, KEP>;
+    case 6: return &k_grad<6, ONEHOT, KEP>;
+    case 8: return &k_grad<8, ONEHOT, KEP>;
+    case 10: return &k_grad<10, ONEHOT, KEP>;
+    case 12: return &k_grad<12, ONEHOT, KEP>;
+    case 16: return &k_grad<16, ONEHOT, KEP>;
     default: return nullptr;
   }
 }
-GradFn grad_kernel(int D, bool onehot) {
-  return onehot ? grad_kernel_o<true>(D) : grad_kernel_o<false>(D);
+GradFn grad_kernel(const fstat_plan* p, bool onehot) {
+  const int D = p->desc.sinc_halfwidth;
+  if (kepler_plan(p))
+    return onehot ? grad_kernel_o<true, true>(D) : grad_kernel_o<false, true>(D);
+  return onehot ? grad_kernel_o<true, false>(D) : grad_kernel_o<false, false>(D);
 }
 
 using BinFn = void (*)(PlanConst, void*, ChunkMap, const int64_t*);
-BinFn resample_bin_kernel(int D) {
+template <bool KEP>
+BinFn resample_bin_kernel_k(int D) {
   switch (D) {
-    case 4: return &k_resample_bin<4>;
-    case 6: return &k_resample_bin<6>;
-    case 8: return &k_resample_bin<8>;
-    case 10: return &k_resample_bin<10>;
-    case 12: return &k_resample_bin<12>;
-    case 16: return &k_resample_bin<16>;
+    case 4: return &k_resample_bin<4, KEP>;
+    case 6: return &k_resample_bin<6, KEP>;
+    case 8: return &k_resample_bin<8, KEP>;
+    case 10: return &k_resample_bin<10, KEP>;
+    case 12: return &k_resample_bin<12, KEP>;
+    case 16: return &k_resample_bin<16, KEP>;
     default: return nullptr;
   }
+}
+BinFn resample_bin_kernel(const fstat_plan* p) {
+  return kepler_plan(p) ? resample_bin_kernel_k<true>(p->desc.sinc_halfwidth)
+                        : resample_bin_kernel_k<false>(p->desc.sinc_halfwidth);
 }
 
 // Single-bin adjoint slot: the parameter block and 8 doubles of partials per
@@ -557,11 +580,11 @@ fstat_status launch_grad_bin_chunk(const fstat_plan* p, const PlanConst& P,
   const int n = map.n_tmpl;
   const unsigned tiles = unsigned(p->k_pad / kResTile);
   hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, ws);
-  hipLaunchKernelGGL(resample_bin_kernel(p->desc.sinc_halfwidth), dim3(tiles, n),
+  hipLaunchKernelGGL(resample_bin_kernel(p), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws, map, bins);
   hipLaunchKernelGGL(k_bin_final, dim3((n + 63) / 64), dim3(64), 0, st, P, ws, map,
                      int64_t(tiles), bins, twoF);
-  hipLaunchKernelGGL(grad_kernel(p->desc.sinc_halfwidth, true), dim3(tiles, n),
+  hipLaunchKernelGGL(grad_kernel(p, true), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws);
   hipLaunchKernelGGL(k_grad_final, dim3((n * kGradParams + 63) / 64), dim3(64), 0, st, P, ws, map,
                      int64_t(tiles), grad);
@@ -578,14 +601,15 @@ fstat_status launch_grad_chunk(const fstat_plan* p, const PlanConst& P, const do
   const int n = map.n_tmpl;
   const unsigned tiles = unsigned(p->k_pad / kResTile);
   hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, ws);
-  hipLaunchKernelGGL(resample_kernel(p->desc.sinc_halfwidth, false), dim3(tiles, n),
+  hipLaunchKernelGGL(resample_kernel(p, false), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws, map, slots);
   const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), false);
   const ColsFn cols = reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn));
-  const dim3 cgrid(fft_grid(cols_items(p, cv, n)));
+  const dim3 cgrid(fft_grid(cv, cols_items(p, cv, n)));
   const FftVariant ra = pick_rows(p->log_c, rows_choice(p), kRowAdjoint);
   const FftVariant rc = pick_rows(p->log_c, rows_choice(p), kRowConj);
-  const dim3 rgrid_a(fft_grid(rows_items(p, ra, n))), rgrid_c(fft_grid(rows_items(p, rc, n)));
+  const dim3 rgrid_a(fft_grid(ra, rows_items(p, ra, n))),
+      rgrid_c(fft_grid(rc, rows_items(p, rc, n)));
   hipLaunchKernelGGL(cols, cgrid, dim3(cv.threads), cv.lds, st, P, ws, map, slots, 0,
                      p->log_c, p->rows_act);
   RowOutput oa = row_output(twoF, nullptr);
@@ -597,7 +621,7 @@ fstat_status launch_grad_chunk(const fstat_plan* p, const PlanConst& P, const do
   hipLaunchKernelGGL(reinterpret_cast<RowsFn>(const_cast<void*>(rc.fn)), rgrid_c, dim3(rc.threads),
                      rc.lds, st, P, ws, map, slots, p->log_rr,
                      row_output(nullptr, nullptr));
-  hipLaunchKernelGGL(grad_kernel(p->desc.sinc_halfwidth, false), dim3(tiles, n),
+  hipLaunchKernelGGL(grad_kernel(p, false), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws);
   hipLaunchKernelGGL(k_grad_final, dim3((n * kGradParams + 63) / 64), dim3(64), 0, st, P, ws, map,
                      int64_t(tiles), grad);
@@ -665,10 +689,12 @@ void inputs_key(const fstat_plan* p, const fstat_inputs* in, std::vector<uint64_
 }
 
 // Templates with the same sky position and orbit share the resampled series;
-// an isolated source (asini = 0) ignores porb and tp.
-bool same_timing(const double* a, const double* b) {
+// an isolated source (asini = 0) ignores porb and tp (and the Keplerian
+// elements of rows of `stride` 10).
+bool same_timing(const double* a, const double* b, int stride) {
   if (a[0] != b[0] || a[1] != b[1] || a[5] != b[5]) return false;
   if (a[5] == 0.0) return true;
+  if (stride >= FSTAT_TEMPLATE_STRIDE_KEPLER && (a[8] != b[8] || a[9] != b[9])) return false;
   return a[6] == b[6] && a[7] == b[7];
 }
 
@@ -792,9 +818,10 @@ fstat_status fstat_search_create(const fstat_plan* plan, const double* templates
   // (measured: chunks that end on group boundaries run the column pass ~20 %
   // faster than full chunks that split groups); larger groups fill chunks.
   std::vector<int64_t> gstart;
+  const int stride = tmpl_stride(plan);
   for (int64_t t = 0; t < ntmpl; ++t) {
-    const double* row = templates + t * FSTAT_TEMPLATE_STRIDE;
-    if (t == 0 || !same_timing(row, row - FSTAT_TEMPLATE_STRIDE)) gstart.push_back(t);
+    const double* row = templates + t * stride;
+    if (t == 0 || !same_timing(row, row - stride, stride)) gstart.push_back(t);
   }
   gstart.push_back(ntmpl);
   ChunkMap map;
@@ -1079,7 +1106,10 @@ fstat_status fstat_plan_create(const fstat_plan_desc* desc, fstat_plan** out) {
                 (long long)desc->n_fft, (long long)(int64_t(k_act)));
   }
   p->rows_act = p->k_pad >> p->log_c;
-  const double margin = desc->max_delay + 4.0 * desc->dt + 1.0;
+  // a tile evaluates the timing up to D + 2 + G samples beyond the delay
+  // bound (the staged window and its last phase knot)
+  const double margin =
+      desc->max_delay + double(desc->sinc_halfwidth + 2 + (1 << kKnotLogMax)) * desc->dt + 1.0;
   p->t_lo = std::min(desc->tau0, t_beg) - margin;
   p->t_hi = std::max(desc->tau0 + double(p->k_pad) * desc->dt, t_end) + margin;
   *out = p;
@@ -1316,6 +1346,91 @@ fstat_status fstat_compute_2f_grad_bin(const fstat_plan* plan, const fstat_input
     if (s != FSTAT_OK) return s;
   }
   return ok();
+}
+
+fstat_status fstat_sinc_halfwidth_for(double band_fraction, double tol_2f, int32_t* D,
+                                      double* err_2f) {
+  if (!D) return fail(FSTAT_EINVAL, "D is NULL");
+  if (!(band_fraction > 0.0 && band_fraction <= 1.0) || !(tol_2f > 0.0))
+    return fail(FSTAT_EINVAL, "need 0 < band_fraction <= 1 and tol_2f > 0");
+  // |zhat / z|^2 for a tone of nu cycles per sample interpolated at fractional
+  // offset u with the 2D-tap Hann-windowed sinc (taps j = -D+1 .. D)
+  auto power = [](int hw, double nu, double u) {
+    double re = 0.0, im = 0.0;
+    for (int j = -hw + 1; j <= hw; ++j) {
+      const double s = u - j;
+      const double h = s == 0.0 ? 1.0
+                                : std::sin(M_PI * s) / (M_PI * s) * 0.5 *
+                                      (1.0 + std::cos(M_PI * s / hw));
+      const double ph = 2.0 * M_PI * nu * (j - u);
+      re += h * std::cos(ph);
+      im += h * std::sin(ph);
+    }
+    return re * re + im * im;
+  };
+  constexpr int kNu = 65, kU = 32, kRef = 32;
+  const int choices[6] = {4, 6, 8, 10, 12, 16};
+  double err = 0.0;
+  for (int D_try : choices) {
+    err = 0.0;
+    for (int a = 0; a < kNu; ++a) {
+      const double nu = 0.5 * band_fraction * a / (kNu - 1);
+      for (int b = 0; b < kU; ++b) {
+        const double u = double(b) / kU;
+        err = std::max(err, std::fabs(power(D_try, nu, u) / power(kRef, nu, u) - 1.0));
+      }
+    }
+    *D = D_try;
+    if (err <= tol_2f) break;
+  }
+  if (err_2f) *err_2f = err;
+  if (err > tol_2f)
+    return fail(FSTAT_EUNSUPPORTED,
+                "no half-width up to 16 keeps the 2F error below %.3g over %.3g of the band "
+                "(16 gives %.3g)",
+                tol_2f, band_fraction, err);
+  return ok();
+}
+
+fstat_status fstat_sfts_to_series(const fstat_sft_desc* desc, const void* sfts,
+                                  const uint8_t* present, void* x, uint8_t* valid,
+                                  void* stream) {
+  if (!desc || !sfts || !x) return fail(FSTAT_EINVAL, "desc, sfts or x is NULL");
+  if (!finite_pos(desc->t_sft) || !std::isfinite(desc->t_start))
+    return fail(FSTAT_EINVAL, "t_sft must be positive and finite, t_start finite");
+  if (desc->n_sft < 1 || desc->k0 < 0 || desc->reserved != 0)
+    return fail(FSTAT_EINVAL, "need n_sft >= 1, k0 >= 0, reserved = 0");
+  const int K = desc->n_bins;
+  if (K < 2 || K > kSftMaxBins || (K & 1))
+    return fail(FSTAT_EUNSUPPORTED, "n_bins=%d: need an even count in [2, %d]", K, kSftMaxBins);
+  SftPlan sp;
+  std::memset(&sp, 0, sizeof sp);
+  sp.K = K;
+  int rest = K;
+  for (int r : {4, 2, 3, 5}) {
+    while (rest % r == 0 && sp.nstages < kSftMaxStages) {
+      sp.radix[sp.nstages++] = r;
+      rest /= r;
+    }
+  }
+  if (rest != 1)
+    return fail(FSTAT_EUNSUPPORTED, "n_bins=%d has a prime factor above 5", K);
+  // f_h t_start in cycles, reduced exactly: f_h t_start = kc t_start / t_sft
+  const double kc = double(desc->k0) + 0.5 * K;
+  const double turns = desc->t_start / desc->t_sft;
+  const double cyc = std::fmod(kc * (turns - std::floor(turns)), 1.0);
+  sp.het = make_float2(float(std::cos(2.0 * M_PI * cyc)), float(-std::sin(2.0 * M_PI * cyc)));
+  sp.scale = float(1.0 / desc->t_sft);
+  const size_t lds = size_t(3) * K * sizeof(float2);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sft_series),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  fstat_status s = check_hip(e, "hipFuncSetAttribute(sft)");
+  if (s != FSTAT_OK) return s;
+  hipLaunchKernelGGL(k_sft_series, dim3(unsigned(desc->n_sft)), dim3(kSftThreads), lds,
+                     static_cast<hipStream_t>(stream), sp, static_cast<const float2*>(sfts),
+                     present, static_cast<float2*>(x), valid);
+  s = check_hip(hipGetLastError(), "sft launch");
+  return s == FSTAT_OK ? ok() : s;
 }
 
 fstat_status fstat_flagged_count(const void* workspace, size_t ws_bytes, void* stream,

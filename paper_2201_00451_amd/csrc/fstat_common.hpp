@@ -29,6 +29,17 @@ constexpr int kResWcap = kResTile + kResTile / 16 + 64 + 8;
 // Ephemeris nodes a resampling tile stages in LDS (projected on the sky).
 constexpr int kNodeCap = 512;
 
+// Knot interpolation of the timing in the resampling kernel: the grid delays
+// and the heterodyne phases of the input samples are solved exactly every G
+// points (G = 2^knot_log2, 4 <= G <= 16, chosen per template from an error
+// bound) and interpolated in between by cubic Hermite in FP64; knot_log2 = 0
+// solves every point.  Knot capacities of one tile: grid knots G apart over
+// the tile and its end, sample knots G apart over the staged window.
+constexpr int kKnotLogMin = 2;
+constexpr int kKnotLogMax = 4;
+constexpr int kGridKnots = kResTile / (1 << kKnotLogMin) + 1;
+constexpr int kSampKnots = (kResWcap - 1) / (1 << kKnotLogMin) + 2;
+
 // Moment reduction: fixed block count per detector (deterministic order).
 constexpr int kMomBlocks = 256;
 constexpr int kMomThreads = 256;
@@ -51,6 +62,7 @@ struct DetConst {
 // Everything a kernel needs about the plan and the inputs (passed by value).
 struct PlanConst {
   int32_t ndet, D;
+  int32_t tmpl_stride;  // doubles per template row (8, or 10 for Keplerian orbits)
   double dt, inv_dt, f_het, t_ref, tau0, max_delay;
   double sid_rate_cyc;  // sidereal rate / 2 pi (cycles per s)
   int64_t n_fft, bin_lo, n_bins;
@@ -70,6 +82,10 @@ struct TmplParams {
   double nhat[3];
   double df, f1dot, f2dot, asini, om_b, tp;
   double nu_b;  // orbital frequency 1 / porb (0 for an isolated source)
+  // Keplerian orbit (kepler != 0): eccentricity, sin and cos of the argument
+  // of periapsis, sqrt(1 - ecc^2)
+  int32_t kepler;
+  double ecc, sin_w, cos_w, sq_e;
   // spin-down and sub-bin phase in quarter turns (4 x cycles) as a cubic in
   // the grid index k: 4 Phi(k) = sd[0] + k (sd[1] + k (sd[2] + k sd[3]))
   double sd[4];
@@ -81,6 +97,7 @@ struct TmplParams {
   float cb[kMaxDet][5];
   float l11, l21, l22;        // L, to report Fa = l11 Fa', Fb = l21 Fa' + l22 Fb'
   int32_t status;             // nonzero: every output bin of the template is NaN
+  int32_t knot_log2;          // knot spacing of the resampling's timing (0: none)
   // Adjoint only: derivatives of the sky direction and of the whitened
   // coefficients with respect to (alpha, delta) at fixed x, and 2 pi / porb.
   double dnhat[2][3];
@@ -356,10 +373,57 @@ __device__ inline void sincos_cycles(double c, double& sn, double& cs) {
   sn = (n & 2) ? -y1 : y1;
 }
 
-// Binary Roemer delay R(tau) = asini sin(2 pi (tau - tp) / porb) of the
-// source (0 for an isolated source).
+// Keplerian orbit: R(t') and R'(t') from the eccentric anomaly E of Kepler's
+// equation E - ecc sin E = M, M = 2 pi (t' - tp) / porb reduced to half a
+// turn in FP64 cycles; Newton's iteration from E = M + ecc sin M until the
+// update is at the rounding level (at most 12 steps; quadratic convergence
+// from this start for ecc < 0.95).
+__device__ inline void kepler_delay(const TmplParams& tp, double t, double& r, double& rp) {
+  double mc = (t - tp.tp) * tp.nu_b;
+  mc -= rint(mc);
+  const double M = 2.0 * kPi * mc;
+  double sm, cm;
+  sincos_cycles(mc, sm, cm);
+  double E = M + tp.ecc * sm, sE = 0.0, cE = 1.0;
+  for (int it = 0; it < 12; ++it) {
+    sincos_cycles(E * (0.5 / kPi), sE, cE);
+    const double step = (E - tp.ecc * sE - M) / (1.0 - tp.ecc * cE);
+    E -= step;
+    if (fabs(step) < 1e-15) break;
+  }
+  sincos_cycles(E * (0.5 / kPi), sE, cE);
+  r = tp.asini * (tp.sin_w * (cE - tp.ecc) + tp.cos_w * tp.sq_e * sE);
+  const double dr_de = tp.asini * (tp.cos_w * tp.sq_e * cE - tp.sin_w * sE);
+  rp = dr_de * tp.om_b / (1.0 - tp.ecc * cE);
+}
+
+// The source's orbital Roemer delay R(t') and its rate R'(t') (both 0 for
+// an isolated source): circular asini sin(2 pi (t' - tp) / porb), or the
+// Keplerian orbit.  KEP = false compiles the circular orbit only (plans
+// without Keplerian rows), so those kernels carry no Kepler solver.
+template <bool KEP>
+__device__ inline void orbit_delay(const TmplParams& tp, double t, double& r, double& rp) {
+  if (tp.asini == 0.0) {
+    r = rp = 0.0;
+  } else if (KEP && tp.kepler) {
+    kepler_delay(tp, t, r, rp);
+  } else {
+    double s, c;
+    sincos_cycles((t - tp.tp) * tp.nu_b, s, c);
+    r = tp.asini * s;
+    rp = tp.asini * tp.om_b * c;
+  }
+}
+
+// Binary Roemer delay R(tau) of the source (0 for an isolated source).
+template <bool KEP>
 __device__ inline double binary_delay(const TmplParams& tp, double tau) {
   if (tp.asini == 0.0) return 0.0;
+  if (KEP && tp.kepler) {
+    double r, rp;
+    kepler_delay(tp, tau, r, rp);
+    return r;
+  }
   double s, c;
   sincos_cycles((tau - tp.tp) * tp.nu_b, s, c);
   return tp.asini * s;
@@ -369,10 +433,10 @@ __device__ inline double binary_delay(const TmplParams& tp, double tau) {
 // time T satisfies T + roemer(T) = tau + R(tau).  One fixed-point step from
 // T = t_b then one Newton step; 1/(1 + roemer') by its series to third order
 // (|roemer'| < 1e-3 for any Earth-bound detector: residual < 1e-12 s).
-template <class RoemerFn, class... Flag>
+template <bool KEP, class RoemerFn, class... Flag>
 __device__ inline double grid_delay(const RoemerFn& roemer, const TmplParams& tp, double tau,
                                     Flag&... oob) {
-  const double rb = binary_delay(tp, tau);
+  const double rb = binary_delay<KEP>(tp, tau);
   double d0, dd0;
   roemer(tau + rb, d0, dd0, oob...);
   double dl = rb - d0;
@@ -418,20 +482,75 @@ __device__ inline double binary_inverse(const TmplParams& tp, double tb, double&
   return r0 - h * fma(g, fma(g, 1.0 - g, -1.0), 1.0);
 }
 
+// R(t_src) for a Keplerian orbit, t_src + R(t_src) = tb: Newton's iteration
+// from t_src = tb - R(tb), three steps (contraction max|R'| < 1e-2: residual
+// below 1e-12 s).
+__device__ inline double kepler_inverse(const TmplParams& tp, double tb) {
+  double r, rp;
+  kepler_delay(tp, tb, r, rp);
+  double ts = tb - r;
+  for (int it = 0; it < 3; ++it) {
+    kepler_delay(tp, ts, r, rp);
+    ts -= (ts + r - tb) / (1.0 + rp);
+  }
+  return tb - ts;
+}
+
+// R(t_src) for the emission that reaches the barycentre at tb, either orbit.
+template <bool KEP>
+__device__ inline double orbit_inverse(const TmplParams& tp, double tb) {
+  if (KEP && tp.kepler) return kepler_inverse(tp, tb);
+  double s, c;
+  return binary_inverse(tp, tb, s, c);
+}
+
 // Step (iii): for the detector sample time t return t_src - t, where
 // t_src + R(t_src) = t + roemer(t).  R is found by one Newton step from
-// R(t_b) (contraction asini * om_b < 1e-2: residual < 1e-12 s).
-template <class RoemerFn, class... Flag>
+// R(t_b) (contraction asini * om_b < 1e-2: residual < 1e-12 s), or for a
+// Keplerian orbit by kepler_inverse.
+template <bool KEP, class RoemerFn, class... Flag>
 __device__ inline double sample_delay(const RoemerFn& roemer, const TmplParams& tp, double t,
                                       Flag&... oob) {
   double dr, ddr;
   roemer(t, dr, ddr, oob...);
   double r = 0.0;
-  if (tp.asini != 0.0) {
-    double s, c;
-    r = binary_inverse(tp, t + dr, s, c);
-  }
+  if (tp.asini != 0.0) r = orbit_inverse<KEP>(tp, t + dr);
   return dr - r;
+}
+
+// Step (iii) at a knot: the heterodyne phase f_h (t_src - t) in cycles at
+// the detector sample time t and its rate per second,
+//   d(t_src - t)/dt = roemer'(t) - R'(t_src) (1 + roemer'(t)) / (1 + R'(t_src)),
+// with the orbital phase at t_src taken again after the inverse (its first
+// iterate is 1e-3 s off, too far for the rate).
+template <bool KEP, class RoemerFn, class... Flag>
+__device__ inline void sample_phase(const RoemerFn& roemer, const TmplParams& tp, double t,
+                                    double f_het, double& ph, double& dph, Flag&... oob) {
+  double dr, ddr;
+  roemer(t, dr, ddr, oob...);
+  double r = 0.0, rate = 0.0;
+  if (tp.asini != 0.0) {
+    r = orbit_inverse<KEP>(tp, t + dr);
+    double r2, rp;
+    orbit_delay<KEP>(tp, t + dr - r, r2, rp);
+    rate = rp * (1.0 + ddr) / (1.0 + rp);
+  }
+  ph = f_het * (dr - r);
+  dph = f_het * (ddr - rate);
+}
+
+// Cubic Hermite coefficients in u in [0, 1] of one knot interval from the
+// values and the derivatives per unit step at its ends, the ends g steps
+// apart: p(u) = c0 + u (c1 + u (c2 + u c3)).
+__device__ inline void hermite_interval(double2 a, double2 b, double g, double2& lo,
+                                        double2& hi) {
+  lo = make_double2(a.x, g * a.y);
+  hi = make_double2(3.0 * (b.x - a.x) - g * (2.0 * a.y + b.y),
+                    2.0 * (a.x - b.x) + g * (a.y + b.y));
+}
+__device__ __forceinline__ double hermite_eval(const double2* c, int seg, double u) {
+  const double2 lo = c[2 * seg], hi = c[2 * seg + 1];
+  return fma(fma(fma(hi.y, u, hi.x), u, lo.y), u, lo.x);
 }
 
 // Split a fractional sample position into floor and fraction, keeping the

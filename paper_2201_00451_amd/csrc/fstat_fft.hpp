@@ -228,33 +228,28 @@ constexpr int kPer0 = (NL * ((1 << LOGL) / kR0<LOGL, MLR>) + NT - 1) / NT;
 
 struct ColItem {
   int live, g, arr;
-  int64_t c0;
+  int64_t cg;  // column group: columns cg * NL .. cg * NL + NL - 1
   double sd[4];
 };
 
 // Column pass: lines are NL consecutive columns [c0, c0 + NL) of one array of
-// one template slot; line length Rr = 2^LOGL.  Rows at or beyond rows_act are
-// zero padding and are not read.  The first Stockham stage reads its inputs
-// straight from HBM and the last one writes its outputs, times the four-step
-// twiddle W_N^{q c}, straight back (both with columns fastest across
-// threads: NL-element contiguous runs); only the middle stages go through
-// LDS.  Items: (C / NL column groups) x 2 arrays x template slots.
+// one template slot; line length Rr = 2^LOGL.  Rows at or beyond rows_act
+// are zero padding and are not read.  The first Stockham stage reads its
+// inputs straight from HBM and the last one writes its outputs, times the
+// four-step twiddle W_N^{q c}, straight back (both with columns fastest
+// across threads: NL-element contiguous runs); only the middle stages go
+// through LDS.  Items: (C / NL column groups) x 2 arrays x template slots.
 // GROUPED: the input is the unphased series of the slot's sky/orbit group;
 // stage 0 applies the template's spin-down phase while loading and the
 // output goes to the slot's own buffer.
-template <int LOGL, int NL, int NT, bool GROUPED, int MLR>
-__device__ __forceinline__ ColItem cols_fetch(const PlanConst& P, void* ws, const ChunkMap& map,
-                                              int slots, int arr_base, int64_t C,
-                                              int64_t rows_act, int item,
-                                              float2 (&v)[kPer0<LOGL, NL, NT, MLR>]
-                                                         [kR0<LOGL, MLR>]) {
-  constexpr int L = 1 << LOGL;
-  constexpr int R0 = kR0<LOGL, MLR>, NB0 = NL * (L / R0);
-  constexpr int PER = kPer0<LOGL, NL, NT, MLR>;
+//
+// Item description (status, columns, array, spin-down coefficients).
+template <bool GROUPED>
+__device__ __forceinline__ ColItem cols_item(const PlanConst& P, void* ws, const ChunkMap& map,
+                                             int slots, int n_gx, int item) {
   ColItem it;
   it.live = 0;
-  const int n_gx = int(C / NL);
-  it.c0 = int64_t(item % n_gx) * NL;
+  it.cg = int64_t(item % n_gx);
   const int rest = item / n_gx;
   it.arr = rest & 1;
   it.g = rest >> 1;
@@ -269,50 +264,49 @@ __device__ __forceinline__ ColItem cols_fetch(const PlanConst& P, void* ws, cons
   it.live = 1;
 #pragma unroll
   for (int q = 0; q < 4; ++q) it.sd[q] = tpp->sd[q];
+  return it;
+}
+
+// The item's first-stage inputs into registers (buffer loads; rows at or
+// beyond rows_act lie past the descriptor's end and read as zero).
+template <int LOGL, int NL, int NT, bool GROUPED, int MLR>
+__device__ __forceinline__ void cols_load(const PlanConst& P, void* ws, const ChunkMap& map,
+                                          int slots, int arr_base, int64_t C, int64_t rows_act,
+                                          const ColItem& it,
+                                          float2 (&v)[kPer0<LOGL, NL, NT, MLR>]
+                                                     [kR0<LOGL, MLR>]) {
+  constexpr int L = 1 << LOGL;
+  constexpr int R0 = kR0<LOGL, MLR>, NB0 = NL * (L / R0);
+  constexpr int PER = kPer0<LOGL, NL, NT, MLR>;
   const float2* src = GROUPED ? group_buf(ws, P, slots, map.tmpl_buf[it.g], it.arr)
                               : slot_buf(ws, P, it.g, arr_base + it.arr);
-  // rows at or beyond rows_act lie past the descriptor's end and read as zero
   const auto rs = buf_rsrc(src, uint32_t(rows_act * C * int64_t(sizeof(float2))));
   const int tid = threadIdx.x;
+  const int64_t c0 = it.cg * NL;
 #pragma unroll
   for (int s = 0; s < PER; ++s) {
     const int b = tid + s * NT;
     if (NB0 % NT == 0 || b < NB0) {
       const int line = b % NL, i = b / NL;
-      const uint32_t voff = uint32_t((int64_t(i) * C + it.c0 + line) * int64_t(sizeof(float2)));
+      const uint32_t voff = uint32_t((int64_t(i) * C + c0 + line) * int64_t(sizeof(float2)));
 #pragma unroll
       for (int j = 0; j < R0; ++j)
         v[s][j] = buf_load2(rs, voff, uint32_t(int64_t(j) * (L / R0) * C * int64_t(sizeof(float2))));
     }
   }
-  return it;
 }
 
+// Stage 0: registers -> (spin-down phase-in) -> DFT -> LDS.
 template <int LOGL, int NL, int NT, bool GROUPED, int MLR>
-__global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap map, int slots,
-                                                 int arr_base, int log_c, int64_t rows_act) {
-  extern __shared__ float2 lds[];
+__device__ __forceinline__ void cols_stage0(const ColItem& it, int64_t C, int64_t rows_act,
+                                            float2 (&v)[kPer0<LOGL, NL, NT, MLR>]
+                                                       [kR0<LOGL, MLR>],
+                                            float2* lds, int tid) {
   constexpr int L = 1 << LOGL;
-  constexpr int NS = stage_count(LOGL, MLR);
   constexpr int R0 = kR0<LOGL, MLR>, NB0 = NL * (L / R0);
-  constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = NL * PL;
   constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
   using Lay = LdsLayout<L, R0, NL>;
-  float2* twl = lds + NL * Lay::pitch;
-  const int tid = threadIdx.x;
-  const int64_t C = int64_t(1) << log_c;
-  {
-    const float2* __restrict__ tws = tw_stage(ws);
-    for (int e = tid; e < L / 2; e += NT) twl[e] = tws[e * (kTwLen / L)];
-  }
-  float2 v[PER0][R0];
-  const ColItem it = cols_fetch<LOGL, NL, NT, GROUPED, MLR>(
-      P, ws, map, slots, arr_base, C, rows_act, int(xcd_remap(blockIdx.x, gridDim.x)), v);
-  if (!it.live) return;
-  const int64_t nmask = P.n_fft - 1;
-  const auto wr = buf_rsrc(slot_buf(ws, P, it.g, arr_base + it.arr),
-                           uint32_t(P.n_fft * int64_t(sizeof(float2))));
-  // stage 0: registers -> DFT -> LDS
+  const int64_t c0 = it.cg * NL;
 #pragma unroll
   for (int s = 0; s < PER0; ++s) {
     const int b = tid + s * NT;
@@ -323,7 +317,7 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
         for (int j = 0; j < R0; ++j) {
           const int r = i + j * (L / R0);
           if (r < rows_act)
-            v[s][j] = cmul_exact(v[s][j], spindown_rotation(it.sd, int64_t(r) * C + it.c0 + line));
+            v[s][j] = cmul_exact(v[s][j], spindown_rotation(it.sd, int64_t(r) * C + c0 + line));
         }
       }
       dft<R0>(v[s]);
@@ -331,9 +325,23 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
       for (int m = 0; m < R0; ++m) lds[Lay::at_block(i, m, line)] = v[s][m];
     }
   }
-  __syncthreads();
+}
+
+// Middle stages in LDS, then the last stage: LDS -> DFT -> x W_N^{q c} -> HBM.
+template <int LOGL, int NL, int NT, int MLR>
+__device__ __forceinline__ void cols_finish(const PlanConst& P, void* ws, int arr_base,
+                                            int64_t C, const ColItem& it, float2* lds,
+                                            const float2* twl, int tid) {
+  constexpr int L = 1 << LOGL;
+  constexpr int NS = stage_count(LOGL, MLR);
+  constexpr int R0 = kR0<LOGL, MLR>;
+  constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = NL * PL;
+  using Lay = LdsLayout<L, R0, NL>;
   fft_middle<LOGL, NL, NT, 1, MLR, Lay>(lds, twl, tid);
-  // last stage: LDS -> registers -> DFT -> x W_N^{q c} -> HBM
+  const int64_t nmask = P.n_fft - 1;
+  const int64_t c0 = it.cg * NL;
+  const auto wr = buf_rsrc(slot_buf(ws, P, it.g, arr_base + it.arr),
+                           uint32_t(P.n_fft * int64_t(sizeof(float2))));
   constexpr int PER = (NBL + NT - 1) / NT;
 #pragma unroll
   for (int s = 0; s < PER; ++s) {
@@ -344,7 +352,7 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
 #pragma unroll
       for (int j = 0; j < RL; ++j) u[j] = lds[Lay::template at_step<PL>(i, j, line)];
       twiddle_dft<RL, PL, L>(u, i, twl);
-      const int64_t c = it.c0 + line;
+      const int64_t c = c0 + line;
       // W_N^{c (i + m PL)} = W_N^{c i} (W_N^{c PL})^m
       float2 w = tw_n((int64_t(i) * c) & nmask, P.n_fft);
       const float2 step = tw_n((int64_t(PL) * c) & nmask, P.n_fft);
@@ -357,6 +365,31 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
       }
     }
   }
+}
+
+template <int LOGL, int NL, int NT, bool GROUPED, int MLR>
+__global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap map, int slots,
+                                                 int arr_base, int log_c, int64_t rows_act) {
+  extern __shared__ float2 lds[];
+  constexpr int L = 1 << LOGL;
+  constexpr int R0 = kR0<LOGL, MLR>;
+  constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
+  using Lay = LdsLayout<L, R0, NL>;
+  float2* twl = lds + NL * Lay::pitch;
+  const int tid = threadIdx.x;
+  const int64_t C = int64_t(1) << log_c;
+  {
+    const float2* __restrict__ tws = tw_stage(ws);
+    for (int e = tid; e < L / 2; e += NT) twl[e] = tws[e * (kTwLen / L)];
+  }
+  float2 v[PER0][R0];
+  const ColItem it = cols_item<GROUPED>(P, ws, map, slots, int(C / NL),
+                                        int(xcd_remap(blockIdx.x, gridDim.x)));
+  if (!it.live) return;
+  cols_load<LOGL, NL, NT, GROUPED, MLR>(P, ws, map, slots, arr_base, C, rows_act, it, v);
+  cols_stage0<LOGL, NL, NT, GROUPED, MLR>(it, C, rows_act, v, lds, tid);
+  __syncthreads();
+  cols_finish<LOGL, NL, NT, MLR>(P, ws, arr_base, C, it, lds, twl, tid);
 }
 
 // Row pass with the 2F epilogue (eq. Fstat, normalised as 2F = 2 F^T M^-1 F,
@@ -531,17 +564,93 @@ __device__ __forceinline__ void rows_flagged(const PlanConst& P, void* ws, const
   }
 }
 
+// Stage 0 of both arrays (registers -> DFT -> LDS).
+template <int LOGL, int RQ, int NT, int MLR, int NL>
+__device__ __forceinline__ void rows_stage0(float2* lds, int tid,
+                                            float2 (&v)[kPer0<LOGL, NL, NT, MLR>]
+                                                       [kR0<LOGL, MLR>]) {
+  constexpr int L = 1 << LOGL;
+  constexpr int R0 = kR0<LOGL, MLR>, NBL0 = L / R0;
+  constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
+  using Lay = LdsLayout<L, R0, RQ>;
+#pragma unroll
+  for (int s = 0; s < PER0; ++s) {
+    const int b = tid + s * NT;
+    if ((NL * NBL0) % NT == 0 || b < NL * NBL0) {
+      const int i = b % NBL0, line = b / NBL0;
+      dft<R0>(v[s]);
+#pragma unroll
+      for (int m = 0; m < R0; ++m) lds[Lay::at_block(i, m, line)] = v[s][m];
+    }
+  }
+}
+
+// Middle stages, then the last stage of both arrays and the epilogue.
+template <int LOGL, int RQ, int NT, int MODE, int MLR>
+__device__ __forceinline__ void rows_finish(const PlanConst& P, void* ws, const RowItem& it,
+                                            const RowOutput& out, int64_t Rr, float2* lds,
+                                            const float2* twl, int tid) {
+  constexpr int L = 1 << LOGL;
+  constexpr int NL = 2 * RQ;
+  constexpr int NS = stage_count(LOGL, MLR);
+  constexpr int R0 = kR0<LOGL, MLR>;
+  constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = RQ * PL;
+  constexpr int PER = (NBL + NT - 1) / NT;
+  using Lay = LdsLayout<L, R0, RQ>;
+  fft_middle<LOGL, NL, NT, 1, MLR, Lay>(lds, twl, tid);
+  unsigned long long bkey = 0ull;
+  // plain 2F: band offsets o = ((nat + N/2) mod N) - bin_lo in 32 bits; the
+  // descriptor spans this template's n_bins floats, so the store of a bin
+  // outside the band (o >= n_bins, also when the subtraction wraps) is dropped
+  const auto tf = buf_rsrc(MODE == kRow2F ? out.twoF + it.tmpl * P.n_bins : nullptr,
+                           MODE == kRow2F ? uint32_t(P.n_bins * int64_t(sizeof(float))) : 0u);
+  const uint32_t nmask = uint32_t(P.n_fft - 1), lo = uint32_t(P.bin_lo);
+  const uint32_t ostep = uint32_t(Rr * PL);
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int b = tid + s * NT;
+    if (NBL % NT == 0 || b < NBL) {
+      const int ql = b % RQ, i = b / RQ;
+      float2 va[RL], vb[RL];
+#pragma unroll
+      for (int j = 0; j < RL; ++j) {
+        va[j] = lds[Lay::template at_step<PL>(i, j, ql)];
+        vb[j] = lds[Lay::template at_step<PL>(i, j, RQ + ql)];
+      }
+      twiddle_dft<RL, PL, L>(va, i, twl);
+      twiddle_dft<RL, PL, L>(vb, i, twl);
+      if (MODE == kRow2F) {
+        const uint32_t o0 = uint32_t(it.q0 + ql + Rr * i) + uint32_t(P.n_fft / 2);
+#pragma unroll
+        for (int m = 0; m < RL; ++m) {
+          const uint32_t o = ((o0 + uint32_t(m) * ostep) & nmask) - lo;
+          buf_store1(two_f(va[m], vb[m]), tf, o * uint32_t(sizeof(float)));
+        }
+        continue;
+      }
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        const int64_t nat = it.q0 + ql + Rr * int64_t(i + m * PL);
+        const float v2 = rows_out<MODE>(P, ws, it, nat, va[m], vb[m], out);
+        if (v2 >= 0.0f) {
+          const unsigned long long key =
+              best_key(v2, ((nat + P.n_fft / 2) & (P.n_fft - 1)) - P.bin_lo);
+          bkey = key > bkey ? key : bkey;
+        }
+      }
+    }
+  }
+  if (MODE == kRow2FExt && out.best) best_to_global(out, it.tmpl, bkey);
+}
+
 template <int LOGL, int RQ, int NT, int MODE, int MLR>
 __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap map, int slots,
                                                  int log_rr, RowOutput out) {
   extern __shared__ float2 lds[];
   constexpr int L = 1 << LOGL;
   constexpr int NL = 2 * RQ;  // lines: the a rows then the b rows
-  constexpr int NS = stage_count(LOGL, MLR);
-  constexpr int R0 = kR0<LOGL, MLR>, NBL0 = L / R0;
-  constexpr int RL = 1 << stage_logr(LOGL, NS - 1, MLR), PL = L / RL, NBL = RQ * PL;
+  constexpr int R0 = kR0<LOGL, MLR>;
   constexpr int PER0 = kPer0<LOGL, NL, NT, MLR>;
-  constexpr int PER = (NBL + NT - 1) / NT;
   using Lay = LdsLayout<L, R0, RQ>;
   float2* twl = lds + NL * Lay::pitch;
   const int64_t Rr = int64_t(1) << log_rr;
@@ -557,66 +666,11 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
       rows_item<MODE>(P, ws, map, int(xcd_remap(blockIdx.x, gridDim.x)), int(Rr / RQ), RQ);
   if (it.flagged && MODE != kRowConj) rows_flagged<LOGL, RQ, NT>(P, ws, it, Rr, out);
   if (!it.live) return;
-  {
-    float2 v[PER0][R0];
-    rows_load<LOGL, RQ, NT, MODE, MLR, 0, PER0>(P, ws, it, v);
-    // stage 0 of both arrays: registers -> DFT -> LDS
-#pragma unroll
-    for (int s = 0; s < PER0; ++s) {
-      const int b = tid + s * NT;
-      if ((NL * NBL0) % NT == 0 || b < NL * NBL0) {
-        const int i = b % NBL0, line = b / NBL0;
-        dft<R0>(v[s]);
-#pragma unroll
-        for (int m = 0; m < R0; ++m) lds[Lay::at_block(i, m, line)] = v[s][m];
-      }
-    }
-    __syncthreads();
-    fft_middle<LOGL, NL, NT, 1, MLR, Lay>(lds, twl, tid);
-    unsigned long long bkey = 0ull;
-    // plain 2F: band offsets o = ((nat + N/2) mod N) - bin_lo in 32 bits; the
-    // descriptor spans this template's n_bins floats, so the store of a bin
-    // outside the band (o >= n_bins, also when the subtraction wraps) is dropped
-    const auto tf = buf_rsrc(MODE == kRow2F ? out.twoF + it.tmpl * P.n_bins : nullptr,
-                             MODE == kRow2F ? uint32_t(P.n_bins * int64_t(sizeof(float))) : 0u);
-    const uint32_t nmask = uint32_t(P.n_fft - 1), lo = uint32_t(P.bin_lo);
-    const uint32_t ostep = uint32_t(Rr * PL);
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int b = tid + s * NT;
-      if (NBL % NT == 0 || b < NBL) {
-        const int ql = b % RQ, i = b / RQ;
-        float2 va[RL], vb[RL];
-#pragma unroll
-        for (int j = 0; j < RL; ++j) {
-          va[j] = lds[Lay::template at_step<PL>(i, j, ql)];
-          vb[j] = lds[Lay::template at_step<PL>(i, j, RQ + ql)];
-        }
-        twiddle_dft<RL, PL, L>(va, i, twl);
-        twiddle_dft<RL, PL, L>(vb, i, twl);
-        if (MODE == kRow2F) {
-          const uint32_t o0 = uint32_t(it.q0 + ql + Rr * i) + uint32_t(P.n_fft / 2);
-#pragma unroll
-          for (int m = 0; m < RL; ++m) {
-            const uint32_t o = ((o0 + uint32_t(m) * ostep) & nmask) - lo;
-            buf_store1(two_f(va[m], vb[m]), tf, o * uint32_t(sizeof(float)));
-          }
-          continue;
-        }
-#pragma unroll
-        for (int m = 0; m < RL; ++m) {
-          const int64_t nat = it.q0 + ql + Rr * int64_t(i + m * PL);
-          const float v2 = rows_out<MODE>(P, ws, it, nat, va[m], vb[m], out);
-          if (v2 >= 0.0f) {
-            const unsigned long long key =
-                best_key(v2, ((nat + P.n_fft / 2) & (P.n_fft - 1)) - P.bin_lo);
-            bkey = key > bkey ? key : bkey;
-          }
-        }
-      }
-    }
-    if (MODE == kRow2FExt && out.best) best_to_global(out, it.tmpl, bkey);
-  }
+  float2 v[PER0][R0];
+  rows_load<LOGL, RQ, NT, MODE, MLR, 0, PER0>(P, ws, it, v);
+  rows_stage0<LOGL, RQ, NT, MLR, NL>(lds, tid, v);
+  __syncthreads();
+  rows_finish<LOGL, RQ, NT, MODE, MLR>(P, ws, it, out, Rr, lds, twl, tid);
 }
 
 // Plain 2F row pass holding one array at a time: the RQ rows of y_a' are

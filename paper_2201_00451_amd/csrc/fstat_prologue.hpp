@@ -135,6 +135,8 @@ __host__ __device__ inline void template_params(const PlanConst& P, const double
   tp.asini = row[5];
   double porb = row[6];
   tp.tp = row[7];
+  const double ecc = P.tmpl_stride >= FSTAT_TEMPLATE_STRIDE_KEPLER ? row[8] : 0.0;
+  const double argp = P.tmpl_stride >= FSTAT_TEMPLATE_STRIDE_KEPLER ? row[9] : 0.0;
   int status = 0;
   // porb and tp describe the orbit only when asini != 0: an isolated
   // source (asini = 0) ignores them, whatever they hold
@@ -145,9 +147,43 @@ __host__ __device__ inline void template_params(const PlanConst& P, const double
       !__builtin_isfinite(tp.f2dot))
     status |= kStatusPhase;
   if (tp.asini < 0.0 || (tp.asini != 0.0 && !(porb > 0.0))) status |= kStatusTiming;
+  // Keplerian elements (used only when asini != 0)
+  if (tp.asini != 0.0 && !(ecc >= 0.0 && ecc < 1.0 && __builtin_isfinite(argp)))
+    status |= kStatusTiming;
+  tp.kepler = (tp.asini != 0.0 && (ecc != 0.0 || argp != 0.0)) ? 1 : 0;
+  tp.ecc = tp.kepler ? ecc : 0.0;
+  tp.sq_e = sqrt(1.0 - tp.ecc * tp.ecc);
+  if (tp.kepler) {
+    sincos(argp, &tp.sin_w, &tp.cos_w);
+  } else {
+    tp.sin_w = 0.0;
+    tp.cos_w = 1.0;
+  }
   if (tp.asini > P.max_delay) status |= kStatusCoverage;
   tp.om_b = (tp.asini != 0.0 && porb > 0.0) ? 2.0 * kPi / porb : 0.0;
   tp.nu_b = (tp.asini != 0.0 && porb > 0.0) ? 1.0 / porb : 0.0;
+  // Knot spacing of the resampling's timing: the largest G = 2^l <= 16 for
+  // which the cubic Hermite bound (G dt)^4 / 384 max|delay''''| stays below
+  // 2e-7 cycles of the heterodyne phase f_h and 1e-7 samples of grid
+  // position.  The binary delay contributes asini om^4; the Earth's motion,
+  // tabulated as C1-joined cubics, contributes far less than the floor
+  // taken here.  Below G = 4, every point is solved (knot_log2 = 0).
+  {
+    // the Keplerian delay's fourth derivative grows like (om / (1 - ecc)^2)^4
+    // near periapsis (a bound, not the exact maximum)
+    const double w = tp.om_b / ((1.0 - tp.ecc) * (1.0 - tp.ecc));
+    const double om2 = w * w;
+    const double d4 = fabs(tp.asini) * om2 * om2 + 1e-16;
+    const double budget = fmin(2e-7 / fmax(fabs(P.f_het), 1.0), 1e-7 * P.dt);
+    tp.knot_log2 = 0;
+    for (int l = kKnotLogMax; l >= kKnotLogMin; --l) {
+      const double h = double(1 << l) * P.dt, h2 = h * h;
+      if (h2 * h2 / 384.0 * d4 <= budget) {
+        tp.knot_log2 = l;
+        break;
+      }
+    }
+  }
   spindown_coefficients(P, tp.f1dot, tp.f2dot, tp.df, tp.sd);
   double sa, ca_, sd, cdl;
   sincos(alpha, &sa, &ca_);
@@ -265,9 +301,9 @@ __device__ inline void full_params(const PlanConst& P, const double* row, TmplPa
       if (X >= P.ndet) continue;
       const DetConst& d = P.det[X];
       const GlobalRoemer re{d.ephem, tp.nhat, P.n_eph, P.eph_t0, P.eph_dt, P.inv_eph_dt};
-      double u_first = 0.0 + d.off + grid_delay(re, tp, P.tau0) * P.inv_dt;
+      double u_first = 0.0 + d.off + grid_delay<true>(re, tp, P.tau0) * P.inv_dt;
       double k_last = double(P.k_pad - 1);
-      double u_last = k_last + d.off + grid_delay(re, tp, P.tau0 + k_last * P.dt) * P.inv_dt;
+      double u_last = k_last + d.off + grid_delay<true>(re, tp, P.tau0 + k_last * P.dt) * P.inv_dt;
       if (!(u_first <= 0.0) || !(u_last >= double(d.n - 1 + P.D))) status |= kStatusCoverage;
     }
   }
@@ -289,7 +325,7 @@ __global__ __launch_bounds__(64) void k_prologue(PlanConst P, const double* __re
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= map.n_tmpl) return;
   TmplParams tp;
-  full_params(P, templates + map.tmpl[g] * FSTAT_TEMPLATE_STRIDE, tp);
+  full_params(P, templates + map.tmpl[g] * P.tmpl_stride, tp);
   *slot_params(ws, P, g) = tp;
 }
 
@@ -306,7 +342,7 @@ __global__ __launch_bounds__(64) void k_params(PlanConst P, const double* __rest
   if (t >= ntmpl) return;
   if (out.best) out.best[t] = 0ull;
   TmplParams tp;
-  full_params(P, templates + t * FSTAT_TEMPLATE_STRIDE, tp);
+  full_params(P, templates + t * P.tmpl_stride, tp);
   *reinterpret_cast<TmplParams*>(P.params + size_t(t) * kParamBytes) = tp;
 }
 

@@ -32,6 +32,8 @@
 // accumulation; sin(pi f) multiplies the finished sum.
 #pragma once
 
+#include <utility>
+
 #include "fstat_common.hpp"
 
 namespace fstat {
@@ -105,12 +107,49 @@ __host__ __device__ constexpr TapConst make_taps() {
 template <int D>
 __constant__ TapConst kTaps = make_taps<D>();
 
+// One tap of the forward interpolation with its constants as compile-time
+// literals: with c = D - 1 - T the tap's integer offset,
+//   h_T (up to the common factor sin(pi f) / (2 pi)) =
+//     (-1)^c (1 + cos(pi c/D) cos(pi f/D) - sin(pi c/D) sin(pi f/D)) / (f + c),
+// the Hann window by angle addition and the sinc's alternating sign folded
+// into the accumulation.  Two literal FMAs for the window, one reciprocal,
+// one multiply and two FMAs per tap; no constant reaches a register.
+template <int D, int T>
+__device__ __forceinline__ void interp_tap(float f, float wc, float ws, const float2* zp,
+                                           float& sx, float& sy) {
+  constexpr int c = D - 1 - T;
+  constexpr float cs = float(ct_cospi(c, D));
+  constexpr float sn = float(ct_sinpi(c, D));
+  const float w = fmaf(wc, cs, fmaf(ws, -sn, 1.0f));
+  float h = w * __builtin_amdgcn_rcpf(f + float(c));
+  if constexpr ((c & 1) != 0) h = -h;
+  const float2 zv = zp[T];
+  sx = fmaf(h, zv.x, sx);
+  sy = fmaf(h, zv.y, sy);
+}
+template <int D, int... T>
+__device__ __forceinline__ void interp_taps(std::integer_sequence<int, T...>, float f, float wc,
+                                            float ws, const float2* zp, float& sx, float& sy) {
+  (interp_tap<D, T>(f, wc, ws, zp, sx, sy), ...);
+}
+
 // Steps (iii)-(v) and the antenna weighting for the kResTile grid points of
 // the tile starting at k_s: acc_a[i], acc_b[i] receive sum_X a'_X(T_k)
 // zhat_X(u_k) (and b'), k = k_s + tid + i kResThreads, before the spin-down
 // phase.  Returns false, after flagging the template's status word, when the
 // template must report NaN (the return is uniform across the block).
-template <int D>
+//
+// Timing (tp.knot_log2 = log2 G > 0): the grid delays q_k = (T_k - tau_k)/dt
+// are solved exactly at every G-th grid point of the tile and its end, the
+// heterodyne phases f_h (t_src,j - t_j) at every G-th staged sample, each
+// with its derivative, and every point in between takes the cubic Hermite of
+// its interval (FP64).  G is chosen per template so that the interpolation
+// error stays below 2e-7 cycles of phase and 1e-7 samples of grid position.
+// knot_log2 = 0: every grid point and sample is solved.
+// Zero samples (gaps, and outside the data) are staged as zeros without any
+// timing; a wave whose outputs' taps all fall on zero samples skips the
+// interpolation (it would add zeros).
+template <int D, bool KEP>
 __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
                                      int32_t* status_word, int64_t k_s,
                                      float2 (&acc_a)[kResPerThread],
@@ -118,6 +157,10 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
   const int tid = threadIdx.x;
   __shared__ float2 zs[kResWcap];
   __shared__ double2 coef[2 * kNodeCap];
+  __shared__ double2 knot[kSampKnots];           // knot values and derivatives
+  __shared__ double2 gc[2 * (kGridKnots - 1)];   // grid-delay intervals
+  __shared__ double2 sc[2 * (kSampKnots - 1)];   // sample-phase intervals
+  __shared__ int32_t blk[(kResWcap + kResThreads) / 32 + 2];
   __shared__ int64_t win_lo, win_hi;
   __shared__ int bad;
 
@@ -128,8 +171,14 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
     acc_a[i] = make_float2(0.f, 0.f);
     acc_b[i] = make_float2(0.f, 0.f);
   }
-  // time span any delay evaluation of this tile can reach
-  const double pad = P.max_delay + double(D + 2) * P.dt;
+  const int kl = tp.knot_log2;
+  const bool knots = kl != 0;
+  const int G = 1 << kl;
+  const double inv_g = 1.0 / double(G);
+  const int nkg = kResTile / G + 1;
+  // time span any delay evaluation of this tile can reach (sample knots run
+  // up to G samples past the staged window)
+  const double pad = P.max_delay + double(D + 2 + (1 << kKnotLogMax)) * P.dt;
   const double t_first = P.tau0 + P.dt * double(k_s) - pad;
   const double t_last = P.tau0 + P.dt * double(k_s + kResTile - 1) + pad;
   int64_t n_lo = int64_t(floor((t_first - P.eph_t0) * P.inv_eph_dt)) - 1;
@@ -141,11 +190,17 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
   const CubicRoemer re{coef, n_count, P.eph_t0 + double(n_lo) * P.eph_dt, P.inv_eph_dt};
   const double tau_s = P.tau0 + P.dt * double(k_s);
   // the binary delay depends on the grid point only: once for all detectors
-  const double rb0 = binary_delay(tp, tau_s);
+  // (at the own grid knot, with its rate, or at the own grid points)
+  double rb0 = 0.0, rbd0 = 0.0;
   double rbk[kResPerThread];
+  if (knots) {
+    if (tid < nkg) orbit_delay<KEP>(tp, tau_s + P.dt * double(tid * G), rb0, rbd0);
+  } else {
+    rb0 = binary_delay<KEP>(tp, tau_s);
 #pragma unroll
-  for (int i = 0; i < kResPerThread; ++i)
-    rbk[i] = binary_delay(tp, tau_s + P.dt * double(tid + i * kResThreads));
+    for (int i = 0; i < kResPerThread; ++i)
+      rbk[i] = binary_delay<KEP>(tp, tau_s + P.dt * double(tid + i * kResThreads));
+  }
 
   for (int X = 0; X < P.ndet; ++X) {
     const DetConst& d = P.det[X];
@@ -159,28 +214,53 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
       cubic_interval(p0, v0, p1, v1, P.eph_dt, coef[2 * i], coef[2 * i + 1]);
     }
     __syncthreads();
-    // 2. detector epochs: the tile's first point in full (fixed point, two
-    // Newton steps), the rest by one Newton step from a prediction that
-    // carries the exact binary delay and linearises the Roemer delay about
-    // the first point: T ~ T_s + (t_b - t_b,s) / (1 + roemer'(T_s)).
-    double x0;
-    double d0 = grid_delay(re, tp, tau_s, oob);
-    d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
-    d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
-    const double inv0 = 1.0 - x0 * (1.0 - x0 * (1.0 - x0));
-    double dly[kResPerThread];
+    // 2. detector epochs of the own grid points as q = (T - tau)/dt and
+    // u = (T - t0)/dt = k + off + q
+    double q[kResPerThread];
     int64_t j0[kResPerThread];
     float fr[kResPerThread];
+    if (knots) {
+      // exact solves at the grid knots (fixed point and three Newton steps),
+      // with dq/dk = d(T - tau)/dtau = (R'(tau) - roemer'(T)) / (1 + roemer'(T))
+      if (tid < nkg) {
+        const double tau = tau_s + P.dt * double(tid * G);
+        double x;
+        double dl = grid_delay<KEP>(re, tp, tau, oob);
+        dl = grid_delay_newton(re, tau, rb0, dl, x, oob);
+        dl = grid_delay_newton(re, tau, rb0, dl, x, oob);
+        knot[tid] = make_double2(dl * P.inv_dt, (rbd0 - x) / (1.0 + x));
+      }
+      __syncthreads();
+      if (tid < nkg - 1) hermite_interval(knot[tid], knot[tid + 1], double(G), gc[2 * tid],
+                                          gc[2 * tid + 1]);
+      __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kResPerThread; ++i) {
-      const int64_t kk = tid + i * kResThreads;
-      const double dtau = P.dt * double(kk);
-      const double tau = tau_s + dtau;
-      const double rb = rbk[i];
-      const double guess = d0 + (dtau + rb - rb0) * inv0 - dtau;
-      double x;
-      dly[i] = grid_delay_newton(re, tau, rb, guess, x, oob);
-      split_u(double(k_s + kk) + d.off + dly[i] * P.inv_dt, j0[i], fr[i]);
+      for (int i = 0; i < kResPerThread; ++i) {
+        const int kk = tid + i * kResThreads;
+        q[i] = hermite_eval(gc, kk >> kl, double(kk & (G - 1)) * inv_g);
+        split_u(double(k_s + kk) + d.off + q[i], j0[i], fr[i]);
+      }
+    } else {
+      // the tile's first point in full (fixed point, two Newton steps), the
+      // rest by one Newton step from a prediction that carries the exact
+      // binary delay and linearises the Roemer delay about the first point:
+      // T ~ T_s + (t_b - t_b,s) / (1 + roemer'(T_s))
+      double x0;
+      double d0 = grid_delay<KEP>(re, tp, tau_s, oob);
+      d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
+      d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
+      const double inv0 = 1.0 - x0 * (1.0 - x0 * (1.0 - x0));
+#pragma unroll
+      for (int i = 0; i < kResPerThread; ++i) {
+        const int64_t kk = tid + i * kResThreads;
+        const double dtau = P.dt * double(kk);
+        const double tau = tau_s + dtau;
+        const double rb = rbk[i];
+        const double guess = d0 + (dtau + rb - rb0) * inv0 - dtau;
+        double x;
+        q[i] = grid_delay_newton(re, tau, rb, guess, x, oob) * P.inv_dt;
+        split_u(double(k_s + kk) + d.off + q[i], j0[i], fr[i]);
+      }
     }
     if (tid == 0) win_lo = j0[0] - D + 1;
     if (tid == kResThreads - 1) win_hi = j0[kResPerThread - 1] + D;
@@ -193,18 +273,42 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
       return false;
     }
     const int W = int(nwin);
-    // 3. corrected input samples
-    for (int w = tid; w < W; w += kResThreads) {
-      int64_t j = lo + w;
+    // 3. corrected input samples: knots of the heterodyne phase first
+    if (knots) {
+      const int nks = ((W - 1) >> kl) + 2;
+      if (tid < nks) {
+        double ph, dph;
+        sample_phase<KEP>(re, tp, d.t0 + P.dt * double(lo + int64_t(tid) * G), P.f_het, ph, dph,
+                     oob);
+        knot[tid] = make_double2(ph, dph * P.dt);
+      }
+      __syncthreads();
+      if (tid < nks - 1) hermite_interval(knot[tid], knot[tid + 1], double(G), sc[2 * tid],
+                                          sc[2 * tid + 1]);
+      __syncthreads();
+    }
+    for (int w0 = 0; w0 < W; w0 += kResThreads) {
+      const int w = w0 + tid;
+      const int64_t j = lo + w;
+      const float2 xv = (w < W && j >= 0 && j < d.n) ? d.x[j] : make_float2(0.f, 0.f);
+      // a zero sample (outside the data, or in a gap) stays zero: no timing
+      const bool live = xv.x != 0.f || xv.y != 0.f;
       float2 z = make_float2(0.f, 0.f);
-      if (j >= 0 && j < d.n) {
-        float2 xv = d.x[j];
-        double dl = sample_delay(re, tp, d.t0 + P.dt * double(j), oob);
-        const float2 e = cis_cycles(P.f_het * dl);
+      if (live) {
+        const double ph = knots ? hermite_eval(sc, w >> kl, double(w & (G - 1)) * inv_g)
+                                : P.f_het * sample_delay<KEP>(re, tp, d.t0 + P.dt * double(j), oob);
+        const float2 e = cis_cycles(ph);
         // x * exp(-2 pi i f_h dl)
         z = make_float2(xv.x * e.x + xv.y * e.y, xv.y * e.x - xv.x * e.y);
       }
-      zs[w] = z;
+      if (w < W) zs[w] = z;
+      // which 32-sample blocks of the window hold a live sample
+      const unsigned long long m = __ballot(live);
+      if ((tid & 63) == 0) {
+        const int b = (w0 + tid) >> 5;
+        blk[b] = uint32_t(m) != 0u;
+        blk[b + 1] = uint32_t(m >> 32) != 0u;
+      }
     }
     __syncthreads();
     // 4. interpolation and antenna weighting
@@ -215,6 +319,7 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
       // the clamp only guards memory
       int base = int(j0[i] - lo) - (D - 1);
       base = base < 0 ? 0 : (base > W - 2 * D ? W - 2 * D : base);
+      if (!(blk[base >> 5] | blk[(base + 2 * D - 1) >> 5])) continue;
       const float2* zp = zs + base;
       float2 zh;
       if (f == 0.0f) {
@@ -222,22 +327,14 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
       } else {
         // window phase pi f / D and sinc numerator sin(pi f), in cycles
         const float2 wcs = cis_cycles_f32(f * (0.5f / float(D)));
-        const float ws_ = wcs.y, wc_ = wcs.x;
         float sx = 0.f, sy = 0.f;
-#pragma unroll
-        for (int t = 0; t < 2 * D; ++t) {
-          const float win = fmaf(kTaps<D>.B[t], ws_, fmaf(kTaps<D>.A[t], wc_, kTaps<D>.C[t]));
-          const float h = win * __builtin_amdgcn_rcpf(f + float(D - 1 - t));
-          const float2 zv = zp[t];
-          sx = fmaf(h, zv.x, sx);
-          sy = fmaf(h, zv.y, sy);
-        }
-        const float sp = cis_cycles_f32(0.5f * f).y;
+        interp_taps<D>(std::make_integer_sequence<int, 2 * D>{}, f, wcs.x, wcs.y, zp, sx, sy);
+        const float sp = cis_cycles_f32(0.5f * f).y * float(0.5 / kPi);
         zh = make_float2(sx * sp, sy * sp);
       }
       // antenna patterns at T_k: x = alpha - phi(T_k), in cycles
       const double tau = tau_s + P.dt * double(tid + i * kResThreads);
-      const float2 ex = cis_cycles(tp.alpha_cyc[X] - P.sid_rate_cyc * (tau + dly[i]));
+      const float2 ex = cis_cycles(tp.alpha_cyc[X] - P.sid_rate_cyc * (tau + q[i] * P.dt));
       const float cx = ex.x, sx = ex.y;
       const float c2 = cx * cx - sx * sx, s2 = 2.0f * sx * cx;
       const float a = tp.ca[X][0] + tp.ca[X][1] * cx + tp.ca[X][2] * sx + tp.ca[X][3] * c2 +
@@ -272,7 +369,7 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
 // thread): the timing's FP64 and LDS latency chains hide better with more
 // waves (measured at 1024-point tiles: three waves against two, 11 % on sky
 // positions and 17 % on binary orbits).
-template <int D, bool GROUPED>
+template <int D, bool GROUPED, bool KEP>
 __global__ __launch_bounds__(kResThreads, 4) void k_resample(PlanConst P, void* ws, ChunkMap map,
                                                          int slots) {
   const int gi = blockIdx.y;
@@ -297,7 +394,7 @@ __global__ __launch_bounds__(kResThreads, 4) void k_resample(PlanConst P, void* 
     return;
   }
   float2 acc_a[kResPerThread], acc_b[kResPerThread];
-  if (!resample_tile<D>(P, tp, status_word, k_s, acc_a, acc_b)) return;
+  if (!resample_tile<D, KEP>(P, tp, status_word, k_s, acc_a, acc_b)) return;
 #pragma unroll
   for (int i = 0; i < kResPerThread; ++i) {
     const int64_t k = k_s + threadIdx.x + i * kResThreads;
@@ -328,7 +425,7 @@ __host__ __device__ inline int64_t band_bin_nat(const PlanConst& P, int64_t i) {
 // m per template as a direct sum over the grid, sum_k y'_k exp(-2 pi i m k/N)
 // (step (vi) restricted to one output bin), reduced per tile into the slot's
 // partials (Fa'.re, Fa'.im, Fb'.re, Fb'.im in FP64).
-template <int D>
+template <int D, bool KEP>
 __global__ __launch_bounds__(kResThreads, 4) void k_resample_bin(PlanConst P, void* ws, ChunkMap map,
                                                              const int64_t* __restrict__ bins) {
   const int slot = blockIdx.y;
@@ -339,7 +436,7 @@ __global__ __launch_bounds__(kResThreads, 4) void k_resample_bin(PlanConst P, vo
   const int tid = threadIdx.x;
   if (tp.status != 0) return;
   float2 acc_a[kResPerThread], acc_b[kResPerThread];
-  if (!resample_tile<D>(P, tp, &tpp->status, k_s, acc_a, acc_b)) return;
+  if (!resample_tile<D, KEP>(P, tp, &tpp->status, k_s, acc_a, acc_b)) return;
   const int64_t bin = bins[map.tmpl[slot]];
   const int64_t nat = band_bin_nat(P, bin);
   double s[4] = {0.0, 0.0, 0.0, 0.0};

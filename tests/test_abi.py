@@ -57,6 +57,8 @@ int main(void) {
   F(fstat_plan_desc, det); F(fstat_plan_desc, dt); F(fstat_plan_desc, n_fft);
   F(fstat_plan_desc, flags); F(fstat_inputs, valid); F(fstat_inputs, n_eph);
   F(fstat_inputs, moments); F(fstat_detector, n); F(fstat_detector, noise_var);
+  printf("fstat_sft_desc %zu\n", sizeof(fstat_sft_desc));
+  F(fstat_sft_desc, n_sft); F(fstat_sft_desc, n_bins); F(fstat_sft_desc, reserved);
   return 0;
 }
 ''')
@@ -78,6 +80,10 @@ int main(void) {
         "fstat_inputs.moments": B.FstatInputs.moments.offset,
         "fstat_detector.n": B.FstatDetector.n.offset,
         "fstat_detector.noise_var": B.FstatDetector.noise_var.offset,
+        "fstat_sft_desc": ctypes.sizeof(B.FstatSftDesc),
+        "fstat_sft_desc.n_sft": B.FstatSftDesc.n_sft.offset,
+        "fstat_sft_desc.n_bins": B.FstatSftDesc.n_bins.offset,
+        "fstat_sft_desc.reserved": B.FstatSftDesc.reserved.offset,
     }
     assert {k: int(v) for k, v in got.items()} == want
 
@@ -127,7 +133,7 @@ def test_plan_accepts_valid_setup(lib):
     (lambda d: setattr(d, "dt", 0.0), "dt"),
     (lambda d: setattr(d, "dt", float("nan")), "dt"),
     (lambda d: setattr(d, "sid_rate", -1.0), "sid_rate"),
-    (lambda d: setattr(d, "flags", 1), "flags"),
+    (lambda d: setattr(d, "flags", 2), "flags"),
     (lambda d: setattr(d.det[1], "noise_var", 0.0), "noise_var"),
     (lambda d: setattr(d.det[0], "n", 0), "n must be"),
     (lambda d: setattr(d.det[0], "az_y", d.det[0].az_x + 1.0), "orthogonal"),
@@ -346,3 +352,55 @@ def test_batch_checks_arguments_before_any_launch(lib):
     assert run(b, ins, ptrs, ptrs, ptrs, sizes, vp(4096)) == B.FSTAT_EINVAL
     lib.fstat_batch_destroy(b)
     lib.fstat_search_destroy(h)
+
+
+def test_sft_entry_checks_arguments_before_any_launch(lib):
+    """fstat_sfts_to_series: invalid descriptions are refused on the host."""
+    buf = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails first
+
+    def call(**kw):
+        d = B.FstatSftDesc(0.0, 300.0, 10, 29925, 150, 0)
+        for k, v in kw.items():
+            setattr(d, k, v)
+        return lib.fstat_sfts_to_series(ctypes.byref(d), buf, None, buf, None, None)
+
+    assert lib.fstat_sfts_to_series(None, buf, None, buf, None, None) == B.FSTAT_EINVAL
+    assert call(t_sft=0.0) == B.FSTAT_EINVAL
+    assert call(n_sft=0) == B.FSTAT_EINVAL
+    assert call(k0=-1) == B.FSTAT_EINVAL
+    assert call(reserved=1) == B.FSTAT_EINVAL
+    assert call(n_bins=151) == B.FSTAT_EUNSUPPORTED        # odd
+    assert call(n_bins=2 * 7 * 11) == B.FSTAT_EUNSUPPORTED  # prime factors above 5
+    assert call(n_bins=8192) == B.FSTAT_EUNSUPPORTED        # beyond 4096
+    d = B.FstatSftDesc(0.0, 300.0, 10, 29925, 150, 0)
+    assert lib.fstat_sfts_to_series(ctypes.byref(d), None, None, buf, None, None) == B.FSTAT_EINVAL
+
+
+def test_sinc_halfwidth_for_accuracy_bound(lib):
+    """The accuracy rule for D against the oracle's own kernel definition
+    (Hann-windowed sinc, 2D taps) evaluated here: the chosen D meets the bound
+    over the band and the next smaller choice does not."""
+    from oracle import fstat_oracle as O
+    import numpy as np
+
+    def worst(D, frac):
+        e = 0.0
+        for nu in np.linspace(0.0, frac / 2, 33):
+            for u in np.linspace(0.0, 1.0, 17)[:-1]:
+                j = np.arange(-D + 1, D + 1)
+                jr = np.arange(-31, 33)
+                a = np.abs(np.sum(O.sinc_kernel(u - j, D) * np.exp(2j * np.pi * nu * (j - u)))) ** 2
+                r = np.abs(np.sum(O.sinc_kernel(u - jr, 32) * np.exp(2j * np.pi * nu * (jr - u)))) ** 2
+                e = max(e, abs(a / r - 1))
+        return e
+
+    choices = (4, 6, 8, 10, 12, 16)
+    for frac, tol in ((0.3, 1e-3), (0.5, 1e-3), (0.5, 1e-2)):
+        D, err = B.sinc_halfwidth_for(frac, tol)
+        assert D in choices and err <= tol
+        assert worst(D, frac) <= tol * 1.05
+        if D != choices[0]:
+            smaller = choices[choices.index(D) - 1]
+            assert worst(smaller, frac) > tol
+    with pytest.raises(B.FstatError):
+        B.sinc_halfwidth_for(0.95, 1e-6)

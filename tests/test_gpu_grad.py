@@ -44,6 +44,8 @@ CASES = {
                          noise_vars=[1.0, 0.7, 1.4]),
     "ragged_band": dict(seed=55, n=3000, n_fft=1 << 13, ndet=1, rho=25, bin_lo=1500,
                         n_bins=3001),
+    "kepler": dict(seed=52, n=3000, n_fft=1 << 13, ndet=2, gaps=True, rho=20, binary=True,
+                   ecc=0.3, argp=0.9),
 }
 
 
