@@ -426,6 +426,22 @@ FSTAT_API fstat_status fstat_compute_2f_grad_bin(const fstat_plan* plan, const f
 FSTAT_API fstat_status fstat_flagged_count(const void* workspace, size_t ws_bytes, void* stream,
                                            int64_t* count);
 
+/* fstat_compute_2f_grad_bin for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same computation, with the workspace taken from a static
+ * device array of the library (32 MiB per GPU, held until the process ends)
+ * instead of an argument.  Calls nothing that allocates.  Fails with
+ * FSTAT_EWORKSPACE when fstat_grad_bin_workspace_size(plan, 1) exceeds the
+ * array (a 2^24-point grid needs about 2.2 MB per template); as many
+ * templates as fit, up to 32, share each launch.  Every call on one GPU
+ * uses that GPU's one array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller. */
+FSTAT_API fstat_status fstat_compute_2f_grad_bin_noalloc(const fstat_plan* plan,
+                                                         const fstat_inputs* in,
+                                                         const double* templates, int64_t ntmpl,
+                                                         const int64_t* bins, float* twoF,
+                                                         double* grad, void* stream);
+
 /* Wait for the stream and report any asynchronous HIP error as FSTAT_EHIP. */
 FSTAT_API fstat_status fstat_sync_check(void* stream);
 

@@ -30,7 +30,7 @@ EXPORTED = ("fstat_plan_create", "fstat_plan_destroy", "fstat_workspace_size",
             "fstat_grad_bin_workspace_size", "fstat_compute_2f_grad_bin", "fstat_autotune",
             "fstat_search_run_candidates", "fstat_batch_create", "fstat_batch_destroy",
             "fstat_batch_run", "fstat_flagged_count", "fstat_sfts_to_series",
-            "fstat_sinc_halfwidth_for")
+            "fstat_compute_2f_grad_bin_noalloc", "fstat_sinc_halfwidth_for")
 GRAD_PARAMS = ("df", "f1dot", "alpha", "delta", "asini", "porb", "tp")
 # template-row column of each gradient parameter
 GRAD_COLUMNS = (2, 3, 0, 1, 5, 6, 7)
@@ -134,6 +134,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fstat_sinc_halfwidth_for.argtypes = [ctypes.c_double, ctypes.c_double,
                                              ctypes.POINTER(ctypes.c_int32),
                                              ctypes.POINTER(ctypes.c_double)]
+    lib.fstat_compute_2f_grad_bin_noalloc.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, i64,
+                                                      vp, vp, vp, vp]
     lib.fstat_sfts_to_series.argtypes = [ctypes.POINTER(FstatSftDesc), vp, vp, vp, vp, vp]
     lib.fstat_sync_check.argtypes = [vp]
     lib.fstat_last_error.restype = ctypes.c_char_p
@@ -375,6 +377,22 @@ def compute_2f_grad_bin(dd: DeviceData, templates, bins, batch=32, stream=None):
     _check(load_library().fstat_compute_2f_grad_bin(
         dd.plan.handle, ctypes.byref(dd.inputs), _ptr(tm), n, _ptr(b), _ptr(tf), _ptr(grad),
         _ptr(dd.grad_bin_ws), dd.grad_bin_ws.numel(), _stream_ptr(stream)))
+    return grad, tf
+
+
+def compute_2f_grad_bin_noalloc(dd: DeviceData, templates, bins, stream=None):
+    """compute_2f_grad_bin without a workspace argument: the library's static
+    device scratch (fstat_compute_2f_grad_bin_noalloc).  Returns (grad [n, 7]
+    float64, 2F [n] float32) on the device."""
+    import torch
+    tm = _templates(dd, templates)
+    n = tm.shape[0]
+    b = torch.as_tensor(np.asarray(bins, dtype=np.int64)).to(dd.device).contiguous()
+    grad = torch.empty((n, len(GRAD_PARAMS)), dtype=torch.float64, device=dd.device)
+    tf = torch.empty((n,), dtype=torch.float32, device=dd.device)
+    _check(load_library().fstat_compute_2f_grad_bin_noalloc(
+        dd.plan.handle, ctypes.byref(dd.inputs), _ptr(tm), n, _ptr(b), _ptr(tf), _ptr(grad),
+        _stream_ptr(stream)))
     return grad, tf
 
 

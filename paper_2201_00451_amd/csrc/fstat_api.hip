@@ -21,6 +21,13 @@
 
 using namespace fstat;
 
+// Device scratch of the entry point that allocates nothing: one copy per GPU
+// the library runs on, kept until the process ends.  Host code never uses
+// the array's name as an address: each device's address comes from
+// hipGetSymbolAddress (static_scratch below).
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
 struct fstat_plan {
   fstat_plan_desc desc;
   int log_n, log_rr, log_c;  // N = Rr * C
@@ -1448,6 +1455,53 @@ fstat_status fstat_flagged_count(const void* workspace, size_t ws_bytes, void* s
   if (s != FSTAT_OK) return s;
   *count = int64_t(v);
   return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // device address of `scratch`, per device
+
+// The current device's copy of the static scratch, looked up once per device.
+fstat_status static_scratch(void** out) {
+  int dev = 0;
+  fstat_status s = check_hip(hipGetDevice(&dev), "get device");
+  if (s != FSTAT_OK) return s;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr.size() <= size_t(dev)) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    s = check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch symbol address");
+    if (s != FSTAT_OK) return s;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FSTAT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fstat_status fstat_compute_2f_grad_bin_noalloc(const fstat_plan* plan, const fstat_inputs* in,
+                                               const double* templates, int64_t ntmpl,
+                                               const int64_t* bins, float* twoF, double* grad,
+                                               void* stream) {
+  if (!plan) return fail(FSTAT_EINVAL, "plan is NULL");
+  size_t need = 0;
+  fstat_status s = fstat_grad_bin_workspace_size(plan, 1, &need);
+  if (s != FSTAT_OK) return s;
+  if (need > kStaticScratchBytes)
+    return fail(FSTAT_EWORKSPACE,
+                "this plan needs %zu bytes of scratch for one template; the static scratch "
+                "holds %zu",
+                need, kStaticScratchBytes);
+  void* ws = nullptr;
+  if ((s = static_scratch(&ws)) != FSTAT_OK) return s;
+  return fstat_compute_2f_grad_bin(plan, in, templates, ntmpl, bins, twoF, grad, ws,
+                                   kStaticScratchBytes, stream);
 }
 
 fstat_status fstat_sync_check(void* stream) {
