@@ -249,6 +249,27 @@ int tmpl_stride(const fstat_plan* p) {
                                              : FSTAT_TEMPLATE_STRIDE;
 }
 
+// Knot area of the search and plain forward paths (per detector: grid knots,
+// then sample knots, at the capacities of the smallest knot spacing that is
+// solved ahead of the resampling).
+int64_t knot_gcap(const fstat_plan* p) { return knot_grid_cap(p->k_pad); }
+int64_t knot_stride(const fstat_plan* p) {
+  int64_t scap = 0;
+  for (int X = 0; X < p->desc.ndet; ++X)
+    scap = std::max<int64_t>(scap, knot_samp_cap(p->desc.det[X].n));
+  return knot_gcap(p) + scap;
+}
+size_t knot_area_bytes(const fstat_plan* p) {
+  return (size_t(p->desc.ndet) * size_t(knot_stride(p)) * sizeof(double2) + 255) / 256 * 256;
+}
+// Plain-path slot: parameter block, y_a' and y_b' (n_fft each), knot area.
+size_t plain_slot_bytes(const fstat_plan* p) {
+  return slot_bytes(p->desc.n_fft, 2, knot_area_bytes(p));
+}
+int64_t plain_knot_offset(const fstat_plan* p) {
+  return int64_t(kParamBytes + size_t(2) * p->desc.n_fft * sizeof(float2));
+}
+
 PlanConst make_const(const fstat_plan* p, const fstat_inputs* in) {
   const fstat_plan_desc& d = p->desc;
   PlanConst P;
@@ -267,7 +288,13 @@ PlanConst make_const(const fstat_plan* p, const fstat_inputs* in) {
   P.bin_lo = d.bin_lo;
   P.n_bins = d.n_bins;
   P.k_pad = p->k_pad;
-  P.slot_stride = int64_t(slot_bytes(d.n_fft));
+  P.knot_stride = knot_stride(p);
+  P.knot_gcap = knot_gcap(p);
+  P.knot_bytes = int64_t(knot_area_bytes(p));
+  // the plain forward path's slot layout; the search and the adjoint paths
+  // set their own
+  P.slot_stride = int64_t(plain_slot_bytes(p));
+  P.knot_offset = plain_knot_offset(p);
   if (in) {
     P.n_eph = in->n_eph;
     P.eph_t0 = in->eph_t0;
@@ -326,7 +353,7 @@ fstat_status validate_ws(const fstat_plan* p, void* ws, size_t ws_bytes, int64_t
   if (!ws) return fail(FSTAT_EINVAL, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
     return fail(FSTAT_EINVAL, "workspace must be 256-byte aligned");
-  const size_t sb = slot_bytes(p->desc.n_fft);
+  const size_t sb = plain_slot_bytes(p);
   if (ws_bytes < kHeaderBytes + sb)
     return fail(FSTAT_EWORKSPACE, "workspace %zu bytes < %zu needed for one template", ws_bytes,
                 kHeaderBytes + sb);
@@ -361,6 +388,22 @@ ResFn resample_kernel_g(int D) {
 }
 // Plans with Keplerian rows take the kernels that carry the Kepler solver.
 bool kepler_plan(const fstat_plan* p) { return (p->desc.flags & FSTAT_PLAN_KEPLER) != 0; }
+using KnotFn = void (*)(PlanConst, void*, ChunkMap, int);
+KnotFn knot_kernel(const fstat_plan* p, bool grouped) {
+  if (kepler_plan(p)) return grouped ? &k_knots<true, true> : &k_knots<false, true>;
+  return grouped ? &k_knots<true, false> : &k_knots<false, false>;
+}
+// Timing knots of the chunk's groups (grouped) or slots, ahead of the
+// resampling (templates with a coarser knot spacing only; the kernel skips
+// the others).  Nothing when the slots carry no knot area.
+void launch_knots(const fstat_plan* p, const PlanConst& P, const ChunkMap& map, int slots,
+                  bool grouped, int n_res, void* ws, hipStream_t st) {
+  if (n_res < 1 || (!grouped && P.knot_offset == 0)) return;
+  hipLaunchKernelGGL(knot_kernel(p, grouped),
+                     dim3(unsigned((P.knot_stride + 255) / 256), n_res, p->desc.ndet), dim3(256),
+                     0, st, P, ws, map, slots);
+}
+
 ResFn resample_kernel(const fstat_plan* p, bool grouped) {
   const int D = p->desc.sinc_halfwidth;
   if (kepler_plan(p))
@@ -425,6 +468,9 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
     return fail(FSTAT_EINTERNAL, "no kernel for D=%d, FFT lines 2^%d x 2^%d",
                 p->desc.sinc_halfwidth, p->log_rr, p->log_c);
   if (n_res > 0) {
+    // (the knots are timed with the prologue)
+    if ((s = tm.open(0)) != FSTAT_OK) return s;
+    launch_knots(p, P, map, slots, grouped, n_res, ws, st);
     if ((s = tm.open(1)) != FSTAT_OK) return s;
     hipLaunchKernelGGL(resample_kernel(p, grouped),
                        dim3(unsigned(p->k_pad / kResTile), n_res), dim3(kResThreads), 0, st, P,
@@ -525,11 +571,14 @@ fstat_status run(const fstat_plan* p, const fstat_inputs* in, const double* temp
 }
 
 // Adjoint workspace slot: parameters, four arrays (y' / F', then the adjoint
-// spectrum and its transform) and 8 doubles of gradient partials per
-// resampling tile, padded to 256 bytes.
+// spectrum and its transform), 8 doubles of gradient partials per resampling
+// tile (padded to 256 bytes), and the knot area of the forward resampling
+// (so that its 2F is the forward path's, bit for bit).
+size_t grad_part_bytes(const fstat_plan* p) {
+  return (size_t(p->k_pad / kResTile) * 8 * sizeof(double) + 255) / 256 * 256;
+}
 size_t grad_slot_bytes(const fstat_plan* p) {
-  const size_t tiles = size_t(p->k_pad / kResTile);
-  return slot_bytes(p->desc.n_fft, 4, (tiles * 8 * sizeof(double) + 255) / 256 * 256);
+  return slot_bytes(p->desc.n_fft, 4, grad_part_bytes(p) + knot_area_bytes(p));
 }
 
 using GradFn = void (*)(PlanConst, void*);
@@ -608,6 +657,7 @@ fstat_status launch_grad_chunk(const fstat_plan* p, const PlanConst& P, const do
   const int n = map.n_tmpl;
   const unsigned tiles = unsigned(p->k_pad / kResTile);
   hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, ws);
+  launch_knots(p, P, map, slots, false, n, ws, st);
   hipLaunchKernelGGL(resample_kernel(p, false), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws, map, slots);
   const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), false);
@@ -710,7 +760,7 @@ bool same_timing(const double* a, const double* b, int stride) {
 size_t search_params_offset(const fstat_search* sr) {
   const fstat_plan* p = sr->plan;
   return kHeaderBytes + size_t(sr->slots) * slot_bytes(p->desc.n_fft) +
-         size_t(sr->slots) * group_bytes(p->k_pad);
+         size_t(sr->slots) * group_bytes(p->k_pad, int64_t(knot_area_bytes(p)));
 }
 size_t search_ws_bytes(const fstat_search* sr) {
   return search_params_offset(sr) + size_t(sr->ntmpl) * kParamBytes;
@@ -720,6 +770,10 @@ fstat_status search_launch(fstat_search* sr, const fstat_inputs* in, const doubl
                            const RowOutput& out, void* ws, hipStream_t st, KernelTimer& tm) {
   const fstat_plan* p = sr->plan;
   PlanConst P = make_const(p, in);
+  // template slots hold parameters and transforms only; the knots live in the
+  // group buffers
+  P.slot_stride = int64_t(slot_bytes(p->desc.n_fft));
+  P.knot_offset = 0;
   P.params = static_cast<char*>(ws) + search_params_offset(sr);
   hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, ws);
   fstat_status s0 = tm.open(0);
@@ -1137,7 +1191,7 @@ fstat_status fstat_plan_info(const fstat_plan* plan, int64_t* k_pad, int32_t* lo
 fstat_status fstat_workspace_size(const fstat_plan* plan, int64_t batch, size_t* bytes) {
   if (!plan || !bytes) return fail(FSTAT_EINVAL, "plan or bytes is NULL");
   if (batch < 1) return fail(FSTAT_EINVAL, "batch must be >= 1");
-  *bytes = kHeaderBytes + size_t(batch) * slot_bytes(plan->desc.n_fft);
+  *bytes = kHeaderBytes + size_t(batch) * plain_slot_bytes(plan);
   return ok();
 }
 
@@ -1296,6 +1350,7 @@ fstat_status fstat_compute_2f_grad(const fstat_plan* plan, const fstat_inputs* i
   PlanConst P = make_const(plan, in);
   P.slot_stride = int64_t(sb);
   P.part_offset = int64_t(kParamBytes + size_t(4) * plan->desc.n_fft * sizeof(float2));
+  P.knot_offset = P.part_offset + int64_t(grad_part_bytes(plan));
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, workspace);
   for (int64_t t = 0; t < ntmpl; t += slots) {
@@ -1340,6 +1395,7 @@ fstat_status fstat_compute_2f_grad_bin(const fstat_plan* plan, const fstat_input
   PlanConst P = make_const(plan, in);
   P.slot_stride = int64_t(sb);
   P.part_offset = int64_t(kParamBytes);
+  P.knot_offset = 0;  // the single-bin tiles solve their own knots
   hipStream_t st = static_cast<hipStream_t>(stream);
   // (clears the flagged-template counter)
   hipLaunchKernelGGL(k_twiddles, dim3(kTwLen / 256), dim3(256), 0, st, workspace);

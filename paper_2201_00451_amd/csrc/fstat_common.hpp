@@ -25,20 +25,42 @@ constexpr int kResTile = 512;
 constexpr int kResThreads = 256;
 constexpr int kResPerThread = kResTile / kResThreads;
 constexpr int kResWcap = kResTile + kResTile / 16 + 64 + 8;
+// Flags of the staged window's 32-sample blocks (any live sample).
+constexpr int kResBlk = (kResWcap + kResThreads) / 32 + 2;
 
-// Ephemeris nodes a resampling tile stages in LDS (projected on the sky).
-constexpr int kNodeCap = 512;
+// Ephemeris nodes a resampling tile stages in LDS (projected on the sky), per
+// detector: bounds the ephemeris spacing from below (a tile spans its
+// kResTile points plus twice the plan's max_delay and the tap reach).
+constexpr int kNodeCap = 128;
+
+// Detectors a resampling tile processes together: their timing solves,
+// staging and interpolation share the tile's phases (and barriers).
+constexpr int kDetPass = 2;
 
 // Knot interpolation of the timing in the resampling kernel: the grid delays
 // and the heterodyne phases of the input samples are solved exactly every G
-// points (G = 2^knot_log2, 4 <= G <= 16, chosen per template from an error
+// points (G = 2^knot_log2, 4 <= G <= 64, chosen per template from an error
 // bound) and interpolated in between by cubic Hermite in FP64; knot_log2 = 0
 // solves every point.  Knot capacities of one tile: grid knots G apart over
 // the tile and its end, sample knots G apart over the staged window.
 constexpr int kKnotLogMin = 2;
-constexpr int kKnotLogMax = 4;
+constexpr int kKnotLogMax = 6;
 constexpr int kGridKnots = kResTile / (1 << kKnotLogMin) + 1;
 constexpr int kSampKnots = (kResWcap - 1) / (1 << kKnotLogMin) + 2;
+
+// On the search and plain forward paths the knots of templates with
+// G >= 2^kKnotLogGlobal are solved ahead of the resampling, all in parallel,
+// into a knot area of the series' buffer; per detector: grid knots
+// (q, dq/dk) at k = m G, m = 0 .. k_pad / G, then sample knots (heterodyne
+// phase in cycles, its change per sample) at j = m G, m = 0 .. (n_X - 1) / G
+// + 1.  Capacities at the smallest such G.
+constexpr int kKnotLogGlobal = 4;
+__host__ __device__ inline int64_t knot_grid_cap(int64_t k_pad) {
+  return (k_pad >> kKnotLogGlobal) + 1;
+}
+__host__ __device__ inline int64_t knot_samp_cap(int64_t n) {
+  return ((n - 1) >> kKnotLogGlobal) + 2;
+}
 
 // Moment reduction: fixed block count per detector (deterministic order).
 constexpr int kMomBlocks = 256;
@@ -69,6 +91,11 @@ struct PlanConst {
   int64_t k_pad;        // grid points computed by the resampler (multiple of tile and row)
   int64_t slot_stride;  // bytes per template slot of the workspace (path dependent)
   int64_t part_offset;  // adjoint paths: bytes from a slot's start to its tile partials
+  int64_t knot_stride;  // double2 per detector of a knot area
+  int64_t knot_gcap;    // grid knots of a detector's area (its sample knots follow)
+  int64_t knot_bytes;   // bytes of a knot area (each group buffer holds one)
+  int64_t knot_offset;  // plain path: bytes from a slot's start to its knot area;
+                        // 0: the slots have none (the tiles solve their knots)
   char* params;         // search path: per-template parameter blocks (kParamBytes
                         // each, by template index); null: the slots' own blocks
   int64_t n_eph;
@@ -209,14 +236,22 @@ __host__ __device__ inline double* slot_partials(void* ws, const PlanConst& P, i
 }
 
 // Grouped path: after `slots` template slots come group buffers of
-// [status (256 B) | y_a : k_pad float2 | y_b : k_pad float2], the resampled
-// series of one sky/orbit group before its spin-down phase.
+// [status (256 B) | y_a : k_pad float2 | y_b : k_pad float2 | knot area], the
+// resampled series of one sky/orbit group before its spin-down phase.
 constexpr size_t kGroupHeader = 256;
-__host__ __device__ inline size_t group_bytes(int64_t k_pad) {
-  return kGroupHeader + size_t(k_pad) * 2 * sizeof(float2);
+__host__ __device__ inline size_t group_bytes(int64_t k_pad, int64_t knot_bytes) {
+  return kGroupHeader + size_t(k_pad) * 2 * sizeof(float2) + size_t(knot_bytes);
 }
 __host__ __device__ inline char* group_base(void* ws, const PlanConst& P, int slots, int b) {
-  return slot_base(ws, P, slots) + size_t(b) * group_bytes(P.k_pad);
+  return slot_base(ws, P, slots) + size_t(b) * group_bytes(P.k_pad, P.knot_bytes);
+}
+__host__ __device__ inline double2* group_knots(void* ws, const PlanConst& P, int slots, int b) {
+  return reinterpret_cast<double2*>(group_base(ws, P, slots, b) + kGroupHeader +
+                                    size_t(P.k_pad) * 2 * sizeof(float2));
+}
+__host__ __device__ inline double2* slot_knots(void* ws, const PlanConst& P, int g) {
+  return P.knot_offset ? reinterpret_cast<double2*>(slot_base(ws, P, g) + P.knot_offset)
+                       : nullptr;
 }
 __host__ __device__ inline int32_t* group_status(void* ws, const PlanConst& P, int slots, int b) {
   return reinterpret_cast<int32_t*>(group_base(ws, P, slots, b));
@@ -433,10 +468,10 @@ __device__ inline double binary_delay(const TmplParams& tp, double tau) {
 // time T satisfies T + roemer(T) = tau + R(tau).  One fixed-point step from
 // T = t_b then one Newton step; 1/(1 + roemer') by its series to third order
 // (|roemer'| < 1e-3 for any Earth-bound detector: residual < 1e-12 s).
-template <bool KEP, class RoemerFn, class... Flag>
-__device__ inline double grid_delay(const RoemerFn& roemer, const TmplParams& tp, double tau,
-                                    Flag&... oob) {
-  const double rb = binary_delay<KEP>(tp, tau);
+// grid_delay_rb takes the binary delay rb = R(tau) already evaluated.
+template <class RoemerFn, class... Flag>
+__device__ inline double grid_delay_rb(const RoemerFn& roemer, double rb, double tau,
+                                       Flag&... oob) {
   double d0, dd0;
   roemer(tau + rb, d0, dd0, oob...);
   double dl = rb - d0;
@@ -444,6 +479,11 @@ __device__ inline double grid_delay(const RoemerFn& roemer, const TmplParams& tp
   roemer(tau + dl, d1, x, oob...);
   double g = dl + d1 - rb;
   return dl - g * (1.0 - x * (1.0 - x * (1.0 - x)));
+}
+template <bool KEP, class RoemerFn, class... Flag>
+__device__ inline double grid_delay(const RoemerFn& roemer, const TmplParams& tp, double tau,
+                                    Flag&... oob) {
+  return grid_delay_rb(roemer, binary_delay<KEP>(tp, tau), tau, oob...);
 }
 
 
@@ -523,9 +563,11 @@ __device__ inline double sample_delay(const RoemerFn& roemer, const TmplParams& 
 //   d(t_src - t)/dt = roemer'(t) - R'(t_src) (1 + roemer'(t)) / (1 + R'(t_src)),
 // with the orbital phase at t_src taken again after the inverse (its first
 // iterate is 1e-3 s off, too far for the rate).
+// sample_phase_d also returns the delay t_src - t itself.
 template <bool KEP, class RoemerFn, class... Flag>
-__device__ inline void sample_phase(const RoemerFn& roemer, const TmplParams& tp, double t,
-                                    double f_het, double& ph, double& dph, Flag&... oob) {
+__device__ inline void sample_phase_d(const RoemerFn& roemer, const TmplParams& tp, double t,
+                                      double f_het, double& ph, double& dph, double& delay,
+                                      Flag&... oob) {
   double dr, ddr;
   roemer(t, dr, ddr, oob...);
   double r = 0.0, rate = 0.0;
@@ -535,8 +577,15 @@ __device__ inline void sample_phase(const RoemerFn& roemer, const TmplParams& tp
     orbit_delay<KEP>(tp, t + dr - r, r2, rp);
     rate = rp * (1.0 + ddr) / (1.0 + rp);
   }
-  ph = f_het * (dr - r);
+  delay = dr - r;
+  ph = f_het * delay;
   dph = f_het * (ddr - rate);
+}
+template <bool KEP, class RoemerFn, class... Flag>
+__device__ inline void sample_phase(const RoemerFn& roemer, const TmplParams& tp, double t,
+                                    double f_het, double& ph, double& dph, Flag&... oob) {
+  double delay;
+  sample_phase_d<KEP>(roemer, tp, t, f_het, ph, dph, delay, oob...);
 }
 
 // Cubic Hermite coefficients in u in [0, 1] of one knot interval from the

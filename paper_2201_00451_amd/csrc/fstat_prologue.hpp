@@ -162,7 +162,7 @@ __host__ __device__ inline void template_params(const PlanConst& P, const double
   if (tp.asini > P.max_delay) status |= kStatusCoverage;
   tp.om_b = (tp.asini != 0.0 && porb > 0.0) ? 2.0 * kPi / porb : 0.0;
   tp.nu_b = (tp.asini != 0.0 && porb > 0.0) ? 1.0 / porb : 0.0;
-  // Knot spacing of the resampling's timing: the largest G = 2^l <= 16 for
+  // Knot spacing of the resampling's timing: the largest G = 2^l <= 64 for
   // which the cubic Hermite bound (G dt)^4 / 384 max|delay''''| stays below
   // 2e-7 cycles of the heterodyne phase f_h and 1e-7 samples of grid
   // position.  The binary delay contributes asini om^4; the Earth's motion,

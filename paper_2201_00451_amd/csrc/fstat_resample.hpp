@@ -133,11 +133,79 @@ __device__ __forceinline__ void interp_taps(std::integer_sequence<int, T...>, fl
   (interp_tap<D, T>(f, wc, ws, zp, sx, sy), ...);
 }
 
+// Step (v) and the weighting of step (vi) at one grid point k_s + kk of
+// detector X, whose epoch is T_k = tau_k + q dt: the 2D-tap interpolation of
+// the staged window zs (starting at sample lo, W samples, block flags blk)
+// at u = k + off + q, times the whitened antenna patterns at T_k, added to
+// acc_a, acc_b.  A point whose taps all fall on zero samples adds nothing.
+template <int D>
+__device__ __forceinline__ void interp_point(const PlanConst& P, const TmplParams& tp, int X,
+                                             const float2* zs, const int32_t* blk, int64_t lo,
+                                             int W, int64_t k_s, int kk, double q, double tau_s,
+                                             float2& acc_a, float2& acc_b) {
+  int64_t j0;
+  float f;
+  split_u(double(k_s + kk) + P.det[X].off + q, j0, f);
+  // taps j0-D+1 .. j0+D; monotonic T_k keeps them inside the window, the
+  // clamp only guards memory
+  int base = int(j0 - lo) - (D - 1);
+  base = base < 0 ? 0 : (base > W - 2 * D ? W - 2 * D : base);
+  if (!(blk[base >> 5] | blk[(base + 2 * D - 1) >> 5])) return;
+  const float2* zp = zs + base;
+  float2 zh;
+  if (f == 0.0f) {
+    zh = zp[D - 1];
+  } else {
+    // window phase pi f / D and sinc numerator sin(pi f), in cycles
+    const float2 wcs = cis_cycles_f32(f * (0.5f / float(D)));
+    float sx = 0.f, sy = 0.f;
+    interp_taps<D>(std::make_integer_sequence<int, 2 * D>{}, f, wcs.x, wcs.y, zp, sx, sy);
+    const float sp = cis_cycles_f32(0.5f * f).y * float(0.5 / kPi);
+    zh = make_float2(sx * sp, sy * sp);
+  }
+  // antenna patterns at T_k: x = alpha - phi(T_k), in cycles
+  const double tau = tau_s + P.dt * double(kk);
+  const float2 ex = cis_cycles(tp.alpha_cyc[X] - P.sid_rate_cyc * (tau + q * P.dt));
+  const float cx = ex.x, sx = ex.y;
+  const float c2 = cx * cx - sx * sx, s2 = 2.0f * sx * cx;
+  const float a = tp.ca[X][0] + tp.ca[X][1] * cx + tp.ca[X][2] * sx + tp.ca[X][3] * c2 +
+                  tp.ca[X][4] * s2;
+  const float b = tp.cb[X][0] + tp.cb[X][1] * cx + tp.cb[X][2] * sx + tp.cb[X][3] * c2 +
+                  tp.cb[X][4] * s2;
+  acc_a.x = fmaf(a, zh.x, acc_a.x);
+  acc_a.y = fmaf(a, zh.y, acc_a.y);
+  acc_b.x = fmaf(b, zh.x, acc_b.x);
+  acc_b.y = fmaf(b, zh.y, acc_b.y);
+}
+
+// q = (T_k - tau_k)/dt at grid offset k within its knot interval from the
+// interval's two knots (value, derivative per grid step) G steps apart.
+__device__ __forceinline__ double knot_hermite(const double2* kn, int G, double u) {
+  double2 c[2];
+  hermite_interval(kn[0], kn[1], double(G), c[0], c[1]);
+  return hermite_eval(c, 0, u);
+}
+
+// A value every lane of the wave holds, moved to scalar registers.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const uint64_t u = uint64_t(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(u));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(u >> 32));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+
 // Steps (iii)-(v) and the antenna weighting for the kResTile grid points of
 // the tile starting at k_s: acc_a[i], acc_b[i] receive sum_X a'_X(T_k)
 // zhat_X(u_k) (and b'), k = k_s + tid + i kResThreads, before the spin-down
 // phase.  Returns false, after flagging the template's status word, when the
 // template must report NaN (the return is uniform across the block).
+//
+// Detectors are taken kDetPass at a time, each pass in five phases separated
+// by barriers: (1) the pass's ephemeris intervals, and the binary delay at
+// the grid knots; (2) the detector epochs at the grid knots; (3) each
+// detector's staged window from them, the loads of its input samples, and the
+// heterodyne phase at the sample knots while those loads are in flight;
+// (4) the corrected samples into LDS; (5) interpolation and weighting.
 //
 // Timing (tp.knot_log2 = log2 G > 0): the grid delays q_k = (T_k - tau_k)/dt
 // are solved exactly at every G-th grid point of the tile and its end, the
@@ -151,18 +219,22 @@ __device__ __forceinline__ void interp_taps(std::integer_sequence<int, T...>, fl
 // interpolation (it would add zeros).
 template <int D, bool KEP>
 __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
-                                     int32_t* status_word, int64_t k_s,
-                                     float2 (&acc_a)[kResPerThread],
+                                     int32_t* status_word, int64_t k_s, float2* zsa,
+                                     int32_t* blka, float2 (&acc_a)[kResPerThread],
                                      float2 (&acc_b)[kResPerThread]) {
+  constexpr int kRounds = (kResWcap + kResThreads - 1) / kResThreads;
   const int tid = threadIdx.x;
-  __shared__ float2 zs[kResWcap];
-  __shared__ double2 coef[2 * kNodeCap];
-  __shared__ double2 knot[kSampKnots];           // knot values and derivatives
-  __shared__ double2 gc[2 * (kGridKnots - 1)];   // grid-delay intervals
-  __shared__ double2 sc[2 * (kSampKnots - 1)];   // sample-phase intervals
-  __shared__ int32_t blk[(kResWcap + kResThreads) / 32 + 2];
-  __shared__ int64_t win_lo, win_hi;
+  __shared__ double2 coef[kDetPass][2 * kNodeCap];
+  __shared__ double2 orb[kGridKnots];  // binary delay and rate at the grid knots
+  // knot path: grid knots (q, dq/dk) of each detector, then its sample knots
+  // (phase, dphase/dj); exact path: q of every grid point of each detector
+  __shared__ double2 kbuf[kDetPass * (kGridKnots + kSampKnots)];
   __shared__ int bad;
+  static_assert(kDetPass * (kGridKnots + kSampKnots) * 2 >= kDetPass * kResTile,
+                "exact-path delays must fit the knot buffer");
+  double2* const gk = kbuf;                          // [kDetPass][kGridKnots]
+  double2* const sk = kbuf + kDetPass * kGridKnots;  // [kDetPass][kSampKnots]
+  double* const qx = reinterpret_cast<double*>(kbuf);  // [kDetPass][kResTile]
 
   if (tid == 0) bad = 0;
   bool oob = false;
@@ -187,166 +259,192 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
   n_hi = n_hi > P.n_eph - 1 ? P.n_eph - 1 : n_hi;
   int n_count = int(n_hi - n_lo + 1);
   n_count = n_count > kNodeCap ? kNodeCap : (n_count < 2 ? 2 : n_count);
-  const CubicRoemer re{coef, n_count, P.eph_t0 + double(n_lo) * P.eph_dt, P.inv_eph_dt};
+  const double node_t0 = P.eph_t0 + double(n_lo) * P.eph_dt;
   const double tau_s = P.tau0 + P.dt * double(k_s);
-  // the binary delay depends on the grid point only: once for all detectors
-  // (at the own grid knot, with its rate, or at the own grid points)
-  double rb0 = 0.0, rbd0 = 0.0;
+  // exact path: the binary delay at the own grid points (all detectors)
   double rbk[kResPerThread];
-  if (knots) {
-    if (tid < nkg) orbit_delay<KEP>(tp, tau_s + P.dt * double(tid * G), rb0, rbd0);
-  } else {
+  double rb0 = 0.0;
+  if (!knots) {
     rb0 = binary_delay<KEP>(tp, tau_s);
 #pragma unroll
     for (int i = 0; i < kResPerThread; ++i)
       rbk[i] = binary_delay<KEP>(tp, tau_s + P.dt * double(tid + i * kResThreads));
   }
 
-  for (int X = 0; X < P.ndet; ++X) {
-    const DetConst& d = P.det[X];
-    // 1. interval coefficients from the projected nodes i and i + 1
-    for (int i = tid; i < n_count - 1; i += kResThreads) {
-      const double* e = d.ephem + 6 * (n_lo + i);
-      const double p0 = tp.nhat[0] * e[0] + tp.nhat[1] * e[1] + tp.nhat[2] * e[2];
-      const double v0 = tp.nhat[0] * e[3] + tp.nhat[1] * e[4] + tp.nhat[2] * e[5];
-      const double p1 = tp.nhat[0] * e[6] + tp.nhat[1] * e[7] + tp.nhat[2] * e[8];
-      const double v1 = tp.nhat[0] * e[9] + tp.nhat[1] * e[10] + tp.nhat[2] * e[11];
-      cubic_interval(p0, v0, p1, v1, P.eph_dt, coef[2 * i], coef[2 * i + 1]);
+  for (int X0 = 0; X0 < P.ndet; X0 += kDetPass) {
+    const int np = P.ndet - X0 < kDetPass ? P.ndet - X0 : kDetPass;
+    // 1. interval coefficients from the projected nodes i and i + 1 of each
+    // detector of the pass; the binary delay and its rate at the grid knots
+    {
+      const int ni = n_count - 1;
+      for (int e = tid; e < np * ni; e += kResThreads) {
+        const int xp = e >= ni ? 1 : 0;
+        const int i = e - xp * ni;
+        const double* n = P.det[X0 + xp].ephem + 6 * (n_lo + i);
+        const double p0 = tp.nhat[0] * n[0] + tp.nhat[1] * n[1] + tp.nhat[2] * n[2];
+        const double v0 = tp.nhat[0] * n[3] + tp.nhat[1] * n[4] + tp.nhat[2] * n[5];
+        const double p1 = tp.nhat[0] * n[6] + tp.nhat[1] * n[7] + tp.nhat[2] * n[8];
+        const double v1 = tp.nhat[0] * n[9] + tp.nhat[1] * n[10] + tp.nhat[2] * n[11];
+        cubic_interval(p0, v0, p1, v1, P.eph_dt, coef[xp][2 * i], coef[xp][2 * i + 1]);
+      }
+      if (knots && X0 == 0 && tid < nkg) {
+        double r, rp;
+        orbit_delay<KEP>(tp, tau_s + P.dt * double(tid * G), r, rp);
+        orb[tid] = make_double2(r, rp);
+      }
     }
     __syncthreads();
-    // 2. detector epochs of the own grid points as q = (T - tau)/dt and
-    // u = (T - t0)/dt = k + off + q
-    double q[kResPerThread];
-    int64_t j0[kResPerThread];
-    float fr[kResPerThread];
+    // 2. detector epochs as q = (T - tau)/dt: at the grid knots (fixed point
+    // and three Newton steps, with dq/dk = (R'(tau) - roemer'(T)) /
+    // (1 + roemer'(T))), or at every own grid point (the tile's first point
+    // in full, the rest by one Newton step from a prediction that carries the
+    // exact binary delay and linearises the Roemer delay about the first
+    // point: T ~ T_s + (t_b - t_b,s) / (1 + roemer'(T_s)))
     if (knots) {
-      // exact solves at the grid knots (fixed point and three Newton steps),
-      // with dq/dk = d(T - tau)/dtau = (R'(tau) - roemer'(T)) / (1 + roemer'(T))
-      if (tid < nkg) {
-        const double tau = tau_s + P.dt * double(tid * G);
+      for (int e = tid; e < np * nkg; e += kResThreads) {
+        const int xp = e >= nkg ? 1 : 0;
+        const int t = e - xp * nkg;
+        const CubicRoemer re{coef[xp], n_count, node_t0, P.inv_eph_dt};
+        const double tau = tau_s + P.dt * double(t * G);
+        const double2 o = orb[t];
         double x;
-        double dl = grid_delay<KEP>(re, tp, tau, oob);
-        dl = grid_delay_newton(re, tau, rb0, dl, x, oob);
-        dl = grid_delay_newton(re, tau, rb0, dl, x, oob);
-        knot[tid] = make_double2(dl * P.inv_dt, (rbd0 - x) / (1.0 + x));
-      }
-      __syncthreads();
-      if (tid < nkg - 1) hermite_interval(knot[tid], knot[tid + 1], double(G), gc[2 * tid],
-                                          gc[2 * tid + 1]);
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < kResPerThread; ++i) {
-        const int kk = tid + i * kResThreads;
-        q[i] = hermite_eval(gc, kk >> kl, double(kk & (G - 1)) * inv_g);
-        split_u(double(k_s + kk) + d.off + q[i], j0[i], fr[i]);
+        double dl = grid_delay_rb(re, o.x, tau, oob);
+        dl = grid_delay_newton(re, tau, o.x, dl, x, oob);
+        dl = grid_delay_newton(re, tau, o.x, dl, x, oob);
+        gk[xp * kGridKnots + t] = make_double2(dl * P.inv_dt, (o.y - x) / (1.0 + x));
       }
     } else {
-      // the tile's first point in full (fixed point, two Newton steps), the
-      // rest by one Newton step from a prediction that carries the exact
-      // binary delay and linearises the Roemer delay about the first point:
-      // T ~ T_s + (t_b - t_b,s) / (1 + roemer'(T_s))
-      double x0;
-      double d0 = grid_delay<KEP>(re, tp, tau_s, oob);
-      d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
-      d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
-      const double inv0 = 1.0 - x0 * (1.0 - x0 * (1.0 - x0));
+      for (int xp = 0; xp < np; ++xp) {
+        const CubicRoemer re{coef[xp], n_count, node_t0, P.inv_eph_dt};
+        double x0;
+        double d0 = grid_delay_rb(re, rb0, tau_s, oob);
+        d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
+        d0 = grid_delay_newton(re, tau_s, rb0, d0, x0, oob);
+        const double inv0 = 1.0 - x0 * (1.0 - x0 * (1.0 - x0));
 #pragma unroll
-      for (int i = 0; i < kResPerThread; ++i) {
-        const int64_t kk = tid + i * kResThreads;
-        const double dtau = P.dt * double(kk);
-        const double tau = tau_s + dtau;
-        const double rb = rbk[i];
-        const double guess = d0 + (dtau + rb - rb0) * inv0 - dtau;
-        double x;
-        q[i] = grid_delay_newton(re, tau, rb, guess, x, oob) * P.inv_dt;
-        split_u(double(k_s + kk) + d.off + q[i], j0[i], fr[i]);
+        for (int i = 0; i < kResPerThread; ++i) {
+          const int kk = tid + i * kResThreads;
+          const double dtau = P.dt * double(kk);
+          const double guess = d0 + (dtau + rbk[i] - rb0) * inv0 - dtau;
+          double x;
+          qx[xp * kResTile + kk] =
+              grid_delay_newton(re, tau_s + dtau, rbk[i], guess, x, oob) * P.inv_dt;
+        }
       }
     }
-    if (tid == 0) win_lo = j0[0] - D + 1;
-    if (tid == kResThreads - 1) win_hi = j0[kResPerThread - 1] + D;
     __syncthreads();
-    const int64_t lo = win_lo;
-    const int64_t nwin = win_hi - lo + 1;
-    if (nwin > kResWcap || nwin < 2 * D) {
+    // 3. each detector's staged window from its first and last epochs (T_k
+    // is monotonic in k; the knot path bounds the last point by the knot
+    // just past the tile), the loads of its samples, and the heterodyne
+    // phase at its sample knots while they are in flight
+    int64_t lo[kDetPass];
+    int W[kDetPass];
+    bool wbad = false;
+#pragma unroll
+    for (int xp = 0; xp < kDetPass; ++xp) {
+      lo[xp] = 0;
+      W[xp] = 0;
+      if (xp >= np) continue;
+      const double q0 = knots ? gk[xp * kGridKnots].x : qx[xp * kResTile];
+      const double q1 = knots ? gk[xp * kGridKnots + nkg - 1].x : qx[xp * kResTile + kResTile - 1];
+      const int64_t k1 = knots ? k_s + kResTile : k_s + kResTile - 1;
+      int64_t j_first, j_last;
+      float f;
+      split_u(double(k_s) + P.det[X0 + xp].off + q0, j_first, f);
+      split_u(double(k1) + P.det[X0 + xp].off + q1, j_last, f);
+      // every thread computes the same window from LDS: keep it in scalar
+      // registers
+      lo[xp] = uniform_i64(j_first - D + 1);
+      const int64_t nwin = j_last + D - lo[xp] + 1;
       // delay drift beyond 1/16 per tile: flag the template (NaN output)
+      if (nwin > kResWcap || nwin < 2 * D) wbad = true;
+      W[xp] = __builtin_amdgcn_readfirstlane(int(nwin));
+    }
+    if (wbad) {
       if (tid == 0) atomicOr(status_word, kStatusWindow);
       return false;
     }
-    const int W = int(nwin);
-    // 3. corrected input samples: knots of the heterodyne phase first
-    if (knots) {
-      const int nks = ((W - 1) >> kl) + 2;
-      if (tid < nks) {
-        double ph, dph;
-        sample_phase<KEP>(re, tp, d.t0 + P.dt * double(lo + int64_t(tid) * G), P.f_het, ph, dph,
-                     oob);
-        knot[tid] = make_double2(ph, dph * P.dt);
-      }
-      __syncthreads();
-      if (tid < nks - 1) hermite_interval(knot[tid], knot[tid + 1], double(G), sc[2 * tid],
-                                          sc[2 * tid + 1]);
-      __syncthreads();
-    }
-    for (int w0 = 0; w0 < W; w0 += kResThreads) {
-      const int w = w0 + tid;
-      const int64_t j = lo + w;
-      const float2 xv = (w < W && j >= 0 && j < d.n) ? d.x[j] : make_float2(0.f, 0.f);
-      // a zero sample (outside the data, or in a gap) stays zero: no timing
-      const bool live = xv.x != 0.f || xv.y != 0.f;
-      float2 z = make_float2(0.f, 0.f);
-      if (live) {
-        const double ph = knots ? hermite_eval(sc, w >> kl, double(w & (G - 1)) * inv_g)
-                                : P.f_het * sample_delay<KEP>(re, tp, d.t0 + P.dt * double(j), oob);
-        const float2 e = cis_cycles(ph);
-        // x * exp(-2 pi i f_h dl)
-        z = make_float2(xv.x * e.x + xv.y * e.y, xv.y * e.x - xv.x * e.y);
-      }
-      if (w < W) zs[w] = z;
-      // which 32-sample blocks of the window hold a live sample
-      const unsigned long long m = __ballot(live);
-      if ((tid & 63) == 0) {
-        const int b = (w0 + tid) >> 5;
-        blk[b] = uint32_t(m) != 0u;
-        blk[b + 1] = uint32_t(m >> 32) != 0u;
-      }
-    }
-    __syncthreads();
-    // 4. interpolation and antenna weighting
+    float2 xv[kDetPass][kRounds];
 #pragma unroll
-    for (int i = 0; i < kResPerThread; ++i) {
-      const float f = fr[i];
-      // taps j0-D+1 .. j0+D; monotonic T_k keeps them inside the window,
-      // the clamp only guards memory
-      int base = int(j0[i] - lo) - (D - 1);
-      base = base < 0 ? 0 : (base > W - 2 * D ? W - 2 * D : base);
-      if (!(blk[base >> 5] | blk[(base + 2 * D - 1) >> 5])) continue;
-      const float2* zp = zs + base;
-      float2 zh;
-      if (f == 0.0f) {
-        zh = zp[D - 1];
-      } else {
-        // window phase pi f / D and sinc numerator sin(pi f), in cycles
-        const float2 wcs = cis_cycles_f32(f * (0.5f / float(D)));
-        float sx = 0.f, sy = 0.f;
-        interp_taps<D>(std::make_integer_sequence<int, 2 * D>{}, f, wcs.x, wcs.y, zp, sx, sy);
-        const float sp = cis_cycles_f32(0.5f * f).y * float(0.5 / kPi);
-        zh = make_float2(sx * sp, sy * sp);
+    for (int xp = 0; xp < kDetPass; ++xp) {
+      const DetConst& d = P.det[X0 + (xp < np ? xp : 0)];
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        const int w = r * kResThreads + tid;
+        const int64_t j = lo[xp] + w;
+        xv[xp][r] = (xp < np && w < W[xp] && j >= 0 && j < d.n) ? d.x[j] : make_float2(0.f, 0.f);
       }
-      // antenna patterns at T_k: x = alpha - phi(T_k), in cycles
-      const double tau = tau_s + P.dt * double(tid + i * kResThreads);
-      const float2 ex = cis_cycles(tp.alpha_cyc[X] - P.sid_rate_cyc * (tau + q[i] * P.dt));
-      const float cx = ex.x, sx = ex.y;
-      const float c2 = cx * cx - sx * sx, s2 = 2.0f * sx * cx;
-      const float a = tp.ca[X][0] + tp.ca[X][1] * cx + tp.ca[X][2] * sx + tp.ca[X][3] * c2 +
-                      tp.ca[X][4] * s2;
-      const float b = tp.cb[X][0] + tp.cb[X][1] * cx + tp.cb[X][2] * sx + tp.cb[X][3] * c2 +
-                      tp.cb[X][4] * s2;
-      acc_a[i].x = fmaf(a, zh.x, acc_a[i].x);
-      acc_a[i].y = fmaf(a, zh.y, acc_a[i].y);
-      acc_b[i].x = fmaf(b, zh.x, acc_b[i].x);
-      acc_b[i].y = fmaf(b, zh.y, acc_b[i].y);
+    }
+    if (knots) {
+      const int nks0 = ((W[0] - 1) >> kl) + 2;
+      const int nks1 = np > 1 ? ((W[1] - 1) >> kl) + 2 : 0;
+      for (int e = tid; e < nks0 + nks1; e += kResThreads) {
+        const int xp = e >= nks0 ? 1 : 0;
+        const int t = e - xp * nks0;
+        const CubicRoemer re{coef[xp], n_count, node_t0, P.inv_eph_dt};
+        double ph, dph;
+        const int64_t lox = xp ? lo[1] : lo[0];
+        sample_phase<KEP>(re, tp, P.det[X0 + xp].t0 + P.dt * double(lox + int64_t(t) * G),
+                          P.f_het, ph, dph, oob);
+        sk[xp * kSampKnots + t] = make_double2(ph, dph * P.dt);
+      }
     }
     __syncthreads();
+    // 4. corrected input samples z_j = x_j exp(-2 pi i f_h (t_src,j - t_j));
+    // a zero sample (outside the data, or in a gap) stays zero, untimed
+#pragma unroll 1
+    for (int xp = 0; xp < np; ++xp) {
+      const CubicRoemer re{coef[xp], n_count, node_t0, P.inv_eph_dt};
+      const int64_t lox = xp ? lo[1] : lo[0];
+      const int Wx = xp ? W[1] : W[0];
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        const int w = r * kResThreads + tid;
+        if (r * kResThreads >= Wx) break;
+        const float2 x = xp ? xv[1][r] : xv[0][r];
+        const bool live = x.x != 0.f || x.y != 0.f;
+        float2 z = make_float2(0.f, 0.f);
+        if (live) {
+          double ph;
+          if (knots) {
+            ph = knot_hermite(sk + xp * kSampKnots + (w >> kl), G, double(w & (G - 1)) * inv_g);
+          } else {
+            ph = P.f_het * sample_delay<KEP>(re, tp, P.det[X0 + xp].t0 + P.dt * double(lox + w),
+                                             oob);
+          }
+          const float2 e = cis_cycles(ph);
+          // x * exp(-2 pi i f_h dl)
+          z = make_float2(x.x * e.x + x.y * e.y, x.y * e.x - x.x * e.y);
+        }
+        if (w < Wx) zsa[xp * kResWcap + w] = z;
+        // which 32-sample blocks of the window hold a live sample
+        const unsigned long long m = __ballot(live);
+        if ((tid & 63) == 0) {
+          const int b = w >> 5;
+          blka[xp * kResBlk + b] = uint32_t(m) != 0u;
+          blka[xp * kResBlk + b + 1] = uint32_t(m >> 32) != 0u;
+        }
+      }
+    }
+    __syncthreads();
+    // 5. interpolation and antenna weighting (each accumulator takes the
+    // detectors in order)
+#pragma unroll 1
+    for (int xp = 0; xp < np; ++xp) {
+      const int X = X0 + xp;
+      const int64_t lox = xp ? lo[1] : lo[0];
+      const int Wx = xp ? W[1] : W[0];
+#pragma unroll
+      for (int i = 0; i < kResPerThread; ++i) {
+        const int kk = tid + i * kResThreads;
+        const double q = knots ? knot_hermite(gk + xp * kGridKnots + (kk >> kl), G,
+                                              double(kk & (G - 1)) * inv_g)
+                               : qx[xp * kResTile + kk];
+        interp_point<D>(P, tp, X, zsa + xp * kResWcap, blka + xp * kResBlk, lox, Wx, k_s, kk, q,
+                        tau_s, acc_a[i], acc_b[i]);
+      }
+    }
+    if (X0 + kDetPass < P.ndet) __syncthreads();
   }
   if (oob) bad = 1;
   __syncthreads();
@@ -357,6 +455,170 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
     return false;
   }
   return true;
+}
+
+// The tile for a template whose timing knots k_knots solved ahead (knot
+// area kn): each thread reads the knots of its own samples and grid points,
+// so a pass of kDetPass detectors has two phases, the corrected samples into
+// LDS and then interpolation and weighting, with one barrier between them.
+// The window of a detector runs from the tile's first epoch to the one of
+// the knot just past the tile (T_k is monotonic in k).
+template <int D>
+__device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp,
+                                        const double2* __restrict__ kn, int32_t* status_word,
+                                        int64_t k_s, float2* zsa, int32_t* blka,
+                                        float2 (&acc_a)[kResPerThread],
+                                        float2 (&acc_b)[kResPerThread]) {
+  constexpr int kRounds = (kResWcap + kResThreads - 1) / kResThreads;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < kResPerThread; ++i) {
+    acc_a[i] = make_float2(0.f, 0.f);
+    acc_b[i] = make_float2(0.f, 0.f);
+  }
+  const int kl = tp.knot_log2;
+  const int G = 1 << kl;
+  const double inv_g = 1.0 / double(G);
+  const double tau_s = P.tau0 + P.dt * double(k_s);
+  for (int X0 = 0; X0 < P.ndet; X0 += kDetPass) {
+    const int np = P.ndet - X0 < kDetPass ? P.ndet - X0 : kDetPass;
+    int64_t lo[kDetPass];
+    int W[kDetPass];
+    bool wbad = false;
+#pragma unroll
+    for (int xp = 0; xp < kDetPass; ++xp) {
+      lo[xp] = 0;
+      W[xp] = 0;
+      if (xp >= np) continue;
+      const double2* gk = kn + (X0 + xp) * P.knot_stride;
+      const double q0 = gk[k_s >> kl].x, q1 = gk[(k_s + kResTile) >> kl].x;
+      int64_t j_first, j_last;
+      float f;
+      split_u(double(k_s) + P.det[X0 + xp].off + q0, j_first, f);
+      split_u(double(k_s + kResTile) + P.det[X0 + xp].off + q1, j_last, f);
+      lo[xp] = uniform_i64(j_first - D + 1);
+      const int64_t nwin = j_last + D - lo[xp] + 1;
+      // delay drift beyond 1/16 per tile: flag the template (NaN output)
+      if (nwin > kResWcap || nwin < 2 * D) wbad = true;
+      W[xp] = __builtin_amdgcn_readfirstlane(int(nwin));
+    }
+    if (wbad) {
+      if (tid == 0) atomicOr(status_word, kStatusWindow);
+      return false;
+    }
+    // corrected input samples z_j = x_j exp(-2 pi i f_h (t_src,j - t_j)) from
+    // the sample knots; a zero sample (outside the data, or in a gap) stays
+    // zero
+#pragma unroll 1
+    for (int xp = 0; xp < np; ++xp) {
+      const DetConst& d = P.det[X0 + xp];
+      const double2* sk = kn + (X0 + xp) * P.knot_stride + P.knot_gcap;
+      const int64_t lox = xp ? lo[1] : lo[0];
+      const int Wx = xp ? W[1] : W[0];
+      float2 xv[kRounds];
+      double2 k0[kRounds], k1[kRounds];
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        const int w = r * kResThreads + tid;
+        const int64_t j = lox + w;
+        const bool in = w < Wx && j >= 0 && j < d.n;
+        xv[r] = in ? d.x[j] : make_float2(0.f, 0.f);
+        // knots of the sample's interval (of the last sample outside the data)
+        const int64_t m = (j < 0 ? 0 : (j >= d.n ? d.n - 1 : j)) >> kl;
+        k0[r] = sk[m];
+        k1[r] = sk[m + 1];
+      }
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        if (r * kResThreads >= Wx) break;
+        const int w = r * kResThreads + tid;
+        const float2 x = xv[r];
+        const bool live = x.x != 0.f || x.y != 0.f;
+        float2 z = make_float2(0.f, 0.f);
+        if (live) {
+          const double2 kk2[2] = {k0[r], k1[r]};
+          const double ph = knot_hermite(kk2, G, double((lox + w) & (G - 1)) * inv_g);
+          const float2 e = cis_cycles(ph);
+          // x * exp(-2 pi i f_h dl)
+          z = make_float2(x.x * e.x + x.y * e.y, x.y * e.x - x.x * e.y);
+        }
+        if (w < Wx) zsa[xp * kResWcap + w] = z;
+        // which 32-sample blocks of the window hold a live sample
+        const unsigned long long mb = __ballot(live);
+        if ((tid & 63) == 0) {
+          const int b = w >> 5;
+          blka[xp * kResBlk + b] = uint32_t(mb) != 0u;
+          blka[xp * kResBlk + b + 1] = uint32_t(mb >> 32) != 0u;
+        }
+      }
+    }
+    __syncthreads();
+    // interpolation and antenna weighting (each accumulator takes the
+    // detectors in order)
+#pragma unroll 1
+    for (int xp = 0; xp < np; ++xp) {
+      const int X = X0 + xp;
+      const double2* gk = kn + X * P.knot_stride;
+      const int64_t lox = xp ? lo[1] : lo[0];
+      const int Wx = xp ? W[1] : W[0];
+#pragma unroll
+      for (int i = 0; i < kResPerThread; ++i) {
+        const int kk = tid + i * kResThreads;
+        const int64_t k = k_s + kk;
+        const double q = knot_hermite(gk + (k >> kl), G, double(k & (G - 1)) * inv_g);
+        interp_point<D>(P, tp, X, zsa + xp * kResWcap, blka + xp * kResBlk, lox, Wx, k_s, kk, q,
+                        tau_s, acc_a[i], acc_b[i]);
+      }
+    }
+    if (X0 + kDetPass < P.ndet) __syncthreads();
+  }
+  return true;
+}
+
+// Timing knots of one template (slot) or sky/orbit group whose knot spacing
+// G = 2^tp.knot_log2 is at least 2^kKnotLogGlobal, for the detector
+// blockIdx.z: the same FP64 solves as the tiles' own knots (steps (iv) and
+// (iii) of Sec. 3), one knot per thread, with the Roemer delay from the
+// detector's tabulated trajectory.  A delay beyond the plan's max_delay flags
+// the template (as a tile whose delay leaves its staged nodes does).
+template <bool GROUPED, bool KEP>
+__global__ __launch_bounds__(256) void k_knots(PlanConst P, void* ws, ChunkMap map, int slots) {
+  const int gi = blockIdx.y;
+  const int slot = GROUPED ? map.grp_slot[gi] : gi;
+  const TmplParams& tp = *tmpl_params(ws, P, map, slot);
+  if (GROUPED ? (tp.status & kStatusGroupMask) != 0 : tp.status != 0) return;
+  const int kl = tp.knot_log2;
+  if (kl < kKnotLogGlobal) return;
+  int32_t* status_word = GROUPED ? group_status(ws, P, slots, map.grp_buf[gi])
+                                 : &tmpl_params(ws, P, map, slot)->status;
+  const int X = blockIdx.z;
+  const DetConst& d = P.det[X];
+  double2* kn = (GROUPED ? group_knots(ws, P, slots, map.grp_buf[gi]) : slot_knots(ws, P, slot)) +
+                X * P.knot_stride;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int G = 1 << kl;
+  const GlobalRoemer re{d.ephem, tp.nhat, P.n_eph, P.eph_t0, P.eph_dt, P.inv_eph_dt};
+  bool far = false;
+  if (e <= (P.k_pad >> kl)) {
+    // grid knot e: detector epoch of tau = tau0 + e G dt (fixed point and
+    // two Newton steps) and dq/dk = (R'(tau) - roemer'(T)) / (1 + roemer'(T))
+    const double tau = P.tau0 + P.dt * double(e * G);
+    double rb, rbd, x;
+    orbit_delay<KEP>(tp, tau, rb, rbd);
+    double dl = grid_delay_rb(re, rb, tau);
+    dl = grid_delay_newton(re, tau, rb, dl, x);
+    dl = grid_delay_newton(re, tau, rb, dl, x);
+    kn[e] = make_double2(dl * P.inv_dt, (rbd - x) / (1.0 + x));
+    far = !(fabs(dl) <= P.max_delay);
+  } else if (e >= P.knot_gcap && e - P.knot_gcap <= ((d.n - 1) >> kl) + 1) {
+    // sample knot m: heterodyne phase at t = t0 + m G dt and its change per sample
+    const int64_t m = e - P.knot_gcap;
+    double ph, dph, delay;
+    sample_phase_d<KEP>(re, tp, d.t0 + P.dt * double(m * G), P.f_het, ph, dph, delay);
+    kn[e] = make_double2(ph, dph * P.dt);
+    far = !(fabs(delay) <= P.max_delay);
+  }
+  if (far) atomicOr(status_word, kStatusNodes);
 }
 
 // GROUPED = false: blockIdx.y is a template slot; the spin-down phase is
@@ -393,8 +655,16 @@ __global__ __launch_bounds__(kResThreads, 4) void k_resample(PlanConst P, void* 
   } else if (tp.status != 0) {
     return;
   }
+  __shared__ float2 zs[kDetPass * kResWcap];
+  __shared__ int32_t blk[kDetPass * kResBlk];
+  const double2* kn = GROUPED ? group_knots(ws, P, slots, map.grp_buf[gi])
+                              : slot_knots(ws, P, slot);
   float2 acc_a[kResPerThread], acc_b[kResPerThread];
-  if (!resample_tile<D, KEP>(P, tp, status_word, k_s, acc_a, acc_b)) return;
+  if (P.knot_bytes != 0 && kn != nullptr && tp.knot_log2 >= kKnotLogGlobal) {
+    if (!resample_tile_gk<D>(P, tp, kn, status_word, k_s, zs, blk, acc_a, acc_b)) return;
+  } else if (!resample_tile<D, KEP>(P, tp, status_word, k_s, zs, blk, acc_a, acc_b)) {
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < kResPerThread; ++i) {
     const int64_t k = k_s + threadIdx.x + i * kResThreads;
@@ -435,8 +705,10 @@ __global__ __launch_bounds__(kResThreads, 4) void k_resample_bin(PlanConst P, vo
   const int64_t k_s = int64_t(blockIdx.x) * kResTile;
   const int tid = threadIdx.x;
   if (tp.status != 0) return;
+  __shared__ float2 zs[kDetPass * kResWcap];
+  __shared__ int32_t blk[kDetPass * kResBlk];
   float2 acc_a[kResPerThread], acc_b[kResPerThread];
-  if (!resample_tile<D, KEP>(P, tp, &tpp->status, k_s, acc_a, acc_b)) return;
+  if (!resample_tile<D, KEP>(P, tp, &tpp->status, k_s, zs, blk, acc_a, acc_b)) return;
   const int64_t bin = bins[map.tmpl[slot]];
   const int64_t nat = band_bin_nat(P, bin);
   double s[4] = {0.0, 0.0, 0.0, 0.0};
