@@ -372,17 +372,30 @@ int64_t rows_items(const fstat_plan* p, const FftVariant& v, int n) {
   return ((int64_t(1) << p->log_rr) / v.lines) * n;
 }
 
-// Resampling kernel for a supported interpolation half-width.
+// Resampling kernels for a supported interpolation half-width: knots solved
+// ahead, and the tiles that solve their own timing.
 using ResFn = void (*)(PlanConst, void*, ChunkMap, int);
-template <bool GROUPED, bool KEP>
+template <bool GROUPED>
 ResFn resample_kernel_g(int D) {
   switch (D) {
-    case 4: return &k_resample<4, GROUPED, KEP>;
-    case 6: return &k_resample<6, GROUPED, KEP>;
-    case 8: return &k_resample<8, GROUPED, KEP>;
-    case 10: return &k_resample<10, GROUPED, KEP>;
-    case 12: return &k_resample<12, GROUPED, KEP>;
-    case 16: return &k_resample<16, GROUPED, KEP>;
+    case 4: return &k_resample<4, GROUPED>;
+    case 6: return &k_resample<6, GROUPED>;
+    case 8: return &k_resample<8, GROUPED>;
+    case 10: return &k_resample<10, GROUPED>;
+    case 12: return &k_resample<12, GROUPED>;
+    case 16: return &k_resample<16, GROUPED>;
+    default: return nullptr;
+  }
+}
+template <bool GROUPED, bool KEP>
+ResFn resample_own_kernel_g(int D) {
+  switch (D) {
+    case 4: return &k_resample_own<4, GROUPED, KEP>;
+    case 6: return &k_resample_own<6, GROUPED, KEP>;
+    case 8: return &k_resample_own<8, GROUPED, KEP>;
+    case 10: return &k_resample_own<10, GROUPED, KEP>;
+    case 12: return &k_resample_own<12, GROUPED, KEP>;
+    case 16: return &k_resample_own<16, GROUPED, KEP>;
     default: return nullptr;
   }
 }
@@ -406,9 +419,25 @@ void launch_knots(const fstat_plan* p, const PlanConst& P, const ChunkMap& map, 
 
 ResFn resample_kernel(const fstat_plan* p, bool grouped) {
   const int D = p->desc.sinc_halfwidth;
+  return grouped ? resample_kernel_g<true>(D) : resample_kernel_g<false>(D);
+}
+ResFn resample_own_kernel(const fstat_plan* p, bool grouped) {
+  const int D = p->desc.sinc_halfwidth;
   if (kepler_plan(p))
-    return grouped ? resample_kernel_g<true, true>(D) : resample_kernel_g<false, true>(D);
-  return grouped ? resample_kernel_g<true, false>(D) : resample_kernel_g<false, false>(D);
+    return grouped ? resample_own_kernel_g<true, true>(D) : resample_own_kernel_g<false, true>(D);
+  return grouped ? resample_own_kernel_g<true, false>(D) : resample_own_kernel_g<false, false>(D);
+}
+// Both resampling kernels over the chunk's groups (grouped) or slots; each
+// skips the templates the other takes.  The own-timing kernel walks the tiles
+// with at most 256 blocks per template.
+void launch_resample(const fstat_plan* p, const PlanConst& P, const ChunkMap& map, int slots,
+                     bool grouped, int n_res, void* ws, hipStream_t st) {
+  const int64_t tiles = p->k_pad / kResTile;
+  hipLaunchKernelGGL(resample_kernel(p, grouped), dim3(unsigned(tiles), n_res),
+                     dim3(kResThreads), 0, st, P, ws, map, slots);
+  hipLaunchKernelGGL(resample_own_kernel(p, grouped),
+                     dim3(unsigned(std::min<int64_t>(tiles, 256)), n_res), dim3(kResThreads), 0,
+                     st, P, ws, map, slots);
 }
 
 // Optional per-kernel timing: events recorded before and after each launch.
@@ -464,7 +493,7 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
   const int n_res = grouped ? map.n_grp : n;
   const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), grouped);
   const FftVariant rv = pick_rows(p->log_c, rows_choice(p), forward_row_mode(out));
-  if (!resample_kernel(p, grouped) || !cv.fn || !rv.fn)
+  if (!resample_kernel(p, grouped) || !resample_own_kernel(p, grouped) || !cv.fn || !rv.fn)
     return fail(FSTAT_EINTERNAL, "no kernel for D=%d, FFT lines 2^%d x 2^%d",
                 p->desc.sinc_halfwidth, p->log_rr, p->log_c);
   if (n_res > 0) {
@@ -472,9 +501,7 @@ fstat_status launch_chunk(const fstat_plan* p, const PlanConst& P, const double*
     if ((s = tm.open(0)) != FSTAT_OK) return s;
     launch_knots(p, P, map, slots, grouped, n_res, ws, st);
     if ((s = tm.open(1)) != FSTAT_OK) return s;
-    hipLaunchKernelGGL(resample_kernel(p, grouped),
-                       dim3(unsigned(p->k_pad / kResTile), n_res), dim3(kResThreads), 0, st, P,
-                       ws, map, slots);
+    launch_resample(p, P, map, slots, grouped, n_res, ws, st);
   }
   if (y_out) {
     if ((s = tm.close()) != FSTAT_OK) return s;
@@ -658,8 +685,7 @@ fstat_status launch_grad_chunk(const fstat_plan* p, const PlanConst& P, const do
   const unsigned tiles = unsigned(p->k_pad / kResTile);
   hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, ws);
   launch_knots(p, P, map, slots, false, n, ws, st);
-  hipLaunchKernelGGL(resample_kernel(p, false), dim3(tiles, n),
-                     dim3(kResThreads), 0, st, P, ws, map, slots);
+  launch_resample(p, P, map, slots, false, n, ws, st);
   const FftVariant cv = pick_cols(p->log_rr, cols_choice(p), false);
   const ColsFn cols = reinterpret_cast<ColsFn>(const_cast<void*>(cv.fn));
   const dim3 cgrid(fft_grid(cv, cols_items(p, cv, n)));

@@ -24,6 +24,9 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kResTile = 512;
 constexpr int kResThreads = 256;
 constexpr int kResPerThread = kResTile / kResThreads;
+// Waves per SIMD of the resampling kernel whose timing knots were solved
+// ahead (its registers: 512 / waves).
+constexpr int kResWavesAhead = 5;
 constexpr int kResWcap = kResTile + kResTile / 16 + 64 + 8;
 // Flags of the staged window's 32-sample blocks (any live sample).
 constexpr int kResBlk = (kResWcap + kResThreads) / 32 + 2;
@@ -324,6 +327,34 @@ struct GlobalRoemer {
     double v0 = nh[0] * e0[3] + nh[1] * e0[4] + nh[2] * e0[5];
     double p1 = nh[0] * e1[0] + nh[1] * e1[1] + nh[2] * e1[2];
     double v1 = nh[0] * e1[3] + nh[1] * e1[4] + nh[2] * e1[5];
+    hermite(p0, v0, p1, v1, s - static_cast<double>(i), h, inv_h, d, dd);
+  }
+};
+
+// GlobalRoemer that keeps the interval it read last in registers: the
+// successive evaluations of one fixed-point or Newton solve fall in the same
+// interval (they differ by far less than its length), so a solve reads the
+// trajectory about once.  Same arithmetic, so the same values.
+struct CachedRoemer {
+  const double* tab;
+  const double* nh;
+  int64_t n_eph;
+  double t0, h, inv_h;
+  mutable int64_t i_cached = -1;
+  mutable double p0 = 0.0, v0 = 0.0, p1 = 0.0, v1 = 0.0;
+  __device__ void operator()(double t, double& d, double& dd) const {
+    double s = (t - t0) * inv_h;
+    int64_t i = static_cast<int64_t>(floor(s));
+    i = i < 0 ? 0 : (i > n_eph - 2 ? n_eph - 2 : i);
+    if (i != i_cached) {
+      const double* e0 = tab + 6 * i;
+      const double* e1 = e0 + 6;
+      p0 = nh[0] * e0[0] + nh[1] * e0[1] + nh[2] * e0[2];
+      v0 = nh[0] * e0[3] + nh[1] * e0[4] + nh[2] * e0[5];
+      p1 = nh[0] * e1[0] + nh[1] * e1[1] + nh[2] * e1[2];
+      v1 = nh[0] * e1[3] + nh[1] * e1[4] + nh[2] * e1[5];
+      i_cached = i;
+    }
     hermite(p0, v0, p1, v1, s - static_cast<double>(i), h, inv_h, d, dd);
   }
 };

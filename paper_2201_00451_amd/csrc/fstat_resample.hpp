@@ -579,8 +579,9 @@ __device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp
 // G = 2^tp.knot_log2 is at least 2^kKnotLogGlobal, for the detector
 // blockIdx.z: the same FP64 solves as the tiles' own knots (steps (iv) and
 // (iii) of Sec. 3), one knot per thread, with the Roemer delay from the
-// detector's tabulated trajectory.  A delay beyond the plan's max_delay flags
-// the template (as a tile whose delay leaves its staged nodes does).
+// detector's tabulated trajectory (the interval read last kept in
+// registers).  A delay beyond the plan's max_delay flags the template (as a
+// tile whose delay leaves its staged nodes does).
 template <bool GROUPED, bool KEP>
 __global__ __launch_bounds__(256) void k_knots(PlanConst P, void* ws, ChunkMap map, int slots) {
   const int gi = blockIdx.y;
@@ -597,7 +598,7 @@ __global__ __launch_bounds__(256) void k_knots(PlanConst P, void* ws, ChunkMap m
                 X * P.knot_stride;
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int G = 1 << kl;
-  const GlobalRoemer re{d.ephem, tp.nhat, P.n_eph, P.eph_t0, P.eph_dt, P.inv_eph_dt};
+  const CachedRoemer re{d.ephem, tp.nhat, P.n_eph, P.eph_t0, P.eph_dt, P.inv_eph_dt};
   bool far = false;
   if (e <= (P.k_pad >> kl)) {
     // grid knot e: detector epoch of tau = tau0 + e G dt (fixed point and
@@ -621,62 +622,111 @@ __global__ __launch_bounds__(256) void k_knots(PlanConst P, void* ws, ChunkMap m
   if (far) atomicOr(status_word, kStatusNodes);
 }
 
-// GROUPED = false: blockIdx.y is a template slot; the spin-down phase is
-// applied and y_a', y_b' go to the slot's arrays 0 and 1.  GROUPED = true:
-// blockIdx.y is a sky/orbit group of the chunk; the series is written without
-// the spin-down phase to the group's buffer, which every template of the
-// group reads (the reuse of the sky-dependent barycentring across spin-down
-// templates that Sec. 4.1 measures).
-// Four waves per SIMD (at most 128 registers, no spills at two outputs per
-// thread): the timing's FP64 and LDS latency chains hide better with more
-// waves (measured at 1024-point tiles: three waves against two, 11 % on sky
-// positions and 17 % on binary orbits).
-template <int D, bool GROUPED, bool KEP>
-__global__ __launch_bounds__(kResThreads, 4) void k_resample(PlanConst P, void* ws, ChunkMap map,
-                                                         int slots) {
+// Resampling kernels.  GROUPED = false: blockIdx.y is a template slot; the
+// spin-down phase is applied and y_a', y_b' go to the slot's arrays 0 and 1.
+// GROUPED = true: blockIdx.y is a sky/orbit group of the chunk; the series is
+// written without the spin-down phase to the group's buffer, which every
+// template of the group reads (the reuse of the sky-dependent barycentring
+// across spin-down templates that Sec. 4.1 measures).
+//
+// Where a resampling block writes, and whether the template (group) is
+// live: a leader whose sky or orbit is invalid invalidates the whole group
+// (its status word tells every member's column pass not to read the buffer).
+struct ResTarget {
+  const TmplParams* tp;
+  int32_t* status;
+  float2* ya;
+  float2* yb;
+  const double2* kn;  // knot area (null: none)
+  bool live;
+};
+template <bool GROUPED>
+__device__ __forceinline__ ResTarget res_target(const PlanConst& P, void* ws, const ChunkMap& map,
+                                                int slots) {
   const int gi = blockIdx.y;
   const int slot = GROUPED ? map.grp_slot[gi] : gi;
-  const TmplParams& tp = *tmpl_params(ws, P, map, slot);
-  int32_t* status_word = GROUPED ? group_status(ws, P, slots, map.grp_buf[gi])
-                                 : &tmpl_params(ws, P, map, slot)->status;
-  float2* ya = GROUPED ? group_buf(ws, P, slots, map.grp_buf[gi], 0)
-                       : slot_buf(ws, P, slot, 0);
-  float2* yb = GROUPED ? group_buf(ws, P, slots, map.grp_buf[gi], 1)
-                       : slot_buf(ws, P, slot, 1);
-  const int64_t k_s = int64_t(blockIdx.x) * kResTile;
+  ResTarget r;
+  r.tp = tmpl_params(ws, P, map, slot);
+  r.status = GROUPED ? group_status(ws, P, slots, map.grp_buf[gi])
+                     : &tmpl_params(ws, P, map, slot)->status;
+  r.ya = GROUPED ? group_buf(ws, P, slots, map.grp_buf[gi], 0) : slot_buf(ws, P, slot, 0);
+  r.yb = GROUPED ? group_buf(ws, P, slots, map.grp_buf[gi], 1) : slot_buf(ws, P, slot, 1);
+  r.kn = P.knot_bytes == 0 ? nullptr
+         : GROUPED         ? group_knots(ws, P, slots, map.grp_buf[gi])
+                           : slot_knots(ws, P, slot);
+  r.live = true;
   if (GROUPED) {
-    // a leader whose sky or orbit is invalid invalidates the whole group:
-    // its status word tells every member's column pass not to read the buffer
-    const int32_t gflag = tp.status & kStatusGroupMask;
+    const int32_t gflag = r.tp->status & kStatusGroupMask;
     if (gflag != 0) {
-      if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(status_word, gflag);
-      return;
+      if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(r.status, gflag);
+      r.live = false;
     }
-  } else if (tp.status != 0) {
-    return;
+  } else if (r.tp->status != 0) {
+    r.live = false;
   }
-  __shared__ float2 zs[kDetPass * kResWcap];
-  __shared__ int32_t blk[kDetPass * kResBlk];
-  const double2* kn = GROUPED ? group_knots(ws, P, slots, map.grp_buf[gi])
-                              : slot_knots(ws, P, slot);
-  float2 acc_a[kResPerThread], acc_b[kResPerThread];
-  if (P.knot_bytes != 0 && kn != nullptr && tp.knot_log2 >= kKnotLogGlobal) {
-    if (!resample_tile_gk<D>(P, tp, kn, status_word, k_s, zs, blk, acc_a, acc_b)) return;
-  } else if (!resample_tile<D, KEP>(P, tp, status_word, k_s, zs, blk, acc_a, acc_b)) {
-    return;
-  }
+  return r;
+}
+// Whether a template's timing knots were solved ahead (k_knots).
+__device__ __forceinline__ bool knots_ahead(const ResTarget& r) {
+  return r.kn != nullptr && r.tp->knot_log2 >= kKnotLogGlobal;
+}
+template <bool GROUPED>
+__device__ __forceinline__ void res_store(const ResTarget& r, int64_t k_s,
+                                          const float2 (&acc_a)[kResPerThread],
+                                          const float2 (&acc_b)[kResPerThread]) {
 #pragma unroll
   for (int i = 0; i < kResPerThread; ++i) {
     const int64_t k = k_s + threadIdx.x + i * kResThreads;
     if (GROUPED) {
-      ya[k] = acc_a[i];
-      yb[k] = acc_b[i];
+      r.ya[k] = acc_a[i];
+      r.yb[k] = acc_b[i];
     } else {
       // spin-down phase and sub-bin offset: y = acc * exp(-2 pi i cyc)
-      const float2 e = spindown_rotation(tp.sd, k);
-      ya[k] = cmul_exact(acc_a[i], e);
-      yb[k] = cmul_exact(acc_b[i], e);
+      const float2 e = spindown_rotation(r.tp->sd, k);
+      r.ya[k] = cmul_exact(acc_a[i], e);
+      r.yb[k] = cmul_exact(acc_b[i], e);
     }
+  }
+}
+
+// Templates whose knots were solved ahead: one tile per block.  Without the
+// in-tile timing the kernel fits 96 registers without spills, five waves per
+// SIMD, which covers the tile's memory latencies better (binary workload, per
+// template: 102 us at four waves, 89 at five, 96 at six with 48 bytes
+// spilled, 153 at eight).
+template <int D, bool GROUPED>
+__global__ __launch_bounds__(kResThreads, kResWavesAhead) void k_resample(PlanConst P, void* ws,
+                                                                       ChunkMap map, int slots) {
+  const ResTarget r = res_target<GROUPED>(P, ws, map, slots);
+  if (!r.live || !knots_ahead(r)) return;
+  __shared__ float2 zs[kDetPass * kResWcap];
+  __shared__ int32_t blk[kDetPass * kResBlk];
+  const int64_t k_s = int64_t(blockIdx.x) * kResTile;
+  float2 acc_a[kResPerThread], acc_b[kResPerThread];
+  if (!resample_tile_gk<D>(P, *r.tp, r.kn, r.status, k_s, zs, blk, acc_a, acc_b)) return;
+  res_store<GROUPED>(r, k_s, acc_a, acc_b);
+}
+
+// The other templates (knot spacing below 16 points, or no knot area): the
+// tile solves its own timing (four waves per SIMD, 128 registers: its FP64
+// and LDS latency chains hide better with more waves).  A block walks tiles
+// blockIdx.x, + gridDim.x, ..., so that a launch over templates that all had
+// their knots solved ahead is a few thousand blocks that return at once.
+template <int D, bool GROUPED, bool KEP>
+__global__ __launch_bounds__(kResThreads, 4) void k_resample_own(PlanConst P, void* ws,
+                                                               ChunkMap map, int slots) {
+  const ResTarget r = res_target<GROUPED>(P, ws, map, slots);
+  if (!r.live || knots_ahead(r)) return;
+  __shared__ float2 zs[kDetPass * kResWcap];
+  __shared__ int32_t blk[kDetPass * kResBlk];
+  const int64_t tiles = P.k_pad / kResTile;
+  for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int64_t k_s = t * kResTile;
+    float2 acc_a[kResPerThread], acc_b[kResPerThread];
+    if (!resample_tile<D, KEP>(P, *r.tp, r.status, k_s, zs, blk, acc_a, acc_b)) return;
+    res_store<GROUPED>(r, k_s, acc_a, acc_b);
+    // the next tile's first phase rewrites what this one's last read
+    __syncthreads();
   }
 }
 
