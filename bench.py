@@ -40,8 +40,11 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # header and build flags with this digest; for any other version the
 # roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "",
-    "bytes_per_template": {"binary": {}, "sky_spindown": {}},
+    "sources_sha256": "308645821e5edcba951e4e70f00f707096af101ed130fdd55249b4b4b9d77828",
+    "bytes_per_template": {
+        "binary": {"resample": 182439560, "fft_columns": 231440820, "fft_rows_2f": 182990053},
+        "sky_spindown": {"resample": 3073919, "fft_columns": 48075845, "fft_rows_2f": 41979985},
+    },
 }
 
 
@@ -200,7 +203,23 @@ def headline(args, ds, refs):
     import numpy as np
     import torch
     from paper_2201_00451_amd import binding
-    dd = binding.DeviceData(ds, batch=1)
+    tune, tuned = None, None
+    if args.autotune > 0:
+        # the FFT launch shape from the search-path autotuner (median of three
+        # timed searches of a sample per shape; FSTAT_AUTOTUNE_CACHE, if set,
+        # keeps the result across runs)
+        dd0 = binding.DeviceData(ds, batch=1)
+        sample = ds.templates[:args.autotune]
+        t0 = time.perf_counter()
+        tune, tms, hit = binding.autotune_search(dd0, sample, slots=args.batch, repeats=3)
+        tuned = {"tune": tune, "median_ms_sample": round(tms, 3),
+                 "sample_templates": len(sample), "from_cache": hit,
+                 "seconds": round(time.perf_counter() - t0, 2)}
+        say(f"autotune: {tune} ({tms:.2f} ms per {len(sample)}-template search, "
+            f"{'cached' if hit else 'timed'})")
+        del dd0
+        torch.cuda.empty_cache()
+    dd = binding.DeviceData(ds, batch=1, tune=tune)
     k_pad, _, _ = dd.plan.info()
     ring = min(args.ring, ds.ntmpl)
     blocks = [(i, min(i + ring, ds.ntmpl)) for i in range(0, ds.ntmpl, ring)]
@@ -252,7 +271,7 @@ def headline(args, ds, refs):
 
     res = {"value": value, "ms_per_step": ms_step, "wall_s_timed": wall, "kernels": kern,
            "roofline": roof, "blocks": len(blocks), "ring": ring, "nchunks": nchunks,
-           "ngroups": ngroups, "flagged_templates": flagged}
+           "ngroups": ngroups, "flagged_templates": flagged, "autotune": tuned}
 
     def timed(fn, steps):
         torch.cuda.synchronize()
@@ -578,6 +597,9 @@ def main():
     ap.add_argument("--ring", type=int, default=1024,
                     help="headline: templates per block (rows of the reused output array)")
     ap.add_argument("--ntmpl", type=int, default=10000, help="headline bank size")
+    ap.add_argument("--autotune", type=int, default=64,
+                    help="headline: templates of the sample the search-path autotuner times "
+                         "each FFT launch shape on (0: the default shape)")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--graph-steps", type=int, default=1)
     ap.add_argument("--cand-steps", type=int, default=1)
@@ -601,6 +623,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--errors", type=int, default=1,
                     help="error against the FP64 oracle for each workload (0: skip)")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="run only the other workloads asked for (profiling and the full-scale "
+                         "refinement and uneven-batch runs); the line's value is null")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the measurements, run one plain device copy of this many MiB "
                          "(a reference kernel of known traffic for hardware counters)")
@@ -615,8 +640,12 @@ def main():
     import numpy as np
     from paper_2201_00451_amd import synth
 
-    say("generating the headline workload (2 x 5184000 samples, 10^4 binary templates)")
-    ds = synth.config_binary(ntmpl=args.ntmpl)
+    if args.no_headline:
+        args.no_cpu_baseline = True
+        ds = None
+    else:
+        say("generating the headline workload (2 x 5184000 samples, 10^4 binary templates)")
+        ds = synth.config_binary(ntmpl=args.ntmpl)
     # oracle on the host before the GPU is touched (its worker processes are
     # forked): the template nearest the injection, then a seeded sample
     cpu, refs = None, {}
@@ -637,8 +666,8 @@ def main():
 
     import torch
     from paper_2201_00451_amd import binding
-    hl = headline(args, ds, refs)
-    plain = hl.get("plain")
+    hl = headline(args, ds, refs) if ds is not None else None
+    plain = hl.get("plain") if hl else None
     others = {}
     if args.sky:
         others["sky_spindown"] = sky_leg(args)
@@ -659,6 +688,12 @@ def main():
         del src, dst
     binding.sync_check()
 
+    if hl is None:
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "templates/s", "n_gpus": 1,
+                          "headline": "skipped (--no-headline)", "other_workloads": others,
+                          "refinement": refine, "uneven_batch": uneven,
+                          "calibration_copy": calib}), flush=True)
+        return
     value = hl["value"]
     ms_step = hl["ms_per_step"]
     line = {
@@ -686,6 +721,7 @@ def main():
         "tau_eff_s_per_bin_per_det": (ms_step / 1e3) / (ds.ntmpl * ds.n_bins * ds.ndet),
         "kernels": hl["kernels"],
         "roofline": hl["roofline"],
+        "autotune": hl["autotune"],
         "error_vs_oracle": hl.get("error_vs_oracle"),
         "flagged_templates": hl["flagged_templates"],
         "cpu_baseline": cpu,

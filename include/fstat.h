@@ -356,6 +356,35 @@ FSTAT_API fstat_status fstat_autotune(const fstat_plan_desc* desc, const fstat_i
                                       void* workspace, size_t ws_bytes, void* stream,
                                       fstat_plan_desc* best, float* best_ms);
 
+/* The launch-shape autotuner on the search path (fstat_search_*, the path of
+ * large banks): every FFT launch shape fstat_autotune tries runs a search of
+ * the sample templates (templates_host: host copy of the rows, templates:
+ * device copy, ntmpl >= 1, both of the plan's row width) with `slots`
+ * template slots, once untimed and then `repeats` (>= 3) times timed with
+ * HIP events on `stream`; the shape with the smallest median time is
+ * returned in *best (desc with the tune fields set) and that median in
+ * *best_ms.  in->moments must hold the data set's antenna moments.  twoF: a
+ * device [ntmpl][n_bins] scratch output.  Each shape's workspace is
+ * allocated and freed inside the call (hipMalloc), so this is a set-up call,
+ * not one for a loop.  Synchronises the stream.
+ * Cache: cache_path, or if it is NULL the environment variable
+ * FSTAT_AUTOTUNE_CACHE (unset or empty: no cache), names a text file of one
+ * JSON object per line,
+ *   {"key": "n_fft=N ndet=K D=D flags=F slots=S n0=.. n1=..", "tune": [col_log_len,
+ *    col_lines, row_lines, radix], "ms": median}
+ * (n0.. the samples of each detector).  When a line with this set-up's key
+ * holds a shape the plan accepts, that shape is returned without running
+ * anything (*from_cache = 1; no input is read); otherwise the tuned result
+ * is appended (*from_cache = 0).  from_cache may be NULL.  Fails if no shape
+ * ran (with the last failure's status). */
+FSTAT_API fstat_status fstat_autotune_search(const fstat_plan_desc* desc, const fstat_inputs* in,
+                                             const double* templates_host,
+                                             const double* templates, int64_t ntmpl,
+                                             int32_t slots, int32_t repeats, float* twoF,
+                                             const char* cache_path, void* stream,
+                                             fstat_plan_desc* best, float* best_ms,
+                                             int32_t* from_cache);
+
 /* Diagnostic: steps (iii)-(v) and the weighting of (vi) only.  Writes the
  * weighted, resampled series before the transform, y: float2 [ntmpl][2][n_fft]
  * (y_a then y_b, zero beyond the data).  Needs fstat_workspace_size(plan, 1). */

@@ -30,7 +30,8 @@ EXPORTED = ("fstat_plan_create", "fstat_plan_destroy", "fstat_workspace_size",
             "fstat_grad_bin_workspace_size", "fstat_compute_2f_grad_bin", "fstat_autotune",
             "fstat_search_run_candidates", "fstat_batch_create", "fstat_batch_destroy",
             "fstat_batch_run", "fstat_flagged_count", "fstat_sfts_to_series",
-            "fstat_compute_2f_grad_bin_noalloc", "fstat_sinc_halfwidth_for")
+            "fstat_compute_2f_grad_bin_noalloc", "fstat_sinc_halfwidth_for",
+            "fstat_autotune_search")
 GRAD_PARAMS = ("df", "f1dot", "alpha", "delta", "asini", "porb", "tp")
 # template-row column of each gradient parameter
 GRAD_COLUMNS = (2, 3, 0, 1, 5, 6, 7)
@@ -117,6 +118,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fstat_autotune.argtypes = [ctypes.POINTER(FstatPlanDesc), ctypes.POINTER(FstatInputs),
                                    vp, i64, vp, vp, sz, vp, ctypes.POINTER(FstatPlanDesc),
                                    ctypes.POINTER(ctypes.c_float)]
+    lib.fstat_autotune_search.argtypes = [ctypes.POINTER(FstatPlanDesc),
+                                          ctypes.POINTER(FstatInputs), vp, vp, i64,
+                                          ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_char_p,
+                                          vp, ctypes.POINTER(FstatPlanDesc),
+                                          ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(ctypes.c_int32)]
     lib.fstat_grad_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
     lib.fstat_grad_bin_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
     lib.fstat_compute_2f_grad_bin.argtypes = [vp, ctypes.POINTER(FstatInputs), vp, i64, vp, vp,
@@ -505,6 +512,29 @@ def autotune(ds, templates, batch=8, device="cuda:0", stream=None):
                                          _stream_ptr(stream), ctypes.byref(best),
                                          ctypes.byref(ms)))
     return {k: int(getattr(best, k)) for k in TUNE_FIELDS}, float(ms.value)
+
+
+def autotune_search(dd: "DeviceData", templates, slots=32, repeats=3, cache=None,
+                    stream=None):
+    """fstat_autotune_search: the fastest FFT launch shape of this set-up on
+    the search path, timed as the median of `repeats` searches of the sample
+    `templates` with `slots` slots.  cache: a JSON-lines file (None: the
+    library reads FSTAT_AUTOTUNE_CACHE).  Returns (tune dict, median ms,
+    from_cache); pass the dict as ``tune`` to DeviceData."""
+    import torch
+    host = np.ascontiguousarray(np.asarray(templates, dtype=np.float64))
+    tm = _templates(dd, host)
+    n = tm.shape[0]
+    tf = torch.empty((n, dd.n_bins), dtype=torch.float32, device=dd.device)
+    best = FstatPlanDesc()
+    ms = ctypes.c_float()
+    hit = ctypes.c_int32()
+    _check(load_library().fstat_autotune_search(
+        ctypes.byref(dd.plan.desc), ctypes.byref(dd.inputs),
+        host.ctypes.data_as(ctypes.c_void_p), _ptr(tm), n, int(slots), int(repeats), _ptr(tf),
+        None if cache is None else str(cache).encode(), _stream_ptr(stream),
+        ctypes.byref(best), ctypes.byref(ms), ctypes.byref(hit)))
+    return {k: int(getattr(best, k)) for k in TUNE_FIELDS}, float(ms.value), bool(hit.value)
 
 
 def sfts_to_series(sfts, present, k0, t_sft, t_start=0.0, device="cuda:0", stream=None):

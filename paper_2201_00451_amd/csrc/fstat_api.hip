@@ -1339,6 +1339,183 @@ fstat_status fstat_autotune(const fstat_plan_desc* desc, const fstat_inputs* in,
   return ok();
 }
 
+}  // extern "C"
+
+namespace {
+
+// Autotune cache: one JSON object per line,
+//   {"key": "<key>", "tune": [col_log_len, col_lines, row_lines, radix], "ms": <median>}
+// with the key built from the set-up fields that decide the shapes' speed.
+std::string tune_key(const fstat_plan_desc* d, int32_t slots) {
+  char buf[256];
+  const int n = std::snprintf(buf, sizeof buf, "n_fft=%lld ndet=%d D=%d flags=%u slots=%d",
+                              static_cast<long long>(d->n_fft), d->ndet, d->sinc_halfwidth,
+                              static_cast<unsigned>(d->flags), slots);
+  std::string k(buf, size_t(n));
+  for (int X = 0; X < d->ndet; ++X)
+    k += " n" + std::to_string(X) + "=" + std::to_string(static_cast<long long>(d->det[X].n));
+  return k;
+}
+
+// The last cache line with this key (false: none, or the file is absent).
+bool tune_cache_find(const char* path, const std::string& key, int32_t v[4], float* ms) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  const std::string kq = "\"key\": \"" + key + "\"";
+  char line[4096];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    if (!std::strstr(line, kq.c_str())) continue;
+    const char* t = std::strstr(line, "\"tune\": [");
+    const char* m = std::strstr(line, "\"ms\": ");
+    int32_t a[4];
+    float x = 0.f;
+    if (t && m && std::sscanf(t + 9, "%d , %d , %d , %d", &a[0], &a[1], &a[2], &a[3]) == 4 &&
+        std::sscanf(m + 6, "%f", &x) == 1) {
+      for (int i = 0; i < 4; ++i) v[i] = a[i];
+      *ms = x;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_add(const char* path, const std::string& key, const fstat_plan_desc& d,
+                    float ms) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%s\", \"tune\": [%d, %d, %d, %d], \"ms\": %.6g}\n",
+               key.c_str(), d.tune_col_log_len, d.tune_col_lines, d.tune_row_lines,
+               d.tune_fft_radix, double(ms));
+  std::fclose(f);
+}
+
+// Median device time of `repeats` searches (after one untimed) with the
+// shape d; INFINITY with *err set when the shape does not run.
+float time_search_shape(const fstat_plan_desc& d, const fstat_inputs* in,
+                        const double* templates_host, const double* templates, int64_t ntmpl,
+                        int32_t slots, int32_t repeats, float* twoF, hipStream_t st,
+                        fstat_status* err) {
+  *err = FSTAT_OK;
+  fstat_plan* p = nullptr;
+  if ((*err = fstat_plan_create(&d, &p)) != FSTAT_OK) return INFINITY;
+  fstat_search* sr = nullptr;
+  void* ws = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<float> t;
+  fstat_status r = fstat_search_create(p, templates_host, ntmpl, slots, 0u, &sr);
+  size_t wsb = 0;
+  if (r == FSTAT_OK) r = fstat_search_info(sr, &wsb, nullptr, nullptr);
+  if (r == FSTAT_OK) r = check_hip(hipMalloc(&ws, wsb), "autotune workspace");
+  if (r == FSTAT_OK) r = check_hip(hipEventCreate(&e0), "event");
+  if (r == FSTAT_OK) r = check_hip(hipEventCreate(&e1), "event");
+  if (r == FSTAT_OK) r = fstat_search_run(sr, in, templates, twoF, nullptr, ws, wsb, st);
+  for (int i = 0; r == FSTAT_OK && i < repeats; ++i) {
+    float ms = 0.f;
+    r = check_hip(hipEventRecord(e0, st), "event record");
+    if (r == FSTAT_OK) r = fstat_search_run(sr, in, templates, twoF, nullptr, ws, wsb, st);
+    if (r == FSTAT_OK) r = check_hip(hipEventRecord(e1, st), "event record");
+    if (r == FSTAT_OK) r = check_hip(hipEventSynchronize(e1), "event synchronise");
+    if (r == FSTAT_OK) r = check_hip(hipEventElapsedTime(&ms, e0, e1), "event time");
+    if (r == FSTAT_OK) t.push_back(ms);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (ws) (void)hipFree(ws);
+  fstat_search_destroy(sr);
+  fstat_plan_destroy(p);
+  *err = r;
+  if (r != FSTAT_OK || t.empty()) return INFINITY;
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+}  // namespace
+
+extern "C" {
+
+fstat_status fstat_autotune_search(const fstat_plan_desc* desc, const fstat_inputs* in,
+                                   const double* templates_host, const double* templates,
+                                   int64_t ntmpl, int32_t slots, int32_t repeats, float* twoF,
+                                   const char* cache_path, void* stream, fstat_plan_desc* best,
+                                   float* best_ms, int32_t* from_cache) {
+  if (!best || !best_ms) return fail(FSTAT_EINVAL, "best or best_ms is NULL");
+  fstat_status s = validate_desc(desc);
+  if (s != FSTAT_OK) return s;
+  if (ntmpl < 1 || !templates_host || !templates || !twoF)
+    return fail(FSTAT_EINVAL, "need ntmpl >= 1 sample templates (host and device) and twoF");
+  if (slots < 1 || slots > kMaxSlots)
+    return fail(FSTAT_EINVAL, "slots=%d outside [1, %d]", slots, kMaxSlots);
+  if (repeats < 3) return fail(FSTAT_EINVAL, "repeats=%d: at least 3 timed runs", repeats);
+  if (from_cache) *from_cache = 0;
+  const char* cache = cache_path ? cache_path : std::getenv("FSTAT_AUTOTUNE_CACHE");
+  if (cache && !*cache) cache = nullptr;
+  const std::string key = tune_key(desc, slots);
+  if (cache) {
+    int32_t v[4];
+    float ms = 0.f;
+    if (tune_cache_find(cache, key, v, &ms)) {
+      fstat_plan_desc d = *desc;
+      d.tune_col_log_len = v[0];
+      d.tune_col_lines = v[1];
+      d.tune_row_lines = v[2];
+      d.tune_fft_radix = v[3];
+      fstat_plan* p = nullptr;
+      if (fstat_plan_create(&d, &p) == FSTAT_OK) {
+        fstat_plan_destroy(p);
+        *best = d;
+        *best_ms = ms;
+        if (from_cache) *from_cache = 1;
+        return ok();
+      }
+    }
+  }
+  if (!in) return fail(FSTAT_EINVAL, "inputs is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int log_n = ilog2(desc->n_fft);
+  const int splits[2] = {log_n / 2, (log_n + 1) / 2};
+  float best_t = INFINITY;
+  fstat_plan_desc cand_best = *desc;
+  fstat_status last = FSTAT_OK;
+  std::string last_msg;
+  for (int si = 0; si < 2; ++si) {
+    if (si == 1 && splits[1] == splits[0]) break;
+    const int lr = splits[si], lc = log_n - lr;
+    if (lr < 6 || lr > 12 || lc < 6 || lc > 12) continue;
+    for (int ch = 0; ch < 2; ++ch)
+      for (int rh = 0; rh < 2; ++rh)
+        for (int radix = 16; radix <= 32; radix *= 2) {
+          fstat_plan_desc d = *desc;
+          d.tune_col_log_len = lr;
+          d.tune_col_lines = ch ? cols_lines_max(lr) / 2 : cols_lines_max(lr);
+          d.tune_row_lines = rh ? rows_lines_max(lc) / 2 : rows_lines_max(lc);
+          d.tune_fft_radix = radix;
+          if (d.tune_col_lines < 1 || d.tune_row_lines < 1) continue;
+          fstat_status r;
+          const float ms = time_search_shape(d, in, templates_host, templates, ntmpl, slots,
+                                             repeats, twoF, st, &r);
+          if (r != FSTAT_OK) {
+            last = r;
+            last_msg = g_err;
+            if (r == FSTAT_EHIP) break;
+            continue;
+          }
+          if (ms < best_t) {
+            best_t = ms;
+            cand_best = d;
+          }
+        }
+  }
+  if (!(best_t < INFINITY))
+    return fail(last != FSTAT_OK ? last : FSTAT_EINVAL, "autotune: no launch shape ran (%s)",
+                last_msg.c_str());
+  *best = cand_best;
+  *best_ms = best_t;
+  if (cache) tune_cache_add(cache, key, cand_best, best_t);
+  return ok();
+}
+
 fstat_status fstat_resample(const fstat_plan* plan, const fstat_inputs* in,
                             const double* templates, int64_t ntmpl, void* y, void* workspace,
                             size_t ws_bytes, void* stream) {

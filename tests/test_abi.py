@@ -322,6 +322,48 @@ def test_autotune_checks_arguments_before_any_launch(lib):
                 vp(0), ctypes.byref(best), ctypes.byref(ms)) == B.FSTAT_EINVAL
 
 
+def test_autotune_search_cache_hit_runs_nothing(lib, tmp_path):
+    """fstat_autotune_search with a cache line for this set-up returns its
+    shape without touching the device (here, with no GPU at all); a line for
+    another set-up, or a shape the plan refuses, is not taken; the argument
+    checks come first."""
+    ds, d = good_desc()
+    vp = ctypes.c_void_p
+    best = B.FstatPlanDesc()
+    ms = ctypes.c_float()
+    hit = ctypes.c_int32(7)
+    inp = B.FstatInputs()
+    tm = np.zeros((1, 8))
+    key = f"n_fft={d.n_fft} ndet={d.ndet} D={d.sinc_halfwidth} flags={d.flags} slots=4" + \
+        "".join(f" n{x}={d.det[x].n}" for x in range(d.ndet))
+    log_n = int(math.log2(d.n_fft))
+    lr = log_n // 2
+    # line counts the plan accepts: the largest that fits the LDS, or half
+    cmax, rmax = min(16384 >> lr, 64), min(8192 >> (log_n - lr), 32)
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text(
+        '{"key": "' + key.replace("slots=4", "slots=5") + f'", "tune": [{lr}, {cmax}, {rmax}, '
+        '16], "ms": 1.5}\n'
+        '{"key": "' + key + f'", "tune": [{lr}, {cmax // 2}, {rmax}, 32], "ms": 2.25}}\n')
+    call = lib.fstat_autotune_search
+    args = lambda slots, reps, c: (ctypes.byref(d), ctypes.byref(inp), tm.ctypes.data_as(vp),
+                                    vp(4096), 1, slots, reps, vp(4096), c, vp(0),
+                                    ctypes.byref(best), ctypes.byref(ms), ctypes.byref(hit))
+    assert call(*args(4, 2, str(cache).encode())) == B.FSTAT_EINVAL
+    assert "repeats" in B.last_error()
+    assert call(*args(0, 3, str(cache).encode())) == B.FSTAT_EINVAL
+    assert call(*args(4, 3, str(cache).encode())) == B.FSTAT_OK
+    assert hit.value == 1 and abs(ms.value - 2.25) < 1e-6
+    assert (best.tune_col_log_len, best.tune_col_lines, best.tune_row_lines,
+            best.tune_fft_radix) == (lr, cmax // 2, rmax, 32)
+    assert best.n_fft == d.n_fft and best.ndet == d.ndet
+    # a refused shape (column length outside [6, 12]) is not taken: the call
+    # goes on to time shapes, which needs a device
+    cache.write_text('{"key": "' + key + f'", "tune": [13, {cmax}, {rmax}, 32], "ms": 2.25}}\n')
+    r = call(*args(4, 3, str(cache).encode()))
+    assert r != B.FSTAT_OK and hit.value == 0
+
+
 def test_batch_checks_arguments_before_any_launch(lib):
     """fstat_batch_create/run validate every argument on the host."""
     vp = ctypes.c_void_p

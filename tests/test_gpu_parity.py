@@ -365,6 +365,33 @@ def test_autotuned_launch_shape(torch_dev):
         assert_2f_parity(got[i], ref[i], f"autotuned tmpl {i}")
 
 
+def test_autotuned_search_shape_and_cache(torch_dev, tmp_path):
+    """The search-path autotuner (median of three timed searches per shape)
+    returns a shape the plan accepts, writes it to the cache, and a second
+    call takes it from there without timing; a search with the shape meets
+    the bar against the oracle."""
+    from paper_2201_00451_amd import binding
+    ds = synth.small_case(**dict(CASES["binary"], n=3000, n_fft=1 << 13, ntmpl=4))
+    dd = binding.DeviceData(ds)
+    cache = tmp_path / "tune.jsonl"
+    tune, ms, hit = binding.autotune_search(dd, ds.templates, slots=2, repeats=3, cache=cache)
+    say(f"  search-path autotune {tune}, median {ms:.3f} ms, cached {hit}")
+    assert not hit and ms > 0.0
+    assert tune["tune_col_log_len"] in (6, 7) and tune["tune_fft_radix"] in (16, 32)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and '"tune": [' in lines[0]
+    tune2, ms2, hit2 = binding.autotune_search(dd, ds.templates, slots=2, repeats=3,
+                                               cache=cache)
+    assert hit2 and tune2 == tune and abs(ms2 - ms) <= 1e-5 * ms
+    assert len(cache.read_text().splitlines()) == 1
+    dd2 = binding.DeviceData(ds, tune=tune)
+    got = binding.Search(dd2, ds.templates, slots=2).run().cpu().numpy()
+    binding.sync_check()
+    ref = O.oracle_twoF(ds)
+    for i in range(ds.ntmpl):
+        assert_2f_parity(got[i], ref[i], f"search-autotuned tmpl {i}")
+
+
 def test_second_spindown_term_grouped_and_peak(torch_dev):
     """f2dot moving the phase by several cycles over the data: a sky group of
     templates that differ only in f2dot (one shared resampled series, each
