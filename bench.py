@@ -89,7 +89,8 @@ def step_bytes(ds, k_pad, n_resampled, ntmpl=None):
 def error_stats(gpu, ref):
     """Error of GPU 2F against the oracle over the given bins: the bar's two
     measures (relative where the oracle's 2F >= 10, absolute elsewhere), the
-    RMS fractional error and r_2 of Sec. 4.2."""
+    RMS fractional error, and Sec. 4.2's r_1, r_2 (relative L1 and L2 errors)
+    and theta (the angle between the two 2F vectors)."""
     import numpy as np
     from oracle import fstat_oracle as O
     gpu = np.asarray(gpu, dtype=np.float64).ravel()
@@ -102,7 +103,9 @@ def error_stats(gpu, ref):
             "max_rel_2F_ge_10": float(f"{rel.max():.3e}"),
             "max_abs_else": float(f"{ab.max():.3e}"),
             "rms_frac": float(f"{np.sqrt(np.mean(frac ** 2)):.3e}"),
+            "r1": float(f"{O.rel_err(gpu, ref, 1):.3e}"),
             "r2": float(f"{O.rel_err(gpu, ref, 2):.3e}"),
+            "theta": float(f"{O.angle(gpu, ref):.3e}"),
             "within_bar": bool(rel.max() <= 1e-4 and ab.max() <= 1e-3)}
 
 
@@ -126,25 +129,30 @@ def host_cpu():
 _POOL_DS = None
 
 
-def _oracle_one(t):
+def _oracle_one(t, fafb=False):
     from threadpoolctl import threadpool_limits
     from oracle import fstat_oracle as O
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        out = O.oracle_twoF(_POOL_DS, _POOL_DS.templates[[t]])[0]
-        return t, out, time.perf_counter() - t0
+        out = O.oracle_twoF(_POOL_DS, _POOL_DS.templates[[t]], return_fafb=fafb)
+        el = time.perf_counter() - t0
+        if fafb:
+            tf, ff = out
+            return t, tf[0], el, ff[0][:2]
+        return t, out[0], el
 
 
 def cpu_baseline(ds, picks, workers):
     """The FP64 oracle (numpy, one thread per process) on sampled templates of
     the headline workload: picks[0] alone on one core, then picks[1:] on
     `workers` forked processes at once (run before the GPU is touched).
-    Returns the baseline record and the oracle's 2F of every pick."""
+    Returns the baseline record, the oracle's 2F of every pick, and
+    (picks[0], (Fa, Fb)) of the first."""
     import multiprocessing as mp
     global _POOL_DS
     _POOL_DS = ds
     model, ncpu, avail = host_cpu()
-    t, ref0, el1 = _oracle_one(picks[0])
+    t, ref0, el1, fafb0 = _oracle_one(picks[0], fafb=True)
     say(f"oracle: template {t} on one core in {el1:.1f} s")
     refs = {t: ref0}
     rest = list(picks[1:])
@@ -172,7 +180,7 @@ def cpu_baseline(ds, picks, workers):
            "cpu_model": model, "nproc": ncpu, "cpus_available": avail,
            "tau_eff_s_per_bin_per_det_one_core": el1 / (ds.n_bins * ds.ndet)}
     _POOL_DS = None
-    return rec, refs
+    return rec, refs, (picks[0], fafb0)
 
 
 def kernel_table(totals, bytes_step, steps):
@@ -198,7 +206,7 @@ def roofline(kern, totals, workload, ntmpl):
             "bytes_per_launch": kern[dom]["bytes_per_launch"]}
 
 
-def headline(args, ds, refs):
+def headline(args, ds, refs, fafb_ref=None):
     """The binary workload: 10^4 templates, full band, batched search path."""
     import numpy as np
     import torch
@@ -325,9 +333,10 @@ def headline(args, ds, refs):
         torch.cuda.empty_cache()
     # error against the oracle on the sampled templates
     if refs:
+        from oracle import fstat_oracle as O
         picks = sorted(refs)
         rows = []
-        dd8 = binding.DeviceData(ds, batch=8)
+        dd8 = binding.DeviceData(ds, batch=8, tune=tune)
         for i in range(0, len(picks), 8):
             rows.append(binding.compute_2f_batched(dd8, tm[picks[i:i + 8]]).cpu().numpy())
         got = np.concatenate(rows, axis=0)
@@ -335,6 +344,16 @@ def headline(args, ds, refs):
         ref = np.stack([refs[t] for t in picks])
         st = error_stats(got, ref)
         st["templates"] = picks
+        if fafb_ref is not None:
+            # Sec. 4.2's metrics for Fa and Fb of the template nearest the injection
+            t_f, (fa_ref, fb_ref) = fafb_ref
+            _, fab = binding.compute_2f(dd8, tm[[t_f]], fafb=True)
+            fab = fab[0].cpu().numpy()
+            st["fa_fb"] = {"template": t_f}
+            for name, g, r in (("Fa", fab[0], fa_ref), ("Fb", fab[1], fb_ref)):
+                st["fa_fb"][name] = {"r1": float(f"{O.rel_err(g, r, 1):.3e}"),
+                                     "r2": float(f"{O.rel_err(g, r, 2):.3e}"),
+                                     "theta": float(f"{O.angle(g, r):.3e}")}
         res["error_vs_oracle"] = st
         del dd8
     del searches, shared, out
@@ -538,7 +557,11 @@ def uneven_leg(args):
     from paper_2201_00451_amd import binding, synth
     n_search = args.uneven_searches
     say(f"{n_search} uneven searches")
-    dss = synth.config_uneven(seed=4, n_search=n_search)
+    dss = []
+    for i in range(0, n_search, 32):
+        pick = set(range(i, min(i + 32, n_search)))
+        dss += synth.config_uneven(seed=4, n_search=n_search, pick=pick)
+        say(f"uneven: {len(dss)}/{n_search} searches generated")
     srs = [binding.Search(binding.DeviceData(ds), ds.templates, slots=8) for ds in dss]
     outs = [torch.empty((sr.ntmpl, ds.n_bins), dtype=torch.float32, device="cuda")
             for sr, ds in zip(srs, dss)]
@@ -648,7 +671,7 @@ def main():
         ds = synth.config_binary(ntmpl=args.ntmpl)
     # oracle on the host before the GPU is touched (its worker processes are
     # forked): the template nearest the injection, then a seeded sample
-    cpu, refs = None, {}
+    cpu, refs, fafb_ref = None, {}, None
     if not args.no_cpu_baseline:
         _, _, avail = host_cpu()
         workers = min(16, avail) if args.cpu_samples == 0 else args.cpu_samples
@@ -662,11 +685,11 @@ def main():
                   if t != near][:workers]
         say(f"FP64 oracle on the host: template {near} on one core, {len(others)} on "
             f"{workers} processes")
-        cpu, refs = cpu_baseline(ds, [near] + others, workers)
+        cpu, refs, fafb_ref = cpu_baseline(ds, [near] + others, workers)
 
     import torch
     from paper_2201_00451_amd import binding
-    hl = headline(args, ds, refs) if ds is not None else None
+    hl = headline(args, ds, refs, fafb_ref) if ds is not None else None
     plain = hl.get("plain") if hl else None
     others = {}
     if args.sky:
