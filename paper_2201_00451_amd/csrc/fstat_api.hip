@@ -102,15 +102,35 @@ FftVariant cols_variant_n() {
   constexpr size_t lds = kLdsBytes<1 << LOGL, R0, NL, NL>;
   return {reinterpret_cast<const void*>(&k_fft_cols<LOGL, NL, NT, GROUPED, MLR>), NT, lds, NL};
 }
+// Columns of 2^11 and 2^12 points at the full line count split each column
+// in two halves that go through LDS one after the other (k_fft_cols_half),
+// so two workgroups share a compute unit.
+template <int LOGL, bool GROUPED, int MLR>
+FftVariant cols_half_lds_variant() {
+  constexpr int NL = kColsMax<LOGL>;
+  constexpr int R0 = kR0<LOGL - 1, MLR>;
+  constexpr size_t lds = kLdsBytes<1 << (LOGL - 1), R0, NL, NL>;
+  return {reinterpret_cast<const void*>(&k_fft_cols_half<LOGL, NL, 512, GROUPED, MLR>), 512, lds,
+          NL};
+}
 template <int LOGL, bool GROUPED, int MLR>
 FftVariant cols_variant(bool half) {
   if (half) return cols_variant_n<LOGL, GROUPED, MLR, kColsMax<LOGL> / 2, 256>();
+  if constexpr (LOGL >= 11) return cols_half_lds_variant<LOGL, GROUPED, MLR>();
   return cols_variant_n<LOGL, GROUPED, MLR, kColsMax<LOGL>, 512>();
 }
 template <int LOGL, int MODE, int MLR, int RQ, int NT>
 FftVariant rows_variant_n() {
   constexpr int R0 = kR0<LOGL, MLR>;
   constexpr size_t lds = kLdsBytes<1 << LOGL, R0, RQ, 2 * RQ>;
+  // rows of 2^12 at the full count: two halves through LDS one after the
+  // other (k_fft_rows_half; every epilogue, so that they all give the plain
+  // 2F pass's bits), two workgroups per compute unit for the plain 2F pass
+  if constexpr (LOGL >= 12 && NT == 512 && RQ == kRowsMax<LOGL>) {
+    constexpr int RH = kR0<LOGL - 1, MLR>;
+    return {reinterpret_cast<const void*>(&k_fft_rows_half<LOGL, RQ, NT, MODE, MLR>), NT,
+            kLdsBytes<1 << (LOGL - 1), RH, RQ, 2 * RQ>, RQ};
+  }
   return {reinterpret_cast<const void*>(&k_fft_rows<LOGL, RQ, NT, MODE, MLR>), NT, lds, RQ};
 }
 // The plain 2F pass at the full row count holds one array at a time in LDS

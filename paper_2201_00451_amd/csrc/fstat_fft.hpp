@@ -328,10 +328,12 @@ __device__ __forceinline__ void cols_stage0(const ColItem& it, int64_t C, int64_
 }
 
 // Middle stages in LDS, then the last stage: LDS -> DFT -> x W_N^{q c} -> HBM.
-template <int LOGL, int NL, int NT, int MLR>
+// The line's outputs k go to rows q = QS k + h (QS = 2: one half of a column
+// split in two, see k_fft_cols_half).
+template <int LOGL, int NL, int NT, int MLR, int QS = 1>
 __device__ __forceinline__ void cols_finish(const PlanConst& P, void* ws, int arr_base,
                                             int64_t C, const ColItem& it, float2* lds,
-                                            const float2* twl, int tid) {
+                                            const float2* twl, int tid, int h = 0) {
   constexpr int L = 1 << LOGL;
   constexpr int NS = stage_count(LOGL, MLR);
   constexpr int R0 = kR0<LOGL, MLR>;
@@ -353,14 +355,15 @@ __device__ __forceinline__ void cols_finish(const PlanConst& P, void* ws, int ar
       for (int j = 0; j < RL; ++j) u[j] = lds[Lay::template at_step<PL>(i, j, line)];
       twiddle_dft<RL, PL, L>(u, i, twl);
       const int64_t c = c0 + line;
-      // W_N^{c (i + m PL)} = W_N^{c i} (W_N^{c PL})^m
-      float2 w = tw_n((int64_t(i) * c) & nmask, P.n_fft);
-      const float2 step = tw_n((int64_t(PL) * c) & nmask, P.n_fft);
-      const uint32_t voff = uint32_t((int64_t(i) * C + c) * int64_t(sizeof(float2)));
+      // row q = QS (i + m PL) + h: W_N^{c q} = W_N^{c q0} (W_N^{c QS PL})^m
+      const int64_t q0 = int64_t(QS) * i + h;
+      float2 w = tw_n((q0 * c) & nmask, P.n_fft);
+      const float2 step = tw_n((int64_t(QS) * PL * c) & nmask, P.n_fft);
+      const uint32_t voff = uint32_t((q0 * C + c) * int64_t(sizeof(float2)));
 #pragma unroll
       for (int m = 0; m < RL; ++m) {
         buf_store2(cmul(u[m], w), wr, voff,
-                   uint32_t(int64_t(m) * PL * C * int64_t(sizeof(float2))));
+                   uint32_t(int64_t(m) * QS * PL * C * int64_t(sizeof(float2))));
         w = cmul(w, step);
       }
     }
@@ -390,6 +393,96 @@ __global__ __launch_bounds__(NT) void k_fft_cols(PlanConst P, void* ws, ChunkMap
   cols_stage0<LOGL, NL, NT, GROUPED, MLR>(it, C, rows_act, v, lds, tid);
   __syncthreads();
   cols_finish<LOGL, NL, NT, MLR>(P, ws, arr_base, C, it, lds, twl, tid);
+}
+
+// The column pass for long columns in half the LDS.  With H = L/2 and
+// y_h[r] = (x[r] + (-1)^h x[r + H]) W_L^{r h}, r < H, rows 2k + h of the
+// column's transform are the H-point transform of y_h (one radix-2 step of
+// decimation in frequency).  Each thread loads x[r] and x[r + H] of its
+// first-stage butterflies and combines them in registers; y_0 goes through
+// the LDS stages while y_1 waits in registers, then y_1 follows.  Half the
+// LDS lets two workgroups share a compute unit, so that one's loads and
+// stores overlap the other's transform.
+template <int LOGL, int NL, int NT, bool GROUPED, int MLR>
+__global__ __launch_bounds__(NT, NT / 128) void k_fft_cols_half(PlanConst P, void* ws, ChunkMap map,
+                                                         int slots, int arr_base, int log_c,
+                                                         int64_t rows_act) {
+  extern __shared__ float2 lds[];
+  constexpr int LH = LOGL - 1;
+  constexpr int L = 1 << LOGL, H = L / 2;
+  constexpr int R0 = kR0<LH, MLR>, S0 = H / R0, NB0 = NL * S0;
+  constexpr int PER0 = kPer0<LH, NL, NT, MLR>;
+  using Lay = LdsLayout<H, R0, NL>;
+  float2* twl = lds + NL * Lay::pitch;
+  const int tid = threadIdx.x;
+  const int64_t C = int64_t(1) << log_c;
+  const float2* __restrict__ tws = tw_stage(ws);
+  for (int e = tid; e < H / 2; e += NT) twl[e] = tws[e * (kTwLen / H)];
+  const ColItem it = cols_item<GROUPED>(P, ws, map, slots, int(C / NL),
+                                        int(xcd_remap(blockIdx.x, gridDim.x)));
+  if (!it.live) return;
+  const int64_t c0 = it.cg * NL;
+  float2 a[PER0][R0], b[PER0][R0];
+  {
+    const float2* src = GROUPED ? group_buf(ws, P, slots, map.tmpl_buf[it.g], it.arr)
+                                : slot_buf(ws, P, it.g, arr_base + it.arr);
+    const auto rs = buf_rsrc(src, uint32_t(rows_act * C * int64_t(sizeof(float2))));
+#pragma unroll
+    for (int s = 0; s < PER0; ++s) {
+      const int bb = tid + s * NT;
+      if (NB0 % NT == 0 || bb < NB0) {
+        const int line = bb % NL, i = bb / NL;
+        const uint32_t voff = uint32_t((int64_t(i) * C + c0 + line) * int64_t(sizeof(float2)));
+#pragma unroll
+        for (int j = 0; j < R0; ++j) {
+          a[s][j] = buf_load2(rs, voff, uint32_t(int64_t(j) * S0 * C * int64_t(sizeof(float2))));
+          b[s][j] = buf_load2(rs, voff,
+                              uint32_t((int64_t(j) * S0 + H) * C * int64_t(sizeof(float2))));
+        }
+      }
+    }
+  }
+  // spin-down phase (search path), the radix-2 step and y_1's twiddle W_L^r
+#pragma unroll
+  for (int s = 0; s < PER0; ++s) {
+    const int bb = tid + s * NT;
+    if (NB0 % NT == 0 || bb < NB0) {
+      const int line = bb % NL, i = bb / NL;
+#pragma unroll
+      for (int j = 0; j < R0; ++j) {
+        const int r = i + j * S0;
+        if (GROUPED) {
+          if (r < rows_act)
+            a[s][j] = cmul_exact(a[s][j], spindown_rotation(it.sd, int64_t(r) * C + c0 + line));
+          if (r + H < rows_act)
+            b[s][j] = cmul_exact(b[s][j],
+                                 spindown_rotation(it.sd, int64_t(r + H) * C + c0 + line));
+        }
+        const float2 d = csub(a[s][j], b[s][j]);
+        a[s][j] = cadd(a[s][j], b[s][j]);
+        b[s][j] = cmul(d, tws[r * (kTwLen / L)]);
+      }
+    }
+  }
+  // y_0: first stage into LDS, the other stages, rows 2k; then y_1, rows 2k + 1
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int s = 0; s < PER0; ++s) {
+      const int bb = tid + s * NT;
+      if (NB0 % NT == 0 || bb < NB0) {
+        const int line = bb % NL, i = bb / NL;
+        float2(&v)[R0] = h ? b[s] : a[s];
+        dft<R0>(v);
+#pragma unroll
+        for (int m = 0; m < R0; ++m) lds[Lay::at_block(i, m, line)] = v[m];
+      }
+    }
+    __syncthreads();
+    cols_finish<LH, NL, NT, MLR, 2>(P, ws, arr_base, C, it, lds, twl, tid, h);
+    // the last stage has read the lines before y_1's first stage writes them
+    if (h == 0) __syncthreads();
+  }
 }
 
 // Row pass with the 2F epilogue (eq. Fstat, normalised as 2F = 2 F^T M^-1 F,
@@ -585,11 +678,13 @@ __device__ __forceinline__ void rows_stage0(float2* lds, int tid,
   }
 }
 
-// Middle stages, then the last stage of both arrays and the epilogue.
-template <int LOGL, int RQ, int NT, int MODE, int MLR>
+// Middle stages, then the last stage of both arrays and the epilogue.  The
+// line's outputs k are the row transform's entries p = QS k + h (QS = 2: one
+// half of a row split in two, see k_fft_rows_half).
+template <int LOGL, int RQ, int NT, int MODE, int MLR, int QS = 1>
 __device__ __forceinline__ void rows_finish(const PlanConst& P, void* ws, const RowItem& it,
                                             const RowOutput& out, int64_t Rr, float2* lds,
-                                            const float2* twl, int tid) {
+                                            const float2* twl, int tid, int h = 0) {
   constexpr int L = 1 << LOGL;
   constexpr int NL = 2 * RQ;
   constexpr int NS = stage_count(LOGL, MLR);
@@ -605,7 +700,7 @@ __device__ __forceinline__ void rows_finish(const PlanConst& P, void* ws, const 
   const auto tf = buf_rsrc(MODE == kRow2F ? out.twoF + it.tmpl * P.n_bins : nullptr,
                            MODE == kRow2F ? uint32_t(P.n_bins * int64_t(sizeof(float))) : 0u);
   const uint32_t nmask = uint32_t(P.n_fft - 1), lo = uint32_t(P.bin_lo);
-  const uint32_t ostep = uint32_t(Rr * PL);
+  const uint32_t ostep = uint32_t(Rr * QS * PL);
 #pragma unroll
   for (int s = 0; s < PER; ++s) {
     const int b = tid + s * NT;
@@ -620,7 +715,7 @@ __device__ __forceinline__ void rows_finish(const PlanConst& P, void* ws, const 
       twiddle_dft<RL, PL, L>(va, i, twl);
       twiddle_dft<RL, PL, L>(vb, i, twl);
       if (MODE == kRow2F) {
-        const uint32_t o0 = uint32_t(it.q0 + ql + Rr * i) + uint32_t(P.n_fft / 2);
+        const uint32_t o0 = uint32_t(it.q0 + ql + Rr * (QS * i + h)) + uint32_t(P.n_fft / 2);
 #pragma unroll
         for (int m = 0; m < RL; ++m) {
           const uint32_t o = ((o0 + uint32_t(m) * ostep) & nmask) - lo;
@@ -630,7 +725,7 @@ __device__ __forceinline__ void rows_finish(const PlanConst& P, void* ws, const 
       }
 #pragma unroll
       for (int m = 0; m < RL; ++m) {
-        const int64_t nat = it.q0 + ql + Rr * int64_t(i + m * PL);
+        const int64_t nat = it.q0 + ql + Rr * (int64_t(QS) * (i + m * PL) + h);
         const float v2 = rows_out<MODE>(P, ws, it, nat, va[m], vb[m], out);
         if (v2 >= 0.0f) {
           const unsigned long long key =
@@ -671,6 +766,87 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
   rows_stage0<LOGL, RQ, NT, MLR, NL>(lds, tid, v);
   __syncthreads();
   rows_finish<LOGL, RQ, NT, MODE, MLR>(P, ws, it, out, Rr, lds, twl, tid);
+}
+
+// The row pass for long rows in half the LDS: the radix-2 step of
+// k_fft_cols_half applied to the RQ rows of both arrays (y_h[c] = (x[c] +
+// (-1)^h x[c + L/2]) W_L^{c h}; entries 2k + h of the row transform are the
+// (L/2)-point transform of y_h), y_1 waiting in registers while y_0 goes
+// through LDS and the epilogue, so two workgroups share a compute unit
+// (plain 2F; the other epilogues need more registers and run one).
+template <int LOGL, int RQ, int NT, int MODE, int MLR>
+__global__ __launch_bounds__(NT, MODE == kRow2F ? NT / 128 : NT / 256) void k_fft_rows_half(
+    PlanConst P, void* ws, ChunkMap map, int slots, int log_rr, RowOutput out) {
+  extern __shared__ float2 lds[];
+  constexpr int LH = LOGL - 1;
+  constexpr int L = 1 << LOGL, H = L / 2;
+  constexpr int NL = 2 * RQ;
+  constexpr int R0 = kR0<LH, MLR>, S0 = H / R0, NB0 = NL * S0;
+  constexpr int PER0 = kPer0<LH, NL, NT, MLR>;
+  using Lay = LdsLayout<H, R0, RQ>;
+  float2* twl = lds + NL * Lay::pitch;
+  const int64_t Rr = int64_t(1) << log_rr;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid < map.n_reset) *group_status(ws, P, slots, map.reset_buf[tid]) = 0;
+  const float2* __restrict__ tws = tw_stage(ws);
+  for (int e = tid; e < H / 2; e += NT) twl[e] = tws[e * (kTwLen / H)];
+  const RowItem it =
+      rows_item<MODE>(P, ws, map, int(xcd_remap(blockIdx.x, gridDim.x)), int(Rr / RQ), RQ);
+  if (it.flagged && MODE != kRowConj) rows_flagged<LOGL, RQ, NT>(P, ws, it, Rr, out);
+  if (!it.live) return;
+  float2 a[PER0][R0], b[PER0][R0];
+  {
+    const auto rs = buf_rsrc(slot_buf(ws, P, it.g, MODE == kRowConj ? 2 : 0),
+                             uint32_t(2 * P.n_fft * int64_t(sizeof(float2))));
+#pragma unroll
+    for (int s = 0; s < PER0; ++s) {
+      const int bb = tid + s * NT;
+      if (NB0 % NT == 0 || bb < NB0) {
+        const int i = bb % S0, line = bb / S0;
+        const int64_t e0 = (line < RQ ? 0 : P.n_fft) + (it.q0 + line % RQ) * L + i;
+        const uint32_t voff = uint32_t(e0 * int64_t(sizeof(float2)));
+#pragma unroll
+        for (int j = 0; j < R0; ++j) {
+          const uint32_t soff = uint32_t(j * S0 * int(sizeof(float2)));
+          const uint32_t soff2 = uint32_t((j * S0 + H) * int(sizeof(float2)));
+          a[s][j] = MODE == kRow2F ? buf_load2_stream(rs, voff, soff) : buf_load2(rs, voff, soff);
+          b[s][j] = MODE == kRow2F ? buf_load2_stream(rs, voff, soff2)
+                                   : buf_load2(rs, voff, soff2);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < PER0; ++s) {
+    const int bb = tid + s * NT;
+    if (NB0 % NT == 0 || bb < NB0) {
+      const int i = bb % S0;
+#pragma unroll
+      for (int j = 0; j < R0; ++j) {
+        const int c = i + j * S0;
+        const float2 d = csub(a[s][j], b[s][j]);
+        a[s][j] = cadd(a[s][j], b[s][j]);
+        b[s][j] = cmul(d, tws[c * (kTwLen / L)]);
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int s = 0; s < PER0; ++s) {
+      const int bb = tid + s * NT;
+      if (NB0 % NT == 0 || bb < NB0) {
+        const int i = bb % S0, line = bb / S0;
+        float2(&v)[R0] = h ? b[s] : a[s];
+        dft<R0>(v);
+#pragma unroll
+        for (int m = 0; m < R0; ++m) lds[Lay::at_block(i, m, line)] = v[m];
+      }
+    }
+    __syncthreads();
+    rows_finish<LH, RQ, NT, MODE, MLR, 2>(P, ws, it, out, Rr, lds, twl, tid, h);
+    if (h == 0) __syncthreads();
+  }
 }
 
 // Plain 2F row pass holding one array at a time: the RQ rows of y_a' are
