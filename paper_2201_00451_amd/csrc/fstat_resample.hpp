@@ -133,38 +133,25 @@ __device__ __forceinline__ void interp_taps(std::integer_sequence<int, T...>, fl
   (interp_tap<D, T>(f, wc, ws, zp, sx, sy), ...);
 }
 
-// Step (v) and the weighting of step (vi) at one grid point k_s + kk of
-// detector X, whose epoch is T_k = tau_k + q dt: the 2D-tap interpolation of
-// the staged window zs (starting at sample lo, W samples, block flags blk)
-// at u = k + off + q, times the whitened antenna patterns at T_k, added to
-// acc_a, acc_b.  A point whose taps all fall on zero samples adds nothing.
+// Step (v): the 2D-tap interpolation of the samples zp[0 .. 2D) at the
+// fraction f of the point between zp[D - 1] and zp[D].
 template <int D>
-__device__ __forceinline__ void interp_point(const PlanConst& P, const TmplParams& tp, int X,
-                                             const float2* zs, const int32_t* blk, int64_t lo,
-                                             int W, int64_t k_s, int kk, double q, double tau_s,
-                                             float2& acc_a, float2& acc_b) {
-  int64_t j0;
-  float f;
-  split_u(double(k_s + kk) + P.det[X].off + q, j0, f);
-  // taps j0-D+1 .. j0+D; monotonic T_k keeps them inside the window, the
-  // clamp only guards memory
-  int base = int(j0 - lo) - (D - 1);
-  base = base < 0 ? 0 : (base > W - 2 * D ? W - 2 * D : base);
-  if (!(blk[base >> 5] | blk[(base + 2 * D - 1) >> 5])) return;
-  const float2* zp = zs + base;
-  float2 zh;
-  if (f == 0.0f) {
-    zh = zp[D - 1];
-  } else {
-    // window phase pi f / D and sinc numerator sin(pi f), in cycles
-    const float2 wcs = cis_cycles_f32(f * (0.5f / float(D)));
-    float sx = 0.f, sy = 0.f;
-    interp_taps<D>(std::make_integer_sequence<int, 2 * D>{}, f, wcs.x, wcs.y, zp, sx, sy);
-    const float sp = cis_cycles_f32(0.5f * f).y * float(0.5 / kPi);
-    zh = make_float2(sx * sp, sy * sp);
-  }
-  // antenna patterns at T_k: x = alpha - phi(T_k), in cycles
-  const double tau = tau_s + P.dt * double(kk);
+__device__ __forceinline__ float2 sinc_interp(float f, const float2* zp) {
+  if (f == 0.0f) return zp[D - 1];
+  // window phase pi f / D and sinc numerator sin(pi f), in cycles
+  const float2 wcs = cis_cycles_f32(f * (0.5f / float(D)));
+  float sx = 0.f, sy = 0.f;
+  interp_taps<D>(std::make_integer_sequence<int, 2 * D>{}, f, wcs.x, wcs.y, zp, sx, sy);
+  const float sp = cis_cycles_f32(0.5f * f).y * float(0.5 / kPi);
+  return make_float2(sx * sp, sy * sp);
+}
+
+// The weighting of step (vi): the whitened antenna patterns of detector X
+// at T = tau + q dt times the interpolated value, added to acc_a, acc_b.
+__device__ __forceinline__ void weight_add(const PlanConst& P, const TmplParams& tp, int X,
+                                           double tau, double q, float2 zh, float2& acc_a,
+                                           float2& acc_b) {
+  // x = alpha - phi(T), in cycles
   const float2 ex = cis_cycles(tp.alpha_cyc[X] - P.sid_rate_cyc * (tau + q * P.dt));
   const float cx = ex.x, sx = ex.y;
   const float c2 = cx * cx - sx * sx, s2 = 2.0f * sx * cx;
@@ -176,6 +163,37 @@ __device__ __forceinline__ void interp_point(const PlanConst& P, const TmplParam
   acc_a.y = fmaf(a, zh.y, acc_a.y);
   acc_b.x = fmaf(b, zh.x, acc_b.x);
   acc_b.y = fmaf(b, zh.y, acc_b.y);
+}
+
+// The first tap of grid point k_s + kk in the staged window (start lo, W
+// samples): u = k + off + q = j0 + f, taps j0-D+1 .. j0+D; monotonic T_k keeps
+// them inside the window, the clamp only guards memory.
+template <int D>
+__device__ __forceinline__ int tap_base(const PlanConst& P, int X, int64_t lo, int W,
+                                        int64_t k_s, int kk, double q, float& f) {
+  int64_t j0;
+  split_u(double(k_s + kk) + P.det[X].off + q, j0, f);
+  const int base = int(j0 - lo) - (D - 1);
+  return base < 0 ? 0 : (base > W - 2 * D ? W - 2 * D : base);
+}
+// Whether any tap from base on falls on a live sample (block flags blk).
+template <int D>
+__device__ __forceinline__ bool taps_live(const int32_t* blk, int base) {
+  return (blk[base >> 5] | blk[(base + 2 * D - 1) >> 5]) != 0;
+}
+
+// Steps (v) and the weighting of (vi) at one grid point k_s + kk of detector
+// X, whose epoch is T_k = tau_k + q dt, from the staged window zs.  A point
+// whose taps all fall on zero samples adds nothing.
+template <int D>
+__device__ __forceinline__ void interp_point(const PlanConst& P, const TmplParams& tp, int X,
+                                             const float2* zs, const int32_t* blk, int64_t lo,
+                                             int W, int64_t k_s, int kk, double q, double tau_s,
+                                             float2& acc_a, float2& acc_b) {
+  float f;
+  const int base = tap_base<D>(P, X, lo, W, k_s, kk, q, f);
+  if (!taps_live<D>(blk, base)) return;
+  weight_add(P, tp, X, tau_s + P.dt * double(kk), q, sinc_interp<D>(f, zs + base), acc_a, acc_b);
 }
 
 // q = (T_k - tau_k)/dt at grid offset k within its knot interval from the
