@@ -155,6 +155,10 @@ FftVariant rows_variant(bool half) {
     if constexpr (kR0<LOGL, MLR> <= 16 && kRowsMax<LOGL> >= 4) {
       if (!half) return rows_split_variant<LOGL, MLR, kRowCand>();
     }
+    // rows of 2^12: the half-LDS pass with the candidate epilogue
+    if constexpr (LOGL >= 12) {
+      if (!half) return rows_variant_n<LOGL, kRowCand, MLR, kRowsMax<LOGL>, 512>();
+    }
     return rows_variant<LOGL, kRow2FExt, MLR>(half);
   } else if constexpr (MODE != kRow2F && kR0<LOGL, MLR> == 32) {
     return rows_variant_n<LOGL, MODE, MLR, kRowsMax<LOGL> / 2, 256>();

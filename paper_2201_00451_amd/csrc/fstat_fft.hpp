@@ -694,6 +694,7 @@ __device__ __forceinline__ void rows_finish(const PlanConst& P, void* ws, const 
   using Lay = LdsLayout<L, R0, RQ>;
   fft_middle<LOGL, NL, NT, 1, MLR, Lay>(lds, twl, tid);
   unsigned long long bkey = 0ull;
+  float pa[MODE == kRowCand ? PER : 1][MODE == kRowCand ? RL : 1];
   // plain 2F: band offsets o = ((nat + N/2) mod N) - bin_lo in 32 bits; the
   // descriptor spans this template's n_bins floats, so the store of a bin
   // outside the band (o >= n_bins, also when the subtraction wraps) is dropped
@@ -723,6 +724,12 @@ __device__ __forceinline__ void rows_finish(const PlanConst& P, void* ws, const 
         }
         continue;
       }
+      if (MODE == kRowCand) {
+        // 2F now (the plain pass's bits), candidates after the transforms
+#pragma unroll
+        for (int m = 0; m < RL; ++m) pa[s][m] = two_f(va[m], vb[m]);
+        continue;
+      }
 #pragma unroll
       for (int m = 0; m < RL; ++m) {
         const int64_t nat = it.q0 + ql + Rr * (int64_t(QS) * (i + m * PL) + h);
@@ -735,7 +742,26 @@ __device__ __forceinline__ void rows_finish(const PlanConst& P, void* ws, const 
       }
     }
   }
-  if (MODE == kRow2FExt && out.best) best_to_global(out, it.tmpl, bkey);
+  if constexpr (MODE == kRowCand) {
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int b = tid + s * NT;
+      if (NBL % NT == 0 || b < NBL) {
+        const int ql = b % RQ, i = b / RQ;
+        const uint32_t o0 = uint32_t(it.q0 + ql + Rr * (QS * i + h)) + uint32_t(P.n_fft / 2);
+#pragma unroll
+        for (int m = 0; m < RL; ++m) {
+          const uint32_t o = ((o0 + uint32_t(m) * ostep) & nmask) - lo;
+          if (o < uint32_t(P.n_bins)) {
+            keep_candidate(out, it.tmpl, o, pa[s][m]);
+            const unsigned long long key = best_key(pa[s][m], o);
+            bkey = key > bkey ? key : bkey;
+          }
+        }
+      }
+    }
+  }
+  if ((MODE == kRow2FExt || MODE == kRowCand) && out.best) best_to_global(out, it.tmpl, bkey);
 }
 
 template <int LOGL, int RQ, int NT, int MODE, int MLR>
@@ -773,9 +799,11 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
 // (-1)^h x[c + L/2]) W_L^{c h}; entries 2k + h of the row transform are the
 // (L/2)-point transform of y_h), y_1 waiting in registers while y_0 goes
 // through LDS and the epilogue, so two workgroups share a compute unit
-// (plain 2F; the other epilogues need more registers and run one).
+// (plain 2F and candidates; the other epilogues need more registers and run
+// one).
 template <int LOGL, int RQ, int NT, int MODE, int MLR>
-__global__ __launch_bounds__(NT, MODE == kRow2F ? NT / 128 : NT / 256) void k_fft_rows_half(
+__global__ __launch_bounds__(NT, MODE == kRow2F || MODE == kRowCand ? NT / 128 : NT / 256) void
+k_fft_rows_half(
     PlanConst P, void* ws, ChunkMap map, int slots, int log_rr, RowOutput out) {
   extern __shared__ float2 lds[];
   constexpr int LH = LOGL - 1;
