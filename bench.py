@@ -40,10 +40,10 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # header and build flags with this digest; for any other version the
 # roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "308645821e5edcba951e4e70f00f707096af101ed130fdd55249b4b4b9d77828",
+    "sources_sha256": "61679f00df06cedcf246358b3589ccef16bf12407665fded8c62e22e8b5240cb",
     "bytes_per_template": {
-        "binary": {"resample": 182439560, "fft_columns": 231440820, "fft_rows_2f": 182990053},
-        "sky_spindown": {"resample": 3073919, "fft_columns": 48075845, "fft_rows_2f": 41979985},
+        "binary": {"resample": 182439479, "fft_columns": 260426214, "fft_rows_2f": 231269904},
+        "sky_spindown": {"resample": 3073913, "fft_columns": 48081548, "fft_rows_2f": 41979777},
     },
 }
 
