@@ -313,6 +313,46 @@ def test_full_size_bench_workload_sampled(torch_dev):
     assert ref[1].max() > 30.0
 
 
+def test_max_fft_length_2e24(torch_dev):
+    """n_fft = 2^24, the largest the plan accepts (columns and rows of 2^12,
+    both FFT passes in their half-LDS form), where the oracle's full-grid
+    timing takes minutes: checked by a property that holds at any size.  The
+    same data zero-padded to 2^24 has the 2^23 spectrum at its even bins
+    (bin 2m lies at the frequency of 2^23 bin m); the 2^23 path meets the bar
+    against the oracle at full size.  Also: the grouped search equals the
+    per-template path bit for bit, and candidate retention equals the
+    thresholded band."""
+    import torch
+    from paper_2201_00451_amd import binding
+    kw = dict(seed=41, n=20000, ndet=2, binary=True, gaps=True, ntmpl=2, rho=20.0)
+    ds24 = synth.small_case(n_fft=1 << 24, **kw)
+    ds23 = synth.small_case(n_fft=1 << 23, **kw)
+    dd24 = binding.DeviceData(ds24, batch=2)
+    tf24 = binding.compute_2f(dd24, ds24.templates)
+    sr = binding.Search(dd24, ds24.templates, slots=2)
+    full = sr.run()
+    binding.sync_check()
+    assert torch.equal(full, tf24)
+    thr = float(np.float32(0.5 * float(full.max())))
+    res = sr.run_candidates(thr, capacity=1 << 16)
+    binding.sync_check()
+    want = torch.nonzero(full > thr)
+    assert res["count"] == want.shape[0] > 0
+    got = set(zip(res["tmpl"].cpu().numpy().tolist(), res["bin"].cpu().numpy().tolist()))
+    assert got == set(map(tuple, want.cpu().numpy().tolist()))
+    assert torch.equal(res["best_twoF"], torch.max(full, dim=1)[0])
+    even = tf24[:, 0::2].cpu().numpy()
+    del dd24, sr, full, tf24, res
+    torch.cuda.empty_cache()
+    dd23 = binding.DeviceData(ds23, batch=2)
+    tf23 = binding.compute_2f(dd23, ds23.templates).cpu().numpy()
+    binding.sync_check()
+    for t in range(2):
+        say(f"  2^24 template {t}: peak 2F {even[t].max():.2f}")
+        assert_2f_parity(even[t], tf23[t].astype(np.float64), f"2^24 even bins, template {t}")
+    assert tf23.max() > 30.0
+
+
 def test_full_size_binary_workload_sampled(torch_dev):
     """The binary workload at full size (2 detectors x 5 184 000 samples at 70%
     duty, n_fft 2^23, full band): 32 lattice templates around the injection in
