@@ -273,15 +273,22 @@ int tmpl_stride(const fstat_plan* p) {
                                              : FSTAT_TEMPLATE_STRIDE;
 }
 
-// Knot area of the search and plain forward paths (per detector: grid knots,
-// then sample knots, at the capacities of the smallest knot spacing that is
-// solved ahead of the resampling).
+// Knot area of the search and plain forward paths (per detector: grid
+// intervals, their integer parts, sample knots and tile records, at the
+// capacities of the smallest knot spacing that is solved ahead of the
+// resampling).
 int64_t knot_gcap(const fstat_plan* p) { return knot_grid_cap(p->k_pad); }
-int64_t knot_stride(const fstat_plan* p) {
+int64_t knot_ioff(const fstat_plan* p) { return knot_gcap(p); }
+int64_t knot_soff(const fstat_plan* p) { return knot_ioff(p) + (knot_gcap(p) + 3) / 4; }
+int64_t knot_scap(const fstat_plan* p) {
   int64_t scap = 0;
   for (int X = 0; X < p->desc.ndet; ++X)
     scap = std::max<int64_t>(scap, knot_samp_cap(p->desc.det[X].n));
-  return knot_gcap(p) + scap;
+  return scap;
+}
+int64_t knot_toff(const fstat_plan* p) { return knot_soff(p) + knot_scap(p); }
+int64_t knot_stride(const fstat_plan* p) {
+  return knot_toff(p) + (p->k_pad >> kResTileLog) * kTileRecUnits;
 }
 size_t knot_area_bytes(const fstat_plan* p) {
   return (size_t(p->desc.ndet) * size_t(knot_stride(p)) * sizeof(double2) + 255) / 256 * 256;
@@ -314,7 +321,12 @@ PlanConst make_const(const fstat_plan* p, const fstat_inputs* in) {
   P.k_pad = p->k_pad;
   P.knot_stride = knot_stride(p);
   P.knot_gcap = knot_gcap(p);
+  P.knot_ioff = knot_ioff(p);
+  P.knot_soff = knot_soff(p);
+  P.knot_toff = knot_toff(p);
   P.knot_bytes = int64_t(knot_area_bytes(p));
+  P.res_taylor = std::fabs(2.0 * M_PI * P.sid_rate_cyc * d.dt) * double(kResTile / 2 + 1) <=
+                 kTaylorMaxAngle;
   // the plain forward path's slot layout; the search and the adjoint paths
   // set their own
   P.slot_stride = int64_t(plain_slot_bytes(p));
@@ -436,9 +448,9 @@ KnotFn knot_kernel(const fstat_plan* p, bool grouped) {
 void launch_knots(const fstat_plan* p, const PlanConst& P, const ChunkMap& map, int slots,
                   bool grouped, int n_res, void* ws, hipStream_t st) {
   if (n_res < 1 || (!grouped && P.knot_offset == 0)) return;
-  hipLaunchKernelGGL(knot_kernel(p, grouped),
-                     dim3(unsigned((P.knot_stride + 255) / 256), n_res, p->desc.ndet), dim3(256),
-                     0, st, P, ws, map, slots);
+  const int64_t blocks = knot_grid_blocks(P.knot_gcap) + (P.knot_toff - P.knot_soff + 255) / 256;
+  hipLaunchKernelGGL(knot_kernel(p, grouped), dim3(unsigned(blocks), n_res, p->desc.ndet),
+                     dim3(kKnotThreads), 0, st, P, ws, map, slots);
 }
 
 ResFn resample_kernel(const fstat_plan* p, bool grouped) {

@@ -22,6 +22,8 @@ constexpr double kPi = 3.14159265358979323846;
 // second, resampling 4 % faster on sky positions, 1 % slower on binary
 // orbits).
 constexpr int kResTile = 512;
+constexpr int kResTileLog = 9;
+static_assert(kResTile == 1 << kResTileLog, "tile size is 2^kResTileLog");
 constexpr int kResThreads = 256;
 constexpr int kResPerThread = kResTile / kResThreads;
 // Waves per SIMD of the resampling kernel whose timing knots were solved
@@ -53,11 +55,33 @@ constexpr int kSampKnots = (kResWcap - 1) / (1 << kKnotLogMin) + 2;
 
 // On the search and plain forward paths the knots of templates with
 // G >= 2^kKnotLogGlobal are solved ahead of the resampling, all in parallel,
-// into a knot area of the series' buffer; per detector: grid knots
-// (q, dq/dk) at k = m G, m = 0 .. k_pad / G, then sample knots (heterodyne
-// phase in cycles, its change per sample) at j = m G, m = 0 .. (n_X - 1) / G
-// + 1.  Capacities at the smallest such G.
+// into a knot area of the series' buffer.  Per detector, in 16-byte units:
+//   [0, knot_gcap)   the grid intervals m = 0 .. k_pad / G (from k = m G):
+//                    the source position u = k + off + q of the interval's
+//                    points as I_m + theta(v), v = (k - m G) / G, with the
+//                    cubic theta in FP32 (float4: theta(0), then the
+//                    coefficients of v, v^2, v^3; the last interval holds
+//                    theta(0) only)
+//   [knot_ioff, ..)  the integers I_m (int32)
+//   [knot_soff, ..)  sample knots (heterodyne phase in cycles, its change per
+//                    sample) at j = m G, m = 0 .. (n_X - 1) / G + 1
+//   [knot_toff, ..)  per resampling tile, kTileRecUnits: the antenna Taylor
+//                    coefficients about the tile's middle point and that
+//                    point's theta(0) and I (plans whose tiles take the Taylor
+//                    form only)
+// Capacities at the smallest such G.
 constexpr int kKnotLogGlobal = 4;
+constexpr int kTileRecUnits = 4;
+// k_knots: blocks of kKnotThreads knots, each block's last knot the next
+// block's first, so that every grid interval finds both its ends in one block.
+constexpr int kKnotThreads = 256;
+__host__ __device__ inline int64_t knot_grid_blocks(int64_t gcap) {
+  return (gcap + kKnotThreads - 2) / (kKnotThreads - 1);
+}
+// The whitened antenna patterns over a tile are taken as quintic polynomials
+// in the sidereal angle's offset from the tile's middle point while the tile
+// spans at most this angle on either side (radians).
+constexpr double kTaylorMaxAngle = 0.1;
 __host__ __device__ inline int64_t knot_grid_cap(int64_t k_pad) {
   return (k_pad >> kKnotLogGlobal) + 1;
 }
@@ -94,8 +118,10 @@ struct PlanConst {
   int64_t k_pad;        // grid points computed by the resampler (multiple of tile and row)
   int64_t slot_stride;  // bytes per template slot of the workspace (path dependent)
   int64_t part_offset;  // adjoint paths: bytes from a slot's start to its tile partials
-  int64_t knot_stride;  // double2 per detector of a knot area
-  int64_t knot_gcap;    // grid knots of a detector's area (its sample knots follow)
+  int64_t knot_stride;  // 16-byte units per detector of a knot area
+  int64_t knot_gcap;    // grid intervals of a detector's area
+  int64_t knot_ioff, knot_soff, knot_toff;  // units to the integers, sample knots, tiles
+  int32_t res_taylor;   // the tiles take the antenna patterns' Taylor form
   int64_t knot_bytes;   // bytes of a knot area (each group buffer holds one)
   int64_t knot_offset;  // plain path: bytes from a slot's start to its knot area;
                         // 0: the slots have none (the tiles solve their knots)

@@ -133,16 +133,44 @@ __device__ __forceinline__ void interp_taps(std::integer_sequence<int, T...>, fl
   (interp_tap<D, T>(f, wc, ws, zp, sx, sy), ...);
 }
 
+// sin(pi f) / (2 pi) for 0 <= f < 1 from h = min(f, 1 - f) (exact for f >=
+// 1/2): the odd Taylor series of sin(pi h) / (2 pi) through h^13, whose first
+// omitted term is below 7e-10 of the value at h = 1/2, so the result keeps
+// its relative precision at both ends of the interval, where the sinc's
+// numerator meets the vanishing denominator of the nearest tap.
+struct SinPiCoef {
+  float c[7];
+};
+__host__ __device__ constexpr SinPiCoef make_sinpi_coef() {
+  SinPiCoef k{};
+  double t = 0.5;  // pi / (2 pi)
+  for (int n = 0; n < 7; ++n) {
+    k.c[n] = float(t);
+    t *= -(kPi * kPi) / double((2 * n + 2) * (2 * n + 3));
+  }
+  return k;
+}
+__device__ __forceinline__ float sinpi_over_2pi(float f) {
+  constexpr SinPiCoef k = make_sinpi_coef();
+  const float h = fminf(f, 1.0f - f);
+  const float u = h * h;
+  float p = k.c[6];
+#pragma unroll
+  for (int n = 5; n >= 0; --n) p = fmaf(p, u, k.c[n]);
+  return h * p;
+}
+
 // Step (v): the 2D-tap interpolation of the samples zp[0 .. 2D) at the
 // fraction f of the point between zp[D - 1] and zp[D].
 template <int D>
 __device__ __forceinline__ float2 sinc_interp(float f, const float2* zp) {
+  static_assert(D >= 4, "the window phase stays within one eighth turn");
   if (f == 0.0f) return zp[D - 1];
-  // window phase pi f / D and sinc numerator sin(pi f), in cycles
-  const float2 wcs = cis_cycles_f32(f * (0.5f / float(D)));
+  // window phase pi f / D: 2 f / D <= 1/2 quarter turns, no reduction
+  const float2 wcs = cis_quarter(0, 4.0f * (f * (0.5f / float(D))));
   float sx = 0.f, sy = 0.f;
   interp_taps<D>(std::make_integer_sequence<int, 2 * D>{}, f, wcs.x, wcs.y, zp, sx, sy);
-  const float sp = cis_cycles_f32(0.5f * f).y * float(0.5 / kPi);
+  const float sp = sinpi_over_2pi(f);
   return make_float2(sx * sp, sy * sp);
 }
 
@@ -194,6 +222,59 @@ __device__ __forceinline__ void interp_point(const PlanConst& P, const TmplParam
   const int base = tap_base<D>(P, X, lo, W, k_s, kk, q, f);
   if (!taps_live<D>(blk, base)) return;
   weight_add(P, tp, X, tau_s + P.dt * double(kk), q, sinc_interp<D>(f, zs + base), acc_a, acc_b);
+}
+
+// The whitened antenna patterns of detector X over one tile as quintic
+// polynomials in the sidereal angle's offset d from the tile's middle point:
+// with x = alpha - phi(T), a(x) = ca0 + ca1 cos x + ca2 sin x + ca3 cos 2x
+// + ca4 sin 2x has the Taylor coefficients a_n = a^(n)(x_r) / n! at x_r
+// (and b likewise).  The remainder is below (2|d|)^6 / 6! of the coefficients'
+// scale, 1e-7 at |d| = 0.1 rad, the bound kTaylorMaxAngle under which the
+// tile takes this form.  c[0..5]: a_0..a_5, c[6..11]: b_0..b_5.
+constexpr int kTaylorCoef = 12;
+static_assert(kTaylorCoef + 2 <= kTileRecUnits * 4, "a tile record holds the coefficients");
+__device__ inline void antenna_taylor(const TmplParams& tp, int X, double x_cyc,
+                                      float (&c)[kTaylorCoef]) {
+  const float2 e = cis_cycles(x_cyc);
+  const float c1 = e.x, s1 = e.y;
+  const float c2 = c1 * c1 - s1 * s1, s2 = 2.0f * s1 * c1;
+#pragma unroll
+  for (int ab = 0; ab < 2; ++ab) {
+    const float* k = ab ? tp.cb[X] : tp.ca[X];
+    // value p and derivative q of the first and second harmonic at x_r
+    const float p1 = k[1] * c1 + k[2] * s1, q1 = k[2] * c1 - k[1] * s1;
+    const float p2 = k[3] * c2 + k[4] * s2, q2 = k[4] * c2 - k[3] * s2;
+    float* o = c + 6 * ab;
+    o[0] = k[0] + p1 + p2;
+    o[1] = q1 + 2.0f * q2;
+    o[2] = -(p1 + 4.0f * p2) * (1.0f / 2.0f);
+    o[3] = -(q1 + 8.0f * q2) * (1.0f / 6.0f);
+    o[4] = (p1 + 16.0f * p2) * (1.0f / 24.0f);
+    o[5] = (q1 + 32.0f * q2) * (1.0f / 120.0f);
+  }
+}
+
+// Steps (v) and (vi) at one grid point whose taps start at base in the staged
+// window zs (fraction f), with the antenna patterns from the tile's Taylor
+// coefficients c (uniform across the tile) at the angle offset d (radians).
+template <int D>
+__device__ __forceinline__ void interp_point_taylor(const float2* zs, const int32_t* blk, int W,
+                                                    int base, float f, float d,
+                                                    const float (&c)[kTaylorCoef], float2& acc_a,
+                                                    float2& acc_b) {
+  base = base < 0 ? 0 : (base > W - 2 * D ? W - 2 * D : base);
+  if (!taps_live<D>(blk, base)) return;
+  const float2 zh = sinc_interp<D>(f, zs + base);
+  float a = c[5], b = c[11];
+#pragma unroll
+  for (int n = 4; n >= 0; --n) {
+    a = fmaf(a, d, c[n]);
+    b = fmaf(b, d, c[6 + n]);
+  }
+  acc_a.x = fmaf(a, zh.x, acc_a.x);
+  acc_a.y = fmaf(a, zh.y, acc_a.y);
+  acc_b.x = fmaf(b, zh.x, acc_b.x);
+  acc_b.y = fmaf(b, zh.y, acc_b.y);
 }
 
 // q = (T_k - tau_k)/dt at grid offset k within its knot interval from the
@@ -476,11 +557,15 @@ __device__ inline bool resample_tile(const PlanConst& P, const TmplParams& tp,
 }
 
 // The tile for a template whose timing knots k_knots solved ahead (knot
-// area kn): each thread reads the knots of its own samples and grid points,
-// so a pass of kDetPass detectors has two phases, the corrected samples into
-// LDS and then interpolation and weighting, with one barrier between them.
-// The window of a detector runs from the tile's first epoch to the one of
-// the knot just past the tile (T_k is monotonic in k).
+// area kn): each thread reads the knot records of its own samples and grid
+// points, so a pass of kDetPass detectors has two phases, the corrected
+// samples into LDS and then interpolation and weighting, with one barrier
+// between them.  The window of a detector runs from the tile's first source
+// position to the one of the interval just past the tile (T_k is monotonic in
+// k).  The grid points take their source positions from the FP32 interval
+// cubics relative to the intervals' integers, and (plans with res_taylor) the
+// antenna patterns from the tile's Taylor record, so the interpolation phase
+// runs without FP64 arithmetic.
 template <int D>
 __device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp,
                                         const double2* __restrict__ kn, int32_t* status_word,
@@ -497,7 +582,11 @@ __device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp
   const int kl = tp.knot_log2;
   const int G = 1 << kl;
   const double inv_g = 1.0 / double(G);
+  const float inv_gf = 1.0f / float(G);
   const double tau_s = P.tau0 + P.dt * double(k_s);
+  const int64_t e_s = k_s >> kl;  // the tile's first interval
+  // d(angle)/d(grid step) of the sidereal angle x, radians
+  const float dstep = float(-2.0 * kPi * P.sid_rate_cyc * P.dt);
   for (int X0 = 0; X0 < P.ndet; X0 += kDetPass) {
     const int np = P.ndet - X0 < kDetPass ? P.ndet - X0 : kDetPass;
     int64_t lo[kDetPass];
@@ -508,12 +597,14 @@ __device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp
       lo[xp] = 0;
       W[xp] = 0;
       if (xp >= np) continue;
-      const double2* gk = kn + (X0 + xp) * P.knot_stride;
-      const double q0 = gk[k_s >> kl].x, q1 = gk[(k_s + kResTile) >> kl].x;
-      int64_t j_first, j_last;
-      float f;
-      split_u(double(k_s) + P.det[X0 + xp].off + q0, j_first, f);
-      split_u(double(k_s + kResTile) + P.det[X0 + xp].off + q1, j_last, f);
+      const double2* ka = kn + (X0 + xp) * P.knot_stride;
+      const float4* gr = reinterpret_cast<const float4*>(ka);
+      const int32_t* gi = reinterpret_cast<const int32_t*>(ka + P.knot_ioff);
+      const int64_t e_e = (k_s + kResTile) >> kl;
+      // floor of the source position at the tile's first point and at the
+      // point just past it (theta(0) in [0, 1], 1 after rounding)
+      const int64_t j_first = k_s + gi[e_s] + (gr[e_s].x >= 1.0f ? 1 : 0);
+      const int64_t j_last = k_s + kResTile + gi[e_e] + (gr[e_e].x >= 1.0f ? 1 : 0);
       lo[xp] = uniform_i64(j_first - D + 1);
       const int64_t nwin = j_last + D - lo[xp] + 1;
       // delay drift beyond 1/16 per tile: flag the template (NaN output)
@@ -530,7 +621,7 @@ __device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp
 #pragma unroll 1
     for (int xp = 0; xp < np; ++xp) {
       const DetConst& d = P.det[X0 + xp];
-      const double2* sk = kn + (X0 + xp) * P.knot_stride + P.knot_gcap;
+      const double2* sk = kn + (X0 + xp) * P.knot_stride + P.knot_soff;
       const int64_t lox = xp ? lo[1] : lo[0];
       const int Wx = xp ? W[1] : W[0];
       float2 xv[kRounds];
@@ -576,16 +667,62 @@ __device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp
 #pragma unroll 1
     for (int xp = 0; xp < np; ++xp) {
       const int X = X0 + xp;
-      const double2* gk = kn + X * P.knot_stride;
+      const double2* ka = kn + X * P.knot_stride;
+      const float4* gr = reinterpret_cast<const float4*>(ka) + e_s;
+      const int32_t* gi = reinterpret_cast<const int32_t*>(ka + P.knot_ioff) + e_s;
       const int64_t lox = xp ? lo[1] : lo[0];
       const int Wx = xp ? W[1] : W[0];
+      const int32_t sb = int32_t(k_s - lox) - (D - 1);
+      if (P.res_taylor) {
+        // the tile's record: uniform, scalar registers
+        const float* tr = reinterpret_cast<const float*>(ka + P.knot_toff +
+                                                         (k_s >> kResTileLog) * kTileRecUnits);
+        float c[kTaylorCoef];
 #pragma unroll
-      for (int i = 0; i < kResPerThread; ++i) {
-        const int kk = tid + i * kResThreads;
-        const int64_t k = k_s + kk;
-        const double q = knot_hermite(gk + (k >> kl), G, double(k & (G - 1)) * inv_g);
-        interp_point<D>(P, tp, X, zsa + xp * kResWcap, blka + xp * kResBlk, lox, Wx, k_s, kk, q,
-                        tau_s, acc_a[i], acc_b[i]);
+        for (int n = 0; n < kTaylorCoef; ++n) c[n] = tr[n];
+        const float th_r = tr[kTaylorCoef];
+        const int32_t i_r = __float_as_int(tr[kTaylorCoef + 1]);
+#pragma unroll
+        for (int i = 0; i < kResPerThread; ++i) {
+          const int kk = tid + i * kResThreads;
+          const float4 cq = gr[kk >> kl];
+          const int32_t im = gi[kk >> kl];
+          const float v = float(kk & (G - 1)) * inv_gf;
+          const float th = fmaf(fmaf(fmaf(cq.w, v, cq.z), v, cq.y), v, cq.x);
+          const float fl = floorf(th);
+          float f = th - fl;
+          int base = sb + im + kk + int(fl);
+          if (f >= 1.0f) {
+            f = 0.0f;
+            base += 1;
+          }
+          // sidereal angle offset from the tile's middle point
+          const float d = (float(kk - kResTile / 2 + (im - i_r)) + (th - th_r)) * dstep;
+          interp_point_taylor<D>(zsa + xp * kResWcap, blka + xp * kResBlk, Wx, base, f, d, c,
+                                 acc_a[i], acc_b[i]);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < kResPerThread; ++i) {
+          const int kk = tid + i * kResThreads;
+          const float4 cq = gr[kk >> kl];
+          const int32_t im = gi[kk >> kl];
+          const float v = float(kk & (G - 1)) * inv_gf;
+          const float th = fmaf(fmaf(fmaf(cq.w, v, cq.z), v, cq.y), v, cq.x);
+          const float fl = floorf(th);
+          float f = th - fl;
+          int base = sb + im + kk + int(fl);
+          if (f >= 1.0f) {
+            f = 0.0f;
+            base += 1;
+          }
+          base = base < 0 ? 0 : (base > Wx - 2 * D ? Wx - 2 * D : base);
+          if (!taps_live<D>(blka + xp * kResBlk, base)) continue;
+          const float2 zh = sinc_interp<D>(f, zsa + xp * kResWcap + base);
+          // q = u - k - off
+          const double q = (double(im) - P.det[X].off) + double(th);
+          weight_add(P, tp, X, tau_s + P.dt * double(kk), q, zh, acc_a[i], acc_b[i]);
+        }
       }
     }
     if (X0 + kDetPass < P.ndet) __syncthreads();
@@ -598,10 +735,16 @@ __device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp
 // blockIdx.z: the same FP64 solves as the tiles' own knots (steps (iv) and
 // (iii) of Sec. 3), one knot per thread, with the Roemer delay from the
 // detector's tabulated trajectory (the interval read last kept in
-// registers).  A delay beyond the plan's max_delay flags the template (as a
-// tile whose delay leaves its staged nodes does).
+// registers).  The first knot_grid_blocks blocks solve grid knots and turn
+// each interval's two end knots into its record (the cubic Hermite form of q
+// between them, relative to the integer part of the interval's first source
+// position); the knot at a tile's middle point also writes the tile's
+// antenna Taylor record.  The other blocks solve the sample knots.  A delay
+// beyond the plan's max_delay flags the template (as a tile whose delay
+// leaves its staged nodes does).
 template <bool GROUPED, bool KEP>
-__global__ __launch_bounds__(256) void k_knots(PlanConst P, void* ws, ChunkMap map, int slots) {
+__global__ __launch_bounds__(kKnotThreads) void k_knots(PlanConst P, void* ws, ChunkMap map,
+                                                        int slots) {
   const int gi = blockIdx.y;
   const int slot = GROUPED ? map.grp_slot[gi] : gi;
   const TmplParams& tp = *tmpl_params(ws, P, map, slot);
@@ -614,28 +757,63 @@ __global__ __launch_bounds__(256) void k_knots(PlanConst P, void* ws, ChunkMap m
   const DetConst& d = P.det[X];
   double2* kn = (GROUPED ? group_knots(ws, P, slots, map.grp_buf[gi]) : slot_knots(ws, P, slot)) +
                 X * P.knot_stride;
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int G = 1 << kl;
   const CachedRoemer re{d.ephem, tp.nhat, P.n_eph, P.eph_t0, P.eph_dt, P.inv_eph_dt};
+  const int64_t gblocks = knot_grid_blocks(P.knot_gcap);
   bool far = false;
-  if (e <= (P.k_pad >> kl)) {
-    // grid knot e: detector epoch of tau = tau0 + e G dt (fixed point and
-    // two Newton steps) and dq/dk = (R'(tau) - roemer'(T)) / (1 + roemer'(T))
-    const double tau = P.tau0 + P.dt * double(e * G);
-    double rb, rbd, x;
-    orbit_delay<KEP>(tp, tau, rb, rbd);
-    double dl = grid_delay_rb(re, rb, tau);
-    dl = grid_delay_newton(re, tau, rb, dl, x);
-    dl = grid_delay_newton(re, tau, rb, dl, x);
-    kn[e] = make_double2(dl * P.inv_dt, (rbd - x) / (1.0 + x));
-    far = !(fabs(dl) <= P.max_delay);
-  } else if (e >= P.knot_gcap && e - P.knot_gcap <= ((d.n - 1) >> kl) + 1) {
+  if (int64_t(blockIdx.x) < gblocks) {
+    const int64_t last = P.k_pad >> kl;
+    const int64_t e = int64_t(blockIdx.x) * (kKnotThreads - 1) + threadIdx.x;
+    double2 kv = make_double2(0.0, 0.0);
+    if (e <= last) {
+      // grid knot e: detector epoch of tau = tau0 + e G dt (fixed point and
+      // two Newton steps) and dq/dk = (R'(tau) - roemer'(T)) / (1 + roemer'(T))
+      const double tau = P.tau0 + P.dt * double(e * G);
+      double rb, rbd, x;
+      orbit_delay<KEP>(tp, tau, rb, rbd);
+      double dl = grid_delay_rb(re, rb, tau);
+      dl = grid_delay_newton(re, tau, rb, dl, x);
+      dl = grid_delay_newton(re, tau, rb, dl, x);
+      kv = make_double2(dl * P.inv_dt, (rbd - x) / (1.0 + x));
+      far = !(fabs(dl) <= P.max_delay);
+    }
+    __shared__ double2 nb[kKnotThreads];
+    nb[threadIdx.x] = kv;
+    __syncthreads();
+    if (threadIdx.x < kKnotThreads - 1 && e <= last) {
+      double2 c0, c1;
+      if (e < last) {
+        hermite_interval(kv, nb[threadIdx.x + 1], double(G), c0, c1);
+      } else {
+        c0 = make_double2(kv.x, 0.0);
+        c1 = make_double2(0.0, 0.0);
+      }
+      const double a = d.off + c0.x;
+      const double fa = floor(a);
+      const float th = float(a - fa);
+      reinterpret_cast<float4*>(kn)[e] = make_float4(th, float(c0.y), float(c1.x), float(c1.y));
+      reinterpret_cast<int32_t*>(kn + P.knot_ioff)[e] = int32_t(fa);
+      const int64_t k = e << kl;
+      if (P.res_taylor && (k & (kResTile - 1)) == kResTile / 2) {
+        float c[kTaylorCoef];
+        antenna_taylor(tp, X, tp.alpha_cyc[X] - P.sid_rate_cyc * (P.tau0 + P.dt * double(k) +
+                                                                  kv.x * P.dt), c);
+        float* tr = reinterpret_cast<float*>(kn + P.knot_toff + (k >> kResTileLog) * kTileRecUnits);
+#pragma unroll
+        for (int n = 0; n < kTaylorCoef; ++n) tr[n] = c[n];
+        tr[kTaylorCoef] = th;
+        tr[kTaylorCoef + 1] = __int_as_float(int32_t(fa));
+      }
+    }
+  } else {
     // sample knot m: heterodyne phase at t = t0 + m G dt and its change per sample
-    const int64_t m = e - P.knot_gcap;
-    double ph, dph, delay;
-    sample_phase_d<KEP>(re, tp, d.t0 + P.dt * double(m * G), P.f_het, ph, dph, delay);
-    kn[e] = make_double2(ph, dph * P.dt);
-    far = !(fabs(delay) <= P.max_delay);
+    const int64_t m = (int64_t(blockIdx.x) - gblocks) * kKnotThreads + threadIdx.x;
+    if (m <= ((d.n - 1) >> kl) + 1) {
+      double ph, dph, delay;
+      sample_phase_d<KEP>(re, tp, d.t0 + P.dt * double(m * G), P.f_het, ph, dph, delay);
+      kn[P.knot_soff + m] = make_double2(ph, dph * P.dt);
+      far = !(fabs(delay) <= P.max_delay);
+    }
   }
   if (far) atomicOr(status_word, kStatusNodes);
 }
