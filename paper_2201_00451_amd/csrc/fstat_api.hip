@@ -286,7 +286,7 @@ int64_t knot_scap(const fstat_plan* p) {
     scap = std::max<int64_t>(scap, knot_samp_cap(p->desc.det[X].n));
   return scap;
 }
-int64_t knot_toff(const fstat_plan* p) { return knot_soff(p) + knot_scap(p); }
+int64_t knot_toff(const fstat_plan* p) { return knot_soff(p) + 2 * knot_scap(p); }
 int64_t knot_stride(const fstat_plan* p) {
   return knot_toff(p) + (p->k_pad >> kResTileLog) * kTileRecUnits;
 }
@@ -324,6 +324,7 @@ PlanConst make_const(const fstat_plan* p, const fstat_inputs* in) {
   P.knot_ioff = knot_ioff(p);
   P.knot_soff = knot_soff(p);
   P.knot_toff = knot_toff(p);
+  P.knot_scap = knot_scap(p);
   P.knot_bytes = int64_t(knot_area_bytes(p));
   P.res_taylor = std::fabs(2.0 * M_PI * P.sid_rate_cyc * d.dt) * double(kResTile / 2 + 1) <=
                  kTaylorMaxAngle;
@@ -448,7 +449,8 @@ KnotFn knot_kernel(const fstat_plan* p, bool grouped) {
 void launch_knots(const fstat_plan* p, const PlanConst& P, const ChunkMap& map, int slots,
                   bool grouped, int n_res, void* ws, hipStream_t st) {
   if (n_res < 1 || (!grouped && P.knot_offset == 0)) return;
-  const int64_t blocks = knot_grid_blocks(P.knot_gcap) + (P.knot_toff - P.knot_soff + 255) / 256;
+  const int64_t blocks =
+      knot_grid_blocks(P.knot_gcap) + knot_tile_blocks(P.k_pad) + knot_samp_blocks(P.knot_scap);
   hipLaunchKernelGGL(knot_kernel(p, grouped), dim3(unsigned(blocks), n_res, p->desc.ndet),
                      dim3(kKnotThreads), 0, st, P, ws, map, slots);
 }

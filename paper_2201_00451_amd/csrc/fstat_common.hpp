@@ -63,8 +63,11 @@ constexpr int kSampKnots = (kResWcap - 1) / (1 << kKnotLogMin) + 2;
 //                    coefficients of v, v^2, v^3; the last interval holds
 //                    theta(0) only)
 //   [knot_ioff, ..)  the integers I_m (int32)
-//   [knot_soff, ..)  sample knots (heterodyne phase in cycles, its change per
-//                    sample) at j = m G, m = 0 .. (n_X - 1) / G + 1
+//   [knot_soff, ..)  the sample intervals m = 0 .. (n_X - 1) / G (from
+//                    j = m G), two units each: the heterodyne phase of the
+//                    interval's samples in quarter turns as a cubic in
+//                    t = j - m G, in FP64 (constant term reduced modulo one
+//                    turn)
 //   [knot_toff, ..)  per resampling tile, kTileRecUnits: the antenna Taylor
 //                    coefficients about the tile's middle point and that
 //                    point's theta(0) and I (plans whose tiles take the Taylor
@@ -77,6 +80,12 @@ constexpr int kTileRecUnits = 4;
 constexpr int kKnotThreads = 256;
 __host__ __device__ inline int64_t knot_grid_blocks(int64_t gcap) {
   return (gcap + kKnotThreads - 2) / (kKnotThreads - 1);
+}
+__host__ __device__ inline int64_t knot_samp_blocks(int64_t scap) {
+  return (scap + kKnotThreads - 2) / (kKnotThreads - 1);
+}
+__host__ __device__ inline int64_t knot_tile_blocks(int64_t k_pad) {
+  return ((k_pad >> kResTileLog) + kKnotThreads - 1) / kKnotThreads;
 }
 // The whitened antenna patterns over a tile are taken as quintic polynomials
 // in the sidereal angle's offset from the tile's middle point while the tile
@@ -120,7 +129,8 @@ struct PlanConst {
   int64_t part_offset;  // adjoint paths: bytes from a slot's start to its tile partials
   int64_t knot_stride;  // 16-byte units per detector of a knot area
   int64_t knot_gcap;    // grid intervals of a detector's area
-  int64_t knot_ioff, knot_soff, knot_toff;  // units to the integers, sample knots, tiles
+  int64_t knot_ioff, knot_soff, knot_toff;  // units to the integers, sample intervals, tiles
+  int64_t knot_scap;    // sample intervals of a detector's area
   int32_t res_taylor;   // the tiles take the antenna patterns' Taylor form
   int64_t knot_bytes;   // bytes of a knot area (each group buffer holds one)
   int64_t knot_offset;  // plain path: bytes from a slot's start to its knot area;

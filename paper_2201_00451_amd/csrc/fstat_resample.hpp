@@ -621,33 +621,45 @@ __device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp
 #pragma unroll 1
     for (int xp = 0; xp < np; ++xp) {
       const DetConst& d = P.det[X0 + xp];
-      const double2* sk = kn + (X0 + xp) * P.knot_stride + P.knot_soff;
       const int64_t lox = xp ? lo[1] : lo[0];
       const int Wx = xp ? W[1] : W[0];
+      // window offsets w in [wlo, whi) hold data samples j = lox + w; the
+      // interval records from the one of sample lox on (floor division)
+      const int32_t wlo = lox < 0 ? int32_t(-lox) : 0;
+      const int32_t whi = d.n - lox < int64_t(Wx) ? int32_t(d.n - lox) : Wx;
+      const int32_t jph = int32_t(lox & (G - 1));
+      const double2* sr = kn + (X0 + xp) * P.knot_stride + P.knot_soff + 2 * (lox >> kl);
+      const float2* xs = d.x + lox;
       float2 xv[kRounds];
       double2 k0[kRounds], k1[kRounds];
+      // a wave whose lanes all lie past the window skips the round (its
+      // 32-sample blocks lie past the last one a tap reads)
+      const int w0 = __builtin_amdgcn_readfirstlane(tid) & ~63;
+      const bool any = wlo < whi;
 #pragma unroll
       for (int r = 0; r < kRounds; ++r) {
         const int w = r * kResThreads + tid;
-        const int64_t j = lox + w;
-        const bool in = w < Wx && j >= 0 && j < d.n;
-        xv[r] = in ? d.x[j] : make_float2(0.f, 0.f);
-        // knots of the sample's interval (of the last sample outside the data)
-        const int64_t m = (j < 0 ? 0 : (j >= d.n ? d.n - 1 : j)) >> kl;
-        k0[r] = sk[m];
-        k1[r] = sk[m + 1];
+        const bool in = w >= wlo && w < whi;
+        xv[r] = in ? xs[w] : make_float2(0.f, 0.f);
+        // record of the sample's interval (of the nearest data sample)
+        const int32_t wc = any ? (w < wlo ? wlo : (w >= whi ? whi - 1 : w)) : wlo;
+        const double2* rc = sr + 2 * ((jph + wc) >> kl);
+        k0[r] = any ? rc[0] : make_double2(0.0, 0.0);
+        k1[r] = any ? rc[1] : make_double2(0.0, 0.0);
       }
 #pragma unroll
       for (int r = 0; r < kRounds; ++r) {
-        if (r * kResThreads >= Wx) break;
+        if (r * kResThreads + w0 >= Wx) break;
         const int w = r * kResThreads + tid;
         const float2 x = xv[r];
         const bool live = x.x != 0.f || x.y != 0.f;
         float2 z = make_float2(0.f, 0.f);
         if (live) {
-          const double2 kk2[2] = {k0[r], k1[r]};
-          const double ph = knot_hermite(kk2, G, double((lox + w) & (G - 1)) * inv_g);
-          const float2 e = cis_cycles(ph);
+          // heterodyne phase in quarter turns
+          const double t = double((jph + w) & (G - 1));
+          const double c4 = fma(fma(fma(k1[r].y, t, k1[r].x), t, k0[r].y), t, k0[r].x);
+          const double q = rint(c4);
+          const float2 e = cis_quarter(int(q), static_cast<float>(c4 - q));
           // x * exp(-2 pi i f_h dl)
           z = make_float2(x.x * e.x + x.y * e.y, x.y * e.x - x.x * e.y);
         }
@@ -730,18 +742,36 @@ __device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp
   return true;
 }
 
+// Grid knot at k: q = (T_k - tau_k)/dt from the detector epoch of tau = tau0 +
+// k dt (fixed point and two Newton steps) and dq/dk = (R'(tau) - roemer'(T)) /
+// (1 + roemer'(T)); far: the delay exceeds the plan's max_delay.
+template <bool KEP>
+__device__ __forceinline__ double2 grid_knot(const PlanConst& P, const TmplParams& tp,
+                                             const CachedRoemer& re, int64_t k, bool& far) {
+  const double tau = P.tau0 + P.dt * double(k);
+  double rb, rbd, x;
+  orbit_delay<KEP>(tp, tau, rb, rbd);
+  double dl = grid_delay_rb(re, rb, tau);
+  dl = grid_delay_newton(re, tau, rb, dl, x);
+  dl = grid_delay_newton(re, tau, rb, dl, x);
+  far = !(fabs(dl) <= P.max_delay);
+  return make_double2(dl * P.inv_dt, (rbd - x) / (1.0 + x));
+}
+
 // Timing knots of one template (slot) or sky/orbit group whose knot spacing
 // G = 2^tp.knot_log2 is at least 2^kKnotLogGlobal, for the detector
 // blockIdx.z: the same FP64 solves as the tiles' own knots (steps (iv) and
 // (iii) of Sec. 3), one knot per thread, with the Roemer delay from the
 // detector's tabulated trajectory (the interval read last kept in
-// registers).  The first knot_grid_blocks blocks solve grid knots and turn
-// each interval's two end knots into its record (the cubic Hermite form of q
-// between them, relative to the integer part of the interval's first source
-// position); the knot at a tile's middle point also writes the tile's
-// antenna Taylor record.  The other blocks solve the sample knots.  A delay
-// beyond the plan's max_delay flags the template (as a tile whose delay
-// leaves its staged nodes does).
+// registers).  Three ranges of blocks:
+//  - knot_grid_blocks blocks solve the grid knots and turn each interval's two
+//    end knots into its record (the cubic Hermite form of q between them,
+//    relative to the integer part of the interval's first source position);
+//  - knot_tile_blocks blocks (plans with res_taylor) solve the knot at each
+//    tile's middle point again and write the tile's antenna Taylor record;
+//  - the rest solve the sample knots.
+// A delay beyond the plan's max_delay flags the template (as a tile whose
+// delay leaves its staged nodes does).
 template <bool GROUPED, bool KEP>
 __global__ __launch_bounds__(kKnotThreads) void k_knots(PlanConst P, void* ws, ChunkMap map,
                                                         int slots) {
@@ -760,23 +790,14 @@ __global__ __launch_bounds__(kKnotThreads) void k_knots(PlanConst P, void* ws, C
   const int G = 1 << kl;
   const CachedRoemer re{d.ephem, tp.nhat, P.n_eph, P.eph_t0, P.eph_dt, P.inv_eph_dt};
   const int64_t gblocks = knot_grid_blocks(P.knot_gcap);
+  const int64_t tblocks = knot_tile_blocks(P.k_pad);
+  const int64_t b = blockIdx.x;
   bool far = false;
-  if (int64_t(blockIdx.x) < gblocks) {
+  if (b < gblocks) {
     const int64_t last = P.k_pad >> kl;
-    const int64_t e = int64_t(blockIdx.x) * (kKnotThreads - 1) + threadIdx.x;
+    const int64_t e = b * (kKnotThreads - 1) + threadIdx.x;
     double2 kv = make_double2(0.0, 0.0);
-    if (e <= last) {
-      // grid knot e: detector epoch of tau = tau0 + e G dt (fixed point and
-      // two Newton steps) and dq/dk = (R'(tau) - roemer'(T)) / (1 + roemer'(T))
-      const double tau = P.tau0 + P.dt * double(e * G);
-      double rb, rbd, x;
-      orbit_delay<KEP>(tp, tau, rb, rbd);
-      double dl = grid_delay_rb(re, rb, tau);
-      dl = grid_delay_newton(re, tau, rb, dl, x);
-      dl = grid_delay_newton(re, tau, rb, dl, x);
-      kv = make_double2(dl * P.inv_dt, (rbd - x) / (1.0 + x));
-      far = !(fabs(dl) <= P.max_delay);
-    }
+    if (e <= last) kv = grid_knot<KEP>(P, tp, re, e * G, far);
     __shared__ double2 nb[kKnotThreads];
     nb[threadIdx.x] = kv;
     __syncthreads();
@@ -790,29 +811,51 @@ __global__ __launch_bounds__(kKnotThreads) void k_knots(PlanConst P, void* ws, C
       }
       const double a = d.off + c0.x;
       const double fa = floor(a);
-      const float th = float(a - fa);
-      reinterpret_cast<float4*>(kn)[e] = make_float4(th, float(c0.y), float(c1.x), float(c1.y));
+      reinterpret_cast<float4*>(kn)[e] =
+          make_float4(float(a - fa), float(c0.y), float(c1.x), float(c1.y));
       reinterpret_cast<int32_t*>(kn + P.knot_ioff)[e] = int32_t(fa);
-      const int64_t k = e << kl;
-      if (P.res_taylor && (k & (kResTile - 1)) == kResTile / 2) {
-        float c[kTaylorCoef];
-        antenna_taylor(tp, X, tp.alpha_cyc[X] - P.sid_rate_cyc * (P.tau0 + P.dt * double(k) +
-                                                                  kv.x * P.dt), c);
-        float* tr = reinterpret_cast<float*>(kn + P.knot_toff + (k >> kResTileLog) * kTileRecUnits);
+    }
+  } else if (b < gblocks + tblocks) {
+    const int64_t t = (b - gblocks) * kKnotThreads + threadIdx.x;
+    if (P.res_taylor && t < (P.k_pad >> kResTileLog)) {
+      // the tile's middle point is a knot (G divides half a tile)
+      const int64_t k = (t << kResTileLog) + kResTile / 2;
+      bool far_t;
+      const double2 kv = grid_knot<KEP>(P, tp, re, k, far_t);
+      float c[kTaylorCoef];
+      antenna_taylor(tp, X, tp.alpha_cyc[X] - P.sid_rate_cyc * (P.tau0 + P.dt * double(k) +
+                                                                kv.x * P.dt), c);
+      const double a = d.off + kv.x;
+      const double fa = floor(a);
+      float* tr = reinterpret_cast<float*>(kn + P.knot_toff + t * kTileRecUnits);
 #pragma unroll
-        for (int n = 0; n < kTaylorCoef; ++n) tr[n] = c[n];
-        tr[kTaylorCoef] = th;
-        tr[kTaylorCoef + 1] = __int_as_float(int32_t(fa));
-      }
+      for (int n = 0; n < kTaylorCoef; ++n) tr[n] = c[n];
+      tr[kTaylorCoef] = float(a - fa);
+      tr[kTaylorCoef + 1] = __int_as_float(int32_t(fa));
     }
   } else {
-    // sample knot m: heterodyne phase at t = t0 + m G dt and its change per sample
-    const int64_t m = (int64_t(blockIdx.x) - gblocks) * kKnotThreads + threadIdx.x;
-    if (m <= ((d.n - 1) >> kl) + 1) {
+    // sample knot m: heterodyne phase at t = t0 + m G dt and its change per
+    // sample; the record of interval m from knots m and m + 1
+    const int64_t last = ((d.n - 1) >> kl) + 1;
+    const int64_t m = (b - gblocks - tblocks) * (kKnotThreads - 1) + threadIdx.x;
+    double2 kv = make_double2(0.0, 0.0);
+    if (m <= last) {
       double ph, dph, delay;
       sample_phase_d<KEP>(re, tp, d.t0 + P.dt * double(m * G), P.f_het, ph, dph, delay);
-      kn[P.knot_soff + m] = make_double2(ph, dph * P.dt);
+      kv = make_double2(ph, dph * P.dt);
       far = !(fabs(delay) <= P.max_delay);
+    }
+    __shared__ double2 nb[kKnotThreads];
+    nb[threadIdx.x] = kv;
+    __syncthreads();
+    if (threadIdx.x < kKnotThreads - 1 && m < last) {
+      double2 c0, c1;
+      hermite_interval(kv, nb[threadIdx.x + 1], double(G), c0, c1);
+      // in quarter turns and in t = u G (scalings by powers of two: exact)
+      const double ig = 1.0 / double(G);
+      double2* rec = kn + P.knot_soff + 2 * m;
+      rec[0] = make_double2(fmod(4.0 * c0.x, 4.0), 4.0 * c0.y * ig);
+      rec[1] = make_double2(4.0 * c1.x * ig * ig, 4.0 * c1.y * ig * ig * ig);
     }
   }
   if (far) atomicOr(status_word, kStatusNodes);
