@@ -40,10 +40,10 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # header and build flags with this digest; for any other version the
 # roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "61679f00df06cedcf246358b3589ccef16bf12407665fded8c62e22e8b5240cb",
+    "sources_sha256": "4cf617e30c973fe0e6a26e48c0182e8fee2786a33ea1d9324f3f14b4e5e522df",
     "bytes_per_template": {
-        "binary": {"resample": 182439479, "fft_columns": 260426214, "fft_rows_2f": 231269904},
-        "sky_spindown": {"resample": 3073913, "fft_columns": 48081548, "fft_rows_2f": 41979777},
+        "binary": {"resample": 190060000, "fft_columns": 260410000, "fft_rows_2f": 230840000},
+        "sky_spindown": {"resample": 3171700, "fft_columns": 48130000, "fft_rows_2f": 41990000},
     },
 }
 

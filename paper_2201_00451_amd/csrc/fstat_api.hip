@@ -324,7 +324,6 @@ PlanConst make_const(const fstat_plan* p, const fstat_inputs* in) {
   P.knot_ioff = knot_ioff(p);
   P.knot_soff = knot_soff(p);
   P.knot_toff = knot_toff(p);
-  P.knot_scap = knot_scap(p);
   P.knot_bytes = int64_t(knot_area_bytes(p));
   P.res_taylor = std::fabs(2.0 * M_PI * P.sid_rate_cyc * d.dt) * double(kResTile / 2 + 1) <=
                  kTaylorMaxAngle;
@@ -449,8 +448,12 @@ KnotFn knot_kernel(const fstat_plan* p, bool grouped) {
 void launch_knots(const fstat_plan* p, const PlanConst& P, const ChunkMap& map, int slots,
                   bool grouped, int n_res, void* ws, hipStream_t st) {
   if (n_res < 1 || (!grouped && P.knot_offset == 0)) return;
-  const int64_t blocks =
-      knot_grid_blocks(P.knot_gcap) + knot_tile_blocks(P.k_pad) + knot_samp_blocks(P.knot_scap);
+  // at the coarsest knot spacing (finer ones loop)
+  int64_t scap = 0;
+  for (int X = 0; X < P.ndet; ++X)
+    scap = std::max<int64_t>(scap, ((P.det[X].n - 1) >> kKnotLogMax) + 2);
+  const int64_t blocks = knot_grid_blocks((P.k_pad >> kKnotLogMax) + 1) +
+                         knot_tile_blocks(P.k_pad) + knot_samp_blocks(scap);
   hipLaunchKernelGGL(knot_kernel(p, grouped), dim3(unsigned(blocks), n_res, p->desc.ndet),
                      dim3(kKnotThreads), 0, st, P, ws, map, slots);
 }

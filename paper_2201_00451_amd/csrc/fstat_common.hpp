@@ -130,7 +130,6 @@ struct PlanConst {
   int64_t knot_stride;  // 16-byte units per detector of a knot area
   int64_t knot_gcap;    // grid intervals of a detector's area
   int64_t knot_ioff, knot_soff, knot_toff;  // units to the integers, sample intervals, tiles
-  int64_t knot_scap;    // sample intervals of a detector's area
   int32_t res_taylor;   // the tiles take the antenna patterns' Taylor form
   int64_t knot_bytes;   // bytes of a knot area (each group buffer holds one)
   int64_t knot_offset;  // plain path: bytes from a slot's start to its knot area;

@@ -581,7 +581,6 @@ __device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp
   }
   const int kl = tp.knot_log2;
   const int G = 1 << kl;
-  const double inv_g = 1.0 / double(G);
   const float inv_gf = 1.0f / float(G);
   const double tau_s = P.tau0 + P.dt * double(k_s);
   const int64_t e_s = k_s >> kl;  // the tile's first interval
@@ -764,7 +763,7 @@ __device__ __forceinline__ double2 grid_knot(const PlanConst& P, const TmplParam
 // (iii) of Sec. 3), one knot per thread, with the Roemer delay from the
 // detector's tabulated trajectory (the interval read last kept in
 // registers).  Three ranges of blocks:
-//  - knot_grid_blocks blocks solve the grid knots and turn each interval's two
+//  - the first blocks solve the grid knots and turn each interval's two
 //    end knots into its record (the cubic Hermite form of q between them,
 //    relative to the integer part of the interval's first source position);
 //  - knot_tile_blocks blocks (plans with res_taylor) solve the knot at each
@@ -789,31 +788,45 @@ __global__ __launch_bounds__(kKnotThreads) void k_knots(PlanConst P, void* ws, C
                 X * P.knot_stride;
   const int G = 1 << kl;
   const CachedRoemer re{d.ephem, tp.nhat, P.n_eph, P.eph_t0, P.eph_dt, P.inv_eph_dt};
-  const int64_t gblocks = knot_grid_blocks(P.knot_gcap);
+  // blocks launched per range: enough for the coarsest spacing; a template
+  // with a finer one walks its chunks of kKnotThreads - 1 knots in steps of
+  // the range's block count
+  int64_t scap = 0;
+  for (int Y = 0; Y < P.ndet; ++Y) scap = max(scap, ((P.det[Y].n - 1) >> kKnotLogMax) + 2);
+  const int64_t gblocks = knot_grid_blocks((P.k_pad >> kKnotLogMax) + 1);
   const int64_t tblocks = knot_tile_blocks(P.k_pad);
+  const int64_t sblocks = knot_samp_blocks(scap);
   const int64_t b = blockIdx.x;
+  __shared__ double2 nb[kKnotThreads];
   bool far = false;
   if (b < gblocks) {
     const int64_t last = P.k_pad >> kl;
-    const int64_t e = b * (kKnotThreads - 1) + threadIdx.x;
-    double2 kv = make_double2(0.0, 0.0);
-    if (e <= last) kv = grid_knot<KEP>(P, tp, re, e * G, far);
-    __shared__ double2 nb[kKnotThreads];
-    nb[threadIdx.x] = kv;
-    __syncthreads();
-    if (threadIdx.x < kKnotThreads - 1 && e <= last) {
-      double2 c0, c1;
-      if (e < last) {
-        hermite_interval(kv, nb[threadIdx.x + 1], double(G), c0, c1);
-      } else {
-        c0 = make_double2(kv.x, 0.0);
-        c1 = make_double2(0.0, 0.0);
+    const int64_t chunks = knot_grid_blocks(last + 1);
+    for (int64_t c = b; c < chunks; c += gblocks) {
+      const int64_t e = c * (kKnotThreads - 1) + threadIdx.x;
+      double2 kv = make_double2(0.0, 0.0);
+      if (e <= last) {
+        bool f;
+        kv = grid_knot<KEP>(P, tp, re, e * G, f);
+        far |= f;
       }
-      const double a = d.off + c0.x;
-      const double fa = floor(a);
-      reinterpret_cast<float4*>(kn)[e] =
-          make_float4(float(a - fa), float(c0.y), float(c1.x), float(c1.y));
-      reinterpret_cast<int32_t*>(kn + P.knot_ioff)[e] = int32_t(fa);
+      nb[threadIdx.x] = kv;
+      __syncthreads();
+      if (threadIdx.x < kKnotThreads - 1 && e <= last) {
+        double2 c0, c1;
+        if (e < last) {
+          hermite_interval(kv, nb[threadIdx.x + 1], double(G), c0, c1);
+        } else {
+          c0 = make_double2(kv.x, 0.0);
+          c1 = make_double2(0.0, 0.0);
+        }
+        const double a = d.off + c0.x;
+        const double fa = floor(a);
+        reinterpret_cast<float4*>(kn)[e] =
+            make_float4(float(a - fa), float(c0.y), float(c1.x), float(c1.y));
+        reinterpret_cast<int32_t*>(kn + P.knot_ioff)[e] = int32_t(fa);
+      }
+      __syncthreads();
     }
   } else if (b < gblocks + tblocks) {
     const int64_t t = (b - gblocks) * kKnotThreads + threadIdx.x;
@@ -837,25 +850,28 @@ __global__ __launch_bounds__(kKnotThreads) void k_knots(PlanConst P, void* ws, C
     // sample knot m: heterodyne phase at t = t0 + m G dt and its change per
     // sample; the record of interval m from knots m and m + 1
     const int64_t last = ((d.n - 1) >> kl) + 1;
-    const int64_t m = (b - gblocks - tblocks) * (kKnotThreads - 1) + threadIdx.x;
-    double2 kv = make_double2(0.0, 0.0);
-    if (m <= last) {
-      double ph, dph, delay;
-      sample_phase_d<KEP>(re, tp, d.t0 + P.dt * double(m * G), P.f_het, ph, dph, delay);
-      kv = make_double2(ph, dph * P.dt);
-      far = !(fabs(delay) <= P.max_delay);
-    }
-    __shared__ double2 nb[kKnotThreads];
-    nb[threadIdx.x] = kv;
-    __syncthreads();
-    if (threadIdx.x < kKnotThreads - 1 && m < last) {
-      double2 c0, c1;
-      hermite_interval(kv, nb[threadIdx.x + 1], double(G), c0, c1);
-      // in quarter turns and in t = u G (scalings by powers of two: exact)
-      const double ig = 1.0 / double(G);
-      double2* rec = kn + P.knot_soff + 2 * m;
-      rec[0] = make_double2(fmod(4.0 * c0.x, 4.0), 4.0 * c0.y * ig);
-      rec[1] = make_double2(4.0 * c1.x * ig * ig, 4.0 * c1.y * ig * ig * ig);
+    const int64_t chunks = knot_samp_blocks(last + 1);
+    for (int64_t c = b - gblocks - tblocks; c < chunks; c += sblocks) {
+      const int64_t m = c * (kKnotThreads - 1) + threadIdx.x;
+      double2 kv = make_double2(0.0, 0.0);
+      if (m <= last) {
+        double ph, dph, delay;
+        sample_phase_d<KEP>(re, tp, d.t0 + P.dt * double(m * G), P.f_het, ph, dph, delay);
+        kv = make_double2(ph, dph * P.dt);
+        far |= !(fabs(delay) <= P.max_delay);
+      }
+      nb[threadIdx.x] = kv;
+      __syncthreads();
+      if (threadIdx.x < kKnotThreads - 1 && m < last) {
+        double2 c0, c1;
+        hermite_interval(kv, nb[threadIdx.x + 1], double(G), c0, c1);
+        // in quarter turns and in t = u G (scalings by powers of two: exact)
+        const double ig = 1.0 / double(G);
+        double2* rec = kn + P.knot_soff + 2 * m;
+        rec[0] = make_double2(fmod(4.0 * c0.x, 4.0), 4.0 * c0.y * ig);
+        rec[1] = make_double2(4.0 * c1.x * ig * ig, 4.0 * c1.y * ig * ig * ig);
+      }
+      __syncthreads();
     }
   }
   if (far) atomicOr(status_word, kStatusNodes);
