@@ -494,7 +494,7 @@ def config_refine(seed=5, ndays=30.0, dt=1.0, n_fft=1 << 22, f_het=400.0, band=0
 def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmpl=4, D=8,
                rho=15.0, noise=True, binary=False, gaps=False, noise_vars=None, f_inj=None,
                bin_lo=0, n_bins=None, keep_f64=False, model=None, sites=None, f1dot=None,
-               t0=0.0, noise_seed=None, f2dot=0.0, ecc=None, argp=None):
+               t0=0.0, noise_seed=None, f2dot=0.0, ecc=None, argp=None, eph_spacing=60.0):
     """Small search (a few hours of data) for oracle pins and quick parity.
 
     t0 shifts the data (and the computed grid) in time with the reference time
@@ -503,7 +503,9 @@ def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmp
     f2dot is the injection's second frequency derivative (the templates carry
     it too).  ecc and argp (binary only) make the orbit Keplerian; the
     templates then have ten columns (eccentricity and argument of periapsis
-    last)."""
+    last).  eph_spacing is the tabulated trajectory's time step (coarse grids
+    need a coarser table: a resampling tile stages a bounded number of its
+    nodes)."""
     ss = np.random.SeedSequence(seed)
     s_par, s_gap = ss.spawn(2)
     rng = np.random.default_rng(s_par)
@@ -544,7 +546,7 @@ def small_case(seed=11, n=6000, dt=2.0, n_fft=1 << 14, ndet=1, f_het=100.0, ntmp
     nb = n_fft if n_bins is None else n_bins
     ds = Dataset("small", dt, f_het, 0.0, grid_origin(t0, dt, margin), n_fft, D, bin_lo, nb,
                  dets, xs, vs, tm, ephem_model=model, injections=[inj])
-    return finish(ds)
+    return finish(ds, spacing=eph_spacing)
 
 
 def config_uneven(seed=4, n_search=256, days=(1.0, 30.0), dts=(0.5, 1.0, 2.0, 5.0),

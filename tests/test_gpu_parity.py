@@ -82,6 +82,11 @@ CASES = {
                    argp=1.2),
     "kepler_high_e": dict(seed=67, n=6000, n_fft=1 << 14, ndet=1, binary=True, ecc=0.7,
                           argp=-2.4, D=12),
+    # grids coarse enough that a 512-point tile spans more than 0.1 rad of
+    # sidereal angle: the tiles evaluate the antenna patterns per point (knot
+    # spacing 16 and 32, so the knots are still solved ahead)
+    "dt10": dict(seed=68, n=6000, n_fft=1 << 14, ndet=2, dt=10.0, gaps=True, eph_spacing=120.0),
+    "dt6_binary": dict(seed=69, n=8000, n_fft=1 << 14, ndet=2, dt=6.0, binary=True),
 }
 
 
@@ -101,7 +106,7 @@ def test_antenna_moments_definition(torch_dev):
             assert abs(got[X, 2 * n] + 1j * got[X, 2 * n + 1] - ref) < 1e-9 * det.n
 
 
-@pytest.mark.parametrize("case", ["two_det_gaps", "binary"])
+@pytest.mark.parametrize("case", ["two_det_gaps", "binary", "dt10"])
 def test_resampled_series_parity(torch_dev, case):
     from paper_2201_00451_amd import binding
     say(f"resample parity {case}")
