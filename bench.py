@@ -40,10 +40,10 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # header and build flags with this digest; for any other version the
 # roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "4cf617e30c973fe0e6a26e48c0182e8fee2786a33ea1d9324f3f14b4e5e522df",
+    "sources_sha256": "77f05a6de8d25b92e00922450e45766c372c45a6c01851a78feb5ffbd8403d3a",
     "bytes_per_template": {
-        "binary": {"resample": 190060000, "fft_columns": 260410000, "fft_rows_2f": 230840000},
-        "sky_spindown": {"resample": 3171700, "fft_columns": 48130000, "fft_rows_2f": 41990000},
+        "binary": {"resample": 190060039, "fft_columns": 260397988, "fft_rows_2f": 230578007},
+        "sky_spindown": {"resample": 3171328, "fft_columns": 48131410, "fft_rows_2f": 41980558},
     },
 }
 

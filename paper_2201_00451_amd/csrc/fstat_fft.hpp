@@ -535,14 +535,20 @@ __device__ __forceinline__ unsigned long long best_key(float v2, int64_t o) {
          static_cast<unsigned long long>(o);
 }
 // The workgroup's keys into the template's entry: wavefront maximum, one
-// atomic per wave.
+// atomic per wave, and none where the entry already holds as much (it only
+// grows, so a smaller key can never be the maximum; every row item of a
+// template would otherwise contend for the one address).
 __device__ __forceinline__ void best_to_global(const RowOutput& out, int64_t tmpl,
                                                unsigned long long key) {
   for (int off = 32; off > 0; off >>= 1) {
     const unsigned long long o = __shfl_down(key, off, 64);
     key = o > key ? o : key;
   }
-  if ((threadIdx.x & 63) == 0 && key != 0ull) atomicMax(out.best + tmpl, key);
+  if ((threadIdx.x & 63) == 0 && key != 0ull) {
+    const unsigned long long cur =
+        __hip_atomic_load(out.best + tmpl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (key > cur) atomicMax(out.best + tmpl, key);
+  }
 }
 
 template <int MODE>
@@ -799,10 +805,10 @@ __global__ __launch_bounds__(NT) void k_fft_rows(PlanConst P, void* ws, ChunkMap
 // (-1)^h x[c + L/2]) W_L^{c h}; entries 2k + h of the row transform are the
 // (L/2)-point transform of y_h), y_1 waiting in registers while y_0 goes
 // through LDS and the epilogue, so two workgroups share a compute unit
-// (plain 2F and candidates; the other epilogues need more registers and run
-// one).
+// (plain 2F; the other epilogues need more registers and run one: the
+// candidate epilogue at two would spill the waiting half).
 template <int LOGL, int RQ, int NT, int MODE, int MLR>
-__global__ __launch_bounds__(NT, MODE == kRow2F || MODE == kRowCand ? NT / 128 : NT / 256) void
+__global__ __launch_bounds__(NT, MODE == kRow2F ? NT / 128 : NT / 256) void
 k_fft_rows_half(
     PlanConst P, void* ws, ChunkMap map, int slots, int log_rr, RowOutput out) {
   extern __shared__ float2 lds[];

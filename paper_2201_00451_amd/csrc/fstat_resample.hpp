@@ -640,11 +640,13 @@ __device__ inline bool resample_tile_gk(const PlanConst& P, const TmplParams& tp
         const int w = r * kResThreads + tid;
         const bool in = w >= wlo && w < whi;
         xv[r] = in ? xs[w] : make_float2(0.f, 0.f);
-        // record of the sample's interval (of the nearest data sample)
-        const int32_t wc = any ? (w < wlo ? wlo : (w >= whi ? whi - 1 : w)) : wlo;
+        // record of the sample's interval (of the nearest data sample); none
+        // for a wave past the window
+        const bool rec = any && r * kResThreads + w0 < Wx;
+        const int32_t wc = rec ? (w < wlo ? wlo : (w >= whi ? whi - 1 : w)) : wlo;
         const double2* rc = sr + 2 * ((jph + wc) >> kl);
-        k0[r] = any ? rc[0] : make_double2(0.0, 0.0);
-        k1[r] = any ? rc[1] : make_double2(0.0, 0.0);
+        k0[r] = rec ? rc[0] : make_double2(0.0, 0.0);
+        k1[r] = rec ? rc[1] : make_double2(0.0, 0.0);
       }
 #pragma unroll
       for (int r = 0; r < kRounds; ++r) {
