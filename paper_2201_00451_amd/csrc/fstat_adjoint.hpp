@@ -326,20 +326,24 @@ __global__ __launch_bounds__(kResThreads, 2) void k_grad(PlanConst P, void* ws) 
   }
 }
 
-// Per template: sum the tile partials in tile order; NaN for a flagged
-// template; zero orbit derivatives for an isolated one.
-__global__ void k_grad_final(PlanConst P, void* ws, ChunkMap map, int64_t ntiles,
-                             double* __restrict__ grad) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= map.n_tmpl * kGradParams) return;
-  const int slot = t / kGradParams, q = t % kGradParams;
+// Per template (one workgroup each): the totals of the tile partials in a
+// fixed order; NaN for a flagged template; zero orbit derivatives for an
+// isolated one.
+__global__ __launch_bounds__(kFinalThreads) void k_grad_final(PlanConst P, void* ws, ChunkMap map,
+                                                              int64_t ntiles,
+                                                              double* __restrict__ grad) {
+  const int slot = blockIdx.x;
+  double s[kGradParams];
+  tile_sums<kGradParams>(slot_partials(ws, P, slot), ntiles, s);
+  if (threadIdx.x != 0) return;
   const TmplParams& tp = *slot_params(ws, P, slot);
-  const double* part = slot_partials(ws, P, slot);
-  double s = 0.0;
-  for (int64_t b = 0; b < ntiles; ++b) s += part[b * 8 + q];
-  if (tp.status != 0) s = __builtin_nan("");
-  if (tp.asini == 0.0 && q >= 4 && tp.status == 0) s = 0.0;
-  grad[map.tmpl[slot] * kGradParams + q] = s;
+#pragma unroll
+  for (int q = 0; q < kGradParams; ++q) {
+    double v = s[q];
+    if (tp.status != 0) v = __builtin_nan("");
+    if (tp.asini == 0.0 && q >= 4 && tp.status == 0) v = 0.0;
+    grad[map.tmpl[slot] * kGradParams + q] = v;
+  }
 }
 
 }  // namespace fstat

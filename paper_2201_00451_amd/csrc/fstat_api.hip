@@ -706,11 +706,11 @@ fstat_status launch_grad_bin_chunk(const fstat_plan* p, const PlanConst& P,
   hipLaunchKernelGGL(k_prologue, dim3((n + 63) / 64), dim3(64), 0, st, P, templates, map, ws);
   hipLaunchKernelGGL(resample_bin_kernel(p), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws, map, bins);
-  hipLaunchKernelGGL(k_bin_final, dim3((n + 63) / 64), dim3(64), 0, st, P, ws, map,
+  hipLaunchKernelGGL(k_bin_final, dim3(n), dim3(kFinalThreads), 0, st, P, ws, map,
                      int64_t(tiles), bins, twoF);
   hipLaunchKernelGGL(grad_kernel(p, true), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws);
-  hipLaunchKernelGGL(k_grad_final, dim3((n * kGradParams + 63) / 64), dim3(64), 0, st, P, ws, map,
+  hipLaunchKernelGGL(k_grad_final, dim3(n), dim3(kFinalThreads), 0, st, P, ws, map,
                      int64_t(tiles), grad);
   return check_hip(hipGetLastError(), "single-bin adjoint launch");
 }
@@ -747,7 +747,7 @@ fstat_status launch_grad_chunk(const fstat_plan* p, const PlanConst& P, const do
                      row_output(nullptr, nullptr));
   hipLaunchKernelGGL(grad_kernel(p, false), dim3(tiles, n),
                      dim3(kResThreads), 0, st, P, ws);
-  hipLaunchKernelGGL(k_grad_final, dim3((n * kGradParams + 63) / 64), dim3(64), 0, st, P, ws, map,
+  hipLaunchKernelGGL(k_grad_final, dim3(n), dim3(kFinalThreads), 0, st, P, ws, map,
                      int64_t(tiles), grad);
   return check_hip(hipGetLastError(), "adjoint launch");
 }

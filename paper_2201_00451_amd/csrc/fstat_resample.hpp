@@ -1046,22 +1046,49 @@ __global__ __launch_bounds__(kResThreads, 4) void k_resample_bin(PlanConst P, vo
   }
 }
 
+// Per-template totals of per-tile partials (8 doubles per tile, the first
+// NQ used) by one workgroup: each thread sums a fixed stripe of tiles, then a
+// fixed tree combines the threads, so a template's totals come out the same
+// on every run.  The totals land in s of thread 0.
+constexpr int kFinalThreads = 256;
+template <int NQ>
+__device__ inline void tile_sums(const double* __restrict__ part, int64_t ntiles, double (&s)[NQ]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) s[q] = 0.0;
+  for (int64_t b = tid; b < ntiles; b += kFinalThreads)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) s[q] += part[b * 8 + q];
+  __shared__ double red[NQ][kFinalThreads];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) red[q][tid] = s[q];
+  __syncthreads();
+  for (int off = kFinalThreads / 2; off > 0; off >>= 1) {
+    if (tid < off)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) red[q][tid] += red[q][tid + off];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) s[q] = red[q][0];
+}
+
 // Per template: Fa'(m), Fb'(m) from the tile partials (tile order), 2F at the
 // bin, and the adjoint spectrum of L = 2F(m) at that bin, H = conj(F'(m))
 // (kept in the parameter block for the gradient kernel).  A bin outside the
 // band flags the template.
-__global__ void k_bin_final(PlanConst P, void* ws, ChunkMap map, int64_t ntiles,
-                            const int64_t* __restrict__ bins, float* __restrict__ twoF) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= map.n_tmpl) return;
+__global__ __launch_bounds__(kFinalThreads) void k_bin_final(PlanConst P, void* ws, ChunkMap map,
+                                                             int64_t ntiles,
+                                                             const int64_t* __restrict__ bins,
+                                                             float* __restrict__ twoF) {
+  const int slot = blockIdx.x;
+  double f[4];
+  tile_sums<4>(slot_partials(ws, P, slot), ntiles, f);
+  if (threadIdx.x != 0) return;
   TmplParams& tp = *slot_params(ws, P, slot);
-  const double* part = slot_partials(ws, P, slot);
   const int64_t bin = bins[map.tmpl[slot]];
   if (bin < 0 || bin >= P.n_bins) tp.status |= kStatusBin;
   if (tp.status != 0) atomicAdd(flag_counter(ws), 1ull);
-  double f[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t b = 0; b < ntiles; ++b)
-    for (int q = 0; q < 4; ++q) f[q] += part[b * 8 + q];
   tp.bin_nat = band_bin_nat(P, bin);
   tp.hbin[0] = f[0];
   tp.hbin[1] = -f[1];
