@@ -77,7 +77,9 @@ __global__ __launch_bounds__(kResThreads, 2) void k_grad(PlanConst P, void* ws) 
   const int tid = threadIdx.x;
 
   __shared__ float2 zs[kResWcap];
-  __shared__ float dzs[5][kResWcap];
+  // the staged samples times their five delay derivatives (one product per
+  // sample instead of one per tap)
+  __shared__ float2 zqs[5][kResWcap];
   __shared__ double2 nodes[3][kNodeCap];
   __shared__ int64_t win_lo, win_hi;
   __shared__ int bad;
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(kResThreads, 2) void k_grad(PlanConst P, void* ws) 
       }
       zs[w] = z;
 #pragma unroll
-      for (int q = 0; q < 5; ++q) dzs[q][w] = dz[q];
+      for (int q = 0; q < 5; ++q) zqs[q][w] = make_float2(dz[q] * z.x, dz[q] * z.y);
     }
     __syncthreads();
 #pragma unroll
@@ -258,9 +260,9 @@ __global__ __launch_bounds__(kResThreads, 2) void k_grad(PlanConst P, void* ws) 
         Sd.y = fmaf(hp, zv.y, Sd.y);
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-          const float hq = h * dzs[q][base + t];
-          S[q].x = fmaf(hq, zv.x, S[q].x);
-          S[q].y = fmaf(hq, zv.y, S[q].y);
+          const float2 zq = zqs[q][base + t];
+          S[q].x = fmaf(h, zq.x, S[q].x);
+          S[q].y = fmaf(h, zq.y, S[q].y);
         }
       }
       // antenna patterns and their x derivatives at T_k
