@@ -40,10 +40,10 @@ METRIC = "templates/s (full-band 2F) & % HBM roofline, batched vs plain, rel err
 # header and build flags with this digest; for any other version the
 # roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "77f05a6de8d25b92e00922450e45766c372c45a6c01851a78feb5ffbd8403d3a",
+    "sources_sha256": "86893e7221d92b932e52b8eb5c6a174c272a19769c8573477d2a24167977684c",
     "bytes_per_template": {
-        "binary": {"resample": 190060039, "fft_columns": 260397988, "fft_rows_2f": 230578007},
-        "sky_spindown": {"resample": 3171328, "fft_columns": 48131410, "fft_rows_2f": 41980558},
+        "binary": {"resample": 190059765, "fft_columns": 260420974, "fft_rows_2f": 231387746},
+        "sky_spindown": {"resample": 3171116, "fft_columns": 48114543, "fft_rows_2f": 41978569},
     },
 }
 
